@@ -1,0 +1,216 @@
+/*
+ * sta.h - C ABI of a levelized static timing analysis (STA) engine for AMD MI355X (gfx950).
+ *
+ * The engine runs the four stages of parallel STA described in Warp-STAR
+ * (arXiv 2603.28381, Sec. 2.1): RC net delay, levelization, forward propagation of
+ * arrival times (AT) and backward propagation of required times (RAT) and slack, plus
+ * the LSE-smoothed total/worst negative slack of Sec. 3.2 (Eq. 4) and its gradient
+ * with respect to pin coordinates.  Every step of the sweep runs in hand-written HIP
+ * kernels; the host side only validates, levelizes and launches.
+ *
+ * Conventions
+ *  - Units: um (coordinates), ohm, fF, ps.
+ *  - Timing condition index k = 2*mode + transition; mode 0 = early, 1 = late;
+ *    transition 0 = rise, 1 = fall.  Per-pin 4-condition arrays are [pin][k], float32.
+ *  - Status codes are returned by every call; no C++ exception crosses the ABI.
+ *    sta_last_error() returns a thread-local message for the last failing call.
+ *  - Host arrays passed in are copied; the caller may free them when the call returns.
+ *  - Pointers documented as "device" are caller-owned device memory (for example torch
+ *    tensors).  Work is enqueued on the given HIP stream and is asynchronous: keep the
+ *    buffers alive until the stream has synchronized.
+ *  - Calls that touch one sta_graph from several threads or streams at once race;
+ *    serialize them.
+ */
+#ifndef STA_H
+#define STA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STA_ABI_VERSION 1
+#define STA_LUT_N 7          /* NLDM tables are 7 x 7 */
+#define STA_MAX_FANIN 8      /* inputs per cell */
+
+typedef int32_t sta_status;
+#define STA_OK 0
+#define STA_PENDING 1
+#define STA_E_INVALID (-1)   /* malformed input (bad CSR, index out of range, ...) */
+#define STA_E_CYCLE (-2)     /* combinational loop found while levelizing */
+#define STA_E_NOMEM (-3)     /* device or host allocation failed, or a budget is exceeded */
+#define STA_E_DEVICE (-4)    /* a HIP runtime call failed */
+#define STA_E_BUSY (-5)      /* a queue is full; try again later */
+#define STA_E_STATE (-6)     /* call made in the wrong state (e.g. not levelized) */
+#define STA_E_UNKNOWN_TICKET (-7)
+
+/* Pin kinds. PI and CELL_OUT pins drive nets; CELL_IN, FF_D and PO pins are sinks.
+ * FF_D (flop data) and PO (primary output) pins are the timing endpoints. */
+#define STA_PIN_PI 0
+#define STA_PIN_CELL_IN 1
+#define STA_PIN_CELL_OUT 2
+#define STA_PIN_FF_D 3
+#define STA_PIN_PO 4
+
+typedef struct sta_graph sta_graph;
+typedef void* sta_stream;     /* a hipStream_t; NULL means the null stream */
+
+/* Netlist as a DAG of pins, cells and nets (Sec. 2.1): every net has one driver, listed
+ * first in its pin list, and one or more sinks.  Every cell has 1..STA_MAX_FANIN input
+ * pins and one output pin. */
+typedef struct sta_netlist {
+  int32_t n_pins, n_nets, n_cells;
+  const int32_t* net_offsets;      /* [n_nets+1], CSR offsets into net_pins */
+  const int32_t* net_pins;         /* [n_pins], each pin exactly once, driver first */
+  const int32_t* cell_type;        /* [n_cells], index into the library */
+  const int32_t* cell_in_offsets;  /* [n_cells+1], CSR offsets into cell_in_pins */
+  const int32_t* cell_in_pins;     /* [n_cell_inputs], input j of a cell uses arc j of its type */
+  const int32_t* cell_out_pin;     /* [n_cells] */
+  const float* pin_cap;            /* [n_pins], pin capacitance, fF */
+  const int8_t* pin_kind;          /* [n_pins], STA_PIN_* */
+} sta_netlist;
+
+/* NLDM cell library (Sec. 3.1.2: cell arc delay by table interpolation).  One arc per
+ * cell input.  tables[arc][q][i][j], q = 0 delay-rise, 1 delay-fall, 2 slew-rise,
+ * 3 slew-fall (the output transition); row i follows slew_axis (input slew), column j
+ * follows load_axis (load of the driven net).  Lookups interpolate bilinearly and
+ * extrapolate linearly from the edge cell.  Axes must be strictly increasing. */
+typedef struct sta_library {
+  int32_t n_cell_types;
+  const int32_t* arc_offsets;      /* [n_cell_types+1] */
+  const int8_t* arc_unate;         /* [n_arcs], +1 positive unate, -1 negative unate */
+  const float* slew_axis;          /* [STA_LUT_N], ps */
+  const float* load_axis;          /* [STA_LUT_N], fF */
+  const float* tables;             /* [n_arcs][4][STA_LUT_N][STA_LUT_N], ps */
+} sta_library;
+
+/* Constraints and wire model.  Endpoints: late RAT = t_clk - setup, early RAT = hold.
+ * Primary inputs: AT = pi_at, slew = pi_slew.  Wires: r_per_um ohm/um, c_per_um fF/um. */
+typedef struct sta_constraints {
+  float t_clk, setup, hold, pi_at, pi_slew, r_per_um, c_per_um;
+} sta_constraints;
+
+typedef struct sta_graph_info {
+  int32_t n_pins, n_nets, n_cells, n_cell_inputs, n_endpoints;
+  int32_t n_levels;                /* net levels, 0 .. n_levels-1; 0 until levelized */
+  int32_t n_pi_nets;               /* nets at level 0 */
+  int32_t max_level_nets;          /* widest level */
+  int64_t fwd_state_bytes;         /* size of sta_fwd_out.state */
+  int64_t bwd_workspace_bytes;     /* size of sta_bwd_out.workspace */
+  int64_t device_bytes;            /* graph data held on the device after upload */
+} sta_graph_info;
+
+/* sta_forward / sta_backward flags */
+#define STA_SMOOTH (1u << 0)        /* compute the LSE-smoothed late arrival (Eq. 4) */
+#define STA_CANONICAL_IO (1u << 1)  /* x, y and per-pin outputs use the canonical pin order */
+#define STA_RAT (1u << 2)           /* backward: required times and slack per pin */
+#define STA_GRAD (1u << 3)          /* backward: gradient of the smoothed objective */
+#define STA_GRAD_WNS (1u << 4)      /* with STA_GRAD: differentiate WNS_g instead of TNS_g */
+
+/* Forward outputs.  state is required; every other pointer may be NULL. */
+typedef struct sta_fwd_out {
+  void* state;      /* device, >= fwd_state_bytes: per-net arrival state, wire delays and
+                       loads kept for sta_backward; opaque */
+  float* at;        /* device [n_pins][4] arrival times */
+  float* slew;      /* device [n_pins][4] slews */
+  float* atg;       /* device [n_pins][2] smoothed late arrival (rise, fall) */
+  double* scalars;  /* device [4]: WNS, TNS, WNS_g, TNS_g (g: smoothed with gamma) */
+} sta_fwd_out;
+
+/* Backward outputs.  workspace is required; every other pointer may be NULL. */
+typedef struct sta_bwd_out {
+  void* workspace;  /* device, >= bwd_workspace_bytes; opaque, contents undefined after */
+  float* at;        /* device [n_pins][4] arrival times (written here instead of forward) */
+  float* slew;      /* device [n_pins][4] */
+  float* rat;       /* device [n_pins][4] required arrival times; +inf/-inf if unconstrained */
+  float* slack;     /* device [n_pins][4]; late RAT - AT, early AT - RAT */
+  float* dx;        /* device [n_pins] d objective / d x, times grad_scale */
+  float* dy;        /* device [n_pins] */
+  float grad_scale; /* multiplies the gradient (the incoming gradient of an autograd graph) */
+  const double* grad_scale_dev; /* device scalar, or NULL; if set, also multiplies the gradient */
+} sta_bwd_out;
+
+/* ---------------------------------------------------------------------------------------
+ * Graph construction.  Checks the netlist (Sec. 2.1: one driver per net, every pin in
+ * exactly one net, cell pins consistent with their kinds and the library) and copies it.
+ * Errors: STA_E_INVALID with a message; *out is left NULL.
+ * ------------------------------------------------------------------------------------- */
+sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib,
+                           const sta_constraints* cons, sta_graph** out);
+
+/* Levelization (Sec. 2.1 stage 2; Sec. 3.1.2): a net's level is 0 if a primary input
+ * drives it, else 1 + the deepest level among the nets feeding its driving cell.  Builds
+ * the canonical order: nets sorted by (level, original id); pins renumbered net by net,
+ * driver first, then sinks in input order; cells ordered like the nets they drive.
+ * Host only, idempotent.  Errors: STA_E_CYCLE for a combinational loop. */
+sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out);
+
+/* Copies the levelization out (caller-allocated host arrays, sizes from sta_graph_info):
+ * level[n_nets] by original net id, level_offsets[n_levels+1] over canonical nets,
+ * net_perm[n_nets] and pin_perm[n_pins] giving the original id at each canonical
+ * position.  Any pointer may be NULL.  STA_E_STATE if not levelized. */
+sta_status sta_get_levelization(const sta_graph* g, int32_t* level, int32_t* level_offsets,
+                                int32_t* net_perm, int32_t* pin_perm);
+
+/* Uploads the levelized graph, schedule and library tables to the current HIP device.
+ * Idempotent; sta_forward calls it when needed.  Errors: STA_E_STATE, STA_E_DEVICE,
+ * STA_E_NOMEM. */
+sta_status sta_graph_upload(sta_graph* g);
+
+sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info);
+void sta_graph_destroy(sta_graph* g);
+
+/* ---------------------------------------------------------------------------------------
+ * Forward sweep.  RC net delay of every net (Sec. 3.1.1, Eq. 1-3, star nets, wire length
+ * |dx|+|dy|, half of each wire's capacitance at each end), then levels 1..L-1 in order:
+ * cell-arc delay and slew by table lookup, late AT = max over inputs of (input AT + arc
+ * delay), early = min; worst slew; with STA_SMOOTH the late merge is also taken with
+ * LSE (Eq. 4).  Sink AT = driver AT + wire delay; sink slew = sqrt(driver slew^2 +
+ * Impulse^2).  Endpoint scalars (WNS, TNS over late worst transition; smoothed WNS_g,
+ * TNS_g) go to out->scalars.
+ * x, y: device [n_pins] float32 pin coordinates.  gamma_ps > 0 with STA_SMOOTH.
+ * Errors: STA_E_STATE if not levelized, STA_E_INVALID for NULL state or bad gamma.
+ * ------------------------------------------------------------------------------------- */
+sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out* out,
+                       uint32_t flags, float gamma_ps, sta_stream stream);
+
+/* Backward sweep over levels L-1..0 (Sec. 2.1 stage 4; Sec. 3.1.2): RAT from the
+ * endpoints, RAT(driver) = min over sinks (max early) of RAT(sink) - wire delay,
+ * RAT(cell input) = RAT(output) - arc delay, slack.  With STA_GRAD the adjoint of the
+ * smoothed objective (Sec. 3.2) runs in the same sweep (operation fusion): gradient of
+ * TNS_g (or WNS_g with STA_GRAD_WNS) with respect to x, y.  x, y must hold the same
+ * coordinates given to sta_forward, and fwd->state its result (computed with STA_SMOOTH
+ * for STA_GRAD) on the same graph; flags must carry the same STA_CANONICAL_IO and gamma_ps
+ * the same value as that call.
+ * Errors: STA_E_STATE (not levelized / not uploaded), STA_E_INVALID.
+ * ------------------------------------------------------------------------------------- */
+sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                        sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel timing with HIP events (a profiling aid).  While enabled, every kernel launch that
+ * sta_forward / sta_backward make for g is bracketed by two events on its stream.
+ * sta_profile_read waits for those events and returns, per kernel family (STA_K_*), the
+ * number of launches and their summed duration in milliseconds since the last enable;
+ * the arrays hold STA_K_COUNT entries.  Errors: STA_E_DEVICE.
+ * ------------------------------------------------------------------------------------- */
+#define STA_K_RC 0           /* RC net delay, all nets */
+#define STA_K_FWD_LEVEL 1    /* one forward level */
+#define STA_K_EP_PARTIAL 2   /* endpoint partial sums */
+#define STA_K_EP_FINAL 3     /* endpoint scalars */
+#define STA_K_EXPAND 4       /* per-pin forward outputs */
+#define STA_K_EP_SEED 5      /* backward seeds */
+#define STA_K_BWD_LEVEL 6    /* one backward level (RAT, slack, adjoint) */
+#define STA_K_COUNT 7
+sta_status sta_profile_enable(sta_graph* g, int32_t on);
+sta_status sta_profile_read(sta_graph* g, int64_t* launches, double* total_ms);
+
+const char* sta_last_error(void);
+int32_t sta_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STA_H */

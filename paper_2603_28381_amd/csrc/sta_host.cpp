@@ -1,0 +1,486 @@
+// Host side of libsta: input validation, levelization, canonical ordering, lane-group
+// schedules, device upload and the C ABI bookkeeping calls.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "sta_internal.h"
+
+namespace sta {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sta_status fail(sta_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+sta_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? STA_E_NOMEM : STA_E_DEVICE;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void compute_layouts(sta_graph* g) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  g->n_ep_blocks = (g->E + kBlock - 1) / kBlock;
+  g->state.rec = take(sizeof(float4) * 3 * (size_t)g->N);
+  g->state.wire = take(sizeof(float2) * (size_t)g->P);
+  g->state.load = take(sizeof(float) * (size_t)g->N);
+  g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
+  g->state.fin = take(sizeof(double) * 8);
+  g->state.total = off;
+  off = 0;
+  g->work.ratp = take(sizeof(float4) * (size_t)g->P);
+  g->work.adjp = take(sizeof(float4) * (size_t)g->P);
+  g->work.total = off;
+}
+
+// Bilinear interpolation over cell (i, j) written as a + b*tx + c*ty + d*tx*ty, with
+// tx, ty the unclamped local coordinates; linear extrapolation reuses the edge cell.
+void build_lut_coefficients(const sta_graph* g, std::vector<float4>& grid, std::vector<float4>& coef) {
+  const int n = STA_LUT_N, m = n - 1;
+  grid.resize(kLutCells);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double x0 = g->slew_axis[i], x1 = g->slew_axis[i + 1];
+      double y0 = g->load_axis[j], y1 = g->load_axis[j + 1];
+      grid[i * m + j] = make_float4((float)x0, (float)(1.0 / (x1 - x0)), (float)y0, (float)(1.0 / (y1 - y0)));
+    }
+  coef.resize((size_t)g->n_arcs * 2 * kLutCells * 2);
+  for (int a = 0; a < g->n_arcs; ++a)
+    for (int tr = 0; tr < 2; ++tr)
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j)
+          for (int q = 0; q < 2; ++q) {   // q = 0 delay table, 1 slew table
+            const float* T = &g->tables[(((size_t)a * 4 + (size_t)(2 * q + tr)) * n) * n];
+            double t00 = T[i * n + j], t10 = T[(i + 1) * n + j], t01 = T[i * n + j + 1],
+                   t11 = T[(i + 1) * n + j + 1];
+            size_t idx = ((((size_t)a * 2 + tr) * kLutCells) + (size_t)(i * m + j)) * 2 + q;
+            coef[idx] = make_float4((float)t00, (float)(t10 - t00), (float)(t01 - t00),
+                                    (float)(t11 - t10 - t01 + t00));
+          }
+}
+
+LutKeys lut_keys(const sta_graph* g) {
+  LutKeys k;
+  for (int i = 0; i < STA_LUT_N - 2; ++i) {
+    k.x[i] = g->slew_axis[i + 1];
+    k.y[i] = g->load_axis[i + 1];
+  }
+  return k;
+}
+
+// Lane-group schedule of a set of nets: stable order by class, and per-class wave counts.
+static GroupRange group_range(const int* cls_count, int base) {
+  GroupRange r{};
+  int off = base, waves = 0;
+  for (int c = 0; c < kNumClasses; ++c) {
+    r.cls_off[c] = off;
+    r.wave_off[c] = waves;
+    int per_wave = 64 >> (2 + c);           // 16, 8, 4, 2, 1 nets per wave
+    off += cls_count[c];
+    waves += (cls_count[c] + per_wave - 1) / per_wave;
+  }
+  r.cls_off[kNumClasses] = off;
+  r.wave_off[kNumClasses] = waves;
+  return r;
+}
+
+static void build_schedule(sta_graph* g) {
+  const int N = g->N;
+  std::vector<int> cls(N);
+  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1);
+  g->sched.assign(N, 0);
+  g->lvl_ranges.assign(g->L, GroupRange{});
+  for (int l = 0; l < g->L; ++l) {
+    int b = g->level_off[l], e = g->level_off[l + 1];
+    int cnt[kNumClasses] = {0, 0, 0, 0, 0};
+    for (int n = b; n < e; ++n) cnt[cls[n]]++;
+    int pos[kNumClasses];
+    int o = b;
+    for (int c = 0; c < kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
+    for (int n = b; n < e; ++n) g->sched[pos[cls[n]]++] = n;
+    g->lvl_ranges[l] = group_range(cnt, b);
+  }
+  int cnt[kNumClasses] = {0, 0, 0, 0, 0};
+  for (int n = 0; n < N; ++n) cnt[cls[n]]++;
+  int pos[kNumClasses];
+  int o = 0;
+  for (int c = 0; c < kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
+  g->sched_all.assign(N, 0);
+  for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
+  g->all_range = group_range(cnt, 0);
+}
+
+void free_device(sta_graph* g) {
+  if (g->dev.device >= 0) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->dev.device);
+    for (void* p : g->dev.allocs) (void)hipFree(p);
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+  g->dev = DeviceGraph{};
+  g->uploaded = false;
+}
+
+}  // namespace sta
+
+using namespace sta;
+namespace sta { void free_device(sta_graph* g); }
+
+extern "C" {
+
+const char* sta_last_error(void) { return g_last_error.c_str(); }
+
+int32_t sta_version(void) { return STA_ABI_VERSION; }
+
+sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib, const sta_constraints* cons,
+                           sta_graph** out) {
+  if (!out) return fail(STA_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!nl || !lib || !cons) return fail(STA_E_INVALID, "NULL netlist, library or constraints");
+  const int P = nl->n_pins, N = nl->n_nets, C = nl->n_cells, T = lib->n_cell_types;
+  if (P <= 0 || N <= 0 || C < 0 || T <= 0) return fail(STA_E_INVALID, "sizes must be positive");
+  if (!nl->net_offsets || !nl->net_pins || !nl->pin_cap || !nl->pin_kind ||
+      (C > 0 && (!nl->cell_type || !nl->cell_in_offsets || !nl->cell_in_pins || !nl->cell_out_pin)))
+    return fail(STA_E_INVALID, "NULL netlist array");
+  if (!lib->arc_offsets || !lib->arc_unate || !lib->slew_axis || !lib->load_axis || !lib->tables)
+    return fail(STA_E_INVALID, "NULL library array");
+  // Library.
+  if (lib->arc_offsets[0] != 0) return fail(STA_E_INVALID, "arc_offsets[0] must be 0");
+  for (int t = 0; t < T; ++t) {
+    int k = lib->arc_offsets[t + 1] - lib->arc_offsets[t];
+    if (k < 1 || k > STA_MAX_FANIN) return fail(STA_E_INVALID, "cell type arc count out of 1..STA_MAX_FANIN");
+  }
+  const int n_arcs = lib->arc_offsets[T];
+  for (int a = 0; a < n_arcs; ++a)
+    if (lib->arc_unate[a] != 1 && lib->arc_unate[a] != -1) return fail(STA_E_INVALID, "arc_unate must be +1 or -1");
+  for (int i = 0; i + 1 < STA_LUT_N; ++i)
+    if (!(lib->slew_axis[i] < lib->slew_axis[i + 1]) || !(lib->load_axis[i] < lib->load_axis[i + 1]))
+      return fail(STA_E_INVALID, "table axes must be strictly increasing");
+  for (size_t i = 0; i < (size_t)n_arcs * 4 * STA_LUT_N * STA_LUT_N; ++i)
+    if (!std::isfinite(lib->tables[i])) return fail(STA_E_INVALID, "non-finite table entry");
+  // Nets: CSR, one driver first, every pin exactly once.
+  if (nl->net_offsets[0] != 0 || nl->net_offsets[N] != P) return fail(STA_E_INVALID, "net_offsets must span 0..n_pins");
+  for (int n = 0; n < N; ++n)
+    if (nl->net_offsets[n + 1] <= nl->net_offsets[n]) return fail(STA_E_INVALID, "empty net or non-monotone net_offsets");
+  if (C > 0) {
+    if (nl->cell_in_offsets[0] != 0) return fail(STA_E_INVALID, "cell_in_offsets[0] must be 0");
+    for (int c = 0; c < C; ++c)
+      if (nl->cell_in_offsets[c + 1] <= nl->cell_in_offsets[c]) return fail(STA_E_INVALID, "cell without inputs or non-monotone cell_in_offsets");
+  }
+  std::vector<int> net_of_pin(P, -1);
+  for (int n = 0; n < N; ++n) {
+    int b = nl->net_offsets[n], e = nl->net_offsets[n + 1];
+    if (e - b < 1) return fail(STA_E_INVALID, "empty net or non-monotone net_offsets");
+    for (int i = b; i < e; ++i) {
+      int p = nl->net_pins[i];
+      if (p < 0 || p >= P) return fail(STA_E_INVALID, "net pin index out of range");
+      if (net_of_pin[p] != -1) return fail(STA_E_INVALID, "pin listed in more than one net");
+      net_of_pin[p] = n;
+      int k = nl->pin_kind[p];
+      bool drv = (k == STA_PIN_PI || k == STA_PIN_CELL_OUT);
+      if (k < 0 || k > STA_PIN_PO) return fail(STA_E_INVALID, "bad pin kind");
+      if ((i == b) != drv) return fail(STA_E_INVALID, "net must have exactly one driver (PI or cell output), listed first");
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    if (net_of_pin[p] < 0) return fail(STA_E_INVALID, "pin in no net");
+    if (!std::isfinite(nl->pin_cap[p]) || nl->pin_cap[p] < 0) return fail(STA_E_INVALID, "pin capacitance must be finite and >= 0");
+  }
+  // Cells: kinds and counts consistent with the library.
+  if (C > 0) {
+    if (nl->cell_in_offsets[0] != 0) return fail(STA_E_INVALID, "cell_in_offsets[0] must be 0");
+    std::vector<int8_t> used(P, 0);
+    for (int c = 0; c < C; ++c) {
+      int t = nl->cell_type[c];
+      if (t < 0 || t >= T) return fail(STA_E_INVALID, "cell type out of range");
+      int b = nl->cell_in_offsets[c], e = nl->cell_in_offsets[c + 1];
+      if (e - b != lib->arc_offsets[t + 1] - lib->arc_offsets[t])
+        return fail(STA_E_INVALID, "cell input count differs from its type's arc count");
+      for (int i = b; i < e; ++i) {
+        int p = nl->cell_in_pins[i];
+        if (p < 0 || p >= P) return fail(STA_E_INVALID, "cell input pin out of range");
+        if (nl->pin_kind[p] != STA_PIN_CELL_IN || used[p]) return fail(STA_E_INVALID, "cell input must be an unused CELL_IN pin");
+        used[p] = 1;
+      }
+      int o = nl->cell_out_pin[c];
+      if (o < 0 || o >= P) return fail(STA_E_INVALID, "cell output pin out of range");
+      if (nl->pin_kind[o] != STA_PIN_CELL_OUT || used[o]) return fail(STA_E_INVALID, "cell output must be an unused CELL_OUT pin");
+      used[o] = 1;
+    }
+    for (int p = 0; p < P; ++p) {
+      int k = nl->pin_kind[p];
+      if ((k == STA_PIN_CELL_IN || k == STA_PIN_CELL_OUT) && !used[p])
+        return fail(STA_E_INVALID, "cell pin not attached to any cell");
+    }
+  } else {
+    for (int p = 0; p < P; ++p)
+      if (nl->pin_kind[p] == STA_PIN_CELL_IN || nl->pin_kind[p] == STA_PIN_CELL_OUT)
+        return fail(STA_E_INVALID, "cell pin without cells");
+  }
+  if (!(std::isfinite(cons->t_clk) && std::isfinite(cons->pi_slew) && cons->pi_slew >= 0 &&
+        cons->r_per_um >= 0 && cons->c_per_um >= 0))
+    return fail(STA_E_INVALID, "bad constraints");
+
+  sta_graph* g = new (std::nothrow) sta_graph();
+  if (!g) return fail(STA_E_NOMEM, "host allocation failed");
+  try {
+    const int A = C > 0 ? nl->cell_in_offsets[C] : 0;
+    g->P = P; g->N = N; g->C = C; g->A = A; g->T = T; g->n_arcs = n_arcs;
+    g->net_off.assign(nl->net_offsets, nl->net_offsets + N + 1);
+    g->net_pins.assign(nl->net_pins, nl->net_pins + P);
+    g->pin_cap.assign(nl->pin_cap, nl->pin_cap + P);
+    g->pin_kind.assign(nl->pin_kind, nl->pin_kind + P);
+    if (C > 0) {
+      g->cell_type.assign(nl->cell_type, nl->cell_type + C);
+      g->cell_in_off.assign(nl->cell_in_offsets, nl->cell_in_offsets + C + 1);
+      g->cell_in_pins.assign(nl->cell_in_pins, nl->cell_in_pins + A);
+      g->cell_out_pin.assign(nl->cell_out_pin, nl->cell_out_pin + C);
+    } else {
+      g->cell_in_off.assign(1, 0);
+    }
+    g->arc_off.assign(lib->arc_offsets, lib->arc_offsets + T + 1);
+    g->unate.assign(lib->arc_unate, lib->arc_unate + n_arcs);
+    g->slew_axis.assign(lib->slew_axis, lib->slew_axis + STA_LUT_N);
+    g->load_axis.assign(lib->load_axis, lib->load_axis + STA_LUT_N);
+    g->tables.assign(lib->tables, lib->tables + (size_t)n_arcs * 4 * STA_LUT_N * STA_LUT_N);
+    g->cons = *cons;
+  } catch (const std::bad_alloc&) {
+    delete g;
+    return fail(STA_E_NOMEM, "host allocation failed");
+  }
+  *out = g;
+  return STA_OK;
+}
+
+sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (g->levelized) {
+    if (n_levels_out) *n_levels_out = g->L;
+    return STA_OK;
+  }
+  try {
+    const int P = g->P, N = g->N, C = g->C;
+    std::vector<int> net_of_pin(P);
+    for (int n = 0; n < N; ++n)
+      for (int i = g->net_off[n]; i < g->net_off[n + 1]; ++i) net_of_pin[g->net_pins[i]] = n;
+    std::vector<int> cell_of_out(P, -1);
+    for (int c = 0; c < C; ++c) cell_of_out[g->cell_out_pin[c]] = c;
+    std::vector<int> cell_of_net(N, -1);
+    for (int n = 0; n < N; ++n) cell_of_net[n] = cell_of_out[g->net_pins[g->net_off[n]]];
+    // Successor lists of the net DAG (m -> n when a sink of m is an input of n's cell).
+    std::vector<int> indeg(N, 0), succ_off(N + 1, 0);
+    for (int n = 0; n < N; ++n) {
+      int c = cell_of_net[n];
+      if (c < 0) continue;
+      for (int i = g->cell_in_off[c]; i < g->cell_in_off[c + 1]; ++i) {
+        succ_off[net_of_pin[g->cell_in_pins[i]] + 1]++;
+        indeg[n]++;
+      }
+    }
+    for (int n = 0; n < N; ++n) succ_off[n + 1] += succ_off[n];
+    std::vector<int> succ(succ_off[N]), fill(succ_off.begin(), succ_off.end() - 1);
+    for (int n = 0; n < N; ++n) {
+      int c = cell_of_net[n];
+      if (c < 0) continue;
+      for (int i = g->cell_in_off[c]; i < g->cell_in_off[c + 1]; ++i)
+        succ[fill[net_of_pin[g->cell_in_pins[i]]]++] = n;
+    }
+    // Kahn frontiers: a net is placed once all its predecessors are.
+    std::vector<int> level(N, 0), frontier, next;
+    for (int n = 0; n < N; ++n)
+      if (indeg[n] == 0) frontier.push_back(n);
+    int placed = 0;
+    while (!frontier.empty()) {
+      next.clear();
+      for (int m : frontier) {
+        ++placed;
+        for (int i = succ_off[m]; i < succ_off[m + 1]; ++i) {
+          int n = succ[i];
+          level[n] = std::max(level[n], level[m] + 1);
+          if (--indeg[n] == 0) next.push_back(n);
+        }
+      }
+      frontier.swap(next);
+    }
+    if (placed != N) return fail(STA_E_CYCLE, "combinational cycle: " + std::to_string(N - placed) + " nets never become ready");
+    int L = 0;
+    for (int n = 0; n < N; ++n) L = std::max(L, level[n] + 1);
+    // Canonical net order: (level, original id) by a counting sort.
+    std::vector<int> lcount(L + 1, 0);
+    for (int n = 0; n < N; ++n) lcount[level[n] + 1]++;
+    for (int l = 0; l < L; ++l) lcount[l + 1] += lcount[l];
+    g->level_off = lcount;
+    std::vector<int> pos(lcount.begin(), lcount.end() - 1);
+    g->net_perm.assign(N, 0);
+    for (int n = 0; n < N; ++n) g->net_perm[pos[level[n]]++] = n;
+    std::vector<int> net_new(N);
+    for (int i = 0; i < N; ++i) net_new[g->net_perm[i]] = i;
+    // Canonical pins, net by net.
+    g->pin_perm.assign(P, 0);
+    g->c_net_off.assign(N + 1, 0);
+    std::vector<int> pin_new(P);
+    int k = 0;
+    for (int i = 0; i < N; ++i) {
+      int n = g->net_perm[i];
+      g->c_net_off[i] = k;
+      for (int q = g->net_off[n]; q < g->net_off[n + 1]; ++q) {
+        g->pin_perm[k] = g->net_pins[q];
+        pin_new[g->net_pins[q]] = k;
+        ++k;
+      }
+    }
+    g->c_net_off[N] = P;
+    g->c_pin_cap.resize(P);
+    for (int i = 0; i < P; ++i) g->c_pin_cap[i] = g->pin_cap[g->pin_perm[i]];
+    // Level 0 holds exactly the PI-driven nets; every later net is driven by a cell.
+    const int N0 = lcount[1];
+    for (int i = 0; i < N; ++i) {
+      bool pi = g->pin_kind[g->net_pins[g->net_off[g->net_perm[i]]]] == STA_PIN_PI;
+      if (pi != (i < N0)) return fail(STA_E_INVALID, "a primary input drives a net that also has a cell driver");
+    }
+    g->N0 = N0;
+    // Canonical cells: cell c drives canonical net N0 + c.
+    const int Cc = N - N0;
+    if (Cc != C) return fail(STA_E_INVALID, "every cell must drive exactly one net");
+    g->c_cell_type.assign(C, 0);
+    g->c_cin_off.assign(C + 1, 0);
+    g->c_cin_src.assign(g->A, 0);
+    g->c_cin_pin.assign(g->A, 0);
+    int a = 0;
+    for (int cc = 0; cc < C; ++cc) {
+      int c = cell_of_net[g->net_perm[N0 + cc]];
+      g->c_cell_type[cc] = g->cell_type[c];
+      g->c_cin_off[cc] = a;
+      for (int i = g->cell_in_off[c]; i < g->cell_in_off[c + 1]; ++i) {
+        int p = g->cell_in_pins[i];
+        g->c_cin_pin[a] = pin_new[p];
+        g->c_cin_src[a] = net_new[net_of_pin[p]];
+        ++a;
+      }
+    }
+    g->c_cin_off[C] = a;
+    // Endpoints in canonical order.
+    g->ep_pin.clear();
+    g->ep_net.clear();
+    for (int i = 0; i < N; ++i)
+      for (int q = g->c_net_off[i] + 1; q < g->c_net_off[i + 1]; ++q) {
+        int kd = g->pin_kind[g->pin_perm[q]];
+        if (kd == STA_PIN_FF_D || kd == STA_PIN_PO) {
+          g->ep_pin.push_back(q);
+          g->ep_net.push_back(i);
+        }
+      }
+    g->E = (int)g->ep_pin.size();
+    g->level = level;
+    g->L = L;
+    g->max_level_nets = 0;
+    for (int l = 0; l < L; ++l) g->max_level_nets = std::max(g->max_level_nets, lcount[l + 1] - lcount[l]);
+    build_schedule(g);
+    compute_layouts(g);
+    g->levelized = true;
+  } catch (const std::bad_alloc&) {
+    return fail(STA_E_NOMEM, "host allocation failed");
+  }
+  if (n_levels_out) *n_levels_out = g->L;
+  return STA_OK;
+}
+
+sta_status sta_get_levelization(const sta_graph* g, int32_t* level, int32_t* level_offsets, int32_t* net_perm,
+                                int32_t* pin_perm) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (level) std::copy(g->level.begin(), g->level.end(), level);
+  if (level_offsets) std::copy(g->level_off.begin(), g->level_off.end(), level_offsets);
+  if (net_perm) std::copy(g->net_perm.begin(), g->net_perm.end(), net_perm);
+  if (pin_perm) std::copy(g->pin_perm.begin(), g->pin_perm.end(), pin_perm);
+  return STA_OK;
+}
+
+sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info) {
+  if (!g || !info) return fail(STA_E_INVALID, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_pins = g->P;
+  info->n_nets = g->N;
+  info->n_cells = g->C;
+  info->n_cell_inputs = g->A;
+  info->n_endpoints = g->levelized ? g->E : 0;
+  info->n_levels = g->levelized ? g->L : 0;
+  info->n_pi_nets = g->levelized ? g->N0 : 0;
+  info->max_level_nets = g->levelized ? g->max_level_nets : 0;
+  info->fwd_state_bytes = g->levelized ? (int64_t)g->state.total : 0;
+  info->bwd_workspace_bytes = g->levelized ? (int64_t)g->work.total : 0;
+  info->device_bytes = g->uploaded ? (int64_t)g->dev.bytes : 0;
+  return STA_OK;
+}
+
+void sta_graph_destroy(sta_graph* g) {
+  if (!g) return;
+  for (auto& t : g->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : g->event_pool) (void)hipEventDestroy(e);
+  free_device(g);
+  delete g;
+}
+
+sta_status sta_graph_upload(sta_graph* g) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (g->uploaded) {
+    if (g->dev.device == dev) return STA_OK;
+    return fail(STA_E_STATE, "graph was uploaded to another device");
+  }
+  DeviceGraph& d = g->dev;
+  d.device = dev;
+  std::vector<float4> grid, coef;
+  build_lut_coefficients(g, grid, coef);
+  std::vector<int> type_arc0(g->arc_off);
+  auto up = [&](auto*& dst, const auto& src) -> sta_status {
+    using T = std::remove_reference_t<decltype(*dst)>;
+    size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    void* p = nullptr;
+    hipError_t err = hipMalloc(&p, bytes);
+    if (err != hipSuccess) return hip_fail(err, "hipMalloc");
+    d.allocs.push_back(p);
+    d.bytes += bytes;
+    if (!src.empty()) {
+      err = hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+      if (err != hipSuccess) return hip_fail(err, "hipMemcpy");
+    }
+    dst = static_cast<T*>(p);
+    return STA_OK;
+  };
+  sta_status s = STA_OK;
+  std::vector<int8_t> unate(g->unate);
+  if ((s = up(d.net_off, g->c_net_off)) || (s = up(d.pin_cap, g->c_pin_cap)) ||
+      (s = up(d.cell_type, g->c_cell_type)) || (s = up(d.type_arc0, type_arc0)) || (s = up(d.unate, unate)) ||
+      (s = up(d.cin_off, g->c_cin_off)) || (s = up(d.cin_src, g->c_cin_src)) || (s = up(d.cin_pin, g->c_cin_pin)) ||
+      (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_net)) || (s = up(d.pin_perm, g->pin_perm)) ||
+      (s = up(d.sched, g->sched)) || (s = up(d.sched_all, g->sched_all)) || (s = up(d.lvl, g->lvl_ranges)) ||
+      (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
+    free_device(g);
+    return s;
+  }
+  g->uploaded = true;
+  return STA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations shared by the host code and the HIP kernels of libsta.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sta.h"
+
+namespace sta {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
+constexpr int kNumClasses = 5;       // lane groups of 4, 8, 16, 32, 64 lanes per net
+constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
+
+// Lane-group class of a net with `sinks` sink pins: the smallest group in which every
+// lane holds at most one sink, capped at a whole wave.
+inline int net_class(int sinks) {
+  if (sinks <= 4) return 0;
+  if (sinks <= 8) return 1;
+  if (sinks <= 16) return 2;
+  if (sinks <= 32) return 3;
+  return 4;
+}
+
+// A batch of nets processed by one launch: schedule entries [cls_off[c], cls_off[c+1])
+// belong to class c and are served by waves [wave_off[c], wave_off[c+1]) of the launch.
+struct GroupRange {
+  int cls_off[kNumClasses + 1];
+  int wave_off[kNumClasses + 1];
+};
+
+// Breakpoints compared against when locating a table cell (held in scalar registers).
+struct LutKeys {
+  float x[STA_LUT_N - 2];   // slew_axis[1..5]
+  float y[STA_LUT_N - 2];   // load_axis[1..5]
+};
+
+// Byte offsets of the pieces of the forward state buffer.
+struct StateLayout {
+  size_t rec;      // float4[3 * N]: per net {at[4]}, {slew[4]}, {atg[2], 0, 0}
+  size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
+  size_t load;     // float[N]: root load of each net (Eq. 1)
+  size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
+  size_t fin;      // double[8]: finished scalars and the WNS_g normaliser
+  size_t total;
+};
+
+struct WorkLayout {
+  size_t ratp;     // float4[P]: required time of each sink, by condition
+  size_t adjp;     // float4[P]: adjoint of each sink {a_rise, a_fall, s_rise, s_fall}
+  size_t total;
+};
+
+struct DeviceGraph {
+  int device = -1;
+  std::vector<void*> allocs;
+  int* net_off = nullptr;      // [N+1] canonical
+  float* pin_cap = nullptr;    // [P]
+  int* cell_type = nullptr;    // [C] canonical cells (cell c drives net N0 + c)
+  int* type_arc0 = nullptr;    // [T+1]
+  int8_t* unate = nullptr;     // [n_arcs]
+  int* cin_off = nullptr;      // [C+1]
+  int* cin_src = nullptr;      // [A] canonical source net of each cell input
+  int* cin_pin = nullptr;      // [A] canonical pin of each cell input
+  int* ep_pin = nullptr;       // [E]
+  int* ep_net = nullptr;       // [E]
+  int* pin_perm = nullptr;     // [P] original id of each canonical pin
+  int* sched = nullptr;        // [N] per-level nets ordered by class
+  int* sched_all = nullptr;    // [N] all nets ordered by class
+  GroupRange* lvl = nullptr;   // [L]
+  float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
+  float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
+  size_t bytes = 0;
+};
+
+}  // namespace sta
+
+struct sta_graph {
+  // Input copy (original ids).
+  int P = 0, N = 0, C = 0, A = 0, T = 0, n_arcs = 0;
+  std::vector<int> net_off, net_pins, cell_type, cell_in_off, cell_in_pins, cell_out_pin;
+  std::vector<float> pin_cap;
+  std::vector<int8_t> pin_kind;
+  std::vector<int> arc_off;
+  std::vector<int8_t> unate;
+  std::vector<float> slew_axis, load_axis, tables;
+  sta_constraints cons{};
+
+  // Levelization (canonical order).
+  bool levelized = false;
+  int L = 0, N0 = 0, E = 0, max_level_nets = 0;
+  std::vector<int> level, level_off, net_perm, pin_perm;
+  std::vector<int> c_net_off, c_cell_type, c_cin_off, c_cin_src, c_cin_pin, ep_pin, ep_net;
+  std::vector<float> c_pin_cap;
+  std::vector<int> sched, sched_all;
+  std::vector<sta::GroupRange> lvl_ranges;   // per level
+  sta::GroupRange all_range{};                 // all nets
+  sta::StateLayout state{};
+  sta::WorkLayout work{};
+  int n_ep_blocks = 0;
+
+  // Device copy.
+  bool uploaded = false;
+  sta::DeviceGraph dev;
+
+  // Event timing of launches (sta_profile_enable).
+  bool profiling = false;
+  struct TimedLaunch { int kind; hipEvent_t start, stop; };
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace sta {
+void set_error(const std::string& msg);
+sta_status fail(sta_status code, const std::string& msg);
+sta_status hip_fail(hipError_t e, const char* what);
+void compute_layouts(sta_graph* g);
+void build_lut_coefficients(const sta_graph* g, std::vector<float4>& grid, std::vector<float4>& coef);
+LutKeys lut_keys(const sta_graph* g);
+}  // namespace sta

@@ -1,0 +1,330 @@
+"""Python binding of libsta (the C ABI in include/sta.h).
+
+Argument marshalling only: every step of the timing sweep runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  The library must have been
+built (``python -m paper_2603_28381_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsta.so")
+
+STA_OK, STA_PENDING = 0, 1
+STA_E_INVALID, STA_E_CYCLE, STA_E_NOMEM, STA_E_DEVICE = -1, -2, -3, -4
+STA_E_BUSY, STA_E_STATE, STA_E_UNKNOWN_TICKET = -5, -6, -7
+
+STA_SMOOTH = 1 << 0
+STA_CANONICAL_IO = 1 << 1
+STA_RAT = 1 << 2
+STA_GRAD = 1 << 3
+STA_GRAD_WNS = 1 << 4
+
+EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
+            "sta_graph_info_get", "sta_graph_destroy", "sta_forward", "sta_backward",
+            "sta_profile_enable", "sta_profile_read", "sta_last_error", "sta_version"]
+
+KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level"]
+
+_P = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+
+class StaNetlist(ctypes.Structure):
+    _fields_ = [("n_pins", ctypes.c_int32), ("n_nets", ctypes.c_int32), ("n_cells", ctypes.c_int32),
+                ("net_offsets", _P), ("net_pins", _P), ("cell_type", _P), ("cell_in_offsets", _P),
+                ("cell_in_pins", _P), ("cell_out_pin", _P), ("pin_cap", _P), ("pin_kind", _P)]
+
+
+class StaLibrary(ctypes.Structure):
+    _fields_ = [("n_cell_types", ctypes.c_int32), ("arc_offsets", _P), ("arc_unate", _P),
+                ("slew_axis", _P), ("load_axis", _P), ("tables", _P)]
+
+
+class StaConstraints(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("t_clk", "setup", "hold", "pi_at", "pi_slew",
+                                              "r_per_um", "c_per_um")]
+
+
+class StaGraphInfo(ctypes.Structure):
+    _fields_ = [("n_pins", ctypes.c_int32), ("n_nets", ctypes.c_int32), ("n_cells", ctypes.c_int32),
+                ("n_cell_inputs", ctypes.c_int32), ("n_endpoints", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("n_pi_nets", ctypes.c_int32),
+                ("max_level_nets", ctypes.c_int32), ("fwd_state_bytes", ctypes.c_int64),
+                ("bwd_workspace_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class StaFwdOut(ctypes.Structure):
+    _fields_ = [("state", _P), ("at", _P), ("slew", _P), ("atg", _P), ("scalars", _P)]
+
+
+class StaBwdOut(ctypes.Structure):
+    _fields_ = [("workspace", _P), ("at", _P), ("slew", _P), ("rat", _P), ("slack", _P),
+                ("dx", _P), ("dy", _P), ("grad_scale", ctypes.c_float), ("grad_scale_dev", _P)]
+
+
+class StaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsta error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libsta.so once.  torch is imported first so the HIP runtime is shared."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libsta.so not built at {path}; run python -m paper_2603_28381_amd.build")
+    lib = ctypes.CDLL(path)
+    S = ctypes.c_int32
+    lib.sta_build_graph.argtypes = [ctypes.POINTER(StaNetlist), ctypes.POINTER(StaLibrary),
+                                    ctypes.POINTER(StaConstraints), ctypes.POINTER(_P)]
+    lib.sta_build_graph.restype = S
+    lib.sta_levelize.argtypes = [_P, _I32P]
+    lib.sta_levelize.restype = S
+    lib.sta_get_levelization.argtypes = [_P, _P, _P, _P, _P]
+    lib.sta_get_levelization.restype = S
+    lib.sta_graph_upload.argtypes = [_P]
+    lib.sta_graph_upload.restype = S
+    lib.sta_graph_info_get.argtypes = [_P, ctypes.POINTER(StaGraphInfo)]
+    lib.sta_graph_info_get.restype = S
+    lib.sta_graph_destroy.argtypes = [_P]
+    lib.sta_graph_destroy.restype = None
+    lib.sta_forward.argtypes = [_P, _P, _P, ctypes.POINTER(StaFwdOut), ctypes.c_uint32, ctypes.c_float, _P]
+    lib.sta_forward.restype = S
+    lib.sta_backward.argtypes = [_P, _P, _P, ctypes.POINTER(StaFwdOut), ctypes.POINTER(StaBwdOut),
+                                 ctypes.c_uint32, ctypes.c_float, _P]
+    lib.sta_backward.restype = S
+    lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
+    lib.sta_profile_enable.restype = S
+    lib.sta_profile_read.argtypes = [_P, _P, _P]
+    lib.sta_profile_read.restype = S
+    lib.sta_last_error.argtypes = []
+    lib.sta_last_error.restype = ctypes.c_char_p
+    lib.sta_version.argtypes = []
+    lib.sta_version.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != STA_OK:
+        raise StaError(code, (_lib.sta_last_error() or b"").decode())
+
+
+def _ptr(a) -> int | None:
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _stream_handle(stream=None) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+def _dev_f32(a, device) -> torch.Tensor:
+    t = torch.as_tensor(a)
+    if t.dtype != torch.float32 or t.device != torch.device(device) or not t.is_contiguous():
+        t = t.to(device=device, dtype=torch.float32).contiguous()
+    return t
+
+
+@dataclass
+class Forward:
+    """Result of Graph.forward: the opaque state plus the requested outputs."""
+    state: torch.Tensor
+    scalars: torch.Tensor          # float64 [4]: WNS, TNS, WNS_g, TNS_g
+    at: torch.Tensor | None = None
+    slew: torch.Tensor | None = None
+    atg: torch.Tensor | None = None
+    gamma: float = 10.0
+    canonical: bool = False
+
+
+class Graph:
+    """A netlist handed to libsta: validated, levelized and (lazily) uploaded."""
+
+    def __init__(self, netlist: dict, library: dict, constraints: dict):
+        lib = load_library()
+        self._keep = []
+
+        def arr(v, dt):
+            a = np.ascontiguousarray(v, dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data
+
+        nl = StaNetlist(int(netlist["n_pins"]), int(netlist["n_nets"]), int(netlist["n_cells"]),
+                        arr(netlist["net_offsets"], np.int32), arr(netlist["net_pins"], np.int32),
+                        arr(netlist["cell_type"], np.int32), arr(netlist["cell_in_offsets"], np.int32),
+                        arr(netlist["cell_in_pins"], np.int32), arr(netlist["cell_out_pin"], np.int32),
+                        arr(netlist["pin_cap"], np.float32), arr(netlist["pin_kind"], np.int8))
+        lb = StaLibrary(int(library["n_cell_types"]), arr(library["arc_offsets"], np.int32),
+                        arr(library["arc_unate"], np.int8), arr(library["slew_axis"], np.float32),
+                        arr(library["load_axis"], np.float32), arr(library["tables"], np.float32))
+        cs = StaConstraints(*[float(constraints[k]) for k in ("t_clk", "setup", "hold", "pi_at", "pi_slew",
+                                                               "r_per_um", "c_per_um")])
+        h = _P()
+        _check(lib.sta_build_graph(ctypes.byref(nl), ctypes.byref(lb), ctypes.byref(cs), ctypes.byref(h)))
+        self._keep = []
+        self._h = h
+        self.n_pins = int(netlist["n_pins"])
+
+    @classmethod
+    def from_design(cls, d) -> "Graph":
+        """From a gen.netlist.Design (numpy arrays)."""
+        nl = dict(n_pins=d.n_pins, n_nets=d.n_nets, n_cells=d.n_cells, net_offsets=d.net_offsets,
+                  net_pins=d.net_pins, cell_type=d.cell_type, cell_in_offsets=d.cell_in_offsets,
+                  cell_in_pins=d.cell_in_pins, cell_out_pin=d.cell_out_pin, pin_cap=d.pin_cap,
+                  pin_kind=d.pin_kind)
+        lb = dict(n_cell_types=d.lib.n_cell_types, arc_offsets=d.lib.arc_offsets, arc_unate=d.lib.arc_unate,
+                  slew_axis=d.lib.slew_axis, load_axis=d.lib.load_axis, tables=d.lib.tables)
+        c = d.cons
+        cs = dict(t_clk=c.t_clk, setup=c.setup, hold=c.hold, pi_at=c.pi_at, pi_slew=c.pi_slew,
+                  r_per_um=c.r_per_um, c_per_um=c.c_per_um)
+        return cls(nl, lb, cs)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sta_graph_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def levelize(self) -> int:
+        n = ctypes.c_int32()
+        _check(_lib.sta_levelize(self._h, ctypes.byref(n)))
+        return n.value
+
+    def info(self) -> dict:
+        i = StaGraphInfo()
+        _check(_lib.sta_graph_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in StaGraphInfo._fields_}
+
+    def levelization(self) -> dict:
+        inf = self.info()
+        level = np.empty(inf["n_nets"], np.int32)
+        loff = np.empty(inf["n_levels"] + 1, np.int32)
+        nperm = np.empty(inf["n_nets"], np.int32)
+        pperm = np.empty(inf["n_pins"], np.int32)
+        _check(_lib.sta_get_levelization(self._h, level.ctypes.data, loff.ctypes.data, nperm.ctypes.data,
+                                         pperm.ctypes.data))
+        return dict(level=level, level_offsets=loff, net_perm=nperm, pin_perm=pperm)
+
+    def upload(self):
+        _check(_lib.sta_graph_upload(self._h))
+
+    def profile(self, on: bool = True):
+        _check(_lib.sta_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        n = np.zeros(len(KERNELS), np.int64)
+        ms = np.zeros(len(KERNELS), np.float64)
+        _check(_lib.sta_profile_read(self._h, n.ctypes.data, ms.ctypes.data))
+        return {k: (int(n[i]), float(ms[i])) for i, k in enumerate(KERNELS)}
+
+    # ------------------------------------------------------------------ sweeps
+    def new_state(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.info()["fwd_state_bytes"], dtype=torch.uint8, device=device)
+
+    def new_workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(self.info()["bwd_workspace_bytes"], dtype=torch.uint8, device=device)
+
+    def forward(self, x, y, gamma: float = 10.0, smooth: bool = True, canonical: bool = False,
+                pins: bool = False, state: torch.Tensor | None = None, scalars: torch.Tensor | None = None,
+                stream=None) -> Forward:
+        dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
+        x = _dev_f32(x, dev)
+        y = _dev_f32(y, dev)
+        P = self.n_pins
+        state = self.new_state(dev) if state is None else state
+        scalars = torch.empty(4, dtype=torch.float64, device=dev) if scalars is None else scalars
+        at = slew = atg = None
+        if pins:
+            at = torch.empty((P, 4), dtype=torch.float32, device=dev)
+            slew = torch.empty((P, 4), dtype=torch.float32, device=dev)
+            atg = torch.empty((P, 2), dtype=torch.float32, device=dev) if smooth else None
+        fo = StaFwdOut(_ptr(state), _ptr(at), _ptr(slew), _ptr(atg), _ptr(scalars))
+        flags = (STA_SMOOTH if smooth else 0) | (STA_CANONICAL_IO if canonical else 0)
+        _check(_lib.sta_forward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), flags, float(gamma),
+                                _stream_handle(stream)))
+        return Forward(state, scalars, at, slew, atg, float(gamma), canonical)
+
+    def backward(self, x, y, fwd: Forward, rat: bool = True, grad: bool = True, wns: bool = False,
+                 pins: bool = True, grad_scale: float = 1.0, grad_scale_dev: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None, out: dict | None = None, stream=None) -> dict:
+        dev = fwd.state.device
+        x = _dev_f32(x, dev)
+        y = _dev_f32(y, dev)
+        P = self.n_pins
+        ws = self.new_workspace(dev) if workspace is None else workspace
+        if out is None:
+            out = {}
+            if pins:
+                for k in ("at", "slew"):
+                    out[k] = torch.empty((P, 4), dtype=torch.float32, device=dev)
+            if rat:
+                out["rat"] = torch.empty((P, 4), dtype=torch.float32, device=dev)
+                out["slack"] = torch.empty((P, 4), dtype=torch.float32, device=dev)
+            if grad:
+                out["dx"] = torch.empty(P, dtype=torch.float32, device=dev)
+                out["dy"] = torch.empty(P, dtype=torch.float32, device=dev)
+        bo = StaBwdOut(_ptr(ws), _ptr(out.get("at")), _ptr(out.get("slew")), _ptr(out.get("rat")),
+                       _ptr(out.get("slack")), _ptr(out.get("dx")), _ptr(out.get("dy")), float(grad_scale),
+                       _ptr(grad_scale_dev))
+        fo = StaFwdOut(_ptr(fwd.state), None, None, None, None)
+        flags = ((STA_RAT if rat else 0) | (STA_GRAD if grad else 0) | (STA_GRAD_WNS if wns else 0)
+                 | (STA_CANONICAL_IO if fwd.canonical else 0))
+        _check(_lib.sta_backward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), ctypes.byref(bo), flags,
+                                 float(fwd.gamma), _stream_handle(stream)))
+        return out
+
+
+class SmoothedSlack(torch.autograd.Function):
+    """Smoothed TNS (or WNS) of a placement as a differentiable function of pin x, y.
+
+    forward returns the float64 scalar TNS_g (WNS_g with which="wns"); backward runs the
+    fused backward sweep of libsta and returns d/dx, d/dy scaled by the incoming gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, x, y, graph: Graph, gamma: float = 10.0, which: str = "tns"):
+        fwd = graph.forward(x, y, gamma=gamma, smooth=True)
+        ctx.graph, ctx.fwd, ctx.which = graph, fwd, which
+        ctx.save_for_backward(x, y)
+        return fwd.scalars[3 if which == "tns" else 2].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y = ctx.saved_tensors
+        gd = g.detach().to(torch.float64).reshape(1).contiguous()
+        out = ctx.graph.backward(x, y, ctx.fwd, rat=False, grad=True, wns=ctx.which == "wns", pins=False,
+                                 grad_scale_dev=gd)
+        return out["dx"].to(x.dtype), out["dy"].to(y.dtype), None, None, None
+
+
+def smoothed_tns(x, y, graph: Graph, gamma: float = 10.0) -> torch.Tensor:
+    return SmoothedSlack.apply(x, y, graph, gamma, "tns")
+
+
+def smoothed_wns(x, y, graph: Graph, gamma: float = 10.0) -> torch.Tensor:
+    return SmoothedSlack.apply(x, y, graph, gamma, "wns")

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP sweep (through the C ABI) against the FP64 oracle, element by element."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gen.netlist import CFG0, CFG1, Constraints, make_design, scaled_spec
+from oracle import sta_oracle as O
+from paper_2603_28381_amd import Graph, smoothed_tns, smoothed_wns
+from tests._designs import PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D, PIN_PI, PIN_PO, build
+from tests._parity import assert_times, grad_stats
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 10.0
+
+
+def gpu_run(d, gamma=GAMMA, canonical=False, wns=False, graph=None):
+    g = graph or Graph.from_design(d)
+    g.levelize()
+    g.upload()
+    x = torch.tensor(d.x, device="cuda")
+    y = torch.tensor(d.y, device="cuda")
+    if canonical:
+        perm = torch.tensor(g.levelization()["pin_perm"].astype(np.int64), device="cuda")
+        x, y = x[perm].contiguous(), y[perm].contiguous()
+    fwd = g.forward(x, y, gamma=gamma, pins=True, canonical=canonical)
+    out = g.backward(x, y, fwd, rat=True, grad=True, wns=wns, pins=True)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["fwd_at"] = fwd.at.cpu().numpy()
+    res["fwd_slew"] = fwd.slew.cpu().numpy()
+    res["atg"] = fwd.atg.cpu().numpy()
+    res["scalars"] = fwd.scalars.cpu().numpy()
+    res["graph"] = g
+    return res
+
+
+def check_values(d, got, ref):
+    print(f"[{d.spec.name}] pins={d.n_pins} worst/tol:", end=" ")
+    w = []
+    w.append(assert_times(got["at"], ref["at"], "AT"))
+    w.append(assert_times(got["slew"], ref["slew"], "slew"))
+    w.append(assert_times(got["fwd_at"], ref["at"], "AT (forward expand)"))
+    w.append(assert_times(got["fwd_slew"], ref["slew"], "slew (forward expand)"))
+    w.append(assert_times(got["atg"], ref["atg"], "smoothed AT"))
+    w.append(assert_times(got["rat"], ref["rat"], "RAT"))
+    mag = np.abs(np.where(np.isfinite(ref["rat"]), ref["rat"], 0.0)) + np.abs(ref["at"])
+    w.append(assert_times(got["slack"], ref["slack"], "slack", scale=mag))
+    print(" ".join(f"{v:.3g}" for v in w))
+    wns, tns, wns_g, tns_g = got["scalars"]
+    assert wns == pytest.approx(ref["wns"], rel=1e-4, abs=1e-3)
+    assert tns == pytest.approx(ref["tns"], rel=1e-4, abs=1e-3)
+    assert wns_g == pytest.approx(ref["wns_g"], rel=1e-4, abs=1e-3)
+    assert tns_g == pytest.approx(ref["tns_g"], rel=1e-4, abs=1e-3)
+
+
+def check_grad(got, ref, rel, floor):
+    for k in ("dx", "dy"):
+        st = grad_stats(got[k], ref[k])
+        print(f"  {k}: {st}")
+        g, r = np.asarray(got[k], np.float64), ref[k]
+        tol = rel * np.abs(r) + floor * np.abs(r).max()
+        bad = np.abs(g - r) > tol
+        assert not bad.any(), f"{k}: {bad.sum()} pins outside tolerance; worst {np.max(np.abs(g - r) / tol):.3g}x"
+
+
+def test_parity_cfg0_all_outputs():
+    d = make_design(CFG0)
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    got = gpu_run(d)
+    check_values(d, got, ref)
+    check_grad(got, ref, 1e-3, 1e-6)
+
+
+def test_parity_cfg0_wns_gradient():
+    d = make_design(CFG0)
+    ref = O.run(d, gamma=GAMMA, grad="wns")
+    got = gpu_run(d, wns=True)
+    check_grad(got, ref, 1e-3, 1e-6)
+
+
+def test_parity_heavy_tail_midsize():
+    # Heavy-tailed nets (up to 500 pins) on a small box: every lane-group class, ragged tails.
+    d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
+    assert d.stats["max_pins_per_net"] > 64
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    got = gpu_run(d)
+    check_values(d, got, ref)
+    check_grad(got, ref, 1e-3, 1e-6)
+
+
+def test_canonical_io_matches_original_order():
+    d = make_design(CFG0)
+    a = gpu_run(d)
+    b = gpu_run(d, canonical=True)
+    perm = a["graph"].levelization()["pin_perm"]
+    for k in ("at", "slew", "rat", "slack", "dx", "dy", "fwd_at", "atg"):
+        assert np.array_equal(a[k][perm], b[k]), k
+    assert np.array_equal(a["scalars"], b["scalars"])
+
+
+def test_bitwise_deterministic():
+    d = make_design(scaled_spec(30_000, cfg_id=42, box_um=500.0))
+    a = gpu_run(d)
+    b = gpu_run(d, graph=a["graph"])
+    for k in ("at", "slew", "rat", "slack", "dx", "dy", "atg", "scalars"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_edge_cases_small_graph():
+    # Net A (PI 0) -> sinks: 1 (cell0 in), 2 (PO, co-located with the driver), 7 (cell1 in 0)
+    # Net B (cell0 out 3) -> sink 4 (cell1 in 1); Net C (cell1 out 5) -> no sinks at all
+    # Net D (PI 6) -> sink 8 (FF_D)
+    kinds = [PIN_PI, PIN_CELL_IN, PIN_PO, PIN_CELL_OUT, PIN_CELL_IN, PIN_CELL_OUT, PIN_PI, PIN_CELL_IN, PIN_FF_D]
+    d = build([[0, 1, 2, 7], [3, 4], [5], [6, 8]], [(0, [1], 3), (8, [7, 4], 5)], kinds,
+              [0, 2, 3, 0, 1.5, 0, 0, 2.5, 4], [0, 10, 0, 40, 55, 90, 5, -20, 60], [0, 5, 0, 20, 25, 30, 5, 7, 80],
+              cons=Constraints(t_clk=60.0))
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    got = gpu_run(d)
+    check_values(d, got, ref)
+    check_grad(got, ref, 1e-3, 1e-6)
+    assert np.isinf(got["rat"][5, 2]) and got["rat"][5, 2] > 0     # unconstrained output
+
+
+def test_no_endpoints_gives_zero_scalars():
+    d = build([[0, 1], [2]], [(0, [1], 2)], [PIN_PI, PIN_CELL_IN, PIN_CELL_OUT], [0, 1, 0], [0, 3, 5], [0, 4, 6])
+    got = gpu_run(d)
+    assert np.array_equal(got["scalars"], np.zeros(4))
+    assert np.all(got["dx"] == 0) and np.all(got["dy"] == 0)
+
+
+def test_autograd_function_matches_backward():
+    d = make_design(CFG0)
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    g = Graph.from_design(d)
+    g.levelize()
+    x = torch.tensor(d.x, device="cuda", requires_grad=True)
+    y = torch.tensor(d.y, device="cuda", requires_grad=True)
+    loss = 2.5 * smoothed_tns(x, y, g, GAMMA)
+    loss.backward()
+    assert float(loss) / 2.5 == pytest.approx(ref["tns_g"], rel=1e-4)
+    got = {"dx": x.grad.cpu().numpy() / 2.5, "dy": y.grad.cpu().numpy() / 2.5}
+    check_grad(got, ref, 1e-3, 1e-6)
+    w = smoothed_wns(x.detach(), y.detach(), g, GAMMA)
+    assert float(w) == pytest.approx(ref["wns_g"], rel=1e-4)
+
+
+@pytest.mark.slow
+def test_parity_cfg1_full_size():
+    # 0.8M pins, 61 net levels, nets up to 500 pins: the launch configuration of the benchmark.
+    d = make_design(CFG1)
+    lv = O.levelize(d)
+    ref = O.run(d, gamma=GAMMA, grad="tns", lv=lv)
+    got = gpu_run(d)
+    check_values(d, got, ref)
+    for k in ("dx", "dy"):
+        print(k, grad_stats(got[k], ref[k]))

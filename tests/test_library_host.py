@@ -1,0 +1,125 @@
+"""Host-side checks of libsta (no GPU): exported ABI, bit-exact levelization, input validation."""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from gen.netlist import CFG0, CFG1, make_design, tiny_spec
+from oracle import sta_oracle as O
+from paper_2603_28381_amd import sta as S
+from tests._designs import PIN_CELL_IN, PIN_CELL_OUT, PIN_PI, PIN_PO, build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "sta.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sta_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_loads_and_exports_every_declared_function():
+    lib = S.load_library()
+    names = _header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(S.EXPORTED)
+    assert lib.sta_version() == 1
+
+
+def _levelization_matches(d):
+    g = S.Graph.from_design(d)
+    L = g.levelize()
+    got = g.levelization()
+    ref = O.levelize(d)
+    assert L == ref.n_levels
+    for k in ("level", "level_offsets", "net_perm", "pin_perm"):
+        assert np.array_equal(got[k], getattr(ref, k)), k
+    info = g.info()
+    assert info["n_endpoints"] == len(np.nonzero((d.pin_kind == 3) | (d.pin_kind == 4))[0])
+    assert info["n_pi_nets"] == int(ref.level_offsets[1])
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_levelization_bit_exact_tiny(seed):
+    _levelization_matches(make_design(tiny_spec(8 + 5 * seed, 2 + seed, n_pi=3, seed=seed)))
+
+
+def test_levelization_bit_exact_cfg0():
+    _levelization_matches(make_design(CFG0))
+
+
+@pytest.mark.slow
+def test_levelization_bit_exact_cfg1():
+    _levelization_matches(make_design(CFG1))
+
+
+def _small():
+    # PI 0 -> {0, 1}; cell 0 (type 0, 1 input): in 1 -> out 2; net {2, 3}; 3 is a PO.
+    return dict(nets=[[0, 1], [2, 3]], cells=[(0, [1], 2)], kinds=[PIN_PI, PIN_CELL_IN, PIN_CELL_OUT, PIN_PO],
+                caps=[0, 1, 0, 1], x=[0, 1, 2, 3], y=[0, 0, 0, 0])
+
+
+def _expect(code, **over):
+    kw = _small()
+    kw.update(over)
+    d = build(**kw)
+    with pytest.raises(S.StaError) as e:
+        g = S.Graph.from_design(d)
+        g.levelize()
+    assert e.value.code == code
+
+
+def test_valid_small_graph_builds():
+    g = S.Graph.from_design(build(**_small()))
+    assert g.levelize() == 2
+    g.close()
+
+
+def test_rejects_driver_not_first():
+    _expect(S.STA_E_INVALID, nets=[[1, 0], [2, 3]])
+
+
+def test_rejects_pin_in_two_nets():
+    _expect(S.STA_E_INVALID, nets=[[0, 1], [2, 1]], kinds=[PIN_PI, PIN_CELL_IN, PIN_CELL_OUT, PIN_PO])
+
+
+def test_rejects_wrong_fanin_for_type():
+    _expect(S.STA_E_INVALID, cells=[(8, [1], 2)])      # type 8 has two arcs
+
+
+def test_rejects_cell_type_out_of_range():
+    _expect(S.STA_E_INVALID, cells=[(99, [1], 2)])
+
+
+def test_rejects_cell_input_of_wrong_kind():
+    _expect(S.STA_E_INVALID, kinds=[PIN_PI, PIN_PO, PIN_CELL_OUT, PIN_PO])
+
+
+def test_rejects_negative_cap():
+    _expect(S.STA_E_INVALID, caps=[0, -1, 0, 1])
+
+
+def test_rejects_cycle():
+    d = build([[0, 1], [2, 3], [4, 5]], [(8, [1, 5], 2), (0, [3], 4)],
+              [PIN_PI, PIN_CELL_IN, PIN_CELL_OUT, PIN_CELL_IN, PIN_CELL_OUT, PIN_CELL_IN],
+              [0, 1, 0, 1, 0, 1], [0, 1, 2, 3, 4, 5], [0] * 6)
+    g = S.Graph.from_design(d)
+    with pytest.raises(S.StaError) as e:
+        g.levelize()
+    assert e.value.code == S.STA_E_CYCLE
+
+
+def test_levelization_state_errors():
+    g = S.Graph.from_design(build(**_small()))
+    with pytest.raises(S.StaError) as e:
+        g.levelization()
+    assert e.value.code == S.STA_E_STATE
+    assert g.info()["n_levels"] == 0
+    g.levelize()
+    assert g.info()["fwd_state_bytes"] > 0 and g.info()["bwd_workspace_bytes"] > 0
