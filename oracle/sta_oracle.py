@@ -274,16 +274,35 @@ class _Plan:
         self.endpoints = np.nonzero((kind == PIN_FF_D) | (kind == PIN_PO))[0]
 
 
+def fp32_rounding_noise(seed: int):
+    """A perturbation that multiplies each value by (1 + e), e uniform in +-2^-24: the size of
+    one float32 rounding.  Used to measure how far float32 arithmetic can move an exact result
+    (the conditioning of the timing problem at float32 resolution); off by default."""
+    gen = torch.Generator().manual_seed(seed)
+    rng = np.random.default_rng([seed, 24])
+    u = 2.0 ** -24
+
+    def p(v):
+        if isinstance(v, np.ndarray):
+            return v * (1 + rng.uniform(-u, u, v.shape))
+        e = (torch.rand(v.shape, generator=gen, dtype=F64) * 2 - 1) * u
+        return v * (1 + e)
+    return p
+
+
 def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float = 10.0,
-            plan: _Plan | None = None, want_decisions: bool = False):
+            plan: _Plan | None = None, want_decisions: bool = False, perturb=None):
     """Arrival time, slew and smoothed late arrival time for every pin.
 
     x, y: float64 tensors [P] by original pin id (may require grad).
+    perturb: None, or a function applied to each table-lookup result and each propagated
+    arrival and slew (see fp32_rounding_noise).
     Returns dict with at[P,4], slew[P,4], atg[P,2] (torch, by original pin id),
     arc_delay[P,4] (numpy; delay of the arc entered at each cell-input pin, for each
     output condition k), and the RC results.
     """
     plan = plan or _Plan(d, lv)
+    pt = perturb or (lambda v: v)
     lib, cons = d.lib, d.cons
     xa = torch.from_numpy(lib.slew_axis.astype(np.float64))
     ya = torch.from_numpy(lib.load_axis.astype(np.float64))
@@ -324,7 +343,8 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
                 lo = load_o.unsqueeze(1).expand_as(slew_in)
                 dval, di, dj = lut(tables[arc, t], xa, ya, slew_in, lo)
                 sval, si, sj = lut(tables[arc, 2 + t], xa, ya, slew_in, lo)
-                cand = at_in + dval
+                dval, sval = pt(dval), pt(sval)
+                cand = pt(at_in + dval)
                 big = torch.tensor(math.inf, dtype=F64)
                 if m == 1:
                     at_o = torch.where(mask, cand, -big).max(dim=1).values
@@ -355,7 +375,8 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
         dsv = drv_state[sd]
         w = delay[sinks].unsqueeze(1)
         im = imp[sinks].unsqueeze(1)
-        sink_state = torch.cat([dsv[:, 0:4] + w, torch.sqrt(dsv[:, 4:8] ** 2 + im ** 2), dsv[:, 8:10] + w], dim=1)
+        sink_state = torch.cat([pt(dsv[:, 0:4] + w), pt(torch.sqrt(dsv[:, 4:8] ** 2 + im ** 2)), pt(dsv[:, 8:10] + w)],
+                               dim=1)
         blocks.append(torch.cat([drv_state, sink_state]))
     allst = torch.cat(blocks)
     rows = torch.from_numpy(plan.row)
@@ -370,8 +391,12 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
 # --------------------------------------------------------------------------------------
 # Backward propagation of required times and slack (Sec. 2.1 stage 4; Sec. 3.1.2).
 # --------------------------------------------------------------------------------------
-def backward(d, lv: Levelization, fwd) -> dict:
-    """Required arrival time, slack, WNS and TNS (readings R8, R9). numpy float64."""
+def backward(d, lv: Levelization, fwd, perturb=None) -> dict:
+    """Required arrival time, slack, WNS and TNS (readings R8, R9). numpy float64.
+
+    perturb: None, or a function applied to each propagated required time (see
+    fp32_rounding_noise)."""
+    pt = perturb or (lambda v: v)
     plan = fwd["plan"]
     cons = d.cons
     P = d.n_pins
@@ -387,7 +412,7 @@ def backward(d, lv: Levelization, fwd) -> dict:
     for l in range(plan.L - 1, -1, -1):
         drv, sinks, sd = plan.drv[l], plan.sinks[l], plan.sink_drv[l]
         # Net step: the driver needs its tightest sink, less the wire delay.
-        req = rat[sinks] - delay[sinks][:, None]
+        req = pt(rat[sinks] - delay[sinks][:, None])
         rd = np.empty((len(drv), 4))
         rd[:, 0:2] = -np.inf
         rd[:, 2:4] = np.inf
@@ -402,7 +427,7 @@ def backward(d, lv: Levelization, fwd) -> dict:
             m, t = k // 2, k % 2
             tp = np.where(unate > 0, t, 1 - t)
             kp = 2 * m + tp
-            val = rat[drv, k][:, None] - ad[pins, k]
+            val = pt(rat[drv, k][:, None] - ad[pins, k])
             rat[pins[mask], kp[mask]] = val[mask]
     slack = np.empty((P, 4))
     slack[:, 2:4] = rat[:, 2:4] - at[:, 2:4]
@@ -427,7 +452,7 @@ def smoothed_objective(d, fwd, gamma: float) -> dict:
     return dict(tns_g=tns_g, wns_g=wns_g, s=s)
 
 
-def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=None, plan=None):
+def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=None, plan=None, perturb=None):
     """Full oracle: forward, backward, smoothed objective and (optionally) its gradient.
 
     Returns numpy float64 arrays by original pin id.
@@ -435,8 +460,8 @@ def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=Non
     lv = lv or levelize(d)
     xt = torch.tensor(np.asarray(d.x if x is None else x, np.float64), requires_grad=grad is not None)
     yt = torch.tensor(np.asarray(d.y if y is None else y, np.float64), requires_grad=grad is not None)
-    fwd = forward(d, lv, xt, yt, gamma, plan=plan)
-    bwd = backward(d, lv, fwd)
+    fwd = forward(d, lv, xt, yt, gamma, plan=plan, perturb=perturb)
+    bwd = backward(d, lv, fwd, perturb=perturb)
     obj = smoothed_objective(d, fwd, gamma)
     out = dict(at=fwd["at"].detach().numpy(), slew=fwd["slew"].detach().numpy(),
                atg=fwd["atg"].detach().numpy(), rat=bwd["rat"], slack=bwd["slack"],

@@ -354,3 +354,14 @@ def test_generator_levels_are_exact_cfg0():
     lv = O.levelize(d)
     assert lv.n_levels == CFG0.n_levels + 1
     assert np.array_equal(lv.level, d.gen_net_level)
+
+
+# ----------------------------------------------------------------------------- conditioning
+def test_fp32_noise_envelope_small_on_cfg0():
+    # cfg0 stays inside the table range: float32-sized noise moves no arrival beyond 1e-6.
+    d = make_design(CFG0)
+    lv = O.levelize(d)
+    ref = O.run(d, grad=None, lv=lv)
+    r = O.run(d, grad=None, lv=lv, perturb=O.fp32_rounding_noise(0))
+    assert np.max(np.abs(r["at"] - ref["at"]) / np.maximum(np.abs(ref["at"]), 1.0)) < 1e-6
+    assert not np.array_equal(r["at"], ref["at"])      # the perturbation is live
