@@ -149,30 +149,36 @@ def test_autograd_function_matches_backward():
     assert float(w) == pytest.approx(ref["wns_g"], rel=1e-4)
 
 
-def _envelope(d, lv, plan, ref, runs=2):
-    """Largest move of each exact output under float32-sized rounding noise in the oracle."""
+U32 = 2.0 ** -24        # float32 unit roundoff
+ROUNDINGS = 4           # float32 roundings allowed per operation in the first-order error bound
+
+
+def _grad_envelope(d, lv, plan, ref, runs=2):
+    """Largest move of the exact gradient under float32-sized rounding noise in the oracle."""
     env = {}
     for seed in range(runs):
         r = O.run(d, gamma=GAMMA, grad="tns", lv=lv, plan=plan, perturb=O.fp32_rounding_noise(seed))
-        for k in ("at", "slew", "atg", "rat", "slack", "dx", "dy"):
-            a, b = np.asarray(r[k], np.float64), np.asarray(ref[k], np.float64)
-            dev = np.where(np.isfinite(b), np.abs(np.where(np.isfinite(a), a, 0) - np.where(np.isfinite(b), b, 0)), 0.0)
-            env[k] = np.maximum(env.get(k, 0.0), dev)
+        for k in ("dx", "dy"):
+            env[k] = np.maximum(env.get(k, 0.0), np.abs(r[k] - ref[k]))
     return env
 
 
 def full_size_parity(spec):
     """Every output of the benchmark's launch (canonical IO) against the oracle.
 
-    Tolerance per value: the stated max(1e-4 |ref|, 1e-3 ps) widened to 3x the oracle's own
-    float32-noise envelope where the exact problem is ill-conditioned at float32 resolution
-    (extrapolated tables with slew gain > 1 amplify upstream rounding stage after stage).
+    Times and slews: max(1e-4 |ref|, 1e-3 ps, 4 u sigma), u = 2^-24 and sigma the oracle's
+    first-order running bound on float rounding of that value (sum over the operations that
+    produce it of |partial| x operand bound + |result|), allowing four float32 roundings per
+    operation.  4 u is 420x below the stated 1e-4, so the bound only takes over where
+    sigma > 420 |ref|: values that are sums of much larger, cancelling terms (early arc
+    delays of +-1e6 ps at 1e5 fF loads) or slews behind chains of extrapolated tables whose
+    slew gain exceeds 1.
     """
     d = make_design(spec)
     lv = O.levelize(d)
     plan = O._Plan(d, lv)
-    ref = O.run(d, gamma=GAMMA, grad="tns", lv=lv, plan=plan)
-    env = _envelope(d, lv, plan, ref)
+    ref = O.run(d, gamma=GAMMA, grad="tns", lv=lv, plan=plan, scales=True)
+    env = _grad_envelope(d, lv, plan, ref)
     got = gpu_run(d, canonical=True)
     perm = got["graph"].levelization()["pin_perm"]
     inv = np.empty_like(perm)
@@ -183,27 +189,28 @@ def full_size_parity(spec):
         r = ref[k]
         fin = np.isfinite(r)
         assert np.array_equal(np.isinf(g), ~fin) and np.array_equal(np.sign(g[~fin]), np.sign(r[~fin])), k
-        mag = np.abs(r) if k != "slack" else np.abs(np.where(np.isfinite(ref["rat"]), ref["rat"], 0)) + np.abs(ref["at"])
-        base = np.maximum(1e-4 * mag, 1e-3)
-        tol = np.maximum(base, 3.0 * env[k])
+        base = np.maximum(1e-4 * np.abs(np.where(fin, r, 0)), 1e-3)
+        tol = np.maximum(base, ROUNDINGS * U32 * ref[k + "_scale"])
         err = np.where(fin, np.abs(g - np.where(fin, r, 0)), 0)
         bad = err > tol
         widened += int(((err > base) & ~bad).sum())
-        print(f"  {k}: worst {np.max(err / tol):.3g}x tol, {(3.0 * env[k] > base).sum()} values ill-conditioned, "
-              f"{((err > base) & ~bad).sum()} inside the widened band")
+        print(f"  {k}: worst {np.max(err / tol):.3g}x tol, {(tol > base).sum()} values past the conditioning "
+              f"threshold, {((err > base) & ~bad).sum()} of them needed it")
         assert not bad.any(), f"{k}: {bad.sum()} values outside tolerance"
     for k in ("dx", "dy"):
         g = np.asarray(got[k], np.float64)[inv]
         r = ref[k]
-        tol = 1e-3 * np.abs(r) + 1e-6 * np.abs(r).max() + 3.0 * env[k]
+        tol0 = 1e-3 * np.abs(r) + 1e-6 * np.abs(r).max()
+        tol = tol0 + 3.0 * env[k]
         st = grad_stats(g, r)
-        print(f"  {k}: {st}; {(np.abs(g - r) > tol).sum()} outside tolerance")
+        print(f"  {k}: {st}; {(np.abs(g - r) > tol0).sum()} outside the plain bound, "
+              f"{(np.abs(g - r) > tol).sum()} outside the noise-widened bound")
         assert np.all(np.abs(g - r) <= tol), k
     sc = got["scalars"]
     assert sc[1] == pytest.approx(ref["tns"], rel=1e-4)
     assert sc[0] == pytest.approx(ref["wns"], rel=1e-4)
     assert sc[3] == pytest.approx(ref["tns_g"], rel=1e-4)
-    print(f"[{spec.name}] {d.n_pins} pins: {widened} values needed the conditioning band")
+    print(f"[{spec.name}] {d.n_pins} pins: {widened} values needed the rounding bound")
 
 
 @pytest.mark.slow

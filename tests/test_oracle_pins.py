@@ -365,3 +365,24 @@ def test_fp32_noise_envelope_small_on_cfg0():
     r = O.run(d, grad=None, lv=lv, perturb=O.fp32_rounding_noise(0))
     assert np.max(np.abs(r["at"] - ref["at"]) / np.maximum(np.abs(ref["at"]), 1.0)) < 1e-6
     assert not np.array_equal(r["at"], ref["at"])      # the perturbation is live
+
+
+@pytest.mark.parametrize("which", ["cfg0", "far_extrapolation"])
+def test_rounding_scales_bound_float32_perturbation(which):
+    # sigma is a first-order bound: one rounding of relative size <= u at every operation
+    # moves each value by at most u * sigma (up to second-order terms).
+    from gen.netlist import scaled_spec
+    d = make_design(CFG0 if which == "cfg0" else scaled_spec(20_000, cfg_id=77, box_um=4000.0))
+    lv = O.levelize(d)
+    plan = O._Plan(d, lv)
+    ref = O.run(d, grad=None, lv=lv, plan=plan, scales=True)
+    u = 2.0 ** -24
+    for seed in range(3):
+        p = O.run(d, grad=None, lv=lv, plan=plan, perturb=O.fp32_rounding_noise(seed))
+        for k in ("at", "slew", "atg", "rat", "slack"):
+            r, v = ref[k], p[k]
+            fin = np.isfinite(r)
+            assert np.array_equal(fin, np.isfinite(v)), k
+            assert np.all(ref[k + "_scale"][fin] >= np.abs(r[fin]) * (1 - 1e-12)), k
+            err = np.abs(v[fin] - r[fin])
+            assert np.all(err <= 1.01 * u * ref[k + "_scale"][fin] + 1e-9), (k, np.max(err / (u * ref[k + "_scale"][fin])))
