@@ -64,7 +64,8 @@ class Levelization:
     n_levels: int
     level: np.ndarray          # int32 [N], level of each original net
     level_offsets: np.ndarray  # int32 [L+1], over the canonical net order
-    net_perm: np.ndarray       # int32 [N], original id of the net at canonical position i
+    net_perm: np.ndarray       # int32 [N], original id of the net at canonical position i;
+                               # canonical order is (level, pins of the net, original id)
     pin_perm: np.ndarray       # int32 [P], original id of the pin at canonical position i
     net_of_pin: np.ndarray     # int64 [P]
     driver: np.ndarray         # int64 [N], driver pin of each net
@@ -135,7 +136,9 @@ def levelize(d) -> Levelization:
     if seen != N:
         raise CycleError("combinational cycle")
     L = int(level.max()) + 1
-    net_perm = np.argsort(level, kind="stable").astype(np.int32)   # (level, original id)
+    # Canonical order: (level, pins of the net, original id).
+    pins = np.diff(off)
+    net_perm = np.lexsort((np.arange(N), pins, level)).astype(np.int32)
     level_offsets = np.searchsorted(level[net_perm], np.arange(L + 1), side="left").astype(np.int32)
     pin_perm = np.concatenate([d.net_pins[off[n]:off[n + 1]] for n in net_perm]).astype(np.int32)
     return Levelization(L, level.astype(np.int32), level_offsets, net_perm, pin_perm,

@@ -82,45 +82,62 @@ LutKeys lut_keys(const sta_graph* g) {
 }
 
 // Lane-group schedule of a set of nets: stable order by class, and per-class wave counts.
-static GroupRange group_range(const int* cls_count, int base) {
+static GroupRange group_range(const int* cls_count, int base, int g0) {
   GroupRange r{};
+  r.g0 = g0;
   int off = base, waves = 0;
   for (int c = 0; c < kNumClasses; ++c) {
     r.cls_off[c] = off;
     r.wave_off[c] = waves;
-    int per_wave = 64 >> (2 + c);           // 16, 8, 4, 2, 1 nets per wave
+    const int G = (1 << g0) << c;
     off += cls_count[c];
-    waves += (cls_count[c] + per_wave - 1) / per_wave;
+    if (cls_count[c] > 0) waves += (cls_count[c] + 64 / G - 1) / (64 / G);   // 64/G nets per wave
   }
-  r.cls_off[kNumClasses] = off;
   r.wave_off[kNumClasses] = waves;
+  r.cls_off[kHeavy] = off;
+  r.cls_off[kHeavy + 1] = off + cls_count[kHeavy];
   return r;
 }
 
 static void build_schedule(sta_graph* g) {
   const int N = g->N;
   std::vector<int> cls(N);
-  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1);
-  g->sched.assign(N, 0);
+  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, kSweepG0);
+  // Within a level, canonical nets are sorted by size, so classes are contiguous ranges and
+  // a level's GroupRange indexes canonical net ids directly.
   g->lvl_ranges.assign(g->L, GroupRange{});
   for (int l = 0; l < g->L; ++l) {
     int b = g->level_off[l], e = g->level_off[l + 1];
-    int cnt[kNumClasses] = {0, 0, 0, 0, 0};
+    int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
     for (int n = b; n < e; ++n) cnt[cls[n]]++;
-    int pos[kNumClasses];
-    int o = b;
-    for (int c = 0; c < kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
-    for (int n = b; n < e; ++n) g->sched[pos[cls[n]]++] = n;
-    g->lvl_ranges[l] = group_range(cnt, b);
+    g->lvl_ranges[l] = group_range(cnt, b, kSweepG0);
   }
-  int cnt[kNumClasses] = {0, 0, 0, 0, 0};
+  // Cell inputs in a padded slot layout per level: input j of the k-th cell of level l is
+  // entry ell_base[l] + j * (cells of l) + k; missing inputs hold source net -1.
+  g->ell.clear();
+  g->ell_base.assign(g->L, 0);
+  g->ell_slots.assign(g->L, 0);
+  for (int l = 1; l < g->L; ++l) {
+    const int c0 = g->level_off[l] - g->N0, c1 = g->level_off[l + 1] - g->N0, nc = c1 - c0;
+    int F = 1;
+    for (int c = c0; c < c1; ++c) F = std::max(F, g->c_cin_off[c + 1] - g->c_cin_off[c]);
+    g->ell_base[l] = (int)g->ell.size();
+    g->ell_slots[l] = F;
+    g->ell.resize(g->ell.size() + (size_t)F * nc, make_int4(-1, 0, 0, 1));
+    for (int c = c0; c < c1; ++c)
+      for (int j = 0; j < g->c_cin_off[c + 1] - g->c_cin_off[c]; ++j)
+        g->ell[g->ell_base[l] + (size_t)j * nc + (c - c0)] = g->c_cin[g->c_cin_off[c] + j];
+  }
+  if (g->ell.empty()) g->ell.push_back(make_int4(-1, 0, 0, 1));
+  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, kFlatG0);
+  int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
   for (int n = 0; n < N; ++n) cnt[cls[n]]++;
-  int pos[kNumClasses];
+  int pos[kNumClasses + 1];
   int o = 0;
-  for (int c = 0; c < kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
+  for (int c = 0; c <= kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
   g->sched_all.assign(N, 0);
   for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
-  g->all_range = group_range(cnt, 0);
+  g->all_range = group_range(cnt, 0, kFlatG0);
 }
 
 void free_device(sta_graph* g) {
@@ -319,14 +336,18 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
     if (placed != N) return fail(STA_E_CYCLE, "combinational cycle: " + std::to_string(N - placed) + " nets never become ready");
     int L = 0;
     for (int n = 0; n < N; ++n) L = std::max(L, level[n] + 1);
-    // Canonical net order: (level, original id) by a counting sort.
+    // Canonical net order: (level, pins of the net, original id).  Sorting by size inside
+    // a level makes each lane-group class a contiguous range of the level.
     std::vector<int> lcount(L + 1, 0);
     for (int n = 0; n < N; ++n) lcount[level[n] + 1]++;
     for (int l = 0; l < L; ++l) lcount[l + 1] += lcount[l];
     g->level_off = lcount;
-    std::vector<int> pos(lcount.begin(), lcount.end() - 1);
-    g->net_perm.assign(N, 0);
-    for (int n = 0; n < N; ++n) g->net_perm[pos[level[n]]++] = n;
+    g->net_perm.resize(N);
+    std::iota(g->net_perm.begin(), g->net_perm.end(), 0);
+    std::stable_sort(g->net_perm.begin(), g->net_perm.end(), [&](int a, int b) {
+      if (level[a] != level[b]) return level[a] < level[b];
+      return g->net_off[a + 1] - g->net_off[a] < g->net_off[b + 1] - g->net_off[b];
+    });
     std::vector<int> net_new(N);
     for (int i = 0; i < N; ++i) net_new[g->net_perm[i]] = i;
     // Canonical pins, net by net.
@@ -360,6 +381,8 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
     g->c_cin_off.assign(C + 1, 0);
     g->c_cin_src.assign(g->A, 0);
     g->c_cin_pin.assign(g->A, 0);
+    g->c_cin.clear();
+    g->c_cin.reserve(g->A);
     int a = 0;
     for (int cc = 0; cc < C; ++cc) {
       int c = cell_of_net[g->net_perm[N0 + cc]];
@@ -369,6 +392,8 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
         int p = g->cell_in_pins[i];
         g->c_cin_pin[a] = pin_new[p];
         g->c_cin_src[a] = net_new[net_of_pin[p]];
+        const int arc = g->arc_off[g->cell_type[c]] + (i - g->cell_in_off[c]);
+        g->c_cin.push_back(make_int4(g->c_cin_src[a], g->c_cin_pin[a], arc, (int)g->unate[arc]));
         ++a;
       }
     }
@@ -452,7 +477,7 @@ sta_status sta_graph_upload(sta_graph* g) {
   d.device = dev;
   std::vector<float4> grid, coef;
   build_lut_coefficients(g, grid, coef);
-  std::vector<int> type_arc0(g->arc_off);
+
   auto up = [&](auto*& dst, const auto& src) -> sta_status {
     using T = std::remove_reference_t<decltype(*dst)>;
     size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
@@ -469,12 +494,9 @@ sta_status sta_graph_upload(sta_graph* g) {
     return STA_OK;
   };
   sta_status s = STA_OK;
-  std::vector<int8_t> unate(g->unate);
-  if ((s = up(d.net_off, g->c_net_off)) || (s = up(d.pin_cap, g->c_pin_cap)) ||
-      (s = up(d.cell_type, g->c_cell_type)) || (s = up(d.type_arc0, type_arc0)) || (s = up(d.unate, unate)) ||
-      (s = up(d.cin_off, g->c_cin_off)) || (s = up(d.cin_src, g->c_cin_src)) || (s = up(d.cin_pin, g->c_cin_pin)) ||
+  if ((s = up(d.net_off, g->c_net_off)) || (s = up(d.pin_cap, g->c_pin_cap)) || (s = up(d.ell, g->ell)) ||
       (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_net)) || (s = up(d.pin_perm, g->pin_perm)) ||
-      (s = up(d.sched, g->sched)) || (s = up(d.sched_all, g->sched_all)) || (s = up(d.lvl, g->lvl_ranges)) ||
+      (s = up(d.sched_all, g->sched_all)) ||
       (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
     free_device(g);
     return s;

@@ -13,24 +13,30 @@
 namespace sta {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
-constexpr int kNumClasses = 5;       // lane groups of 4, 8, 16, 32, 64 lanes per net
+constexpr int kNumClasses = 5;       // wave lane groups of 4, 8, 16, 32, 64 lanes per net
+constexpr int kHeavy = kNumClasses;  // class of nets served by a whole workgroup
 constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
+constexpr int kFlatG0 = 2;           // flat kernels (RC, outputs): smallest group 4 lanes
+constexpr int kSweepG0 = 4;          // level kernels: smallest group 16 lanes (4 conditions x 4 arcs)
 
-// Lane-group class of a net with `sinks` sink pins: the smallest group in which every
-// lane holds at most one sink, capped at a whole wave.
-inline int net_class(int sinks) {
-  if (sinks <= 4) return 0;
-  if (sinks <= 8) return 1;
-  if (sinks <= 16) return 2;
-  if (sinks <= 32) return 3;
-  return 4;
+// Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0
+// lanes: the smallest wave group (doubling from 1 << g0) in which every lane holds at most
+// one sink; nets with more than 64 sinks get a whole workgroup.
+inline int net_class(int sinks, int g0) {
+  int c = 0;
+  for (int G = 1 << g0; G <= 64; G <<= 1, ++c)
+    if (sinks <= G) return c;
+  return kHeavy;
 }
 
 // A batch of nets processed by one launch: schedule entries [cls_off[c], cls_off[c+1])
-// belong to class c and are served by waves [wave_off[c], wave_off[c+1]) of the launch.
+// belong to class c, served by groups of (1 << g0) << c lanes.  Heavy nets take blocks
+// [0, n_heavy) of the launch, one each; wave classes are served by waves
+// [wave_off[c], wave_off[c+1]) of the blocks after them.
 struct GroupRange {
-  int cls_off[kNumClasses + 1];
+  int cls_off[kNumClasses + 2];
   int wave_off[kNumClasses + 1];
+  int g0;
 };
 
 // Breakpoints compared against when locating a table cell (held in scalar registers).
@@ -60,18 +66,11 @@ struct DeviceGraph {
   std::vector<void*> allocs;
   int* net_off = nullptr;      // [N+1] canonical
   float* pin_cap = nullptr;    // [P]
-  int* cell_type = nullptr;    // [C] canonical cells (cell c drives net N0 + c)
-  int* type_arc0 = nullptr;    // [T+1]
-  int8_t* unate = nullptr;     // [n_arcs]
-  int* cin_off = nullptr;      // [C+1]
-  int* cin_src = nullptr;      // [A] canonical source net of each cell input
-  int* cin_pin = nullptr;      // [A] canonical pin of each cell input
+  int4* ell = nullptr;         // cell inputs {source net, pin, arc, unateness}, padded slots per level
   int* ep_pin = nullptr;       // [E]
   int* ep_net = nullptr;       // [E]
   int* pin_perm = nullptr;     // [P] original id of each canonical pin
-  int* sched = nullptr;        // [N] per-level nets ordered by class
   int* sched_all = nullptr;    // [N] all nets ordered by class
-  GroupRange* lvl = nullptr;   // [L]
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
   size_t bytes = 0;
@@ -95,8 +94,11 @@ struct sta_graph {
   int L = 0, N0 = 0, E = 0, max_level_nets = 0;
   std::vector<int> level, level_off, net_perm, pin_perm;
   std::vector<int> c_net_off, c_cell_type, c_cin_off, c_cin_src, c_cin_pin, ep_pin, ep_net;
+  std::vector<int4> c_cin;                     // packed cell inputs (device layout)
   std::vector<float> c_pin_cap;
-  std::vector<int> sched, sched_all;
+  std::vector<int> sched_all;
+  std::vector<int4> ell;                       // padded per-level cell-input slots
+  std::vector<int> ell_base, ell_slots;        // per level: first entry, slots per cell
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
   sta::StateLayout state{};

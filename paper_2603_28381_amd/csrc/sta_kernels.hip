@@ -1,20 +1,27 @@
 // HIP kernels of the levelized STA sweep for CDNA4 (gfx950, wave64), and the C ABI calls
 // that launch them (sta_forward, sta_backward).
 //
-// Data layout (canonical order from sta_levelize): nets sorted by level, pins net-major
-// with the driver first.  The forward sweep keeps one 48-byte record per net - the
-// driver's arrival time and slew for the four conditions and its smoothed late arrival -
-// and derives a sink's state on demand from its driver record plus the sink's
+// Data layout (canonical order from sta_levelize): nets sorted by (level, pins), pins
+// net-major with the driver first.  The forward sweep keeps one 48-byte record per net -
+// the driver's arrival time and slew for the four conditions and its smoothed late
+// arrival - and derives a sink's state on demand from its driver record plus the sink's
 // {wire delay, impulse}.  A level therefore gathers one record per cell input and writes
 // one record per net; per-pin outputs are written by the backward sweep, which visits
 // every pin anyway.
 //
-// Lane mapping (the pin-based scheme of Sec. 3.1, re-derived for 64-lane wavefronts):
-// net-level work (RC delay, backward net step, adjoint) gives each net a group of 4, 8,
-// 16, 32 or 64 lanes chosen from its sink count, packing 16 small nets into one wave and
-// giving a heavy-tailed net the whole wave; reductions over a net's sinks are xor
-// butterflies inside the group (fixed order, no atomics, Sec. 3.1.1).  Cell-level work
-// gives each cell 4 lanes, one per timing condition (the condition axis of Alg. 1).
+// Lane mapping (the pin-based scheme of Sec. 3.1, re-derived for 64-lane wavefronts).  A
+// level holds a few thousand nets, so a level kernel occupies about one wave per SIMD and
+// its time is the instruction chain of one lane: work is spread over lanes to keep that
+// chain short.
+//  * Cell step: 16 lanes per cell, one per (timing condition, arc) - the condition axis of
+//    Alg. 1 times the arcs - so every lane does one table lookup; max/min, log-sum-exp,
+//    softmax and arg max over a condition's arcs reduce over 4 lanes with DPP quad
+//    permutes.
+//  * Net step: a group of 16, 32 or 64 lanes per net (one sink per lane), or a whole
+//    256-thread workgroup for nets over 64 sinks; reductions over a net's sinks are DPP
+//    and xor butterflies inside the group, across waves through LDS in a fixed order
+//    (no atomics, Sec. 3.1.1).
+//  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
 #include <cmath>
 
 #include "sta_internal.h"
@@ -23,6 +30,9 @@ namespace sta {
 namespace {
 
 constexpr float kInf = __builtin_huge_valf();
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kCellLanes = 16;   // lanes per cell: 4 conditions x 4 arcs
+constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
 
 // ---------------------------------------------------------------------------- helpers
 // Table cell of v along an axis: upper_bound(axis, v) - 1 clamped to [0, 5], computed as
@@ -71,63 +81,141 @@ __device__ __forceinline__ float sink_slew(float drv_slew, float imp) {
   return sqrtf(fmaf(drv_slew, drv_slew, imp * imp));
 }
 
-// Running log-sum-exp (Eq. 4) with the maximum as the shift.
-__device__ __forceinline__ void lse_push(float& m, float& s, float v, float inv_gamma) {
-  if (v > m) {
-    s = fmaf(s, expf((m - v) * inv_gamma), 1.0f);
-    m = v;
-  } else {
-    s += expf((v - m) * inv_gamma);
+// Merges log-sum-exp partials (m, s) <- (m, s) + (m2, s2), each meaning m + gamma*log(s)
+// (Eq. 4 with the maximum as the shift).
+__device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2, float inv_gamma) {
+  if (m2 > m) {
+    s = fmaf(s, expf((m - m2) * inv_gamma), s2);
+    m = m2;
+  } else if (s2 > 0.f) {
+    s = fmaf(s2, expf((m2 - m) * inv_gamma), s);
   }
-}
-
-__device__ __forceinline__ float grp_sum(float v, int G) {
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ __forceinline__ float grp_min(float v, int G) {
-  for (int o = 1; o < G; o <<= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ float grp_max(float v, int G) {
-  for (int o = 1; o < G; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
 }
 
 __device__ __forceinline__ float sgnf(float v) { return (v > 0.f) ? 1.f : ((v < 0.f) ? -1.f : 0.f); }
 
-// Lane-group assignment of one wave inside a GroupRange (all lanes of a wave agree on the
-// class; lanes of one group agree on the net).
+// DPP lane permutes inside a row of 16 lanes: quad xor 1, quad xor 2, reverse within 8,
+// reverse within 16.  Successive steps pair every value with every other exactly once, so
+// sums, minima and maxima come out identical on all lanes of the row.
+enum : int { kDppQuadX1 = 0xB1, kDppQuadX2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+enum RedOp { kSum = 0, kMin = 1, kMax = 2 };
+
+template <int OP>
+__device__ __forceinline__ float red2(float a, float b) {
+  return OP == kSum ? a + b : (OP == kMin ? fminf(a, b) : fmaxf(a, b));
+}
+
+// Reduction over the 4 lanes of a quad (the arcs of one condition).
+template <int OP>
+__device__ __forceinline__ float quad_reduce(float v) {
+  v = red2<OP>(v, dpp<kDppQuadX1>(v));
+  return red2<OP>(v, dpp<kDppQuadX2>(v));
+}
+
+// Largest value over a quad with its lane's arc index; ties go to the lowest index.
+__device__ __forceinline__ void quad_argmax(float& v, int& j) {
+  float v2 = dpp<kDppQuadX1>(v);
+  int j2 = dpp_i<kDppQuadX1>(j);
+  if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+  v2 = dpp<kDppQuadX2>(v);
+  j2 = dpp_i<kDppQuadX2>(j);
+  if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+}
+
+// Reduction over an aligned group of G lanes (G = 16, 32 or 64) of a wave.
+template <int OP, int G>
+__device__ __forceinline__ float wave_group_reduce(float v) {
+  v = red2<OP>(v, dpp<kDppQuadX1>(v));
+  v = red2<OP>(v, dpp<kDppQuadX2>(v));
+  v = red2<OP>(v, dpp<kDppHalfMirror>(v));
+  v = red2<OP>(v, dpp<kDppMirror>(v));
+  if (G >= 32) v = red2<OP>(v, __shfl_xor(v, 16));
+  if (G >= 64) v = red2<OP>(v, __shfl_xor(v, 32));
+  return v;
+}
+
+// Reduction over the lanes of a group of runtime size G = 4..64 (flat kernels).
+__device__ __forceinline__ float wave_group_sum(float v, int G) {
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------- lane groups
+// Which net (schedule entry) a thread serves inside a GroupRange launch.  Blocks
+// [0, n_heavy) take one heavy net each (all 256 threads); the remaining blocks hold waves
+// of the wave classes.  All lanes of a wave agree on the class, all lanes of a group on
+// the net, and all threads of a block on `block`.
 struct GroupSlot {
   int G;        // lanes per net
   int gl;       // lane index inside the group
   int entry;    // schedule entry, valid if active
   bool active;
+  bool block;   // a whole workgroup serves one net
 };
 
-__device__ __forceinline__ bool group_slot(const GroupRange& r, int wave, int lane, GroupSlot& s) {
+__device__ __forceinline__ bool group_slot(const GroupRange& r, GroupSlot& s) {
+  const int nh = r.cls_off[kNumClasses + 1] - r.cls_off[kNumClasses];
+  if ((int)blockIdx.x < nh) {
+    s.block = true;
+    s.G = kBlock;
+    s.gl = threadIdx.x;
+    s.entry = r.cls_off[kNumClasses] + (int)blockIdx.x;
+    s.active = true;
+    return true;
+  }
+  s.block = false;
+  const int wave = ((int)blockIdx.x - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (wave >= r.wave_off[kNumClasses]) return false;
   int c = 0;
   while (c < kNumClasses - 1 && wave >= r.wave_off[c + 1]) ++c;
-  s.G = 4 << c;
+  const int lg = r.g0 + c;           // log2 of the group size
+  s.G = 1 << lg;
   s.gl = lane & (s.G - 1);
-  s.entry = r.cls_off[c] + (wave - r.wave_off[c]) * (64 >> (2 + c)) + (lane >> (2 + c));
+  s.entry = r.cls_off[c] + (wave - r.wave_off[c]) * (64 >> lg) + (lane >> lg);
   s.active = s.entry < r.cls_off[c + 1];
   return true;
 }
 
+inline unsigned range_grid(const GroupRange& r) {
+  const int nh = r.cls_off[kNumClasses + 1] - r.cls_off[kNumClasses];
+  return (unsigned)(nh + (r.wave_off[kNumClasses] + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+// Sum over the 256 threads of a workgroup (fixed order: wave butterflies, then waves in
+// order through LDS).  `sh` holds kWavesPerBlock floats.
+__device__ __forceinline__ float block_sum(float v, float* sh) {
+  v = wave_group_reduce<kSum, 64>(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = sh[0];
+  for (int q = 1; q < kWavesPerBlock; ++q) r += sh[q];
+  __syncthreads();
+  return r;
+}
+
 // ---------------------------------------------------------------------------- RC (Alg. 1)
 struct RcArgs {
-  const int* net_off;
-  const float* pin_cap;
-  const float* x;
-  const float* y;
-  const int* io_perm;        // canonical -> caller index, or NULL
-  const int* sched;
+  const int* __restrict__ net_off;
+  const float* __restrict__ pin_cap;
+  const float* __restrict__ x;
+  const float* __restrict__ y;
+  const int* __restrict__ io_perm;        // canonical -> caller index, or NULL
+  const int* __restrict__ sched;
   GroupRange range;
-  float2* wire;
-  float* load;
-  float4* rec;
+  float2* __restrict__ wire;
+  float* __restrict__ load;
+  float4* __restrict__ rec;
   int N0;
   float r, c, pi_at, pi_slew;
 };
@@ -136,10 +224,9 @@ struct RcArgs {
 // impulse, per net the root load by a group reduction.  Level-0 (primary input) records
 // are initialised here too.
 __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
-  const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
+  __shared__ float sh[kWavesPerBlock];
   GroupSlot gs;
-  if (!group_slot(a.range, wave, lane, gs)) return;
+  if (!group_slot(a.range, gs)) return;
   const int n = gs.active ? a.sched[gs.entry] : 0;
   int p0 = 0, p1 = 0;
   float xd = 0.f, yd = 0.f;
@@ -165,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     a.wire[p] = make_float2(dly, imp);
     sum += cp + cw;                              // the sink's Load plus the root half of the wire
   }
-  sum = grp_sum(sum, gs.G);
+  sum = gs.block ? block_sum(sum, sh) : wave_group_sum(sum, gs.G);
   if (gs.active && gs.gl == 0) {
     a.load[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
     a.wire[p0] = make_float2(0.f, 0.f);
@@ -178,70 +265,104 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------- cell inputs
+// Padded slots of one level's cell inputs: input j of the k-th cell is ell[base + j*nc + k];
+// an empty slot holds source net -1.
+struct Slots {
+  int base, F, c0, nc;
+};
+
+struct ArcIn {          // one cell input seen from one condition
+  float at, slew, atg;  // arrival, slew and smoothed arrival at the input pin
+  int arc, tp, pin;
+  bool valid;
+};
+
+// Input j of cell kc for output condition (m, t): the source net's driver record plus the
+// wire to the input pin, in the input transition the arc's unateness selects.  Missing
+// inputs (j past the cell's fanin) read net 0 and come back invalid.
+__device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const Slots& sl, int kc, int j,
+                                           const float4* __restrict__ rec, const float2* __restrict__ wire,
+                                           int m, int t) {
+  const int4 e = ell[sl.base + (size_t)min(j, sl.F - 1) * sl.nc + kc];
+  ArcIn r;
+  r.valid = j < sl.F && e.x >= 0;
+  r.arc = e.z;
+  r.tp = e.w > 0 ? t : 1 - t;
+  r.pin = e.y;
+  const int kp = 2 * m + r.tp;
+  const float* src = reinterpret_cast<const float*>(rec + 3 * (size_t)max(e.x, 0));
+  const float2 w = wire[e.y];
+  r.at = src[kp] + w.x;
+  r.slew = sink_slew(src[4 + kp], w.y);
+  r.atg = src[8 + r.tp] + w.x;
+  return r;
+}
+
 // ---------------------------------------------------------------------------- forward level
 struct FwdArgs {
-  const int* cell_type;
-  const int* type_arc0;
-  const int8_t* unate;
-  const int* cin_off;
-  const int* cin_src;
-  const int* cin_pin;
-  const float2* wire;
-  const float* load;
-  float4* rec;
-  const float4* grid;
-  const float4* coef;
+  const int4* __restrict__ ell;      // padded cell-input slots {source net, sink pin, arc, unateness}
+  const float2* __restrict__ wire;
+  const float* __restrict__ load;
+  float4* __restrict__ rec;
+  const float4* __restrict__ grid;
+  const float4* __restrict__ coef;
   LutKeys keys;
   int N0;
   float gamma, inv_gamma;
   int smooth;
 };
 
-// One level of forward propagation (Sec. 3.1.2): 4 lanes per cell, lane k handles
-// condition k = 2*mode + transition over all of the cell's arcs.
-__global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, int c0, int c1) {
+// One level of forward propagation (Sec. 3.1.2).  16 lanes per cell: lane (k, j) looks up
+// arc j for condition k = 2*mode + transition; the 4 arc lanes of a condition then merge
+// by max (late) / min (early), worst slew, and log-sum-exp of the late candidates (Eq. 4).
+__global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
   const int gid = (int)(blockIdx.x * kBlock + threadIdx.x);
-  const int cell = c0 + (gid >> 2);
-  if (cell >= c1) return;
-  const int k = gid & 3, m = k >> 1, t = k & 1;
-  const int n = a.N0 + cell;
+  const int kc = gid / kCellLanes;
+  if (kc >= sl.nc) return;                     // uniform over the cell's 16 lanes
+  const int lane = gid & (kCellLanes - 1);
+  const int k = lane >> 2, jl = lane & 3, m = k >> 1, t = k & 1;
+  const int n = a.N0 + sl.c0 + kc;
   const float load = a.load[n];
-  const int arc0 = a.type_arc0[a.cell_type[cell]];
-  const int j0 = a.cin_off[cell], j1 = a.cin_off[cell + 1];
   float best_at = m ? -kInf : kInf;
   float best_sl = best_at;
   float lm = -kInf, ls = 0.f;
-  for (int j = j0; j < j1; ++j) {
-    const int arc = arc0 + (j - j0);
-    const int tp = a.unate[arc] > 0 ? t : 1 - t;     // input transition
-    const int kp = 2 * m + tp;
-    const float* src = reinterpret_cast<const float*>(a.rec + 3 * (size_t)a.cin_src[j]);
-    const float2 w = a.wire[a.cin_pin[j]];
-    const float at_in = src[kp] + w.x;
-    const float sl_in = sink_slew(src[4 + kp], w.y);
-    const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, arc, t, sl_in, load);
-    const float cand = at_in + v.d;
+  for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
+    const ArcIn in = arc_input(a.ell, sl, kc, j0 + jl, a.rec, a.wire, m, t);
+    float cand = m ? -kInf : kInf, s = cand, g = -kInf;
+    if (in.valid) {
+      const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
+      cand = in.at + v.d;
+      s = v.s;
+      g = in.atg + v.d;
+    }
     if (m) {
-      best_at = fmaxf(best_at, cand);
-      best_sl = fmaxf(best_sl, v.s);
-      if (a.smooth) lse_push(lm, ls, (src[8 + tp] + w.x) + v.d, a.inv_gamma);
+      best_at = fmaxf(best_at, quad_reduce<kMax>(cand));
+      best_sl = fmaxf(best_sl, quad_reduce<kMax>(s));
+      if (a.smooth) {
+        const float gm = quad_reduce<kMax>(g);
+        const float gs = quad_reduce<kSum>(in.valid ? expf((g - gm) * a.inv_gamma) : 0.f);
+        lse_merge(lm, ls, gm, gs, a.inv_gamma);
+      }
     } else {
-      best_at = fminf(best_at, cand);
-      best_sl = fminf(best_sl, v.s);
+      best_at = fminf(best_at, quad_reduce<kMin>(cand));
+      best_sl = fminf(best_sl, quad_reduce<kMin>(s));
     }
   }
-  float* o = reinterpret_cast<float*>(a.rec + 3 * (size_t)n);
-  o[k] = best_at;
-  o[4 + k] = best_sl;
-  if (m) o[8 + t] = a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("");
+  if (jl == 0) {
+    float* o = reinterpret_cast<float*>(a.rec + 3 * (size_t)n);
+    o[k] = best_at;
+    o[4 + k] = best_sl;
+    if (m) o[8 + t] = a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("");
+  }
 }
 
 // ---------------------------------------------------------------------------- endpoints
 struct EpArgs {
-  const int* ep_pin;
-  const int* ep_net;
-  const float4* rec;
-  const float2* wire;
+  const int* __restrict__ ep_pin;
+  const int* __restrict__ ep_net;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
   double* part;        // [blocks][5]
   double* fin;         // [8]
   double* scalars;     // [4] or NULL
@@ -367,7 +488,6 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a) {
   if (i >= a.E) return;
   const int e = a.ep_pin[i];
   a.ratp[e] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
-  float g0 = 0.f, g1 = 0.f;
   if (a.adjp) {
     const EpVals ev = endpoint_values(a, i);
     float coef;
@@ -378,20 +498,18 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a) {
     }
     // d s_e / d atg(e, t) = -w_t; the objective's adjoint scales by `scale`.
     const float sc = a.scale_dev ? a.scale * (float)a.scale_dev[0] : a.scale;
-    g0 = -sc * coef * ev.w0;
-    g1 = -sc * coef * ev.w1;
-    a.adjp[e] = make_float4(g0, g1, 0.f, 0.f);
+    a.adjp[e] = make_float4(-sc * coef * ev.w0, -sc * coef * ev.w1, 0.f, 0.f);
   }
 }
 
 // ---------------------------------------------------------------------------- outputs
 struct ExpandArgs {
-  const int* net_off;
-  const int* io_perm;
-  const int* sched;
+  const int* __restrict__ net_off;
+  const int* __restrict__ io_perm;
+  const int* __restrict__ sched;
   GroupRange range;
-  const float4* rec;
-  const float2* wire;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
   float4* at;
   float4* slew;
   float2* atg;
@@ -399,10 +517,8 @@ struct ExpandArgs {
 
 // Per-pin arrival, slew and smoothed arrival from the net records (forward outputs).
 __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
-  const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
   GroupSlot gs;
-  if (!group_slot(a.range, wave, lane, gs) || !gs.active) return;
+  if (!group_slot(a.range, gs) || !gs.active) return;
   const int n = a.sched[gs.entry];
   const int p0 = a.net_off[n], p1 = a.net_off[n + 1];
   const float4 at = a.rec[3 * (size_t)n], sl = a.rec[3 * (size_t)n + 1], ag = a.rec[3 * (size_t)n + 2];
@@ -418,54 +534,164 @@ __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
 
 // ---------------------------------------------------------------------------- backward level
 struct BwdArgs {
-  const int* net_off;
-  const float* pin_cap;
-  const int* cell_type;
-  const int* type_arc0;
-  const int8_t* unate;
-  const int* cin_off;
-  const int* cin_src;
-  const int* cin_pin;
-  const int* sched;
-  const GroupRange* lvl;
-  const int* io_perm;
-  const float* x;
-  const float* y;
-  const float4* grid;
-  const float4* coef;
+  const int* __restrict__ net_off;
+  const float* __restrict__ pin_cap;
+  const int4* __restrict__ ell;
+  const int* __restrict__ io_perm;
+  const float* __restrict__ x;
+  const float* __restrict__ y;
+  const float4* __restrict__ grid;
+  const float4* __restrict__ coef;
   LutKeys keys;
-  const float4* rec;
-  const float2* wire;
-  const float* load;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
+  const float* __restrict__ load;
   float4* ratp;
   float4* adjp;
-  float4* at_out;
-  float4* slew_out;
-  float4* rat_out;
-  float4* slack_out;
-  float* dx;
-  float* dy;
+  float4* __restrict__ at_out;
+  float4* __restrict__ slew_out;
+  float4* __restrict__ rat_out;
+  float4* __restrict__ slack_out;
+  float* __restrict__ dx;
+  float* __restrict__ dy;
   int N0;
   float r, c, inv_gamma;
   int grad;
 };
 
-// One level of backward propagation (Sec. 2.1 stage 4, Sec. 3.1.2) fused with the adjoint
-// of the smoothed objective (Sec. 3.2).  Per net, one lane group:
+// Accumulators of the net step (reduced over the group).
+enum { R_E0, R_E1, R_L0, R_L1, A_R, A_F, S_R, S_F, X_RS, X_N, Y_RS, Y_N, N_ACC };
+
+struct SinkKeep {     // what phase 3 needs of a sink, kept in registers
+  float gx, gy, rest;
+  int q;
+};
+
+// Net step of one sink: per-pin outputs and its contribution to the driver's reductions.
+__device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, int p, const float4& at_d, const float4& sl_d,
+                                              float xd, float yd, float (&acc)[N_ACC], bool write) {
+  const float4 rt = a.ratp[p];
+  const float2 w = a.wire[p];
+  const int q = a.io_perm ? a.io_perm[p] : p;
+  float4 aj = make_float4(0.f, 0.f, 0.f, 0.f);
+  float xs = 0.f, ys = 0.f, cp = 0.f;
+  if (a.grad) {
+    aj = a.adjp[p];
+    xs = a.x[q];
+    ys = a.y[q];
+    cp = a.pin_cap[p];
+  }
+  const float4 ats = make_float4(at_d.x + w.x, at_d.y + w.x, at_d.z + w.x, at_d.w + w.x);
+  const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
+                                 sink_slew(sl_d.w, w.y));
+  if (write) {
+    if (a.at_out) a.at_out[q] = ats;
+    if (a.slew_out) a.slew_out[q] = sls;
+    if (a.rat_out) a.rat_out[q] = rt;
+    if (a.slack_out) a.slack_out[q] = make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w);
+  }
+  acc[R_E0] = fmaxf(acc[R_E0], rt.x - w.x);
+  acc[R_E1] = fmaxf(acc[R_E1], rt.y - w.x);
+  acc[R_L0] = fminf(acc[R_L0], rt.z - w.x);
+  acc[R_L1] = fminf(acc[R_L1], rt.w - w.x);
+  SinkKeep k{0.f, 0.f, 0.f, q};
+  if (a.grad) {
+    const float q0 = sls.z > 0.f ? aj.z / sls.z : 0.f;   // s_bar(s,t) / slew(s,late,t)
+    const float q1 = sls.w > 0.f ? aj.w / sls.w : 0.f;
+    acc[A_R] += aj.x;
+    acc[A_F] += aj.y;
+    acc[S_R] += q0 * sl_d.z;
+    acc[S_F] += q1 * sl_d.w;
+    const float dbar = aj.x + aj.y;                      // adjoint of the wire delay
+    const float ibar = (q0 + q1) * w.y;                  // adjoint of the impulse
+    const float len = fabsf(xs - xd) + fabsf(ys - yd);
+    // d Delay / d len = d Impulse / d len = 1e-3 r (Cpin + c len) for a star sink.
+    k.rest = (dbar + ibar) * (1e-3f * a.r * fmaf(a.c, len, cp));
+    k.gx = sgnf(xs - xd);
+    k.gy = sgnf(ys - yd);
+    acc[X_RS] += k.gx * k.rest;
+    acc[X_N] += k.gx;
+    acc[Y_RS] += k.gy * k.rest;
+    acc[Y_N] += k.gy;
+  }
+  return k;
+}
+
+struct ArcBwd {         // one arc of the cell step, seen from one condition's lane
+  float d, xg, s, ddx, ddy, dsx, dsy;
+  int pin, tp;
+  bool valid;
+};
+
+__device__ __forceinline__ ArcBwd arc_backward(const BwdArgs& a, const Slots& sl, int kc, int j, int m, int t,
+                                               float load) {
+  const ArcIn in = arc_input(a.ell, sl, kc, j, a.rec, a.wire, m, t);
+  ArcBwd r;
+  r.valid = in.valid;
+  r.pin = in.pin;
+  r.tp = in.tp;
+  r.d = r.s = r.ddx = r.ddy = r.dsx = r.dsy = 0.f;
+  r.xg = -kInf;
+  if (in.valid) {
+    const LutVal v = lut_eval<true>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
+    r.d = v.d;
+    r.s = v.s;
+    r.xg = in.atg + v.d;
+    r.ddx = v.ddx;
+    r.ddy = v.ddy;
+    r.dsx = v.dsx;
+    r.dsy = v.dsy;
+  }
+  return r;
+}
+
+// Group-wide reduction of the net-step accumulators (G = 16/32/64 wave groups, or a whole
+// workgroup when `block`).
+template <int G>
+__device__ __forceinline__ void reduce_acc(float (&v)[N_ACC], bool block, float* sh) {
+  v[R_E0] = wave_group_reduce<kMax, G>(v[R_E0]);
+  v[R_E1] = wave_group_reduce<kMax, G>(v[R_E1]);
+  v[R_L0] = wave_group_reduce<kMin, G>(v[R_L0]);
+  v[R_L1] = wave_group_reduce<kMin, G>(v[R_L1]);
+#pragma unroll
+  for (int i = A_R; i < N_ACC; ++i) v[i] = wave_group_reduce<kSum, G>(v[i]);
+  if (block) {
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int i = 0; i < N_ACC; ++i) sh[w * N_ACC + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N_ACC; ++i) {
+      float r = sh[i];
+      for (int q = 1; q < kWavesPerBlock; ++q) {
+        const float b = sh[q * N_ACC + i];
+        r = i <= R_E1 ? fmaxf(r, b) : (i <= R_L1 ? fminf(r, b) : r + b);
+      }
+      v[i] = r;
+    }
+    __syncthreads();
+  }
+}
+
+// Backward work of one net, Sec. 2.1 stage 4 and Sec. 3.1.2, fused with the adjoint of the
+// smoothed objective (Sec. 3.2).  G lanes serve the net (a wave group, or the 256 threads of
+// a workgroup when `block`; the workgroup then reduces through LDS):
 //  1. net step over the sinks: per-pin outputs, RAT(driver) = min/max over sinks of
 //     RAT(sink) - wire delay, sums of the sinks' adjoints into the driver;
-//  2. cell step on lanes 0..3 (one condition each): every input's required time, the
-//     softmax split of the driver's adjoint over the arcs (the LSE gradient), the slew
-//     adjoint through the table partials and the arg-max slew arc, and the load adjoint;
+//  2. cell step on the group's first 16 lanes, lane (k, j) for condition k and arc j:
+//     every input's required time, the softmax split of the driver's adjoint over the arcs
+//     (the LSE gradient), the slew adjoint through the table partials and the arg-max slew
+//     arc, and the load adjoint;
 //  3. Elmore adjoint: each sink's wire-length adjoint and d/dx, d/dy of every pin.
-__global__ __launch_bounds__(kBlock) void k_bwd_level(BwdArgs a, int level) {
-  const int wave = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  const GroupRange rg = a.lvl[level];
-  GroupSlot gs;
-  if (!group_slot(rg, wave, lane, gs)) return;
-  const int G = gs.G, gl = gs.gl;
-  const int n = gs.active ? a.sched[gs.entry] : 0;
+// The cell step's loads and table lookups depend only on forward state, so they are issued
+// before the sink reduction they later combine with.
+template <int G>
+__device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const GroupSlot& gs, float* sh) {
+  const int gl = gs.gl;
+  const bool block = gs.block;
+  const int n = gs.active ? gs.entry : 0;      // level ranges index canonical nets
   int p0 = 0, p1 = 0;
   float xd = 0.f, yd = 0.f;
   float4 at_d = make_float4(0.f, 0.f, 0.f, 0.f), sl_d = at_d;
@@ -480,169 +706,172 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(BwdArgs a, int level) {
       yd = a.y[q];
     }
   }
-  const float k1e3r = 1e-3f * a.r;
 
-  // 1. Net step.
-  float rq0 = -kInf, rq1 = -kInf, rq2 = kInf, rq3 = kInf;
-  float ab0 = 0.f, ab1 = 0.f, sb0 = 0.f, sb1 = 0.f;
-  float sxr = 0.f, sxn = 0.f, syr = 0.f, syn = 0.f;
-  for (int p = p0 + 1 + gl; p < p1; p += G) {
-    const float4 rt = a.ratp[p];
-    const float2 w = a.wire[p];
-    const float4 ats = make_float4(at_d.x + w.x, at_d.y + w.x, at_d.z + w.x, at_d.w + w.x);
-    const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
-                                   sink_slew(sl_d.w, w.y));
-    const int q = a.io_perm ? a.io_perm[p] : p;
-    if (a.at_out) a.at_out[q] = ats;
-    if (a.slew_out) a.slew_out[q] = sls;
-    if (a.rat_out) a.rat_out[q] = rt;
-    if (a.slack_out) a.slack_out[q] = make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w);
-    rq0 = fmaxf(rq0, rt.x - w.x);
-    rq1 = fmaxf(rq1, rt.y - w.x);
-    rq2 = fminf(rq2, rt.z - w.x);
-    rq3 = fminf(rq3, rt.w - w.x);
-    if (a.grad) {
-      const float4 aj = a.adjp[p];
-      const float q0 = sls.z > 0.f ? aj.z / sls.z : 0.f;   // s_bar(s,t) / slew(s,late,t)
-      const float q1 = sls.w > 0.f ? aj.w / sls.w : 0.f;
-      ab0 += aj.x;
-      ab1 += aj.y;
-      sb0 += q0 * sl_d.z;
-      sb1 += q1 * sl_d.w;
-      const float dbar = aj.x + aj.y;                      // adjoint of the wire delay
-      const float ibar = (q0 + q1) * w.y;                  // adjoint of the impulse
-      const float xs = a.x[q], ys = a.y[q];
-      const float len = fabsf(xs - xd) + fabsf(ys - yd);
-      // d Delay / d len = d Impulse / d len = 1e-3 r (Cpin + c len) for a star sink.
-      const float rest = (dbar + ibar) * (k1e3r * fmaf(a.c, len, a.pin_cap[p]));
-      const float gx = sgnf(xs - xd), gy = sgnf(ys - yd);
-      sxr += gx * rest;
-      sxn += gx;
-      syr += gy * rest;
-      syn += gy;
+  // 2a. Cell-step lookups: lane (k, jl) of the group's first 16 lanes takes arc jl.
+  const bool cell_net = gs.active && n >= a.N0;
+  const int lane16 = gl & (kCellLanes - 1);
+  const int k = lane16 >> 2, jl = lane16 & 3, m = k >> 1, t = k & 1;
+  const bool cell_lane = cell_net && gl < kCellLanes;
+  const int kc = n - a.N0 - sl.c0;             // position of the cell in its level
+  float load = 0.f;
+  if (cell_lane) load = a.load[n];
+  ArcBwd arc0;
+  arc0.valid = false;
+  arc0.xg = -kInf;
+  arc0.s = -kInf;
+  if (cell_lane) arc0 = arc_backward(a, sl, kc, jl, m, t, load);
+  // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4).
+  float xmax = quad_reduce<kMax>(arc0.valid ? arc0.xg : -kInf);
+  float z = quad_reduce<kSum>(arc0.valid ? expf((arc0.xg - xmax) * a.inv_gamma) : 0.f);
+  float smax = arc0.valid ? arc0.s : -kInf;
+  int jstar = arc0.valid ? jl : STA_MAX_FANIN;
+  quad_argmax(smax, jstar);
+  for (int j0 = kArcLanes; j0 < sl.F; j0 += kArcLanes) {    // cells wider than 4 inputs
+    ArcBwd v;
+    v.valid = false;
+    if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl, m, t, load);
+    const float cm = quad_reduce<kMax>(v.valid ? v.xg : -kInf);
+    const float cz = quad_reduce<kSum>(v.valid ? expf((v.xg - cm) * a.inv_gamma) : 0.f);
+    lse_merge(xmax, z, cm, cz, a.inv_gamma);
+    float s2 = v.valid ? v.s : -kInf;
+    int j2 = v.valid ? j0 + jl : STA_MAX_FANIN;
+    quad_argmax(s2, j2);
+    if (s2 > smax) {
+      smax = s2;
+      jstar = j2;
     }
   }
-  rq0 = grp_max(rq0, G);
-  rq1 = grp_max(rq1, G);
-  rq2 = grp_min(rq2, G);
-  rq3 = grp_min(rq3, G);
-  if (a.grad) {
-    ab0 = grp_sum(ab0, G);
-    ab1 = grp_sum(ab1, G);
-    sb0 = grp_sum(sb0, G);
-    sb1 = grp_sum(sb1, G);
-    sxr = grp_sum(sxr, G);
-    sxn = grp_sum(sxn, G);
-    syr = grp_sum(syr, G);
-    syn = grp_sum(syn, G);
+
+  // 1. Net step.  A lane holds at most one sink in a wave group and two in a workgroup;
+  //    sinks beyond that (nets over 512 sinks) are recomputed in phase 3.
+  float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  SinkKeep keep0{0.f, 0.f, 0.f, 0}, keep1{0.f, 0.f, 0.f, 0};
+  const int s0 = p0 + 1 + gl;
+  const int gstride = block ? kBlock : G;
+  const bool has0 = s0 < p1;
+  const bool has1 = block && s0 + gstride < p1;
+  if (has0) keep0 = sink_step(a, s0, at_d, sl_d, xd, yd, acc, true);
+  if (has1) keep1 = sink_step(a, s0 + gstride, at_d, sl_d, xd, yd, acc, true);
+  if (block) {
+    for (int p = s0 + 2 * gstride; p < p1; p += gstride) sink_step(a, p, at_d, sl_d, xd, yd, acc, true);
+  }
+  reduce_acc<G>(acc, block, sh);
+
+  // 2b. Cell step: required times of the inputs and the adjoint split.
+  const float rat_o = k == 0 ? acc[R_E0] : (k == 1 ? acc[R_E1] : (k == 2 ? acc[R_L0] : acc[R_L1]));
+  const float abar = t ? acc[A_F] : acc[A_R];
+  const float sbar = t ? acc[S_F] : acc[S_R];
+  const float inv_z = 1.0f / z;
+  float lb = 0.f;
+  for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
+    ArcBwd v = arc0;
+    if (j0 > 0) {
+      v.valid = false;
+      if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl, m, t, load);
+    }
+    if (cell_lane && v.valid) {
+      // RAT(input, k') = RAT(output, k) - arc delay.
+      reinterpret_cast<float*>(a.ratp + v.pin)[2 * m + v.tp] = rat_o - v.d;
+      if (a.grad && m == 1) {
+        const float dbar = expf((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
+        const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
+        float* adj = reinterpret_cast<float*>(a.adjp + v.pin);
+        adj[v.tp] = dbar;
+        adj[2 + v.tp] = fmaf(dbar, v.ddx, s_j * v.dsx);
+        lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
+      }
+    }
   }
 
-  // 2. Cell step.
+  // 3. Load adjoint of the root: arcs (quad sum) of late rise + late fall, lanes 8 and 12.
   float lbar = 0.f;
-  if (gs.active && n >= a.N0 && gl < 4) {
-    const int k = gl, m = k >> 1, t = k & 1;
-    const float rat_o = k == 0 ? rq0 : (k == 1 ? rq1 : (k == 2 ? rq2 : rq3));
-    const int cell = n - a.N0;
-    const float load = a.load[n];
-    const int arc0 = a.type_arc0[a.cell_type[cell]];
-    const int j0 = a.cin_off[cell], nin = a.cin_off[cell + 1] - j0;
-    float xg[STA_MAX_FANIN], ddx[STA_MAX_FANIN], ddy[STA_MAX_FANIN], dsx[STA_MAX_FANIN], dsy[STA_MAX_FANIN];
-    int pin[STA_MAX_FANIN], tpv[STA_MAX_FANIN];
-    float xmax = -kInf, smax = -kInf;
-    int jstar = 0;
-#pragma unroll
-    for (int jj = 0; jj < STA_MAX_FANIN; ++jj) {
-      if (jj < nin) {
-        const int j = j0 + jj;
-        const int arc = arc0 + jj;
-        const int tp = a.unate[arc] > 0 ? t : 1 - t;
-        const int kp = 2 * m + tp;
-        const float* src = reinterpret_cast<const float*>(a.rec + 3 * (size_t)a.cin_src[j]);
-        const int pj = a.cin_pin[j];
-        const float2 w = a.wire[pj];
-        const float sl_in = sink_slew(src[4 + kp], w.y);
-        const LutVal v = lut_eval<true>(a.grid, a.coef, a.keys, arc, t, sl_in, load);
-        // RAT(input, k') = RAT(output, k) - arc delay.
-        reinterpret_cast<float*>(a.ratp + pj)[kp] = rat_o - v.d;
-        pin[jj] = pj;
-        tpv[jj] = tp;
-        xg[jj] = (src[8 + tp] + w.x) + v.d;
-        ddx[jj] = v.ddx;
-        ddy[jj] = v.ddy;
-        dsx[jj] = v.dsx;
-        dsy[jj] = v.dsy;
-        xmax = fmaxf(xmax, xg[jj]);
-        if (v.s > smax) {      // first maximum: ties go to the lowest arc
-          smax = v.s;
-          jstar = jj;
-        }
-      }
-    }
-    if (a.grad && m == 1) {
-      const float abar = t ? ab1 : ab0;
-      const float sbar = t ? sb1 : sb0;
-      float ez[STA_MAX_FANIN];
-      float z = 0.f;
-#pragma unroll
-      for (int jj = 0; jj < STA_MAX_FANIN; ++jj) {
-        if (jj < nin) {
-          ez[jj] = expf((xg[jj] - xmax) * a.inv_gamma);
-          z += ez[jj];
-        }
-      }
-      const float inv_z = 1.0f / z;
-#pragma unroll
-      for (int jj = 0; jj < STA_MAX_FANIN; ++jj) {
-        if (jj < nin) {
-          const float dbar = ez[jj] * inv_z * abar;       // softmax weight times the adjoint
-          const float s_j = jj == jstar ? sbar : 0.f;
-          float* adj = reinterpret_cast<float*>(a.adjp + pin[jj]);
-          adj[tpv[jj]] = dbar;
-          adj[2 + tpv[jj]] = fmaf(dbar, ddx[jj], s_j * dsx[jj]);
-          lbar = fmaf(dbar, ddy[jj], fmaf(s_j, dsy[jj], lbar));
-        }
-      }
-    }
-  }
-
-  // 3. Elmore adjoint and outputs.
   if (a.grad) {
-    const int base = lane & ~(G - 1);
-    lbar = __shfl(lbar, base + 2) + __shfl(lbar, base + 3);
+    lb = quad_reduce<kSum>(lb);
+    if (!block) {
+      const int base = (threadIdx.x & 63) & ~(G - 1);
+      lbar = __shfl(lb, base + 8) + __shfl(lb, base + 12);
+    } else {
+      if (threadIdx.x == 8) sh[0] = lb;
+      if (threadIdx.x == 12) sh[1] = lb;
+      __syncthreads();
+      lbar = sh[0] + sh[1];
+      __syncthreads();
+    }
   }
   if (!gs.active) return;
   if (a.grad && (a.dx || a.dy)) {
     const float cl = a.c * lbar;
-    for (int p = p0 + 1 + gl; p < p1; p += G) {
-      const float4 aj = a.adjp[p];
-      const float2 w = a.wire[p];
-      const float slz = sink_slew(sl_d.z, w.y), slw = sink_slew(sl_d.w, w.y);
-      const float q0 = slz > 0.f ? aj.z / slz : 0.f;
-      const float q1 = slw > 0.f ? aj.w / slw : 0.f;
-      const int q = a.io_perm ? a.io_perm[p] : p;
-      const float xs = a.x[q], ys = a.y[q];
-      const float len = fabsf(xs - xd) + fabsf(ys - yd);
-      const float rest = ((aj.x + aj.y) + (q0 + q1) * w.y) * (k1e3r * fmaf(a.c, len, a.pin_cap[p]));
-      const float lb = cl + rest;                          // adjoint of the wire length
-      if (a.dx) a.dx[q] = sgnf(xs - xd) * lb;
-      if (a.dy) a.dy[q] = sgnf(ys - yd) * lb;
+    if (has0) {
+      if (a.dx) a.dx[keep0.q] = keep0.gx * (cl + keep0.rest);
+      if (a.dy) a.dy[keep0.q] = keep0.gy * (cl + keep0.rest);
+    }
+    if (has1) {
+      if (a.dx) a.dx[keep1.q] = keep1.gx * (cl + keep1.rest);
+      if (a.dy) a.dy[keep1.q] = keep1.gy * (cl + keep1.rest);
+    }
+    if (block) {
+      for (int p = s0 + 2 * gstride; p < p1; p += gstride) {
+        float scratch[N_ACC] = {};
+        const SinkKeep kk = sink_step(a, p, at_d, sl_d, xd, yd, scratch, false);
+        if (a.dx) a.dx[kk.q] = kk.gx * (cl + kk.rest);
+        if (a.dy) a.dy[kk.q] = kk.gy * (cl + kk.rest);
+      }
     }
   }
   if (gl == 0) {
     const int q = a.io_perm ? a.io_perm[p0] : p0;
     if (a.at_out) a.at_out[q] = at_d;
     if (a.slew_out) a.slew_out[q] = sl_d;
-    if (a.rat_out) a.rat_out[q] = make_float4(rq0, rq1, rq2, rq3);
-    if (a.slack_out) a.slack_out[q] = make_float4(at_d.x - rq0, at_d.y - rq1, rq2 - at_d.z, rq3 - at_d.w);
+    if (a.rat_out) a.rat_out[q] = make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]);
+    if (a.slack_out)
+      a.slack_out[q] = make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w);
     if (a.grad) {
       const float cl = a.c * lbar;
-      if (a.dx) a.dx[q] = -(sxr + cl * sxn);
-      if (a.dy) a.dy[q] = -(syr + cl * syn);
+      if (a.dx) a.dx[q] = -(acc[X_RS] + cl * acc[X_N]);
+      if (a.dy) a.dy[q] = -(acc[Y_RS] + cl * acc[Y_N]);
     }
   }
 }
 
-inline unsigned blocks_for_waves(int waves) { return (unsigned)((waves * 64 + kBlock - 1) / kBlock); }
+// One level of backward propagation: heavy nets first (one workgroup each), then waves of
+// 16-, 32- and 64-lane groups.
+__global__ __launch_bounds__(kBlock) void k_bwd_level(BwdArgs a, GroupRange rg, Slots sl) {
+  __shared__ float sh[kWavesPerBlock * N_ACC];
+  GroupSlot gs;
+  if (!group_slot(rg, gs)) return;
+  if (gs.block || gs.G == 64) {
+    bwd_net<64>(a, sl, gs, sh);
+  } else if (gs.G == 32) {
+    bwd_net<32>(a, sl, gs, sh);
+  } else {
+    bwd_net<16>(a, sl, gs, sh);
+  }
+}
+
+Slots level_slots(const sta_graph* g, int l) {
+  Slots sl{0, 1, 0, 0};
+  if (l >= 1) {
+    sl.base = g->ell_base[l];
+    sl.F = g->ell_slots[l];
+    sl.c0 = g->level_off[l] - g->N0;
+    sl.nc = g->level_off[l + 1] - g->level_off[l];
+  }
+  return sl;
+}
+
+sta_status check_ready(sta_graph* g) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (!g->uploaded) {
+    sta_status s = sta_graph_upload(g);
+    if (s != STA_OK) return s;
+  }
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != g->dev.device) return fail(STA_E_STATE, "graph lives on another device than the current one");
+  return STA_OK;
+}
 
 // Event pair around one launch while profiling is on (sta_profile_enable).
 struct LaunchTimer {
@@ -672,20 +901,6 @@ struct LaunchTimer {
   }
 };
 
-sta_status check_ready(sta_graph* g) {
-  if (!g) return fail(STA_E_INVALID, "graph is NULL");
-  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
-  if (!g->uploaded) {
-    sta_status s = sta_graph_upload(g);
-    if (s != STA_OK) return s;
-  }
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  if (dev != g->dev.device) return fail(STA_E_STATE, "graph lives on another device than the current one");
-  return STA_OK;
-}
-
 }  // namespace
 }  // namespace sta
 
@@ -711,16 +926,16 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
             g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew};
   {
     LaunchTimer t(g, s, STA_K_RC);
-    k_rc<<<blocks_for_waves(g->all_range.wave_off[kNumClasses]), kBlock, 0, s>>>(ra);
+    k_rc<<<range_grid(g->all_range), kBlock, 0, s>>>(ra);
   }
 
-  FwdArgs fa{d.cell_type, d.type_arc0, d.unate, d.cin_off, d.cin_src, d.cin_pin, wire, load, rec,
-             d.lut_grid, d.lut_coef, lut_keys(g), g->N0, gamma_ps, smooth ? 1.0f / gamma_ps : 0.f, smooth ? 1 : 0};
+  FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), g->N0, gamma_ps,
+             smooth ? 1.0f / gamma_ps : 0.f, smooth ? 1 : 0};
   for (int l = 1; l < g->L; ++l) {
-    const int c0 = g->level_off[l] - g->N0, c1 = g->level_off[l + 1] - g->N0;
-    const unsigned blocks = (unsigned)((4 * (c1 - c0) + kBlock - 1) / kBlock);
+    const Slots sl = level_slots(g, l);
+    const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
-    k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, c0, c1);
+    k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, sl);
   }
 
   EpArgs ea{d.ep_pin, d.ep_net, rec, wire, reinterpret_cast<double*>(sb + g->state.part),
@@ -740,7 +955,7 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
     ExpandArgs xa{d.net_off, io, d.sched_all, g->all_range, rec, wire, reinterpret_cast<float4*>(out->at),
                   reinterpret_cast<float4*>(out->slew), reinterpret_cast<float2*>(out->atg)};
     LaunchTimer t(g, s, STA_K_EXPAND);
-    k_expand<<<blocks_for_waves(g->all_range.wave_off[kNumClasses]), kBlock, 0, s>>>(xa);
+    k_expand<<<range_grid(g->all_range), kBlock, 0, s>>>(xa);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -767,25 +982,23 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
   EpArgs ea{d.ep_pin, d.ep_net, rec, wire, reinterpret_cast<double*>(sb + g->state.part),
-            reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp, grad ? adjp : nullptr, out->grad_scale_dev, g->E,
-            g->n_ep_blocks, g->cons.t_clk - g->cons.setup, g->cons.hold, grad ? gamma_ps : 1.0f,
+            reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp, grad ? adjp : nullptr, out->grad_scale_dev,
+            g->E, g->n_ep_blocks, g->cons.t_clk - g->cons.setup, g->cons.hold, grad ? gamma_ps : 1.0f,
             grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1, (flags & STA_GRAD_WNS) ? 1 : 0};
   if (g->E > 0) {
     LaunchTimer t(g, s, STA_K_EP_SEED);
     k_ep_seed<<<g->n_ep_blocks, kBlock, 0, s>>>(ea);
   }
 
-  BwdArgs ba{d.net_off, d.pin_cap, d.cell_type, d.type_arc0, d.unate, d.cin_off, d.cin_src, d.cin_pin, d.sched,
-             d.lvl, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g), rec, wire, load, ratp, adjp,
-             reinterpret_cast<float4*>(out->at), reinterpret_cast<float4*>(out->slew),
+  BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
+             rec, wire, load, ratp, adjp, reinterpret_cast<float4*>(out->at), reinterpret_cast<float4*>(out->slew),
              reinterpret_cast<float4*>(out->rat), reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
   for (int l = g->L - 1; l >= 0; --l) {
-    const int waves = g->lvl_ranges[l].wave_off[kNumClasses];
-    if (waves > 0) {
-      LaunchTimer t(g, s, STA_K_BWD_LEVEL);
-      k_bwd_level<<<blocks_for_waves(waves), kBlock, 0, s>>>(ba, l);
-    }
+    const unsigned blocks = range_grid(g->lvl_ranges[l]);
+    if (blocks == 0) continue;
+    LaunchTimer t(g, s, STA_K_BWD_LEVEL);
+    k_bwd_level<<<blocks, kBlock, 0, s>>>(ba, g->lvl_ranges[l], level_slots(g, l));
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward launch");

@@ -327,9 +327,10 @@ def test_levelize_matches_longest_path_and_canonical_rules(seed):
     lv = O.levelize(d)
     assert np.array_equal(lv.level, _longest_path_levels(d, lv))
     assert np.array_equal(lv.level, d.gen_net_level)
-    # nets by (level, original id); offsets delimit levels; pins net-major, driver first,
-    # sinks in the input CSR order.
-    key = [(int(lv.level[n]), int(n)) for n in lv.net_perm]
+    # nets by (level, pins of the net, original id); offsets delimit levels; pins net-major,
+    # driver first, sinks in the input CSR order.
+    size = np.diff(d.net_offsets)
+    key = [(int(lv.level[n]), int(size[n]), int(n)) for n in lv.net_perm]
     assert key == sorted(key)
     assert lv.level_offsets[0] == 0 and lv.level_offsets[-1] == d.n_nets
     for l in range(lv.n_levels):
