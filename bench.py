@@ -26,8 +26,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 
-def algorithmic_bytes(d, lev) -> dict:
+def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict:
     """Bytes each kernel family must move per step (float32 values, int32 indices).
+
+    `level` is the net level of every net of d; the per-level lists are indexed by level
+    (fwd_level: levels 1..L-1; bwd_level: levels L-1..0, the launch order), so the lists of
+    designs swept together in one batch add up element by element.
 
     Counts only what the method reads and writes once; re-reads served by caches are not
     counted.  Per unit:
@@ -44,8 +48,8 @@ def algorithmic_bytes(d, lev) -> dict:
     """
     N, P = d.n_nets, d.n_pins
     sinks = np.diff(d.net_offsets).astype(np.int64) - 1
-    level = lev["level"].astype(np.int64)
-    L = int(level.max()) + 1
+    level = level.astype(np.int64)
+    L = int(level.max()) + 1 if n_levels is None else n_levels
     drv = d.net_pins[d.net_offsets[:-1]]
     cell_of_out = np.full(P, -1, np.int64)
     cell_of_out[d.cell_out_pin] = np.arange(d.n_cells)
@@ -60,30 +64,170 @@ def algorithmic_bytes(d, lev) -> dict:
     E = int(np.count_nonzero((d.pin_kind == 3) | (d.pin_kind == 4)))
     n0 = int(nets_l[0])
     out = {}
-    out["rc"] = [float(N * 24 + n0 * 40 + sinks.sum() * 20)]
-    out["fwd_level"] = [float(cells_l[l] * 56 + ins_l[l] * 57) for l in range(1, L)]
-    out["ep_partial"] = [float(E * 28)]
-    out["ep_seed"] = [float(E * 60)]
-    out["bwd_level"] = [float(nets_l[l] * 48 + cells_l[l] * 16 + ins_l[l] * 73 + sinks_l[l] * 52 + pins_l[l] * 72)
-                        for l in range(L - 1, -1, -1)]
+    out["rc"] = np.array([float(N * 24 + n0 * 40 + sinks.sum() * 20)])
+    out["fwd_level"] = np.array([float(cells_l[l] * 56 + ins_l[l] * 57) for l in range(1, L)])
+    out["ep_partial"] = np.array([float(E * 28)])
+    out["ep_seed"] = np.array([float(E * 60)])
+    out["bwd_level"] = np.array([float(nets_l[l] * 48 + cells_l[l] * 16 + ins_l[l] * 73 + sinks_l[l] * 52
+                                       + pins_l[l] * 72) for l in range(L - 1, -1, -1)])
     return out
 
 
-def main(argv=None) -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2"])
-    ap.add_argument("--gamma", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
-    args = ap.parse_args(argv)
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the STA sweep of one design runs on a single device "
-              "(independent designs would be routed one per GPU); run with --gpus 1.", file=sys.stderr)
-        return 2
+def kernel_table(prof: dict, alg: dict, steps: int) -> tuple[dict, dict]:
+    """Per-kernel launch statistics and the roofline entry of the dominant kernel."""
+    kernels = {}
+    for k, (n, tot) in prof.items():
+        if n == 0:
+            continue
+        per_step = float(np.sum(alg.get(k, [0.0])))
+        kernels[k] = dict(launches_per_step=n // steps, avg_us=1e3 * tot / n, ms_per_step=tot / steps,
+                          alg_bytes_per_step=per_step,
+                          gbs=(per_step * steps / (tot * 1e-3) / 1e9) if per_step else None)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    achieved = kd["gbs"]
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    alg_bytes_per_launch=kd["alg_bytes_per_step"] / kd["launches_per_step"],
+                    avg_launch_us=round(kd["avg_us"], 3))
+    return kernels, roofline
 
+
+def step_buffers(g, P, dev, n_designs=1):
+    import torch
+    state = g.new_state(dev)
+    ws = g.new_workspace(dev)
+    scal = torch.empty((n_designs, 4) if n_designs > 1 else 4, dtype=torch.float64, device=dev)
+    outs = {k: torch.empty((P, 4), dtype=torch.float32, device=dev) for k in ("at", "slew", "rat", "slack")}
+    outs["dx"] = torch.empty(P, dtype=torch.float32, device=dev)
+    outs["dy"] = torch.empty(P, dtype=torch.float32, device=dev)
+    return state, ws, scal, outs
+
+
+def timed(step, steps: int, warmup: int) -> tuple[float, float]:
+    """(ms per step from events on the current stream, wall seconds)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - w0
+
+
+def run_batch(args) -> dict:
+    """Batched sweep: 64 jittered placement snapshots of the 800k-pin design plus 16
+    designs of 10k-400k pins (log-uniform), one union graph, captured into a hipGraph,
+    against the same 80 sweeps issued one plain call pair at a time."""
+    import torch
+    from gen.netlist import CFG1, batch_designs, jitter, make_design
+    from paper_2603_28381_amd import Graph
+
+    t0 = time.time()
+    d1 = make_design(CFG1)
+    others = batch_designs(16, 10_000, 400_000, cfg_id=3)
+    snaps = [jitter(d1, 5.0, stream=s) for s in range(1, 65)]
+    members = [(d1, sx, sy) for sx, sy in snaps] + [(d, d.x, d.y) for d in others]
+    g1 = Graph.from_design(d1)
+    gos = [Graph.from_design(d) for d in others]
+    mgraphs = [g1] * 64 + gos
+    b = Graph.batch(mgraphs)
+    n_levels = b.levelize()
+    b.upload()
+    dsg, pin = b.batch_pin_map()
+    info = b.info()
+    P = info["n_pins"]
+    dev = torch.device("cuda")
+    base = np.cumsum([0] + [m[0].n_pins for m in members])
+    src = base[dsg] + pin
+    x = torch.from_numpy(np.concatenate([m[1] for m in members])[src]).to(dev)
+    y = torch.from_numpy(np.concatenate([m[2] for m in members])[src]).to(dev)
+    t_setup = time.time() - t0
+    best = b.tune(x, y, gamma=args.gamma, reps=2)
+    state, ws, scal, outs = step_buffers(b, P, dev, info["n_designs"])
+
+    def step():
+        f = b.forward(x, y, gamma=args.gamma, canonical=True, state=state, scalars=scal, capture=True)
+        b.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs, capture=True)
+
+    ms, wall = timed(step, args.steps, args.warmup)
+    value = P / (ms * 1e-3)
+
+    # The same 80 sweeps as plain calls, one design at a time, each in canonical order.
+    plain = []
+    for g, (d, mx, my) in zip(mgraphs, members):
+        if g is not g1 or not plain:
+            g.levelize()
+            g.upload()
+        perm = torch.from_numpy(g.levelization()["pin_perm"].astype(np.int64))
+        bufs = step_buffers(g, d.n_pins, dev) if (g is not g1 or not plain) else plain[0][4]
+        plain.append((g, torch.from_numpy(mx)[perm].to(dev), torch.from_numpy(my)[perm].to(dev), d.n_pins, bufs))
+
+    def seq_step():
+        for g, xx, yy, _, (st, w, sc, o) in plain:
+            f = g.forward(xx, yy, gamma=args.gamma, canonical=True, state=st, scalars=sc)
+            g.backward(xx, yy, f, rat=True, grad=True, workspace=w, out=o)
+
+    seq_steps = max(1, args.steps // 4)
+    ms_seq, _ = timed(seq_step, seq_steps, 1)
+    seq_value = P / (ms_seq * 1e-3)
+
+    roofline = kernels = None
+    if not args.no_profile:
+        b.profile(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        prof = b.profile_read()
+        b.profile(False)
+        alg = {}
+        lv_cache = {}
+        for g, (d, _, _) in zip(mgraphs, members):
+            if id(g) not in lv_cache:
+                lv_cache[id(g)] = algorithmic_bytes(d, g.levelization()["level"], n_levels)
+            for k, v in lv_cache[id(g)].items():
+                alg[k] = alg.get(k, 0.0) + v
+        kernels, roofline = kernel_table(prof, alg, args.steps)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import sta_oracle as O
+        c0 = time.perf_counter()
+        done = 0
+        for d, mx, my in members[:1] + members[64:]:
+            O.run(d, x=mx, y=my, gamma=args.gamma, grad="tns")
+            done += d.n_pins
+        ct = time.perf_counter() - c0
+        cpu = dict(value=round(done / ct, 1), unit="pins/s", cores=int(torch.get_num_threads()), kind="oracle",
+                   sample=f"FP64 forward+backward+gradient of snapshot 1 and the 16 designs "
+                          f"({done} of {P} pins, levelization included), {ct:.1f} s")
+    return {
+        "metric": "STA fwd+bwd pins/sec, batched sweep vs plain calls",
+        "value": round(value, 1),
+        "unit": "pins/s",
+        "ms_per_step": round(ms, 4),
+        "dtype": "f32",
+        "config": {"workload": f"cfg3: 64 snapshots (sigma 5 um) of the {d1.n_pins}-pin design + 16 designs "
+                               f"of 10k-400k pins; {P} pins, {n_levels} net levels, fwd+bwd with "
+                               f"d TNS_g/dx,dy, gamma {args.gamma} ps, hipGraph-captured",
+                   "pins": P, "levels": n_levels, "designs": info["n_designs"], "schedule": best,
+                   "io": "canonical order, HBM resident"},
+        "plain_sequential": {"value": round(seq_value, 1), "unit": "pins/s", "ms_per_step": round(ms_seq, 4),
+                             "calls": 2 * len(plain), "speedup_batched": round(value / seq_value, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "wall_s_timed": round(wall, 3),
+        "setup_s": round(t_setup, 2),
+    }
+
+
+def run_single(args) -> dict:
     import torch
     from gen.netlist import CFG0, CFG1, CFG2, make_design
     from paper_2603_28381_amd import Graph
@@ -101,33 +245,17 @@ def main(argv=None) -> int:
     perm = torch.from_numpy(lev["pin_perm"].astype(np.int64))
     x = torch.from_numpy(d.x)[perm].contiguous().to(dev)        # canonical order, resident in HBM
     y = torch.from_numpy(d.y)[perm].contiguous().to(dev)
-    state = g.new_state(dev)
-    ws = g.new_workspace(dev)
-    scal = torch.empty(4, dtype=torch.float64, device=dev)
-    outs = {k: torch.empty((P, 4), dtype=torch.float32, device=dev) for k in ("at", "slew", "rat", "slack")}
-    outs["dx"] = torch.empty(P, dtype=torch.float32, device=dev)
-    outs["dy"] = torch.empty(P, dtype=torch.float32, device=dev)
+    state, ws, scal, outs = step_buffers(g, P, dev)
 
     def step():
-        f = g.forward(x, y, gamma=args.gamma, smooth=True, canonical=True, state=state, scalars=scal)
-        g.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs)
+        f = g.forward(x, y, gamma=args.gamma, smooth=True, canonical=True, state=state, scalars=scal,
+                      capture=args.capture)
+        g.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs, capture=args.capture)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms, wall = timed(step, args.steps, args.warmup)
     value = P / (ms * 1e-3)
 
-    roofline = None
-    kernels = None
+    roofline = kernels = None
     if not args.no_profile:
         # Same steps again with an event pair around every launch, on the library's stream.
         g.profile(True)
@@ -136,23 +264,7 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         prof = g.profile_read()
         g.profile(False)
-        alg = algorithmic_bytes(d, lev)
-        kernels = {}
-        for k, (n, tot) in prof.items():
-            if n == 0:
-                continue
-            per_step = sum(alg.get(k, [0.0]))
-            kernels[k] = dict(launches_per_step=n // args.steps, avg_us=1e3 * tot / n,
-                              ms_per_step=tot / args.steps,
-                              alg_bytes_per_step=per_step,
-                              gbs=(per_step * args.steps / (tot * 1e-3) / 1e9) if per_step else None)
-        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-        kd = kernels[dom]
-        achieved = kd["gbs"]
-        roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
-                        alg_bytes_per_launch=kd["alg_bytes_per_step"] / kd["launches_per_step"],
-                        avg_launch_us=round(kd["avg_us"], 3))
+        kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -165,22 +277,15 @@ def main(argv=None) -> int:
         cpu = dict(value=round(P / ct, 1), unit="pins/s", cores=int(torch.get_num_threads()), kind="oracle",
                    sample=f"one full FP64 forward+backward+gradient of the same {P}-pin design "
                           f"(levelization excluded), {ct:.1f} s")
-
-    line = {
+    return {
         "metric": "STA fwd+bwd pins/sec @2.5M pins",
         "value": round(value, 1),
         "unit": "pins/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
         "config": {"workload": f"{args.workload}: {P} pins, {d.n_nets} nets, {d.n_cells} cells, "
-                               f"{n_levels} net levels, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps",
+                               f"{n_levels} net levels, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps"
+                               + (", hipGraph-captured" if args.capture else ""),
                    "pins": P, "levels": n_levels, "io": "canonical order, HBM resident"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -188,6 +293,29 @@ def main(argv=None) -> int:
         "wall_s_timed": round(wall, 3),
         "setup_s": round(t_setup, 2),
     }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--gamma", type=float, default=10.0)
+    ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the STA sweep of one design runs on a single device "
+              "(independent designs would be routed one per GPU); run with --gpus 1.", file=sys.stderr)
+        return 2
+    res = run_batch(args) if args.workload == "cfg3" else run_single(args)
+    line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),
+            "data": "synthetic"}
+    line.update(res)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -99,6 +99,7 @@ typedef struct sta_graph_info {
   int64_t fwd_state_bytes;         /* size of sta_fwd_out.state */
   int64_t bwd_workspace_bytes;     /* size of sta_bwd_out.workspace */
   int64_t device_bytes;            /* graph data held on the device after upload */
+  int32_t n_designs;               /* designs in the graph: 1, or the size of a batch */
 } sta_graph_info;
 
 /* sta_forward / sta_backward flags */
@@ -107,6 +108,8 @@ typedef struct sta_graph_info {
 #define STA_RAT (1u << 2)           /* backward: required times and slack per pin */
 #define STA_GRAD (1u << 3)          /* backward: gradient of the smoothed objective */
 #define STA_GRAD_WNS (1u << 4)      /* with STA_GRAD: differentiate WNS_g instead of TNS_g */
+#define STA_GRAPH (1u << 5)         /* capture the call's launches into a hipGraph on first use and
+                                       replay it while every argument stays the same */
 
 /* Forward outputs.  state is required; every other pointer may be NULL. */
 typedef struct sta_fwd_out {
@@ -115,7 +118,7 @@ typedef struct sta_fwd_out {
   float* at;        /* device [n_pins][4] arrival times */
   float* slew;      /* device [n_pins][4] slews */
   float* atg;       /* device [n_pins][2] smoothed late arrival (rise, fall) */
-  double* scalars;  /* device [4]: WNS, TNS, WNS_g, TNS_g (g: smoothed with gamma) */
+  double* scalars;  /* device [n_designs][4]: WNS, TNS, WNS_g, TNS_g (g: smoothed with gamma) */
 } sta_fwd_out;
 
 /* Backward outputs.  workspace is required; every other pointer may be NULL. */
@@ -159,6 +162,21 @@ sta_status sta_get_levelization(const sta_graph* g, int32_t* level, int32_t* lev
 sta_status sta_graph_upload(sta_graph* g);
 
 sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info);
+
+/* Batch of designs swept together: a new graph whose netlist is the disjoint union of the
+ * given graphs (design d's pins, nets and cells follow design d-1's; identical libraries
+ * are stored once).  Levelizing it aligns every design's level l in one level l, so each
+ * level launch of sta_forward / sta_backward covers the nets of all designs; results equal
+ * per-design calls.  Placement snapshots of one netlist are passed as the same graph
+ * repeated.  Graphs must share constraints and table axes (else STA_E_INVALID); the inputs
+ * stay owned by the caller and may be destroyed afterwards.  Scalars of the batch are
+ * per design.  Use sta_batch_pin_map to route per-design coordinates and results. */
+sta_status sta_batch_create(sta_graph* const* graphs, int32_t n_graphs, sta_graph** out);
+
+/* For each canonical pin of a levelized batch: its design and its pin id in that design's
+ * own numbering (caller-allocated arrays of n_pins; either may be NULL).
+ * Errors: STA_E_STATE if not levelized. */
+sta_status sta_batch_pin_map(const sta_graph* g, int32_t* design, int32_t* pin);
 void sta_graph_destroy(sta_graph* g);
 
 /* ---------------------------------------------------------------------------------------
@@ -187,6 +205,32 @@ sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out
  * ------------------------------------------------------------------------------------- */
 sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Lane-group schedule.  Nets are served by lane groups sized from their sink count: the
+ * level kernels use groups of (1 << sweep_group_log2) lanes and doublings up to a wave
+ * (16 lanes at least, since a cell step spreads 4 conditions x 4 arcs over 16 lanes), the
+ * one-pass kernels (RC, output expansion) groups from (1 << flat_group_log2) lanes, and
+ * nets with more than heavy_sinks sinks take a whole 256-thread workgroup.  Defaults
+ * {4, 2, 64}.  Setting a schedule rebuilds the launch plan (no result changes beyond
+ * float summation order).  Errors: STA_E_INVALID for out-of-range fields, STA_E_STATE if
+ * not levelized.
+ * ------------------------------------------------------------------------------------- */
+typedef struct sta_schedule {
+  int32_t sweep_group_log2;   /* 4..6 */
+  int32_t flat_group_log2;    /* 2..6 */
+  int32_t heavy_sinks;        /* 1..64 */
+} sta_schedule;
+
+sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);
+sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
+
+/* Autotuner: times one forward+backward (smoothed, gradient, canonical IO, every per-pin
+ * output) of g on the given coordinates for each candidate schedule, `reps` times after a
+ * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Allocates
+ * and frees its own device buffers; synchronizes the stream.  Errors: as sta_forward. */
+sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
+                    sta_schedule* best, sta_stream stream);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel timing with HIP events (a profiling aid).  While enabled, every kernel launch that

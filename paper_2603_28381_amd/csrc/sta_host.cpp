@@ -33,12 +33,17 @@ void compute_layouts(sta_graph* g) {
     off = align_up(off + bytes, 256);
     return at;
   };
-  g->n_ep_blocks = (g->E + kBlock - 1) / kBlock;
+  g->ep_blk_off.assign(g->n_designs + 1, 0);
+  for (int d = 0; d < g->n_designs; ++d) {
+    const int e = g->ep_design_off[d + 1] - g->ep_design_off[d];
+    g->ep_blk_off[d + 1] = g->ep_blk_off[d] + (e + kBlock - 1) / kBlock;
+  }
+  g->n_ep_blocks = g->ep_blk_off[g->n_designs];
   g->state.rec = take(sizeof(float4) * 3 * (size_t)g->N);
   g->state.wire = take(sizeof(float2) * (size_t)g->P);
   g->state.load = take(sizeof(float) * (size_t)g->N);
   g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
-  g->state.fin = take(sizeof(double) * 8);
+  g->state.fin = take(sizeof(double) * 8 * (size_t)g->n_designs);
   g->state.total = off;
   off = 0;
   g->work.ratp = take(sizeof(float4) * (size_t)g->P);
@@ -99,10 +104,10 @@ static GroupRange group_range(const int* cls_count, int base, int g0) {
   return r;
 }
 
-static void build_schedule(sta_graph* g) {
+void build_schedule(sta_graph* g) {
   const int N = g->N;
   std::vector<int> cls(N);
-  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, kSweepG0);
+  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.sweep_group_log2, g->sched_cfg.heavy_sinks);
   // Within a level, canonical nets are sorted by size, so classes are contiguous ranges and
   // a level's GroupRange indexes canonical net ids directly.
   g->lvl_ranges.assign(g->L, GroupRange{});
@@ -110,7 +115,7 @@ static void build_schedule(sta_graph* g) {
     int b = g->level_off[l], e = g->level_off[l + 1];
     int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
     for (int n = b; n < e; ++n) cnt[cls[n]]++;
-    g->lvl_ranges[l] = group_range(cnt, b, kSweepG0);
+    g->lvl_ranges[l] = group_range(cnt, b, g->sched_cfg.sweep_group_log2);
   }
   // Cell inputs in a padded slot layout per level: input j of the k-th cell of level l is
   // entry ell_base[l] + j * (cells of l) + k; missing inputs hold source net -1.
@@ -129,7 +134,7 @@ static void build_schedule(sta_graph* g) {
         g->ell[g->ell_base[l] + (size_t)j * nc + (c - c0)] = g->c_cin[g->c_cin_off[c] + j];
   }
   if (g->ell.empty()) g->ell.push_back(make_int4(-1, 0, 0, 1));
-  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, kFlatG0);
+  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.flat_group_log2, g->sched_cfg.heavy_sinks);
   int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
   for (int n = 0; n < N; ++n) cnt[cls[n]]++;
   int pos[kNumClasses + 1];
@@ -137,10 +142,23 @@ static void build_schedule(sta_graph* g) {
   for (int c = 0; c <= kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
   g->sched_all.assign(N, 0);
   for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
-  g->all_range = group_range(cnt, 0, kFlatG0);
+  g->all_range = group_range(cnt, 0, g->sched_cfg.flat_group_log2);
+}
+
+void drop_captured(sta_graph* g) {
+  for (sta_graph::Captured* c : {&g->cap_fwd, &g->cap_bwd}) {
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    *c = sta_graph::Captured{};
+  }
 }
 
 void free_device(sta_graph* g) {
+  drop_captured(g);
+  if (g->cap_stream) {
+    (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
+  }
   if (g->dev.device >= 0) {
     int cur = -1;
     (void)hipGetDevice(&cur);
@@ -275,11 +293,105 @@ sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib, const 
     g->load_axis.assign(lib->load_axis, lib->load_axis + STA_LUT_N);
     g->tables.assign(lib->tables, lib->tables + (size_t)n_arcs * 4 * STA_LUT_N * STA_LUT_N);
     g->cons = *cons;
+    g->design_pin_off = {0, P};
   } catch (const std::bad_alloc&) {
     delete g;
     return fail(STA_E_NOMEM, "host allocation failed");
   }
   *out = g;
+  return STA_OK;
+}
+
+sta_status sta_batch_create(sta_graph* const* graphs, int32_t n, sta_graph** out) {
+  if (!out) return fail(STA_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!graphs || n < 1) return fail(STA_E_INVALID, "need at least one graph");
+  for (int d = 0; d < n; ++d)
+    if (!graphs[d]) return fail(STA_E_INVALID, "NULL graph in batch");
+  const sta_graph* g0 = graphs[0];
+  for (int d = 1; d < n; ++d) {
+    const sta_graph* h = graphs[d];
+    if (std::memcmp(&h->cons, &g0->cons, sizeof(sta_constraints)) != 0)
+      return fail(STA_E_INVALID, "batched graphs must share constraints and wire model");
+    if (h->slew_axis != g0->slew_axis || h->load_axis != g0->load_axis)
+      return fail(STA_E_INVALID, "batched graphs must share table axes");
+  }
+  sta_graph* u = new (std::nothrow) sta_graph();
+  if (!u) return fail(STA_E_NOMEM, "host allocation failed");
+  try {
+    u->cons = g0->cons;
+    u->slew_axis = g0->slew_axis;
+    u->load_axis = g0->load_axis;
+    u->n_designs = n;
+    u->design_pin_off.assign(n + 1, 0);
+    u->arc_off.assign(1, 0);
+    // Libraries: identical libraries are stored once.
+    std::vector<int> type_base(n, 0);
+    std::vector<int> lib_owner;   // design whose library each stored library is
+    for (int d = 0; d < n; ++d) {
+      const sta_graph* h = graphs[d];
+      int found = -1;
+      for (int o : lib_owner) {
+        const sta_graph* q = graphs[o];
+        if (q->arc_off == h->arc_off && q->unate == h->unate && q->tables == h->tables) {
+          found = o;
+          break;
+        }
+      }
+      if (found >= 0) {
+        type_base[d] = type_base[found];
+        continue;
+      }
+      lib_owner.push_back(d);
+      type_base[d] = u->T;
+      const int arc_base = u->n_arcs;
+      for (int t = 0; t < h->T; ++t) u->arc_off.push_back(arc_base + h->arc_off[t + 1]);
+      u->unate.insert(u->unate.end(), h->unate.begin(), h->unate.end());
+      u->tables.insert(u->tables.end(), h->tables.begin(), h->tables.end());
+      u->T += h->T;
+      u->n_arcs += h->n_arcs;
+    }
+    // Netlists, ids offset design by design.
+    u->net_off.assign(1, 0);
+    u->cell_in_off.assign(1, 0);
+    for (int d = 0; d < n; ++d) {
+      const sta_graph* h = graphs[d];
+      const int pb = u->P, ab = u->A;
+      u->design_pin_off[d] = pb;
+      for (int i = 0; i < h->N; ++i) u->net_off.push_back(pb + h->net_off[i + 1]);
+      for (int q = 0; q < h->P; ++q) u->net_pins.push_back(pb + h->net_pins[q]);
+      u->pin_cap.insert(u->pin_cap.end(), h->pin_cap.begin(), h->pin_cap.end());
+      u->pin_kind.insert(u->pin_kind.end(), h->pin_kind.begin(), h->pin_kind.end());
+      for (int c = 0; c < h->C; ++c) {
+        u->cell_type.push_back(type_base[d] + h->cell_type[c]);
+        u->cell_in_off.push_back(ab + h->cell_in_off[c + 1]);
+        u->cell_out_pin.push_back(pb + h->cell_out_pin[c]);
+      }
+      for (int i = 0; i < h->A; ++i) u->cell_in_pins.push_back(pb + h->cell_in_pins[i]);
+      u->P += h->P;
+      u->N += h->N;
+      u->C += h->C;
+      u->A += h->A;
+    }
+    u->design_pin_off[n] = u->P;
+  } catch (const std::bad_alloc&) {
+    delete u;
+    return fail(STA_E_NOMEM, "host allocation failed");
+  }
+  *out = u;
+  return STA_OK;
+}
+
+sta_status sta_batch_pin_map(const sta_graph* g, int32_t* design, int32_t* pin) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  for (int q = 0; q < g->P; ++q) {
+    const int orig = g->pin_perm[q];
+    const int d = (int)(std::upper_bound(g->design_pin_off.begin(), g->design_pin_off.end(), orig) -
+                        g->design_pin_off.begin()) - 1;
+    if (design) design[q] = d;
+    if (pin) pin[q] = orig - g->design_pin_off[d];
+  }
   return STA_OK;
 }
 
@@ -399,16 +511,33 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
     }
     g->c_cin_off[C] = a;
     // Endpoints in canonical order.
+    // Endpoints in canonical order, grouped by design.
     g->ep_pin.clear();
     g->ep_net.clear();
+    g->ep_design.clear();
+    std::vector<std::vector<int>> ep_by_design(g->n_designs);
     for (int i = 0; i < N; ++i)
       for (int q = g->c_net_off[i] + 1; q < g->c_net_off[i + 1]; ++q) {
-        int kd = g->pin_kind[g->pin_perm[q]];
+        const int orig = g->pin_perm[q];
+        const int kd = g->pin_kind[orig];
         if (kd == STA_PIN_FF_D || kd == STA_PIN_PO) {
-          g->ep_pin.push_back(q);
-          g->ep_net.push_back(i);
+          const int dsg = (int)(std::upper_bound(g->design_pin_off.begin(), g->design_pin_off.end(), orig) -
+                                g->design_pin_off.begin()) - 1;
+          ep_by_design[dsg].push_back(q);
         }
       }
+    std::vector<int> net_of_canon_pin(P);
+    for (int i = 0; i < N; ++i)
+      for (int q = g->c_net_off[i]; q < g->c_net_off[i + 1]; ++q) net_of_canon_pin[q] = i;
+    g->ep_design_off.assign(g->n_designs + 1, 0);
+    for (int dsg = 0; dsg < g->n_designs; ++dsg) {
+      for (int q : ep_by_design[dsg]) {
+        g->ep_pin.push_back(q);
+        g->ep_net.push_back(net_of_canon_pin[q]);
+        g->ep_design.push_back(dsg);
+      }
+      g->ep_design_off[dsg + 1] = (int)g->ep_pin.size();
+    }
     g->E = (int)g->ep_pin.size();
     g->level = level;
     g->L = L;
@@ -435,6 +564,33 @@ sta_status sta_get_levelization(const sta_graph* g, int32_t* level, int32_t* lev
   return STA_OK;
 }
 
+sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch) {
+  if (!g || !sch) return fail(STA_E_INVALID, "NULL argument");
+  *sch = g->sched_cfg;
+  return STA_OK;
+}
+
+sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
+  if (!g || !sch) return fail(STA_E_INVALID, "NULL argument");
+  if (sch->sweep_group_log2 < 4 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
+      sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64)
+    return fail(STA_E_INVALID, "schedule out of range");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  g->sched_cfg = *sch;
+  try {
+    build_schedule(g);
+  } catch (const std::bad_alloc&) {
+    return fail(STA_E_NOMEM, "host allocation failed");
+  }
+  drop_captured(g);
+  if (g->uploaded) {
+    hipError_t e = hipMemcpy(g->dev.sched_all, g->sched_all.data(), g->sched_all.size() * sizeof(int),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  return STA_OK;
+}
+
 sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info) {
   if (!g || !info) return fail(STA_E_INVALID, "NULL argument");
   std::memset(info, 0, sizeof(*info));
@@ -449,6 +605,7 @@ sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info) {
   info->fwd_state_bytes = g->levelized ? (int64_t)g->state.total : 0;
   info->bwd_workspace_bytes = g->levelized ? (int64_t)g->work.total : 0;
   info->device_bytes = g->uploaded ? (int64_t)g->dev.bytes : 0;
+  info->n_designs = g->n_designs;
   return STA_OK;
 }
 
@@ -496,6 +653,8 @@ sta_status sta_graph_upload(sta_graph* g) {
   sta_status s = STA_OK;
   if ((s = up(d.net_off, g->c_net_off)) || (s = up(d.pin_cap, g->c_pin_cap)) || (s = up(d.ell, g->ell)) ||
       (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_net)) || (s = up(d.pin_perm, g->pin_perm)) ||
+      (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
+      (s = up(d.ep_blk_off, g->ep_blk_off)) ||
       (s = up(d.sched_all, g->sched_all)) ||
       (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
     free_device(g);

@@ -16,13 +16,14 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 constexpr int kNumClasses = 5;       // wave lane groups of 4, 8, 16, 32, 64 lanes per net
 constexpr int kHeavy = kNumClasses;  // class of nets served by a whole workgroup
 constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
-constexpr int kFlatG0 = 2;           // flat kernels (RC, outputs): smallest group 4 lanes
-constexpr int kSweepG0 = 4;          // level kernels: smallest group 16 lanes (4 conditions x 4 arcs)
+constexpr int kFlatG0Default = 2;    // flat kernels (RC, outputs): smallest group 4 lanes
+constexpr int kSweepG0Default = 4;   // level kernels: smallest group 16 lanes (4 conditions x 4 arcs)
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0
 // lanes: the smallest wave group (doubling from 1 << g0) in which every lane holds at most
 // one sink; nets with more than 64 sinks get a whole workgroup.
-inline int net_class(int sinks, int g0) {
+inline int net_class(int sinks, int g0, int heavy_sinks) {
+  if (sinks > heavy_sinks) return kHeavy;
   int c = 0;
   for (int G = 1 << g0; G <= 64; G <<= 1, ++c)
     if (sinks <= G) return c;
@@ -51,7 +52,7 @@ struct StateLayout {
   size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
   size_t load;     // float[N]: root load of each net (Eq. 1)
   size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
-  size_t fin;      // double[8]: finished scalars and the WNS_g normaliser
+  size_t fin;      // double[n_designs * 8]: finished scalars and the WNS_g normaliser per design
   size_t total;
 };
 
@@ -67,8 +68,11 @@ struct DeviceGraph {
   int* net_off = nullptr;      // [N+1] canonical
   float* pin_cap = nullptr;    // [P]
   int4* ell = nullptr;         // cell inputs {source net, pin, arc, unateness}, padded slots per level
-  int* ep_pin = nullptr;       // [E]
+  int* ep_pin = nullptr;       // [E] endpoints, grouped by design
   int* ep_net = nullptr;       // [E]
+  int* ep_design = nullptr;    // [E] design of each endpoint
+  int* ep_design_off = nullptr;  // [n_designs+1] endpoint ranges by design
+  int* ep_blk_off = nullptr;   // [n_designs+1] partial-sum blocks by design
   int* pin_perm = nullptr;     // [P] original id of each canonical pin
   int* sched_all = nullptr;    // [N] all nets ordered by class
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
@@ -97,10 +101,16 @@ struct sta_graph {
   std::vector<int4> c_cin;                     // packed cell inputs (device layout)
   std::vector<float> c_pin_cap;
   std::vector<int> sched_all;
+  // Designs of a batch (one for a plain graph): pins [design_pin_off[d], design_pin_off[d+1])
+  // by original id; endpoints grouped by design, each design's partial blocks contiguous.
+  int n_designs = 1;
+  std::vector<int> design_pin_off{0, 0};
+  std::vector<int> ep_design, ep_design_off, ep_blk_off;
   std::vector<int4> ell;                       // padded per-level cell-input slots
   std::vector<int> ell_base, ell_slots;        // per level: first entry, slots per cell
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
+  sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64};
   sta::StateLayout state{};
   sta::WorkLayout work{};
   int n_ep_blocks = 0;
@@ -108,6 +118,16 @@ struct sta_graph {
   // Device copy.
   bool uploaded = false;
   sta::DeviceGraph dev;
+
+  // Launch sequences captured into hipGraphs (STA_GRAPH), keyed by the call's arguments.
+  struct Captured {
+    bool valid = false;
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  Captured cap_fwd, cap_bwd;
+  hipStream_t cap_stream = nullptr;
 
   // Event timing of launches (sta_profile_enable).
   bool profiling = false;
@@ -123,4 +143,6 @@ sta_status hip_fail(hipError_t e, const char* what);
 void compute_layouts(sta_graph* g);
 void build_lut_coefficients(const sta_graph* g, std::vector<float4>& grid, std::vector<float4>& coef);
 LutKeys lut_keys(const sta_graph* g);
+void drop_captured(sta_graph* g);
+void build_schedule(sta_graph* g);
 }  // namespace sta

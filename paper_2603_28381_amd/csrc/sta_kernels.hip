@@ -23,6 +23,7 @@
 //    (no atomics, Sec. 3.1.1).
 //  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
 #include <cmath>
+#include <cstring>
 
 #include "sta_internal.h"
 
@@ -361,15 +362,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
 struct EpArgs {
   const int* __restrict__ ep_pin;
   const int* __restrict__ ep_net;
+  const int* __restrict__ ep_design;      // design of each endpoint
+  const int* __restrict__ ep_design_off;  // [n_designs+1]
+  const int* __restrict__ ep_blk_off;     // [n_designs+1] partial blocks by design
   const float4* __restrict__ rec;
   const float2* __restrict__ wire;
   double* part;        // [blocks][5]
-  double* fin;         // [8]
-  double* scalars;     // [4] or NULL
+  double* fin;         // [designs][8]
+  double* scalars;     // [designs][4] or NULL
   float4* ratp;
   float4* adjp;
   const double* scale_dev;
-  int E, n_blocks;
+  int E, n_designs;
   float rat_late, hold, gamma, inv_gamma, scale;
   int smooth, wns_mode;
 };
@@ -416,10 +420,13 @@ __device__ __forceinline__ double block_reduce(double v, double* sh, bool is_max
 
 // Per-block partial sums over endpoints, in float64 and a fixed order: hard TNS, hard
 // worst slack, smoothed TNS terms, and a shifted sum of exponentials for smoothed WNS.
+// Each design's endpoints fill their own run of blocks.
 __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a) {
   __shared__ double sh[kBlock];
-  const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
-  const bool act = i < a.E;
+  int dsg = 0;
+  while (dsg + 1 < a.n_designs && (int)blockIdx.x >= a.ep_blk_off[dsg + 1]) ++dsg;
+  const int i = a.ep_design_off[dsg] + ((int)blockIdx.x - a.ep_blk_off[dsg]) * kBlock + (int)threadIdx.x;
+  const bool act = i < a.ep_design_off[dsg + 1];
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, v = -__builtin_huge_val();
   if (act) {
     const EpVals ev = endpoint_values(a, i);
@@ -446,10 +453,13 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a) {
   }
 }
 
+// Scalars of design blockIdx.x from its partial blocks (fixed order).
 __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a) {
   __shared__ double sh[kBlock];
+  const int dsg = blockIdx.x;
+  const int b0 = a.ep_blk_off[dsg], b1 = a.ep_blk_off[dsg + 1];
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, mx = -__builtin_huge_val();
-  for (int b = threadIdx.x; b < a.n_blocks; b += kBlock) {
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
     const double* p = a.part + 5 * (size_t)b;
     tns += p[0];
     wmin = fmin(wmin, p[1]);
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a) {
   tnsg = block_reduce<kBlock>(tnsg, sh, false);
   const double M = fmax(0.0, block_reduce<kBlock>(mx, sh, true));   // {0} joins the WNS_g set
   double tot = 0.0;
-  for (int b = threadIdx.x; b < a.n_blocks; b += kBlock) {
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
     const double* p = a.part + 5 * (size_t)b;
     if (p[4] > 0.0) tot += p[4] * exp((p[3] - M) / (double)a.gamma);
   }
@@ -470,13 +480,14 @@ __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a) {
     tot += exp(-M / (double)a.gamma);
     const double lse_all = M + (double)a.gamma * log(tot);
     const double nan = __builtin_nan("");
-    a.fin[0] = fmin(0.0, wmin);
-    a.fin[1] = tns;
-    a.fin[2] = a.smooth ? -lse_all : nan;
-    a.fin[3] = a.smooth ? tnsg : nan;
-    a.fin[4] = lse_all;
+    double* fin = a.fin + 8 * (size_t)dsg;
+    fin[0] = fmin(0.0, wmin);
+    fin[1] = tns;
+    fin[2] = a.smooth ? -lse_all : nan;
+    fin[3] = a.smooth ? tnsg : nan;
+    fin[4] = lse_all;
     if (a.scalars) {
-      for (int q = 0; q < 4; ++q) a.scalars[q] = a.fin[q];
+      for (int q = 0; q < 4; ++q) a.scalars[4 * (size_t)dsg + q] = fin[q];
     }
   }
 }
@@ -492,7 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a) {
     const EpVals ev = endpoint_values(a, i);
     float coef;
     if (a.wns_mode) {
-      coef = (float)exp((-(double)ev.sg - a.fin[4]) / (double)a.gamma);   // d WNS_g / d s_e
+      const double lse_all = a.fin[8 * (size_t)a.ep_design[i] + 4];
+      coef = (float)exp((-(double)ev.sg - lse_all) / (double)a.gamma);     // d WNS_g / d s_e
     } else {
       coef = 1.0f / (1.0f + expf(ev.sg * a.inv_gamma));                    // d TNS_g / d s_e
     }
@@ -906,15 +918,12 @@ struct LaunchTimer {
 
 using namespace sta;
 
-extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out* out, uint32_t flags,
-                                  float gamma_ps, sta_stream stream) {
-  sta_status st = check_ready(g);
-  if (st != STA_OK) return st;
-  if (!out || !out->state) return fail(STA_E_INVALID, "forward state buffer is required");
-  if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
+namespace sta {
+namespace {
+
+sta_status launch_forward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
+                          float gamma_ps, hipStream_t s) {
   const bool smooth = (flags & STA_SMOOTH) != 0;
-  if (smooth && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(out->state);
   float4* rec = reinterpret_cast<float4*>(sb + g->state.rec);
@@ -938,17 +947,17 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
     k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, sl);
   }
 
-  EpArgs ea{d.ep_pin, d.ep_net, rec, wire, reinterpret_cast<double*>(sb + g->state.part),
-            reinterpret_cast<double*>(sb + g->state.fin), out->scalars, nullptr, nullptr, nullptr, g->E, g->n_ep_blocks,
-            g->cons.t_clk - g->cons.setup, g->cons.hold, smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f,
-            1.0f, smooth ? 1 : 0, 0};
+  EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
+            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
+            nullptr, nullptr, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
+            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0};
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
     k_ep_partials<<<g->n_ep_blocks, kBlock, 0, s>>>(ea);
   }
   {
     LaunchTimer t(g, s, STA_K_EP_FINAL);
-    k_ep_finalize<<<1, kBlock, 0, s>>>(ea);
+    k_ep_finalize<<<g->n_designs, kBlock, 0, s>>>(ea);
   }
 
   if (out->at || out->slew || out->atg) {
@@ -962,15 +971,9 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
   return STA_OK;
 }
 
-extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
-                                   sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream) {
-  sta_status st = check_ready(g);
-  if (st != STA_OK) return st;
-  if (!fwd || !fwd->state || !out || !out->workspace) return fail(STA_E_INVALID, "state and workspace are required");
+sta_status launch_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                           const sta_bwd_out* out, uint32_t flags, float gamma_ps, hipStream_t s) {
   const bool grad = (flags & STA_GRAD) != 0;
-  if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
-  if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(fwd->state);
   char* wb = static_cast<char*>(out->workspace);
@@ -981,13 +984,14 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   float4* adjp = reinterpret_cast<float4*>(wb + g->work.adjp);
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
-  EpArgs ea{d.ep_pin, d.ep_net, rec, wire, reinterpret_cast<double*>(sb + g->state.part),
-            reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp, grad ? adjp : nullptr, out->grad_scale_dev,
-            g->E, g->n_ep_blocks, g->cons.t_clk - g->cons.setup, g->cons.hold, grad ? gamma_ps : 1.0f,
-            grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1, (flags & STA_GRAD_WNS) ? 1 : 0};
+  EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
+            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp,
+            grad ? adjp : nullptr, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
+            g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
+            (flags & STA_GRAD_WNS) ? 1 : 0};
   if (g->E > 0) {
     LaunchTimer t(g, s, STA_K_EP_SEED);
-    k_ep_seed<<<g->n_ep_blocks, kBlock, 0, s>>>(ea);
+    k_ep_seed<<<(g->E + kBlock - 1) / kBlock, kBlock, 0, s>>>(ea);
   }
 
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
@@ -1003,6 +1007,155 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return STA_OK;
+}
+
+uint64_t bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof(u));
+  return u;
+}
+
+// Runs `launch` on stream s, through a captured hipGraph when `use_graph` is set: the
+// launches are recorded on a private stream the first time (or when the key changed) and
+// the graph is replayed on s.
+template <class F>
+sta_status run_maybe_captured(sta_graph* g, sta_graph::Captured& cap, bool use_graph,
+                              const std::vector<uint64_t>& key, hipStream_t s, F launch) {
+  if (!use_graph || g->profiling) return launch(s);
+  if (!(cap.valid && cap.key == key)) {
+    if (cap.exec) (void)hipGraphExecDestroy(cap.exec);
+    if (cap.graph) (void)hipGraphDestroy(cap.graph);
+    cap = sta_graph::Captured{};
+    hipError_t e;
+    if (!g->cap_stream) {
+      e = hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    sta_status st = launch(g->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g->cap_stream, &graph);
+    if (st != STA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    cap.graph = graph;
+    cap.exec = exec;
+    cap.key = key;
+    cap.valid = true;
+  }
+  hipError_t e = hipGraphLaunch(cap.exec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return STA_OK;
+}
+
+uint64_t ptr(const void* p) { return (uint64_t)(uintptr_t)p; }
+
+}  // namespace
+}  // namespace sta
+
+extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out* out, uint32_t flags,
+                                  float gamma_ps, sta_stream stream) {
+  sta_status st = check_ready(g);
+  if (st != STA_OK) return st;
+  if (!out || !out->state) return fail(STA_E_INVALID, "forward state buffer is required");
+  if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
+  if ((flags & STA_SMOOTH) && !(gamma_ps > 0.f && std::isfinite(gamma_ps)))
+    return fail(STA_E_INVALID, "gamma must be positive");
+  const std::vector<uint64_t> key{ptr(x), ptr(y), ptr(out->state), ptr(out->at), ptr(out->slew), ptr(out->atg),
+                                  ptr(out->scalars), flags, bits(gamma_ps)};
+  const sta_fwd_out o = *out;
+  return run_maybe_captured(g, g->cap_fwd, (flags & STA_GRAPH) != 0, key, reinterpret_cast<hipStream_t>(stream),
+                            [&](hipStream_t s) { return launch_forward(g, x, y, &o, flags, gamma_ps, s); });
+}
+
+extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                                   sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream) {
+  sta_status st = check_ready(g);
+  if (st != STA_OK) return st;
+  if (!fwd || !fwd->state || !out || !out->workspace) return fail(STA_E_INVALID, "state and workspace are required");
+  const bool grad = (flags & STA_GRAD) != 0;
+  if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
+  if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  const std::vector<uint64_t> key{ptr(x), ptr(y), ptr(fwd->state), ptr(out->workspace), ptr(out->at), ptr(out->slew),
+                                  ptr(out->rat), ptr(out->slack), ptr(out->dx), ptr(out->dy), bits(out->grad_scale),
+                                  ptr(out->grad_scale_dev), flags, bits(gamma_ps)};
+  const sta_fwd_out f = *fwd;
+  const sta_bwd_out o = *out;
+  return run_maybe_captured(g, g->cap_bwd, (flags & STA_GRAPH) != 0, key, reinterpret_cast<hipStream_t>(stream),
+                            [&](hipStream_t s) { return launch_backward(g, x, y, &f, &o, flags, gamma_ps, s); });
+}
+
+extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
+                               sta_schedule* best, sta_stream stream) {
+  sta_status st = check_ready(g);
+  if (st != STA_OK) return st;
+  if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
+  if (!(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t P = (size_t)g->P;
+  const size_t sizes[] = {g->state.total, g->work.total, 16 * P, 16 * P, 16 * P, 16 * P, 4 * P, 4 * P,
+                          32 * (size_t)g->n_designs};
+  void* buf[9] = {};
+  for (int i = 0; i < 9; ++i) {
+    hipError_t e = hipMalloc(&buf[i], sizes[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipFree(buf[j]);
+      return hip_fail(e, "hipMalloc");
+    }
+  }
+  sta_fwd_out fo{buf[0], nullptr, nullptr, nullptr, static_cast<double*>(buf[8])};
+  sta_bwd_out bo{buf[1], static_cast<float*>(buf[2]), static_cast<float*>(buf[3]), static_cast<float*>(buf[4]),
+                 static_cast<float*>(buf[5]), static_cast<float*>(buf[6]), static_cast<float*>(buf[7]), 1.0f, nullptr};
+  const uint32_t ff = STA_SMOOTH | STA_CANONICAL_IO, bf = STA_RAT | STA_GRAD | STA_CANONICAL_IO;
+  const sta_schedule start = g->sched_cfg;
+  sta_schedule best_s = start;
+  float best_ms = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (int sweep = 4; sweep <= 6 && st == STA_OK; ++sweep)
+    for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
+      for (int heavy : {32, 64}) {
+        const sta_schedule cand{sweep, flat, heavy};
+        st = sta_set_schedule(g, &cand);
+        for (int r = -1; r < reps && st == STA_OK; ++r) {
+          if (r == 0) (void)hipEventRecord(e0, s);
+          st = launch_forward(g, x, y, &fo, ff, gamma_ps, s);
+          if (st == STA_OK) st = launch_backward(g, x, y, &fo, &bo, bf, gamma_ps, s);
+        }
+        if (st != STA_OK) break;
+        (void)hipEventRecord(e1, s);
+        hipError_t e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+          st = hip_fail(e, "hipEventSynchronize");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_s = cand;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (void* p : buf) (void)hipFree(p);
+  if (st != STA_OK) {
+    (void)sta_set_schedule(g, &start);
+    return st;
+  }
+  st = sta_set_schedule(g, &best_s);
+  if (best) *best = best_s;
+  return st;
 }
 
 extern "C" sta_status sta_profile_enable(sta_graph* g, int32_t on) {

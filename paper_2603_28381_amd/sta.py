@@ -24,10 +24,13 @@ STA_CANONICAL_IO = 1 << 1
 STA_RAT = 1 << 2
 STA_GRAD = 1 << 3
 STA_GRAD_WNS = 1 << 4
+STA_GRAPH = 1 << 5
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
-            "sta_graph_info_get", "sta_graph_destroy", "sta_forward", "sta_backward",
-            "sta_profile_enable", "sta_profile_read", "sta_last_error", "sta_version"]
+            "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
+            "sta_forward", "sta_backward", "sta_get_schedule", "sta_set_schedule", "sta_tune",
+            "sta_profile_enable", "sta_profile_read", "sta_last_error",
+            "sta_version"]
 
 KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level"]
 
@@ -56,7 +59,13 @@ class StaGraphInfo(ctypes.Structure):
                 ("n_cell_inputs", ctypes.c_int32), ("n_endpoints", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("n_pi_nets", ctypes.c_int32),
                 ("max_level_nets", ctypes.c_int32), ("fwd_state_bytes", ctypes.c_int64),
-                ("bwd_workspace_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("bwd_workspace_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("n_designs", ctypes.c_int32)]
+
+
+class StaSchedule(ctypes.Structure):
+    _fields_ = [("sweep_group_log2", ctypes.c_int32), ("flat_group_log2", ctypes.c_int32),
+                ("heavy_sinks", ctypes.c_int32)]
 
 
 class StaFwdOut(ctypes.Structure):
@@ -104,6 +113,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_backward.argtypes = [_P, _P, _P, ctypes.POINTER(StaFwdOut), ctypes.POINTER(StaBwdOut),
                                  ctypes.c_uint32, ctypes.c_float, _P]
     lib.sta_backward.restype = S
+    lib.sta_batch_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]
+    lib.sta_batch_create.restype = S
+    lib.sta_batch_pin_map.argtypes = [_P, _P, _P]
+    lib.sta_batch_pin_map.restype = S
+    lib.sta_get_schedule.argtypes = [_P, ctypes.POINTER(StaSchedule)]
+    lib.sta_get_schedule.restype = S
+    lib.sta_set_schedule.argtypes = [_P, ctypes.POINTER(StaSchedule)]
+    lib.sta_set_schedule.restype = S
+    lib.sta_tune.argtypes = [_P, _P, _P, ctypes.c_float, ctypes.c_int32, ctypes.POINTER(StaSchedule), _P]
+    lib.sta_tune.restype = S
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_enable.restype = S
     lib.sta_profile_read.argtypes = [_P, _P, _P]
@@ -195,6 +214,27 @@ class Graph:
                   r_per_um=c.r_per_um, c_per_um=c.c_per_um)
         return cls(nl, lb, cs)
 
+    @classmethod
+    def batch(cls, graphs: list["Graph"]) -> "Graph":
+        """One graph sweeping several designs (or placement snapshots: repeat a graph)."""
+        load_library()
+        arr = (_P * len(graphs))(*[g._h.value for g in graphs])
+        h = _P()
+        _check(_lib.sta_batch_create(arr, len(graphs), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj._keep = []
+        obj._h = h
+        obj.n_pins = sum(g.n_pins for g in graphs)
+        return obj
+
+    def batch_pin_map(self) -> tuple[np.ndarray, np.ndarray]:
+        """(design, pin) of every canonical pin of a levelized batch."""
+        P = self.n_pins
+        dsg = np.empty(P, np.int32)
+        pin = np.empty(P, np.int32)
+        _check(_lib.sta_batch_pin_map(self._h, dsg.ctypes.data, pin.ctypes.data))
+        return dsg, pin
+
     @property
     def handle(self) -> int:
         return self._h.value
@@ -233,6 +273,25 @@ class Graph:
     def upload(self):
         _check(_lib.sta_graph_upload(self._h))
 
+    def schedule(self) -> dict:
+        sch = StaSchedule()
+        _check(_lib.sta_get_schedule(self._h, ctypes.byref(sch)))
+        return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
+
+    def set_schedule(self, sweep_group_log2: int, flat_group_log2: int, heavy_sinks: int):
+        sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks)
+        _check(_lib.sta_set_schedule(self._h, ctypes.byref(sch)))
+
+    def tune(self, x, y, gamma: float = 10.0, reps: int = 3, stream=None) -> dict:
+        """Time the candidate lane-group schedules on these coordinates and keep the fastest."""
+        dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
+        x = _dev_f32(x, dev)
+        y = _dev_f32(y, dev)
+        sch = StaSchedule()
+        _check(_lib.sta_tune(self._h, _ptr(x), _ptr(y), float(gamma), int(reps), ctypes.byref(sch),
+                             _stream_handle(stream)))
+        return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
+
     def profile(self, on: bool = True):
         _check(_lib.sta_profile_enable(self._h, 1 if on else 0))
 
@@ -251,27 +310,33 @@ class Graph:
 
     def forward(self, x, y, gamma: float = 10.0, smooth: bool = True, canonical: bool = False,
                 pins: bool = False, state: torch.Tensor | None = None, scalars: torch.Tensor | None = None,
-                stream=None) -> Forward:
+                stream=None, capture: bool = False, out: dict | None = None) -> Forward:
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
         P = self.n_pins
         state = self.new_state(dev) if state is None else state
-        scalars = torch.empty(4, dtype=torch.float64, device=dev) if scalars is None else scalars
+        if scalars is None:
+            nd = self.info()["n_designs"]
+            scalars = torch.empty((nd, 4) if nd > 1 else 4, dtype=torch.float64, device=dev)
         at = slew = atg = None
-        if pins:
+        if out is not None:
+            at, slew, atg = out.get("at"), out.get("slew"), out.get("atg")
+        elif pins:
             at = torch.empty((P, 4), dtype=torch.float32, device=dev)
             slew = torch.empty((P, 4), dtype=torch.float32, device=dev)
             atg = torch.empty((P, 2), dtype=torch.float32, device=dev) if smooth else None
         fo = StaFwdOut(_ptr(state), _ptr(at), _ptr(slew), _ptr(atg), _ptr(scalars))
-        flags = (STA_SMOOTH if smooth else 0) | (STA_CANONICAL_IO if canonical else 0)
+        flags = ((STA_SMOOTH if smooth else 0) | (STA_CANONICAL_IO if canonical else 0)
+                 | (STA_GRAPH if capture else 0))
         _check(_lib.sta_forward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), flags, float(gamma),
                                 _stream_handle(stream)))
         return Forward(state, scalars, at, slew, atg, float(gamma), canonical)
 
     def backward(self, x, y, fwd: Forward, rat: bool = True, grad: bool = True, wns: bool = False,
                  pins: bool = True, grad_scale: float = 1.0, grad_scale_dev: torch.Tensor | None = None,
-                 workspace: torch.Tensor | None = None, out: dict | None = None, stream=None) -> dict:
+                 workspace: torch.Tensor | None = None, out: dict | None = None, stream=None,
+                 capture: bool = False) -> dict:
         dev = fwd.state.device
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
@@ -293,7 +358,7 @@ class Graph:
                        _ptr(grad_scale_dev))
         fo = StaFwdOut(_ptr(fwd.state), None, None, None, None)
         flags = ((STA_RAT if rat else 0) | (STA_GRAD if grad else 0) | (STA_GRAD_WNS if wns else 0)
-                 | (STA_CANONICAL_IO if fwd.canonical else 0))
+                 | (STA_CANONICAL_IO if fwd.canonical else 0) | (STA_GRAPH if capture else 0))
         _check(_lib.sta_backward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), ctypes.byref(bo), flags,
                                  float(fwd.gamma), _stream_handle(stream)))
         return out

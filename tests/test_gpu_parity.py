@@ -223,3 +223,103 @@ def test_parity_cfg1_full_size():
 def test_parity_cfg2_full_size():
     # The benchmark workload: 2.5M pins, 91 net levels.
     full_size_parity(CFG2)
+
+
+def test_batch_matches_designs_run_alone_bitwise():
+    # Three designs plus a second placement of the first, swept as one batch.
+    from gen.netlist import jitter
+    da = make_design(CFG0)
+    db = make_design(scaled_spec(20_000, cfg_id=43, box_um=800.0))
+    dc = make_design(scaled_spec(5_000, cfg_id=44, box_um=300.0))
+    ga, gb, gc = (Graph.from_design(d) for d in (da, db, dc))
+    xa2, ya2 = jitter(da, 5.0, stream=1)
+    members = [(ga, da, da.x, da.y), (gb, db, db.x, db.y), (ga, da, xa2, ya2), (gc, dc, dc.x, dc.y)]
+    batch = Graph.batch([m[0] for m in members])
+    batch.levelize()
+    dsg, pin = batch.batch_pin_map()
+    xs = np.concatenate([m[2] for m in members])
+    ys = np.concatenate([m[3] for m in members])
+    base = np.cumsum([0] + [m[1].n_pins for m in members])
+    src = base[dsg] + pin
+    x = torch.tensor(xs[src], device="cuda")
+    y = torch.tensor(ys[src], device="cuda")
+    fwd = batch.forward(x, y, gamma=GAMMA, canonical=True)
+    out = batch.backward(x, y, fwd, rat=True, grad=True, pins=True)
+    torch.cuda.synchronize()
+    sc = fwd.scalars.cpu().numpy()
+    assert sc.shape == (4, 4)
+    for i, (g, d, mx, my) in enumerate(members):
+        g.levelize()
+        xx = torch.tensor(mx, device="cuda")
+        yy = torch.tensor(my, device="cuda")
+        f1 = g.forward(xx, yy, gamma=GAMMA)
+        o1 = g.backward(xx, yy, f1, rat=True, grad=True, pins=True)
+        torch.cuda.synchronize()
+        sel = dsg == i
+        for k in ("at", "slew", "rat", "slack", "dx", "dy"):
+            alone = o1[k].cpu().numpy()
+            inb = np.empty_like(alone)
+            inb[pin[sel]] = out[k].cpu().numpy()[sel]
+            assert np.array_equal(inb, alone), (i, k)
+        assert np.array_equal(sc[i], f1.scalars.cpu().numpy()), i
+
+
+def test_graph_capture_replays_match_plain_calls():
+    # Captured launches are replayed on the caller's stream and read the current contents of
+    # the argument buffers: move the pins between replays (eager work in between) and compare
+    # each replay with plain calls on the same coordinates.
+    from gen.netlist import jitter
+    d = make_design(scaled_spec(30_000, cfg_id=45, box_um=400.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    g.upload()
+    P = d.n_pins
+    x = torch.empty(P, device="cuda")
+    y = torch.empty(P, device="cuda")
+    state, ws = g.new_state(), g.new_workspace()
+    sc = torch.empty(4, dtype=torch.float64, device="cuda")
+    outs = {k: torch.empty((P, 4), device="cuda") for k in ("at", "slew", "rat", "slack")}
+    outs.update(dx=torch.empty(P, device="cuda"), dy=torch.empty(P, device="cuda"))
+    for rep in range(3):
+        xs, ys = (d.x, d.y) if rep == 0 else jitter(d, 4.0 * rep, stream=rep)
+        x.copy_(torch.tensor(xs))
+        y.copy_(torch.tensor(ys))
+        f = g.forward(x, y, gamma=GAMMA, state=state, scalars=sc, capture=True)
+        g.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs, capture=True)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in outs.items()}
+        got["scalars"] = sc.cpu().numpy()
+        f2 = g.forward(x, y, gamma=GAMMA)
+        o2 = g.backward(x, y, f2, rat=True, grad=True, pins=True)
+        torch.cuda.synchronize()
+        for k in ("at", "slew", "rat", "slack", "dx", "dy"):
+            assert np.array_equal(got[k], o2[k].cpu().numpy(), equal_nan=True), (rep, k)
+        assert np.array_equal(got["scalars"], f2.scalars.cpu().numpy()), rep
+        _ = (x * 2.0).sum().item()          # unrelated eager work between replays
+
+
+def test_schedules_agree_with_oracle():
+    # Every lane-group schedule sweeps the same arithmetic (summation order aside).
+    d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    g = Graph.from_design(d)
+    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1)):
+        g.levelize()
+        g.set_schedule(*sch)
+        print("schedule", sch)
+        got = gpu_run(d, graph=g)
+        check_values(d, got, ref)
+        check_grad(got, ref, 1e-3, 1e-6)
+
+
+def test_tune_keeps_a_valid_schedule():
+    d = make_design(CFG0)
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    g = Graph.from_design(d)
+    g.levelize()
+    g.upload()
+    best = g.tune(torch.tensor(d.x, device="cuda"), torch.tensor(d.y, device="cuda"), gamma=GAMMA, reps=2)
+    assert best == g.schedule()
+    got = gpu_run(d, graph=g)
+    check_values(d, got, ref)
+    check_grad(got, ref, 1e-3, 1e-6)

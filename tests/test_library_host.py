@@ -123,3 +123,73 @@ def test_levelization_state_errors():
     assert g.info()["n_levels"] == 0
     g.levelize()
     assert g.info()["fwd_state_bytes"] > 0 and g.info()["bwd_workspace_bytes"] > 0
+
+
+def test_schedule_roundtrip_and_validation():
+    g = S.Graph.from_design(make_design(tiny_spec(20, 3, n_pi=3, seed=1)))
+    with pytest.raises(S.StaError) as e:
+        g.set_schedule(4, 2, 64)
+    assert e.value.code == S.STA_E_STATE          # not levelized yet
+    g.levelize()
+    assert g.schedule() == dict(sweep_group_log2=4, flat_group_log2=2, heavy_sinks=64)
+    g.set_schedule(5, 3, 32)
+    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32)
+    for bad in ((3, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65)):
+        with pytest.raises(S.StaError) as e:
+            g.set_schedule(*bad)
+        assert e.value.code == S.STA_E_INVALID
+    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32)
+    g.close()
+
+
+def _members():
+    from gen.netlist import scaled_spec
+    return [make_design(tiny_spec(30, 4, n_pi=4, seed=3)), make_design(scaled_spec(3_000, cfg_id=44, box_um=300.0)),
+            make_design(tiny_spec(12, 2, n_pi=2, seed=4))]
+
+
+def test_batch_levels_and_pin_map_match_members():
+    ds = _members()
+    gs = [S.Graph.from_design(d) for d in ds]
+    b = S.Graph.batch(gs + [gs[0]])
+    with pytest.raises(S.StaError) as e:
+        b.batch_pin_map()
+    assert e.value.code == S.STA_E_STATE
+    L = b.levelize()
+    members = ds + [ds[0]]
+    refs = [O.levelize(d) for d in members]
+    assert L == max(r.n_levels for r in refs)
+    info = b.info()
+    assert info["n_designs"] == 4
+    assert info["n_pins"] == sum(d.n_pins for d in members)
+    assert info["n_endpoints"] == sum(int(((d.pin_kind == 3) | (d.pin_kind == 4)).sum()) for d in members)
+    dsg, pin = b.batch_pin_map()
+    # a bijection onto (design, pin)
+    flat = np.cumsum([0] + [d.n_pins for d in members])[dsg] + pin
+    assert np.array_equal(np.sort(flat), np.arange(info["n_pins"]))
+    # every net keeps the level it has in its own design
+    lv = b.levelization()
+    pperm_b = lv["pin_perm"]          # canonical pin -> union pin id
+    pin_off = np.cumsum([0] + [d.n_pins for d in members])
+    assert np.array_equal(pin_off[dsg] + pin, pperm_b)
+    level_of_net = lv["level"]
+    union_net_of_pin = np.concatenate([np.repeat(np.arange(d.n_nets), np.diff(d.net_offsets))[np.argsort(d.net_pins)]
+                                       + sum(m.n_nets for m in members[:i]) for i, d in enumerate(members)])
+    net_off = np.cumsum([0] + [d.n_nets for d in members])
+    for i, (d, r) in enumerate(zip(members, refs)):
+        drivers = d.net_pins[d.net_offsets[:-1]]
+        assert np.array_equal(level_of_net[union_net_of_pin[pin_off[i] + drivers]], r.level), i
+    assert union_net_of_pin.shape[0] == info["n_pins"] and net_off[-1] == info["n_nets"]
+    b.close()
+    for g in gs:
+        g.close()
+
+
+def test_batch_rejects_mismatched_constraints():
+    from gen.netlist import Constraints
+    d0 = build(**_small())
+    kw = _small()
+    d1 = build(**kw, cons=Constraints(t_clk=500.0))
+    with pytest.raises(S.StaError) as e:
+        S.Graph.batch([S.Graph.from_design(d0), S.Graph.from_design(d1)])
+    assert e.value.code == S.STA_E_INVALID
