@@ -266,6 +266,10 @@ def run_single(args) -> dict:
         g.profile(False)
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
 
+    ckpt = None
+    if args.ckpt_compare:
+        ckpt = checkpoint_comparison(g, x, y, P, dev, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import sta_oracle as O
@@ -290,9 +294,45 @@ def run_single(args) -> dict:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "checkpointing": ckpt,
         "wall_s_timed": round(wall, 3),
         "setup_s": round(t_setup, 2),
     }
+
+
+def checkpoint_comparison(g, x, y, P, dev, args) -> dict:
+    """Gradient steps (forward + backward with d TNS_g/dx,dy, no per-pin outputs) with and
+    without per-level checkpointing: time, arrival-state bytes and peak device memory."""
+    import torch
+    res = {}
+    for name, stride in (("plain", 0), ("checkpointed", -1)):
+        g.set_checkpointing(stride)
+        g.upload()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        state, ws = g.new_state(dev), g.new_workspace(dev)
+        scal = torch.empty(4, dtype=torch.float64, device=dev)
+        out = {"dx": torch.empty(P, device=dev), "dy": torch.empty(P, device=dev)}
+
+        def step():
+            f = g.forward(x, y, gamma=args.gamma, canonical=True, state=state, scalars=scal)
+            g.backward(x, y, f, rat=False, grad=True, workspace=ws, out=out)
+
+        ms, _ = timed(step, args.steps, args.warmup)
+        info, ck = g.info(), g.checkpointing()
+        res[name] = dict(ms_per_step=round(ms, 4), stride_levels=ck["stride_levels"],
+                         record_slots=ck["record_slots"], kept_nets=ck["kept_nets"],
+                         fwd_state_bytes=info["fwd_state_bytes"], workspace_bytes=info["bwd_workspace_bytes"],
+                         graph_device_bytes=info["device_bytes"],
+                         peak_bytes=torch.cuda.max_memory_allocated() - base + info["device_bytes"])
+        del state, ws, scal, out
+    g.set_checkpointing(0)
+    res["state_ratio"] = round(res["checkpointed"]["fwd_state_bytes"] / res["plain"]["fwd_state_bytes"], 4)
+    res["peak_ratio"] = round(res["checkpointed"]["peak_bytes"] / res["plain"]["peak_bytes"], 4)
+    res["time_ratio"] = round(res["checkpointed"]["ms_per_step"] / res["plain"]["ms_per_step"], 4)
+    return res
 
 
 def main(argv=None) -> int:
@@ -303,6 +343,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3"])
     ap.add_argument("--gamma", type=float, default=10.0)
     ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")
+    ap.add_argument("--no-ckpt-compare", dest="ckpt_compare", action="store_false",
+                    help="skip the gradient-step comparison with per-level checkpointing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
     args = ap.parse_args(argv)

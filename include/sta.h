@@ -233,6 +233,32 @@ sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps
                     sta_schedule* best, sta_stream stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Per-level checkpointing of the arrival state (the memory/time trade-off of reverse-mode
+ * differentiation applied to the level sweep).  With a stride of k levels, levels 1..L-1
+ * are cut into segments of k levels.  The forward keeps the arrival record (AT, slew,
+ * smoothed AT of the driver) only of the nets still needed after their segment ends: nets
+ * read by a cell in a later segment (the live frontier of a segment boundary; the graph is
+ * a DAG, so a net can be read many levels later), nets driving an endpoint and level-0
+ * nets.  All other nets of a segment share one buffer that the next segment overwrites.
+ * sta_backward walks the segments last to first, recomputes the dropped records of a
+ * segment from the frontier, then runs that segment's backward levels.  Results are
+ * bit-identical to the run without checkpointing; fwd_state_bytes shrinks (see
+ * sta_get_checkpointing), the backward pays one extra forward pass over the dropped nets.
+ *
+ * stride_levels: 0 switches checkpointing off, a negative value picks ceil(sqrt(L-1)).
+ * Changing it rebuilds the launch plan, changes fwd_state_bytes and releases the device
+ * copy (uploaded again on the next call): state buffers must be allocated anew.  With
+ * checkpointing on, sta_forward does not produce per-pin outputs (at/slew/atg must be
+ * NULL; take them from sta_backward), and sta_backward must get the forward's gamma.
+ * Errors: STA_E_STATE if not levelized.
+ * ------------------------------------------------------------------------------------- */
+sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels);
+/* Current stride (0 = off), number of arrival records the state holds (kept nets plus the
+ * shared segment buffer; n_nets without checkpointing) and of those, the kept nets. */
+sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int32_t* record_slots,
+                                 int32_t* kept_nets);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timing with HIP events (a profiling aid).  While enabled, every kernel launch that
  * sta_forward / sta_backward make for g is bracketed by two events on its stream.
  * sta_profile_read waits for those events and returns, per kernel family (STA_K_*), the
@@ -246,7 +272,8 @@ sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps
 #define STA_K_EXPAND 4       /* per-pin forward outputs */
 #define STA_K_EP_SEED 5      /* backward seeds */
 #define STA_K_BWD_LEVEL 6    /* one backward level (RAT, slack, adjoint) */
-#define STA_K_COUNT 7
+#define STA_K_RECOMPUTE 7    /* one forward level recomputed from a checkpoint */
+#define STA_K_COUNT 8
 sta_status sta_profile_enable(sta_graph* g, int32_t on);
 sta_status sta_profile_read(sta_graph* g, int64_t* launches, double* total_ms);
 

@@ -39,7 +39,7 @@ void compute_layouts(sta_graph* g) {
     g->ep_blk_off[d + 1] = g->ep_blk_off[d] + (e + kBlock - 1) / kBlock;
   }
   g->n_ep_blocks = g->ep_blk_off[g->n_designs];
-  g->state.rec = take(sizeof(float4) * 3 * (size_t)g->N);
+  g->state.rec = take(sizeof(float4) * 3 * (size_t)std::max(1, g->n_rec));
   g->state.wire = take(sizeof(float2) * (size_t)g->P);
   g->state.load = take(sizeof(float) * (size_t)g->N);
   g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
@@ -104,10 +104,61 @@ static GroupRange group_range(const int* cls_count, int base, int g0) {
   return r;
 }
 
-void build_schedule(sta_graph* g) {
+// Record slots under checkpointing (stride k > 0): a net of level l >= 1 belongs to
+// segment (l-1)/k, which ends at level 1 + k*((l-1)/k + 1).  It is kept if a cell of a
+// level at or past that end reads it, if it drives an endpoint, or if l = 0; kept nets get
+// slots in canonical order (level-0 nets first, so their slot is their index), the other
+// nets of a segment share the slots after them.  Without checkpointing slot = net.
+static void build_checkpoints(sta_graph* g) {
+  const int N = g->N, L = g->L, k = g->ckpt_stride;
+  g->seg_lo.clear();
+  if (k <= 0) {
+    g->rec_loc.clear();
+    g->n_rec = g->n_kept = N;
+    g->ep_rec = g->ep_net;
+    return;
+  }
+  for (int l = 1; l < L; l += k) g->seg_lo.push_back(l);
+  g->seg_lo.push_back(std::max(L, 1));
+  std::vector<int> lvl(N), maxc(N, -1);
+  for (int l = 0; l < L; ++l)
+    for (int n = g->level_off[l]; n < g->level_off[l + 1]; ++n) lvl[n] = l;
+  for (int c = 0; c < g->C; ++c) {
+    const int lc = lvl[g->N0 + c];
+    for (int a = g->c_cin_off[c]; a < g->c_cin_off[c + 1]; ++a)
+      maxc[g->c_cin_src[a]] = std::max(maxc[g->c_cin_src[a]], lc);
+  }
+  std::vector<char> kept(N, 0);
+  for (int n : g->ep_net) kept[n] = 1;
+  for (int n = 0; n < N; ++n) {
+    const int l = lvl[n];
+    if (l == 0 || maxc[n] >= 1 + k * ((l - 1) / k + 1)) kept[n] = 1;
+  }
+  g->rec_loc.assign(N, 0);
+  int nk = 0;
+  for (int n = 0; n < N; ++n)
+    if (kept[n]) g->rec_loc[n] = nk++;
+  int widest = 0;
+  for (size_t j = 0; j + 1 < g->seg_lo.size(); ++j) {
+    int t = 0;
+    for (int n = g->level_off[g->seg_lo[j]]; n < g->level_off[g->seg_lo[j + 1]]; ++n)
+      if (!kept[n]) g->rec_loc[n] = nk + t++;
+    widest = std::max(widest, t);
+  }
+  g->n_kept = nk;
+  g->n_rec = nk + widest;
+  g->ep_rec.resize(g->ep_net.size());
+  for (size_t i = 0; i < g->ep_net.size(); ++i) g->ep_rec[i] = g->rec_loc[g->ep_net[i]];
+}
+
+// Lane-group work lists: per-level ranges for the level kernels and all nets ordered by
+// class for the one-pass kernels.  Depends on the schedule only.
+void build_groups(sta_graph* g) {
   const int N = g->N;
   std::vector<int> cls(N);
-  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.sweep_group_log2, g->sched_cfg.heavy_sinks);
+  for (int n = 0; n < N; ++n)
+    cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.sweep_group_log2,
+                       g->sched_cfg.heavy_sinks);
   // Within a level, canonical nets are sorted by size, so classes are contiguous ranges and
   // a level's GroupRange indexes canonical net ids directly.
   g->lvl_ranges.assign(g->L, GroupRange{});
@@ -117,8 +168,23 @@ void build_schedule(sta_graph* g) {
     for (int n = b; n < e; ++n) cnt[cls[n]]++;
     g->lvl_ranges[l] = group_range(cnt, b, g->sched_cfg.sweep_group_log2);
   }
-  // Cell inputs in a padded slot layout per level: input j of the k-th cell of level l is
-  // entry ell_base[l] + j * (cells of l) + k; missing inputs hold source net -1.
+  for (int n = 0; n < N; ++n)
+    cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.flat_group_log2,
+                       g->sched_cfg.heavy_sinks);
+  int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
+  for (int n = 0; n < N; ++n) cnt[cls[n]]++;
+  int pos[kNumClasses + 1];
+  int o = 0;
+  for (int c = 0; c <= kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
+  g->sched_all.assign(N, 0);
+  for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
+  g->all_range = group_range(cnt, 0, g->sched_cfg.flat_group_log2);
+}
+
+// Record slots and the cell inputs in a padded slot layout per level: input j of the k-th
+// cell of level l is entry ell_base[l] + j * (cells of l) + k; missing inputs hold source -1.
+void build_ell(sta_graph* g) {
+  build_checkpoints(g);
   g->ell.clear();
   g->ell_base.assign(g->L, 0);
   g->ell_slots.assign(g->L, 0);
@@ -133,16 +199,15 @@ void build_schedule(sta_graph* g) {
       for (int j = 0; j < g->c_cin_off[c + 1] - g->c_cin_off[c]; ++j)
         g->ell[g->ell_base[l] + (size_t)j * nc + (c - c0)] = g->c_cin[g->c_cin_off[c] + j];
   }
+  if (g->ckpt_stride > 0)
+    for (int4& e : g->ell)
+      if (e.x >= 0) e.x = g->rec_loc[e.x];      // sources addressed by record slot
   if (g->ell.empty()) g->ell.push_back(make_int4(-1, 0, 0, 1));
-  for (int n = 0; n < N; ++n) cls[n] = net_class(g->c_net_off[n + 1] - g->c_net_off[n] - 1, g->sched_cfg.flat_group_log2, g->sched_cfg.heavy_sinks);
-  int cnt[kNumClasses + 1] = {0, 0, 0, 0, 0, 0};
-  for (int n = 0; n < N; ++n) cnt[cls[n]]++;
-  int pos[kNumClasses + 1];
-  int o = 0;
-  for (int c = 0; c <= kNumClasses; ++c) { pos[c] = o; o += cnt[c]; }
-  g->sched_all.assign(N, 0);
-  for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
-  g->all_range = group_range(cnt, 0, g->sched_cfg.flat_group_log2);
+}
+
+void build_schedule(sta_graph* g) {
+  build_ell(g);
+  build_groups(g);
 }
 
 void drop_captured(sta_graph* g) {
@@ -510,7 +575,6 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
       }
     }
     g->c_cin_off[C] = a;
-    // Endpoints in canonical order.
     // Endpoints in canonical order, grouped by design.
     g->ep_pin.clear();
     g->ep_net.clear();
@@ -578,7 +642,7 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   g->sched_cfg = *sch;
   try {
-    build_schedule(g);
+    build_groups(g);
   } catch (const std::bad_alloc&) {
     return fail(STA_E_NOMEM, "host allocation failed");
   }
@@ -588,6 +652,32 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
                              hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
+  return STA_OK;
+}
+
+sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  int k = stride_levels;
+  if (k < 0) k = std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, g->L - 1))));
+  g->ckpt_stride = k;
+  try {
+    build_ell(g);
+    compute_layouts(g);
+  } catch (const std::bad_alloc&) {
+    return fail(STA_E_NOMEM, "host allocation failed");
+  }
+  free_device(g);
+  return STA_OK;
+}
+
+sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int32_t* record_slots,
+                                 int32_t* kept_nets) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (stride_levels) *stride_levels = g->ckpt_stride;
+  if (record_slots) *record_slots = g->n_rec;
+  if (kept_nets) *kept_nets = g->n_kept;
   return STA_OK;
 }
 
@@ -652,10 +742,10 @@ sta_status sta_graph_upload(sta_graph* g) {
   };
   sta_status s = STA_OK;
   if ((s = up(d.net_off, g->c_net_off)) || (s = up(d.pin_cap, g->c_pin_cap)) || (s = up(d.ell, g->ell)) ||
-      (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_net)) || (s = up(d.pin_perm, g->pin_perm)) ||
+      (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_rec)) || (s = up(d.pin_perm, g->pin_perm)) ||
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
-      (s = up(d.sched_all, g->sched_all)) ||
+      (s = up(d.sched_all, g->sched_all)) || (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
       (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
     free_device(g);
     return s;

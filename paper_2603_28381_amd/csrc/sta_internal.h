@@ -48,7 +48,7 @@ struct LutKeys {
 
 // Byte offsets of the pieces of the forward state buffer.
 struct StateLayout {
-  size_t rec;      // float4[3 * N]: per net {at[4]}, {slew[4]}, {atg[2], 0, 0}
+  size_t rec;      // float4[3 * record slots]: per net {at[4]}, {slew[4]}, {atg[2], 0, 0}
   size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
   size_t load;     // float[N]: root load of each net (Eq. 1)
   size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
@@ -69,12 +69,13 @@ struct DeviceGraph {
   float* pin_cap = nullptr;    // [P]
   int4* ell = nullptr;         // cell inputs {source net, pin, arc, unateness}, padded slots per level
   int* ep_pin = nullptr;       // [E] endpoints, grouped by design
-  int* ep_net = nullptr;       // [E]
+  int* ep_net = nullptr;       // [E] record slot of the endpoint's net
   int* ep_design = nullptr;    // [E] design of each endpoint
   int* ep_design_off = nullptr;  // [n_designs+1] endpoint ranges by design
   int* ep_blk_off = nullptr;   // [n_designs+1] partial-sum blocks by design
   int* pin_perm = nullptr;     // [P] original id of each canonical pin
   int* sched_all = nullptr;    // [N] all nets ordered by class
+  int* rec_loc = nullptr;      // [N] record slot of each net (checkpointing only)
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
   size_t bytes = 0;
@@ -111,6 +112,11 @@ struct sta_graph {
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
   sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64};
+  // Checkpointing (stride 0 = off): record slot of each canonical net (kept nets first,
+  // level-0 nets at their own index, then the shared segment buffer), segment boundaries
+  // seg_lo (levels [seg_lo[j], seg_lo[j+1])), and the endpoints' record slots.
+  int ckpt_stride = 0, n_rec = 0, n_kept = 0;
+  std::vector<int> rec_loc, seg_lo, ep_rec;
   sta::StateLayout state{};
   sta::WorkLayout work{};
   int n_ep_blocks = 0;

@@ -309,7 +309,9 @@ struct FwdArgs {
   const float4* __restrict__ grid;
   const float4* __restrict__ coef;
   LutKeys keys;
+  const int* __restrict__ loc;       // record slot of each net, NULL: slot = net
   int N0;
+  int min_slot;                      // cells whose net's slot is below this are skipped
   float gamma, inv_gamma;
   int smooth;
 };
@@ -324,6 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
   const int lane = gid & (kCellLanes - 1);
   const int k = lane >> 2, jl = lane & 3, m = k >> 1, t = k & 1;
   const int n = a.N0 + sl.c0 + kc;
+  const int slot = a.loc ? a.loc[n] : n;
+  if (slot < a.min_slot) return;               // kept record, not recomputed
   const float load = a.load[n];
   float best_at = m ? -kInf : kInf;
   float best_sl = best_at;
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
     }
   }
   if (jl == 0) {
-    float* o = reinterpret_cast<float*>(a.rec + 3 * (size_t)n);
+    float* o = reinterpret_cast<float*>(a.rec + 3 * (size_t)slot);
     o[k] = best_at;
     o[4 + k] = best_sl;
     if (m) o[8 + t] = a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("");
@@ -558,6 +562,7 @@ struct BwdArgs {
   const float4* __restrict__ rec;
   const float2* __restrict__ wire;
   const float* __restrict__ load;
+  const int* __restrict__ loc;       // record slot of each net, NULL: slot = net
   float4* ratp;
   float4* adjp;
   float4* __restrict__ at_out;
@@ -710,8 +715,9 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   if (gs.active) {
     p0 = a.net_off[n];
     p1 = a.net_off[n + 1];
-    at_d = a.rec[3 * (size_t)n];
-    sl_d = a.rec[3 * (size_t)n + 1];
+    const int slot = a.loc ? a.loc[n] : n;
+    at_d = a.rec[3 * (size_t)slot];
+    sl_d = a.rec[3 * (size_t)slot + 1];
     if (a.grad) {
       const int q = a.io_perm ? a.io_perm[p0] : p0;
       xd = a.x[q];
@@ -938,7 +944,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
     k_rc<<<range_grid(g->all_range), kBlock, 0, s>>>(ra);
   }
 
-  FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), g->N0, gamma_ps,
+  FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), d.rec_loc, g->N0, 0, gamma_ps,
              smooth ? 1.0f / gamma_ps : 0.f, smooth ? 1 : 0};
   for (int l = 1; l < g->L; ++l) {
     const Slots sl = level_slots(g, l);
@@ -995,14 +1001,36 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
   }
 
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
-             rec, wire, load, ratp, adjp, reinterpret_cast<float4*>(out->at), reinterpret_cast<float4*>(out->slew),
-             reinterpret_cast<float4*>(out->rat), reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
+             rec, wire, load, d.rec_loc, ratp, adjp, reinterpret_cast<float4*>(out->at),
+             reinterpret_cast<float4*>(out->slew), reinterpret_cast<float4*>(out->rat),
+             reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
-  for (int l = g->L - 1; l >= 0; --l) {
+  auto bwd_level = [&](int l) {
     const unsigned blocks = range_grid(g->lvl_ranges[l]);
-    if (blocks == 0) continue;
+    if (blocks == 0) return;
     LaunchTimer t(g, s, STA_K_BWD_LEVEL);
     k_bwd_level<<<blocks, kBlock, 0, s>>>(ba, g->lvl_ranges[l], level_slots(g, l));
+  };
+  if (g->ckpt_stride <= 0) {
+    for (int l = g->L - 1; l >= 0; --l) bwd_level(l);
+  } else {
+    // Segments last to first: rebuild the records the forward dropped (the kept ones are
+    // left alone), then that segment's backward levels.  The recomputation needs the
+    // smoothed arrival only where the gradient reads it.
+    FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), d.rec_loc, g->N0, g->n_kept, gamma_ps,
+               grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
+    for (int j = (int)g->seg_lo.size() - 2; j >= 0; --j) {
+      const int lo = g->seg_lo[j], hi = g->seg_lo[j + 1];
+      for (int l = lo; l < hi; ++l) {
+        const Slots sl = level_slots(g, l);
+        const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
+        if (blocks == 0) continue;
+        LaunchTimer t(g, s, STA_K_RECOMPUTE);
+        k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, sl);
+      }
+      for (int l = hi - 1; l >= lo; --l) bwd_level(l);
+    }
+    bwd_level(0);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward launch");
@@ -1070,6 +1098,9 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
   if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
   if ((flags & STA_SMOOTH) && !(gamma_ps > 0.f && std::isfinite(gamma_ps)))
     return fail(STA_E_INVALID, "gamma must be positive");
+  if (g->ckpt_stride > 0 && (out->at || out->slew || out->atg))
+    return fail(STA_E_INVALID, "per-pin forward outputs need the full arrival state; with checkpointing take "
+                               "them from sta_backward");
   const std::vector<uint64_t> key{ptr(x), ptr(y), ptr(out->state), ptr(out->at), ptr(out->slew), ptr(out->atg),
                                   ptr(out->scalars), flags, bits(gamma_ps)};
   const sta_fwd_out o = *out;

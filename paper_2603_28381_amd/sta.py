@@ -29,10 +29,11 @@ STA_GRAPH = 1 << 5
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
             "sta_forward", "sta_backward", "sta_get_schedule", "sta_set_schedule", "sta_tune",
+            "sta_set_checkpointing", "sta_get_checkpointing",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
-KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level"]
+KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level", "recompute"]
 
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -123,6 +124,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_set_schedule.restype = S
     lib.sta_tune.argtypes = [_P, _P, _P, ctypes.c_float, ctypes.c_int32, ctypes.POINTER(StaSchedule), _P]
     lib.sta_tune.restype = S
+    lib.sta_set_checkpointing.argtypes = [_P, ctypes.c_int32]
+    lib.sta_set_checkpointing.restype = S
+    lib.sta_get_checkpointing.argtypes = [_P, _I32P, _I32P, _I32P]
+    lib.sta_get_checkpointing.restype = S
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_enable.restype = S
     lib.sta_profile_read.argtypes = [_P, _P, _P]
@@ -291,6 +296,15 @@ class Graph:
         _check(_lib.sta_tune(self._h, _ptr(x), _ptr(y), float(gamma), int(reps), ctypes.byref(sch),
                              _stream_handle(stream)))
         return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
+
+    def set_checkpointing(self, stride_levels: int = -1):
+        """Per-level checkpointing of the arrival state: 0 off, < 0 picks ceil(sqrt(L-1))."""
+        _check(_lib.sta_set_checkpointing(self._h, int(stride_levels)))
+
+    def checkpointing(self) -> dict:
+        k, slots, kept = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.sta_get_checkpointing(self._h, ctypes.byref(k), ctypes.byref(slots), ctypes.byref(kept)))
+        return dict(stride_levels=k.value, record_slots=slots.value, kept_nets=kept.value)
 
     def profile(self, on: bool = True):
         _check(_lib.sta_profile_enable(self._h, 1 if on else 0))

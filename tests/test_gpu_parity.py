@@ -323,3 +323,41 @@ def test_tune_keeps_a_valid_schedule():
     got = gpu_run(d, graph=g)
     check_values(d, got, ref)
     check_grad(got, ref, 1e-3, 1e-6)
+
+
+def _ckpt_run(g, d, wns=False):
+    x = torch.tensor(d.x, device="cuda")
+    y = torch.tensor(d.y, device="cuda")
+    f = g.forward(x, y, gamma=GAMMA)
+    o = g.backward(x, y, f, rat=True, grad=True, wns=wns, pins=True)
+    o2 = g.backward(x, y, f, rat=True, grad=True, wns=wns, pins=True)     # a second backward on one state
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in o.items()}
+    res["scalars"] = f.scalars.cpu().numpy()
+    for k, v in o2.items():
+        assert np.array_equal(res[k], v.cpu().numpy(), equal_nan=True), ("second backward", k)
+    return res
+
+
+@pytest.mark.parametrize("wns", [False, True])
+def test_checkpointed_backward_equals_plain_bitwise(wns):
+    from paper_2603_28381_amd.sta import StaError
+    d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    plain = _ckpt_run(g, d, wns)
+    L = g.info()["n_levels"]
+    for k in (1, 3, -1, L + 5):
+        g.set_checkpointing(k)
+        info = g.checkpointing()
+        print(f"stride {info['stride_levels']}: {info['record_slots']} of {d.n_nets} records "
+              f"({info['kept_nets']} kept)")
+        got = _ckpt_run(g, d, wns)
+        for key in plain:
+            assert np.array_equal(got[key], plain[key], equal_nan=True), (k, key)
+    with pytest.raises(StaError):
+        g.forward(torch.tensor(d.x, device="cuda"), torch.tensor(d.y, device="cuda"), pins=True)
+    g.set_checkpointing(0)
+    again = _ckpt_run(g, d, wns)
+    for key in plain:
+        assert np.array_equal(again[key], plain[key], equal_nan=True), key

@@ -10,7 +10,7 @@ import pytest
 from gen.netlist import CFG0, CFG1, make_design, tiny_spec
 from oracle import sta_oracle as O
 from paper_2603_28381_amd import sta as S
-from tests._designs import PIN_CELL_IN, PIN_CELL_OUT, PIN_PI, PIN_PO, build
+from tests._designs import PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D, PIN_PI, PIN_PO, build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -193,3 +193,43 @@ def test_batch_rejects_mismatched_constraints():
     with pytest.raises(S.StaError) as e:
         S.Graph.batch([S.Graph.from_design(d0), S.Graph.from_design(d1)])
     assert e.value.code == S.STA_E_INVALID
+
+
+def _expected_checkpoint_counts(d, k):
+    """Kept nets and record slots of checkpointing with stride k, from the netlist itself."""
+    lv = O.levelize(d)
+    N, lvl, L = d.n_nets, lv.level, lv.n_levels
+    net_of_pin = np.empty(d.n_pins, np.int64)
+    net_of_pin[d.net_pins] = np.repeat(np.arange(N), np.diff(d.net_offsets))
+    reader_level = lvl[net_of_pin[d.cell_out_pin]]                      # level of each cell
+    cell_of_input = np.repeat(np.arange(d.n_cells), np.diff(d.cell_in_offsets))
+    maxc = np.full(N, -1)
+    np.maximum.at(maxc, net_of_pin[d.cell_in_pins], reader_level[cell_of_input])
+    seg_end = np.where(lvl == 0, 1, 1 + k * ((lvl - 1) // k + 1))
+    drives_ep = np.zeros(N, bool)
+    drives_ep[net_of_pin[(d.pin_kind == PIN_FF_D) | (d.pin_kind == PIN_PO)]] = True
+    kept = (lvl == 0) | (maxc >= seg_end) | drives_ep
+    seg = (lvl - 1) // k
+    widest = max([int(np.count_nonzero(~kept & (lvl >= 1) & (seg == j))) for j in range((L - 2) // k + 1)] + [0])
+    return int(kept.sum()), int(kept.sum()) + widest
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 100])
+def test_checkpoint_frontier_counts(k):
+    d = make_design(CFG0)
+    g = S.Graph.from_design(d)
+    with pytest.raises(S.StaError) as e:
+        g.set_checkpointing(k)
+    assert e.value.code == S.STA_E_STATE
+    L = g.levelize()
+    full = g.info()["fwd_state_bytes"]
+    assert g.checkpointing() == dict(stride_levels=0, record_slots=d.n_nets, kept_nets=d.n_nets)
+    g.set_checkpointing(k)
+    kept, slots = _expected_checkpoint_counts(d, k)
+    assert g.checkpointing() == dict(stride_levels=k, record_slots=slots, kept_nets=kept)
+    assert g.info()["fwd_state_bytes"] <= full - 48 * (d.n_nets - slots) + 256
+    g.set_checkpointing(-1)
+    assert g.checkpointing()["stride_levels"] == int(np.ceil(np.sqrt(L - 1)))
+    g.set_checkpointing(0)
+    assert g.info()["fwd_state_bytes"] == full
+    g.close()
