@@ -335,12 +335,131 @@ def checkpoint_comparison(g, x, y, P, dev, args) -> dict:
     return res
 
 
+def run_serve(args) -> dict:
+    """Served workload: 12 resident designs of 5k-2.5M pins (log-uniform), an open-loop
+    Poisson stream of requests (70% forward slack queries on resident coordinates, 30%
+    forward+backward gradient queries on coordinates jittered by N(0, 2 um)), admitted
+    against a 200 GB budget.  Latency runs from the scheduled arrival to the results being
+    on the host."""
+    import threading
+    import torch
+    from gen.netlist import batch_designs, jitter
+    from paper_2603_28381_amd import Graph, Server
+
+    t0 = time.time()
+    designs = batch_designs(12, 5_000, 2_500_000, cfg_id=4)
+    graphs = []
+    for d in designs:
+        g = Graph.from_design(d)
+        g.levelize()
+        graphs.append(g)
+    srv = Server(200 << 30, max_slots=args.serve_slots, queue_capacity=1 << 16)
+    ids = [srv.add_design(g, d.x, d.y) for g, d in zip(graphs, designs)]
+    n_jit = 4
+    jit = [[jitter(d, 2.0, stream=500 + j) for j in range(n_jit)] for d in designs]
+    rng = np.random.default_rng([260328381, 4, 77])
+    n_req = int(args.serve_rate * args.serve_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_rate, n_req))
+    which = rng.integers(len(designs), size=n_req)
+    grad = rng.random(n_req) < 0.3
+    t_setup = time.time() - t0
+    for i in ids:                                   # warm every design once
+        srv.wait(srv.submit(i, grad=True, x=jit[i][0][0], y=jit[i][0][1]))
+    tickets = [None] * n_req
+    lag = np.zeros(n_req)
+    results = [None] * n_req
+    sample_every = 100
+
+    def collect():
+        for r in range(n_req):
+            while tickets[r] is None:
+                time.sleep(0.0002)
+            res = srv.wait(tickets[r])
+            results[r] = (res["latency_ms"], res["queue_ms"], res["scalars"],
+                          (res.get("dx"), res.get("dy")) if r % sample_every == 0 else None)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    start = time.perf_counter()
+    for r in range(n_req):
+        due = start + arrivals[r]
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            time.sleep(min(due - now, 0.001))
+        k = int(which[r])
+        if grad[r]:
+            x, y = jit[k][r % n_jit]
+            tickets[r] = srv.submit(ids[k], grad=True, x=x, y=y)
+        else:
+            tickets[r] = srv.submit(ids[k], grad=False)
+        lag[r] = (time.perf_counter() - due) * 1e3
+    th.join()
+    elapsed = time.perf_counter() - start
+    srv.close()
+    lat = np.array([results[r][0] for r in range(n_req)]) + lag
+    qms = np.array([results[r][1] for r in range(n_req)])
+    pins = np.array([designs[int(k)].n_pins for k in which], np.float64)
+    checked = []
+    if not args.no_cpu_baseline and args.serve_check > 0:
+        from oracle import sta_oracle as O
+        c0 = time.perf_counter()
+        done = 0
+        cands = [r for r in range(0, n_req, sample_every)]
+        cands.sort(key=lambda r: designs[int(which[r])].n_pins)
+        for r in cands[:args.serve_check]:
+            k = int(which[r])
+            d = designs[k]
+            x, y = (jit[k][r % n_jit] if grad[r] else (d.x, d.y))
+            ref = O.run(d, x=x, y=y, gamma=10.0, grad="tns" if grad[r] else None)
+            sc = results[r][2]
+            ok = abs(sc[1] - ref["tns"]) <= 1e-4 * abs(ref["tns"]) + 1e-3 and \
+                abs(sc[3] - ref["tns_g"]) <= 1e-4 * abs(ref["tns_g"]) + 1e-3
+            if grad[r]:
+                gx = results[r][3][0].astype(np.float64)
+                ok = ok and bool(np.all(np.abs(gx - ref["dx"]) <= 1e-3 * np.abs(ref["dx"])
+                                        + 1e-6 * np.abs(ref["dx"]).max()))
+            checked.append(dict(request=r, pins=d.n_pins, grad=bool(grad[r]), ok=bool(ok)))
+            done += d.n_pins
+        cpu_s = time.perf_counter() - c0
+    value = pins.sum() / elapsed
+    return {
+        "metric": "served STA pins/sec with p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "pins/s",
+        "ms_per_step": round(float(np.percentile(lat, 50)), 4),
+        "dtype": "f32",
+        "config": {"workload": f"cfg4: {len(designs)} resident designs of {min(d.n_pins for d in designs)}-"
+                               f"{max(d.n_pins for d in designs)} pins, Poisson {args.serve_rate} req/s for "
+                               f"{args.serve_seconds} s, 30% fwd+bwd (jitter 2 um), budget 200 GB, "
+                               f"{args.serve_slots} slots",
+                   "designs_pins": [d.n_pins for d in designs], "requests": n_req},
+        "serving": {"p50_ms": round(float(np.percentile(lat, 50)), 4),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                    "max_ms": round(float(lat.max()), 4),
+                    "p99_queue_ms": round(float(np.percentile(qms, 99)), 4),
+                    "p99_submit_lag_ms": round(float(np.percentile(lag, 99)), 4),
+                    "fwd_p50_ms": round(float(np.percentile(lat[~grad], 50)), 4),
+                    "fwd_bwd_p50_ms": round(float(np.percentile(lat[grad], 50)), 4) if grad.any() else None,
+                    "achieved_req_per_s": round(n_req / elapsed, 2), "elapsed_s": round(elapsed, 3),
+                    "oracle_checked": checked},
+        "roofline": None,
+        "cpu_baseline": None,
+        "setup_s": round(t_setup, 2),
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-check", type=int, default=6, help="served results checked against the oracle")
     ap.add_argument("--gamma", type=float, default=10.0)
     ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")
     ap.add_argument("--no-ckpt-compare", dest="ckpt_compare", action="store_false",
@@ -352,7 +471,8 @@ def main(argv=None) -> int:
         print("bench.py measures one GPU: the STA sweep of one design runs on a single device "
               "(independent designs would be routed one per GPU); run with --gpus 1.", file=sys.stderr)
         return 2
-    res = run_batch(args) if args.workload == "cfg3" else run_single(args)
+    run = {"cfg3": run_batch, "cfg4": run_serve}.get(args.workload, run_single)
+    res = run(args)
     line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),

@@ -259,6 +259,72 @@ sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int
                                  int32_t* kept_nets);
 
 /* ---------------------------------------------------------------------------------------
+ * Serving: timing queries of resident designs with continuous batching.
+ *
+ * A server owns a scheduler thread, `max_slots` HIP streams (one per slot) and a
+ * stream-ordered device memory pool.  Designs are added once and stay resident in HBM
+ * (topology, library tables and their placement coordinates).  Clients submit requests
+ * from any thread; each request is one forward sweep (slack query: WNS, TNS and their
+ * smoothed forms) or one forward + backward sweep (also d TNS_g / dx, dy), optionally on
+ * new coordinates.  The scheduler admits queued requests in arrival order as soon as a slot
+ * is free and the request's device memory fits the budget beside everything already
+ * resident or in flight, so requests that arrive while others run start at once and their
+ * levels overlap on the device.  Each request runs the same launch sequence as the plain
+ * calls, so its result does not depend on what it ran beside.
+ * ------------------------------------------------------------------------------------- */
+typedef struct sta_server sta_server;
+
+typedef struct sta_server_config {
+  int64_t hbm_budget_bytes;    /* device memory for resident designs plus requests in flight */
+  int32_t max_slots;           /* requests on the device at once (1..64) */
+  int32_t queue_capacity;      /* requests waiting for admission before STA_E_BUSY (>= 1) */
+} sta_server_config;
+
+#define STA_REQ_FWD 0          /* forward sweep: scalars only */
+#define STA_REQ_FWD_BWD 1      /* forward + backward: scalars and the gradient of TNS_g */
+
+typedef struct sta_request {
+  int32_t design;              /* id from sta_server_add_design */
+  int32_t kind;                /* STA_REQ_FWD or STA_REQ_FWD_BWD */
+  const float* x;              /* host [n_pins] by original pin id, copied at submit; NULL: */
+  const float* y;              /*   the design's resident coordinates (both or neither) */
+  float gamma_ps;              /* LSE smoothing (> 0) */
+} sta_request;
+
+typedef struct sta_result {
+  int32_t kind;
+  int32_t n_pins;
+  double scalars[4];           /* WNS, TNS, WNS_g, TNS_g (ps) */
+  const float* dx;             /* host [n_pins] by original pin id (STA_REQ_FWD_BWD), owned */
+  const float* dy;             /*   by the server until sta_release; NULL otherwise */
+  double queue_ms;             /* submit -> admitted to a slot */
+  double latency_ms;           /* submit -> results on the host */
+} sta_result;
+
+/* Creates a server on the current device.  Errors: STA_E_INVALID for out-of-range fields,
+ * STA_E_DEVICE if the device lacks stream-ordered memory pools. */
+sta_status sta_server_create(const sta_server_config* cfg, sta_server** out);
+/* Makes a levelized graph resident (uploading it to the server's device if needed) with
+ * host coordinates x, y [n_pins] by original pin id.  The caller keeps g alive until
+ * sta_server_destroy and makes no other calls on it meanwhile.  Errors: STA_E_STATE (not
+ * levelized, or uploaded to another device), STA_E_NOMEM when the design does not fit the
+ * budget. */
+sta_status sta_server_add_design(sta_server* s, sta_graph* g, const float* x, const float* y, int32_t* id);
+/* Queues a request (non-blocking; copies x, y to pinned staging).  Errors: STA_E_INVALID,
+ * STA_E_NOMEM if the request can never fit the budget, STA_E_BUSY if the queue is full. */
+sta_status sta_submit(sta_server* s, const sta_request* r, uint64_t* ticket);
+/* STA_PENDING while queued or running; STA_OK with *r filled once done; the status of the
+ * failure if the request failed; STA_E_UNKNOWN_TICKET for a ticket never issued or released. */
+sta_status sta_poll(sta_server* s, uint64_t ticket, sta_result* r);
+/* Blocks until the ticket is done (or failed), then as sta_poll. */
+sta_status sta_wait(sta_server* s, uint64_t ticket, sta_result* r);
+/* Releases a finished ticket's result buffers, or cancels a queued one.  STA_E_BUSY for a
+ * request on the device, STA_E_UNKNOWN_TICKET otherwise. */
+sta_status sta_release(sta_server* s, uint64_t ticket);
+/* Waits for the requests on the device, drops queued ones and frees everything. */
+void sta_server_destroy(sta_server* s);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timing with HIP events (a profiling aid).  While enabled, every kernel launch that
  * sta_forward / sta_backward make for g is bracketed by two events on its stream.
  * sta_profile_read waits for those events and returns, per kernel family (STA_K_*), the

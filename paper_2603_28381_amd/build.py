@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsta.so")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["sta_host.cpp"]
+HOST_SOURCES = ["sta_host.cpp", "sta_server.cpp"]
 DEVICE_SOURCES = ["sta_kernels.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function",

@@ -25,11 +25,13 @@ STA_RAT = 1 << 2
 STA_GRAD = 1 << 3
 STA_GRAD_WNS = 1 << 4
 STA_GRAPH = 1 << 5
+STA_REQ_FWD, STA_REQ_FWD_BWD = 0, 1
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
             "sta_forward", "sta_backward", "sta_get_schedule", "sta_set_schedule", "sta_tune",
-            "sta_set_checkpointing", "sta_get_checkpointing",
+            "sta_set_checkpointing", "sta_get_checkpointing", "sta_server_create", "sta_server_add_design",
+            "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
@@ -67,6 +69,22 @@ class StaGraphInfo(ctypes.Structure):
 class StaSchedule(ctypes.Structure):
     _fields_ = [("sweep_group_log2", ctypes.c_int32), ("flat_group_log2", ctypes.c_int32),
                 ("heavy_sinks", ctypes.c_int32)]
+
+
+class StaServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32)]
+
+
+class StaRequest(ctypes.Structure):
+    _fields_ = [("design", ctypes.c_int32), ("kind", ctypes.c_int32), ("x", _P), ("y", _P),
+                ("gamma_ps", ctypes.c_float)]
+
+
+class StaResult(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_pins", ctypes.c_int32), ("scalars", ctypes.c_double * 4),
+                ("dx", ctypes.POINTER(ctypes.c_float)), ("dy", ctypes.POINTER(ctypes.c_float)),
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
 
 
 class StaFwdOut(ctypes.Structure):
@@ -128,6 +146,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_set_checkpointing.restype = S
     lib.sta_get_checkpointing.argtypes = [_P, _I32P, _I32P, _I32P]
     lib.sta_get_checkpointing.restype = S
+    lib.sta_server_create.argtypes = [ctypes.POINTER(StaServerConfig), ctypes.POINTER(_P)]
+    lib.sta_server_create.restype = S
+    lib.sta_server_add_design.argtypes = [_P, _P, _P, _P, _I32P]
+    lib.sta_server_add_design.restype = S
+    lib.sta_submit.argtypes = [_P, ctypes.POINTER(StaRequest), ctypes.POINTER(ctypes.c_uint64)]
+    lib.sta_submit.restype = S
+    for name in ("sta_poll", "sta_wait"):
+        getattr(lib, name).argtypes = [_P, ctypes.c_uint64, ctypes.POINTER(StaResult)]
+        getattr(lib, name).restype = S
+    lib.sta_release.argtypes = [_P, ctypes.c_uint64]
+    lib.sta_release.restype = S
+    lib.sta_server_destroy.argtypes = [_P]
+    lib.sta_server_destroy.restype = None
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_enable.restype = S
     lib.sta_profile_read.argtypes = [_P, _P, _P]
@@ -376,6 +407,78 @@ class Graph:
         _check(_lib.sta_backward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), ctypes.byref(bo), flags,
                                  float(fwd.gamma), _stream_handle(stream)))
         return out
+
+
+class Server:
+    """Serving loop of libsta: resident designs, admission against a device-memory budget
+    and continuous batching of requests (the C server's scheduler thread runs them)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, queue_capacity: int = 4096):
+        load_library()
+        cfg = StaServerConfig(int(hbm_budget_bytes), int(max_slots), int(queue_capacity))
+        h = _P()
+        _check(_lib.sta_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._graphs = []
+
+    def add_design(self, graph: Graph, x, y) -> int:
+        """Make a levelized graph resident with host coordinates (original pin order)."""
+        xa = np.ascontiguousarray(x, dtype=np.float32)
+        ya = np.ascontiguousarray(y, dtype=np.float32)
+        i = ctypes.c_int32()
+        _check(_lib.sta_server_add_design(self._h, graph.handle, xa.ctypes.data, ya.ctypes.data, ctypes.byref(i)))
+        self._graphs.append(graph)
+        return i.value
+
+    def submit(self, design: int, grad: bool = False, x=None, y=None, gamma: float = 10.0) -> int:
+        xa = ya = None
+        if x is not None:
+            xa = np.ascontiguousarray(x, dtype=np.float32)
+            ya = np.ascontiguousarray(y, dtype=np.float32)
+        r = StaRequest(int(design), STA_REQ_FWD_BWD if grad else STA_REQ_FWD,
+                       None if xa is None else xa.ctypes.data, None if ya is None else ya.ctypes.data, float(gamma))
+        t = ctypes.c_uint64()
+        _check(_lib.sta_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _result(r: StaResult) -> dict:
+        out = dict(scalars=np.array(r.scalars[:], np.float64), queue_ms=r.queue_ms, latency_ms=r.latency_ms,
+                   kind=r.kind)
+        if r.dx:
+            out["dx"] = np.ctypeslib.as_array(r.dx, (r.n_pins,)).copy()
+            out["dy"] = np.ctypeslib.as_array(r.dy, (r.n_pins,)).copy()
+        return out
+
+    def poll(self, ticket: int) -> dict | None:
+        r = StaResult()
+        code = _lib.sta_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if code == STA_PENDING:
+            return None
+        _check(code)
+        return self._result(r)
+
+    def wait(self, ticket: int, release: bool = True) -> dict:
+        r = StaResult()
+        _check(_lib.sta_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(r)))
+        out = self._result(r)
+        if release:
+            self.release(ticket)
+        return out
+
+    def release(self, ticket: int):
+        _check(_lib.sta_release(self._h, ctypes.c_uint64(ticket)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.sta_server_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SmoothedSlack(torch.autograd.Function):

@@ -1,0 +1,150 @@
+"""GPU tests of the serving loop (C server through the C ABI): results in a mix of
+concurrent requests equal the same requests run alone, admission under a tight budget."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from gen.netlist import CFG0, jitter, make_design, scaled_spec
+from oracle import sta_oracle as O
+from paper_2603_28381_amd import Graph, Server, StaError
+from paper_2603_28381_amd import sta as S
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 10.0
+
+
+def _designs():
+    ds = [make_design(CFG0), make_design(scaled_spec(20_000, cfg_id=46, box_um=700.0)),
+          make_design(scaled_spec(5_000, cfg_id=47, box_um=300.0))]
+    gs = []
+    for d in ds:
+        g = Graph.from_design(d)
+        g.levelize()
+        gs.append(g)
+    return ds, gs
+
+
+def _requests(ds, n=36):
+    rng = np.random.default_rng(7)
+    reqs = []
+    for i in range(n):
+        k = int(rng.integers(len(ds)))
+        grad = bool(rng.random() < 0.4)
+        xy = jitter(ds[k], 2.0, stream=100 + i) if rng.random() < 0.5 else None
+        reqs.append((k, grad, xy))
+    return reqs
+
+
+def _alone(g, d, grad, xy):
+    x = torch.tensor(d.x if xy is None else xy[0], device="cuda")
+    y = torch.tensor(d.y if xy is None else xy[1], device="cuda")
+    f = g.forward(x, y, gamma=GAMMA)
+    res = {}
+    if grad:
+        o = g.backward(x, y, f, rat=False, grad=True, pins=False)
+        res["dx"], res["dy"] = o["dx"].cpu().numpy(), o["dy"].cpu().numpy()
+    torch.cuda.synchronize()
+    res["scalars"] = f.scalars.cpu().numpy()
+    return res
+
+
+def _serve(ds, gs, reqs, budget, slots=4):
+    srv = Server(budget, max_slots=slots)
+    ids = [srv.add_design(g, d.x, d.y) for g, d in zip(gs, ds)]
+    tickets = []
+    for k, grad, xy in reqs:
+        tickets.append(srv.submit(ids[k], grad=grad, x=None if xy is None else xy[0],
+                                  y=None if xy is None else xy[1], gamma=GAMMA))
+    out = [srv.wait(t) for t in tickets]
+    srv.close()
+    return out
+
+
+def _same(a, b):
+    assert np.array_equal(a["scalars"], b["scalars"])
+    assert ("dx" in a) == ("dx" in b)
+    if "dx" in a:
+        assert np.array_equal(a["dx"], b["dx"]) and np.array_equal(a["dy"], b["dy"])
+
+
+def test_served_mix_equals_requests_run_alone():
+    ds, gs = _designs()
+    reqs = _requests(ds)
+    served = _serve(ds, gs, reqs, budget=8 << 30, slots=4)
+    lat = np.array([r["latency_ms"] for r in served])
+    print(f"latency p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    for (k, grad, xy), r in zip(reqs, served):
+        _same(r, _alone(gs[k], ds[k], grad, xy))
+    # One served gradient against the FP64 oracle.
+    i = next(i for i, (k, grad, xy) in enumerate(reqs) if k == 0 and grad and xy is None)
+    ref = O.run(ds[0], gamma=GAMMA, grad="tns")
+    assert served[i]["scalars"][3] == pytest.approx(ref["tns_g"], rel=1e-4, abs=1e-3)
+    g, r = served[i]["dx"].astype(np.float64), ref["dx"]
+    assert np.all(np.abs(g - r) <= 1e-3 * np.abs(r) + 1e-6 * np.abs(r).max())
+
+
+def _need(g, grad, new_xy):
+    a = lambda v: (v + 255) // 256 * 256
+    info = g.info()
+    P = info["n_pins"]
+    b = a(info["fwd_state_bytes"]) + a(32)
+    if grad:
+        b += a(info["bwd_workspace_bytes"]) + 2 * a(4 * P)
+    if new_xy:
+        b += 2 * a(4 * P)
+    return b
+
+
+def test_tight_budget_queues_and_keeps_results():
+    ds, gs = _designs()
+    reqs = _requests(ds, n=16)
+    wide = _serve(ds, gs, reqs, budget=8 << 30, slots=4)
+    for g in gs:
+        g.upload()
+    resident = sum(g.info()["device_bytes"] + 8 * g.info()["n_pins"] for g in gs)
+    one = max(_need(gs[k], grad, xy is not None) for k, grad, xy in reqs)
+    narrow = _serve(ds, gs, reqs, budget=resident + one, slots=4)   # one request at a time
+    for a, b in zip(wide, narrow):
+        _same(a, b)
+    assert max(r["queue_ms"] for r in narrow) > 0.0
+    # A request that can never fit, and a design that does not fit.
+    srv = Server(resident + 1024, max_slots=2)
+    ids = [srv.add_design(g, d.x, d.y) for g, d in zip(gs, ds)]
+    with pytest.raises(StaError) as e:
+        srv.submit(ids[0], grad=True)
+    assert e.value.code == S.STA_E_NOMEM
+    with pytest.raises(StaError) as e:
+        srv.add_design(gs[0], ds[0].x, ds[0].y)
+    assert e.value.code == S.STA_E_NOMEM
+    srv.close()
+
+
+def test_ticket_errors_and_full_queue():
+    d = make_design(scaled_spec(200_000, cfg_id=48, box_um=1500.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    srv = Server(8 << 30, max_slots=1, queue_capacity=1)
+    i = srv.add_design(g, d.x, d.y)
+    with pytest.raises(StaError) as e:
+        srv.poll(12345)
+    assert e.value.code == S.STA_E_UNKNOWN_TICKET
+    tickets, busy = [], 0
+    for _ in range(5):
+        try:
+            tickets.append(srv.submit(i, grad=True))
+        except StaError as err:
+            assert err.code == S.STA_E_BUSY
+            busy += 1
+    assert busy >= 1
+    res = [srv.wait(t) for t in tickets]
+    for r in res[1:]:
+        _same(r, res[0])
+    with pytest.raises(StaError) as e:
+        srv.release(tickets[0])
+    assert e.value.code == S.STA_E_UNKNOWN_TICKET
+    with pytest.raises(StaError):
+        srv.submit(i, grad=False, gamma=-1.0)
+    srv.close()

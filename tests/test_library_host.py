@@ -1,6 +1,7 @@
 """Host-side checks of libsta (no GPU): exported ABI, bit-exact levelization, input validation."""
 from __future__ import annotations
 
+import ctypes
 import os
 import re
 
@@ -233,3 +234,15 @@ def test_checkpoint_frontier_counts(k):
     g.set_checkpointing(0)
     assert g.info()["fwd_state_bytes"] == full
     g.close()
+
+
+def test_server_rejects_bad_configuration():
+    lib = S.load_library()
+    h = S._P()
+    for cfg in ((0, 4, 16), (1 << 30, 0, 16), (1 << 30, 65, 16), (1 << 30, 4, 0)):
+        c = S.StaServerConfig(*cfg)
+        assert lib.sta_server_create(ctypes.byref(c), ctypes.byref(h)) == S.STA_E_INVALID
+    assert lib.sta_submit(None, None, None) == S.STA_E_INVALID
+    assert lib.sta_poll(None, 1, None) == S.STA_E_INVALID
+    assert lib.sta_release(None, 1) == S.STA_E_INVALID
+    lib.sta_server_destroy(None)
