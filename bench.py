@@ -73,6 +73,31 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict
     return out
 
 
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel sources (kernels and their shared header)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sta_kernels.hip", "sta_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_28381_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(kernel: str) -> float | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary of the 2.5M-pin sweep, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "sta_sweep_2p5Mpins_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic_bytes_per_launch" and f[1] == kernel and f[3] == "kernel_source":
+                return float(f[2]) if f[4] == want else None
+    return None
+
+
 def kernel_table(prof: dict, alg: dict, steps: int) -> tuple[dict, dict]:
     """Per-kernel launch statistics and the roofline entry of the dominant kernel."""
     kernels = {}
@@ -265,6 +290,8 @@ def run_single(args) -> dict:
         prof = g.profile_read()
         g.profile(False)
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
+        if args.workload == "cfg2":
+            roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
 
     ckpt = None
     if args.ckpt_compare:
@@ -464,6 +491,8 @@ def main(argv=None) -> int:
     ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")
     ap.add_argument("--no-ckpt-compare", dest="ckpt_compare", action="store_false",
                     help="skip the gradient-step comparison with per-level checkpointing")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device copy of this size (a reference for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
     args = ap.parse_args(argv)
@@ -471,6 +500,14 @@ def main(argv=None) -> int:
         print("bench.py measures one GPU: the STA sweep of one design runs on a single device "
               "(independent designs would be routed one per GPU); run with --gpus 1.", file=sys.stderr)
         return 2
+    if args.copy_probe_mb > 0:
+        import torch
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     run = {"cfg3": run_batch, "cfg4": run_serve}.get(args.workload, run_single)
     res = run(args)
     line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,

@@ -325,10 +325,11 @@ sta_status sta_release(sta_server* s, uint64_t ticket);
 void sta_server_destroy(sta_server* s);
 
 /* ---------------------------------------------------------------------------------------
- * Kernel timing with HIP events (a profiling aid).  While enabled, every kernel launch that
- * sta_forward / sta_backward make for g is bracketed by two events on its stream.
- * sta_profile_read waits for those events and returns, per kernel family (STA_K_*), the
- * number of launches and their summed duration in milliseconds since the last enable;
+ * Kernel timing with HIP events (a profiling aid).  While enabled, each run of consecutive
+ * launches of one kernel family that sta_forward / sta_backward make for g (for example
+ * all backward levels) is bracketed by two events on its stream, and hipGraph replay is
+ * off.  sta_profile_read waits for those events and returns, per kernel family (STA_K_*),
+ * the number of launches and their summed duration in milliseconds since the last enable;
  * the arrays hold STA_K_COUNT entries.  Errors: STA_E_DEVICE.
  * ------------------------------------------------------------------------------------- */
 #define STA_K_RC 0           /* RC net delay, all nets */

@@ -39,7 +39,7 @@ void compute_layouts(sta_graph* g) {
     g->ep_blk_off[d + 1] = g->ep_blk_off[d] + (e + kBlock - 1) / kBlock;
   }
   g->n_ep_blocks = g->ep_blk_off[g->n_designs];
-  g->state.rec = take(sizeof(float4) * 3 * (size_t)std::max(1, g->n_rec));
+  g->state.rec = take(sizeof(float4) * 4 * (size_t)std::max(1, g->n_rec));
   g->state.wire = take(sizeof(float2) * (size_t)g->P);
   g->state.load = take(sizeof(float) * (size_t)g->N);
   g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
@@ -706,6 +706,7 @@ void sta_graph_destroy(sta_graph* g) {
     (void)hipEventDestroy(t.stop);
   }
   for (hipEvent_t e : g->event_pool) (void)hipEventDestroy(e);
+  if (g->run_start) (void)hipEventDestroy(g->run_start);
   free_device(g);
   delete g;
 }

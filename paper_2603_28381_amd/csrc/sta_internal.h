@@ -48,7 +48,8 @@ struct LutKeys {
 
 // Byte offsets of the pieces of the forward state buffer.
 struct StateLayout {
-  size_t rec;      // float4[3 * record slots]: per net {at[4]}, {slew[4]}, {atg[2], 0, 0}
+  size_t rec;      // float4[4 * record slots]: per net and condition k {AT, slew, smoothed AT
+                   // (late k; 0 for early k), 0}
   size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
   size_t load;     // float[N]: root load of each net (Eq. 1)
   size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
@@ -137,8 +138,12 @@ struct sta_graph {
 
   // Event timing of launches (sta_profile_enable).
   bool profiling = false;
-  struct TimedLaunch { int kind; hipEvent_t start, stop; };
+  // A run of consecutive launches of one kind, bracketed by one event pair.
+  struct TimedLaunch { int kind; int count; hipEvent_t start, stop; };
   std::vector<TimedLaunch> timed;
+  int run_kind = -1;                 // kind of the open run, -1 if none
+  int run_count = 0;
+  hipEvent_t run_start = nullptr;
   std::vector<hipEvent_t> event_pool;
 };
 

@@ -2,12 +2,13 @@
 // that launch them (sta_forward, sta_backward).
 //
 // Data layout (canonical order from sta_levelize): nets sorted by (level, pins), pins
-// net-major with the driver first.  The forward sweep keeps one 48-byte record per net -
-// the driver's arrival time and slew for the four conditions and its smoothed late
-// arrival - and derives a sink's state on demand from its driver record plus the sink's
-// {wire delay, impulse}.  A level therefore gathers one record per cell input and writes
-// one record per net; per-pin outputs are written by the backward sweep, which visits
-// every pin anyway.
+// net-major with the driver first.  The forward sweep keeps one 64-byte record per net -
+// per timing condition a 16-byte chunk {arrival time, slew, smoothed arrival (late
+// conditions), 0} of the driver - and derives a sink's state on demand from its driver
+// record plus the sink's {wire delay, impulse}.  A lane serving one condition of a cell
+// input therefore gathers one aligned chunk, and the four condition lanes of an input
+// share one 64-byte line.  A level writes one record per net; per-pin outputs are written
+// by the backward sweep, which visits every pin anyway.
 //
 // Lane mapping (the pin-based scheme of Sec. 3.1, re-derived for 64-lane wavefronts).  A
 // level holds a few thousand nets, so a level kernel occupies about one wave per SIMD and
@@ -34,6 +35,7 @@ constexpr float kInf = __builtin_huge_valf();
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kCellLanes = 16;   // lanes per cell: 4 conditions x 4 arcs
 constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
+constexpr int kRecChunks = 4;    // float4 chunks per arrival record, one per condition
 
 // ---------------------------------------------------------------------------- helpers
 // Table cell of v along an axis: upper_bound(axis, v) - 1 clamped to [0, 5], computed as
@@ -258,10 +260,11 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     a.load[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
     a.wire[p0] = make_float2(0.f, 0.f);
     if (n < a.N0) {
-      float4* r = a.rec + 3 * (size_t)n;
-      r[0] = make_float4(a.pi_at, a.pi_at, a.pi_at, a.pi_at);
-      r[1] = make_float4(a.pi_slew, a.pi_slew, a.pi_slew, a.pi_slew);
-      r[2] = make_float4(a.pi_at, a.pi_at, 0.f, 0.f);
+      float4* r = a.rec + kRecChunks * (size_t)n;
+      r[0] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
+      r[1] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
+      r[2] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
+      r[3] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
     }
   }
 }
@@ -292,11 +295,11 @@ __device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const S
   r.tp = e.w > 0 ? t : 1 - t;
   r.pin = e.y;
   const int kp = 2 * m + r.tp;
-  const float* src = reinterpret_cast<const float*>(rec + 3 * (size_t)max(e.x, 0));
+  const float4 c = rec[kRecChunks * (size_t)max(e.x, 0) + kp];   // {AT, slew, smoothed AT} of kp
   const float2 w = wire[e.y];
-  r.at = src[kp] + w.x;
-  r.slew = sink_slew(src[4 + kp], w.y);
-  r.atg = src[8 + r.tp] + w.x;
+  r.at = c.x + w.x;
+  r.slew = sink_slew(c.y, w.y);
+  r.atg = c.z + w.x;
   return r;
 }
 
@@ -355,10 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
     }
   }
   if (jl == 0) {
-    float* o = reinterpret_cast<float*>(a.rec + 3 * (size_t)slot);
-    o[k] = best_at;
-    o[4 + k] = best_sl;
-    if (m) o[8 + t] = a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("");
+    const float ag = m ? (a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("")) : 0.f;
+    a.rec[kRecChunks * (size_t)slot + k] = make_float4(best_at, best_sl, ag, 0.f);
   }
 }
 
@@ -390,13 +391,14 @@ struct EpVals {
 
 __device__ __forceinline__ EpVals endpoint_values(const EpArgs& a, int i) {
   const int e = a.ep_pin[i];
-  const float* r = reinterpret_cast<const float*>(a.rec + 3 * (size_t)a.ep_net[i]);
+  const float4 c2 = a.rec[kRecChunks * (size_t)a.ep_net[i] + 2];   // late rise
+  const float4 c3 = a.rec[kRecChunks * (size_t)a.ep_net[i] + 3];   // late fall
   const float dl = a.wire[e].x;
   EpVals v;
-  v.worst = fminf(a.rat_late - (r[2] + dl), a.rat_late - (r[3] + dl));
+  v.worst = fminf(a.rat_late - (c2.x + dl), a.rat_late - (c3.x + dl));
   // s_e = -LSE(-slack_g(rise), -slack_g(fall))
-  const float u0 = -(a.rat_late - (r[8] + dl));
-  const float u1 = -(a.rat_late - (r[9] + dl));
+  const float u0 = -(a.rat_late - (c2.z + dl));
+  const float u1 = -(a.rat_late - (c3.z + dl));
   const float mx = fmaxf(u0, u1);
   const float e0 = expf((u0 - mx) * a.inv_gamma), e1 = expf((u1 - mx) * a.inv_gamma);
   const float z = e0 + e1;
@@ -537,7 +539,10 @@ __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
   if (!group_slot(a.range, gs) || !gs.active) return;
   const int n = a.sched[gs.entry];
   const int p0 = a.net_off[n], p1 = a.net_off[n + 1];
-  const float4 at = a.rec[3 * (size_t)n], sl = a.rec[3 * (size_t)n + 1], ag = a.rec[3 * (size_t)n + 2];
+  const float4 c0 = a.rec[kRecChunks * (size_t)n], c1 = a.rec[kRecChunks * (size_t)n + 1],
+               c2 = a.rec[kRecChunks * (size_t)n + 2], c3 = a.rec[kRecChunks * (size_t)n + 3];
+  const float4 at = make_float4(c0.x, c1.x, c2.x, c3.x), sl = make_float4(c0.y, c1.y, c2.y, c3.y);
+  const float2 ag = make_float2(c2.z, c3.z);
   for (int p = p0 + gs.gl; p < p1; p += gs.G) {
     const float2 w = a.wire[p];
     const int q = a.io_perm ? a.io_perm[p] : p;
@@ -716,8 +721,10 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     p0 = a.net_off[n];
     p1 = a.net_off[n + 1];
     const int slot = a.loc ? a.loc[n] : n;
-    at_d = a.rec[3 * (size_t)slot];
-    sl_d = a.rec[3 * (size_t)slot + 1];
+    const float4* r = a.rec + kRecChunks * (size_t)slot;
+    const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
+    at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
+    sl_d = make_float4(c0.y, c1.y, c2.y, c3.y);
     if (a.grad) {
       const int q = a.io_perm ? a.io_perm[p0] : p0;
       xd = a.x[q];
@@ -891,31 +898,42 @@ sta_status check_ready(sta_graph* g) {
   return STA_OK;
 }
 
-// Event pair around one launch while profiling is on (sta_profile_enable).
-struct LaunchTimer {
-  sta_graph* g;
-  hipStream_t s;
-  int kind;
-  hipEvent_t start = nullptr, stop = nullptr;
-  LaunchTimer(sta_graph* g_, hipStream_t s_, int kind_) : g(g_), s(s_), kind(kind_) {
-    if (!g->profiling) return;
-    start = take();
-    stop = take();
-    if (start && stop) (void)hipEventRecord(start, s);
+// Launch timing while profiling is on (sta_profile_enable).  Consecutive launches of one
+// kind form a run bracketed by one event pair, so that no event sits between two dependent
+// launches of a level loop: the per-launch average is then the kernels' own back-to-back
+// duration.  A run ends when a launch of another kind starts or the call ends (end_run).
+hipEvent_t take_event(sta_graph* g) {
+  if (!g->event_pool.empty()) {
+    hipEvent_t e = g->event_pool.back();
+    g->event_pool.pop_back();
+    return e;
   }
-  ~LaunchTimer() {
-    if (!start || !stop) return;
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void end_run(sta_graph* g, hipStream_t s) {
+  if (g->run_kind < 0) return;
+  hipEvent_t stop = take_event(g);
+  if (stop && g->run_start) {
     (void)hipEventRecord(stop, s);
-    g->timed.push_back({kind, start, stop});
+    g->timed.push_back({g->run_kind, g->run_count, g->run_start, stop});
   }
-  hipEvent_t take() {
-    if (!g->event_pool.empty()) {
-      hipEvent_t e = g->event_pool.back();
-      g->event_pool.pop_back();
-      return e;
+  g->run_kind = -1;
+  g->run_count = 0;
+  g->run_start = nullptr;
+}
+
+struct LaunchTimer {
+  LaunchTimer(sta_graph* g, hipStream_t s, int kind) {
+    if (!g->profiling) return;
+    if (g->run_kind != kind) {
+      end_run(g, s);
+      g->run_kind = kind;
+      g->run_start = take_event(g);
+      if (g->run_start) (void)hipEventRecord(g->run_start, s);
     }
-    hipEvent_t e = nullptr;
-    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    ++g->run_count;
   }
 };
 
@@ -972,6 +990,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
     LaunchTimer t(g, s, STA_K_EXPAND);
     k_expand<<<range_grid(g->all_range), kBlock, 0, s>>>(xa);
   }
+  if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return STA_OK;
@@ -1032,6 +1051,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     }
     bwd_level(0);
   }
+  if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return STA_OK;
@@ -1196,6 +1216,10 @@ extern "C" sta_status sta_profile_enable(sta_graph* g, int32_t on) {
     g->event_pool.push_back(t.stop);
   }
   g->timed.clear();
+  if (g->run_start) g->event_pool.push_back(g->run_start);
+  g->run_kind = -1;
+  g->run_count = 0;
+  g->run_start = nullptr;
   g->profiling = on != 0;
   return STA_OK;
 }
@@ -1212,7 +1236,7 @@ extern "C" sta_status sta_profile_read(sta_graph* g, int64_t* launches, double* 
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, t.start, t.stop);
     if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-    launches[t.kind] += 1;
+    launches[t.kind] += t.count;
     total_ms[t.kind] += ms;
   }
   return STA_OK;
