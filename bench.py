@@ -425,6 +425,31 @@ def run_serve(args) -> dict:
     th.join()
     elapsed = time.perf_counter() - start
     srv.close()
+
+    def burst(slots: int, n: int = 400) -> dict:
+        """Capacity: n requests of the same mix submitted at once, served with `slots` slots."""
+        b = Server(200 << 30, max_slots=slots, queue_capacity=1 << 16)
+        bid = [b.add_design(g, d.x, d.y) for g, d in zip(graphs, designs)]
+        for i in bid:
+            b.wait(b.submit(i, grad=True, x=jit[i][0][0], y=jit[i][0][1]))
+        t = time.perf_counter()
+        tk = []
+        for r in range(n):
+            k = int(which[r])
+            if grad[r]:
+                x, y = jit[k][r % n_jit]
+                tk.append(b.submit(bid[k], grad=True, x=x, y=y))
+            else:
+                tk.append(b.submit(bid[k], grad=False))
+        for q in tk:
+            b.wait(q)
+        dt = time.perf_counter() - t
+        b.close()
+        pp = float(sum(designs[int(which[r])].n_pins for r in range(n)))
+        return {"slots": slots, "requests": n, "s": round(dt, 4), "pins_per_s": round(pp / dt, 1)}
+
+    cap_many = burst(args.serve_slots)
+    cap_one = burst(1)
     lat = np.array([results[r][0] for r in range(n_req)]) + lag
     qms = np.array([results[r][1] for r in range(n_req)])
     pins = np.array([designs[int(k)].n_pins for k in which], np.float64)
@@ -470,6 +495,8 @@ def run_serve(args) -> dict:
                     "fwd_p50_ms": round(float(np.percentile(lat[~grad], 50)), 4),
                     "fwd_bwd_p50_ms": round(float(np.percentile(lat[grad], 50)), 4) if grad.any() else None,
                     "achieved_req_per_s": round(n_req / elapsed, 2), "elapsed_s": round(elapsed, 3),
+                    "capacity": cap_many, "capacity_one_at_a_time": cap_one,
+                    "capacity_speedup": round(cap_many["pins_per_s"] / cap_one["pins_per_s"], 3),
                     "oracle_checked": checked},
         "roofline": None,
         "cpu_baseline": None,
