@@ -23,7 +23,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
           f"-I{INCLUDE}", f"-I{CSRC}"]
 # Packed FP32 instructions are kept out of the device code on purpose.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics",
+          # Leading scalar kernel parameters are preloaded into SGPRs at wave launch.
+          "-mllvm", "-amdgpu-kernarg-preload-count=16"]
 
 
 def _hipcc() -> str:

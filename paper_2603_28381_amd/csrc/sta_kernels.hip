@@ -190,6 +190,37 @@ __device__ __forceinline__ bool group_slot(const GroupRange& r, GroupSlot& s) {
   return true;
 }
 
+// The same mapping for a level kernel, whose smallest group is 2^G0 >= 16 lanes, so that at
+// most three wave classes (16/32/64 lanes) exist.  The level's ranges arrive as scalars -
+// heavy nets [h0, h0 + nh), class c entries [e_c, e_{c+1}) on waves [w_c, w_{c+1}) with
+// w_0 = 0 - and the class is found without indexing an array.
+template <int G0>
+__device__ __forceinline__ bool level_slot(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2, int w3,
+                                           GroupSlot& s) {
+  if ((int)blockIdx.x < nh) {
+    s.block = true;
+    s.G = kBlock;
+    s.gl = threadIdx.x;
+    s.entry = h0 + (int)blockIdx.x;
+    s.active = true;
+    return true;
+  }
+  s.block = false;
+  const int wave = ((int)blockIdx.x - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= w3) return false;
+  const int c = (wave >= w1) + (wave >= w2);
+  const int eb = c == 0 ? e0 : (c == 1 ? e1 : e2);
+  const int ee = c == 0 ? e1 : (c == 1 ? e2 : e3);
+  const int wb = c == 0 ? 0 : (c == 1 ? w1 : w2);
+  const int lg = G0 + c;
+  s.G = 1 << lg;
+  s.gl = lane & (s.G - 1);
+  s.entry = eb + (wave - wb) * (64 >> lg) + (lane >> lg);
+  s.active = s.entry < ee;
+  return true;
+}
+
 inline unsigned range_grid(const GroupRange& r) {
   const int nh = r.cls_off[kNumClasses + 1] - r.cls_off[kNumClasses];
   return (unsigned)(nh + (r.wave_off[kNumClasses] + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -304,17 +335,12 @@ __device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const S
 }
 
 // ---------------------------------------------------------------------------- forward level
+// Arguments of a forward level that the first loads do not need.
 struct FwdArgs {
-  const int4* __restrict__ ell;      // padded cell-input slots {source net, sink pin, arc, unateness}
   const float2* __restrict__ wire;
-  const float* __restrict__ load;
-  float4* __restrict__ rec;
   const float4* __restrict__ grid;
   const float4* __restrict__ coef;
   LutKeys keys;
-  const int* __restrict__ loc;       // record slot of each net, NULL: slot = net
-  int N0;
-  int min_slot;                      // cells whose net's slot is below this are skipped
   float gamma, inv_gamma;
   int smooth;
 };
@@ -322,21 +348,30 @@ struct FwdArgs {
 // One level of forward propagation (Sec. 3.1.2).  16 lanes per cell: lane (k, j) looks up
 // arc j for condition k = 2*mode + transition; the 4 arc lanes of a condition then merge
 // by max (late) / min (early), worst slew, and log-sum-exp of the late candidates (Eq. 4).
-__global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
+// The values the first loads depend on come first, as scalar parameters, so that they are
+// preloaded into scalar registers at wave launch instead of read from the argument buffer:
+// the level's input slots (base, width, first cell, cell count), the level-0 net count,
+// the record slot map (NULL: slot = net) and the smallest slot recomputed (cells whose
+// net's record is below it are kept records and skipped).
+__global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int c0, int base, int F, int N0, int min_slot,
+                                                      const int4* __restrict__ ell, const float* __restrict__ loads,
+                                                      const int* __restrict__ loc, float4* __restrict__ rec,
+                                                      FwdArgs a) {
+  const Slots sl{base, F, c0, nc};
   const int gid = (int)(blockIdx.x * kBlock + threadIdx.x);
   const int kc = gid / kCellLanes;
   if (kc >= sl.nc) return;                     // uniform over the cell's 16 lanes
   const int lane = gid & (kCellLanes - 1);
   const int k = lane >> 2, jl = lane & 3, m = k >> 1, t = k & 1;
-  const int n = a.N0 + sl.c0 + kc;
-  const int slot = a.loc ? a.loc[n] : n;
-  if (slot < a.min_slot) return;               // kept record, not recomputed
-  const float load = a.load[n];
+  const int n = N0 + sl.c0 + kc;
+  const int slot = loc ? loc[n] : n;
+  if (slot < min_slot) return;                 // kept record, not recomputed
+  const float load = loads[n];
   float best_at = m ? -kInf : kInf;
   float best_sl = best_at;
   float lm = -kInf, ls = 0.f;
   for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
-    const ArcIn in = arc_input(a.ell, sl, kc, j0 + jl, a.rec, a.wire, m, t);
+    const ArcIn in = arc_input(ell, sl, kc, j0 + jl, rec, a.wire, m, t);
     float cand = m ? -kInf : kInf, s = cand, g = -kInf;
     if (in.valid) {
       const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
@@ -359,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(FwdArgs a, Slots sl) {
   }
   if (jl == 0) {
     const float ag = m ? (a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("")) : 0.f;
-    a.rec[kRecChunks * (size_t)slot + k] = make_float4(best_at, best_sl, ag, 0.f);
+    rec[kRecChunks * (size_t)slot + k] = make_float4(best_at, best_sl, ag, 0.f);
   }
 }
 
@@ -859,11 +894,18 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 }
 
 // One level of backward propagation: heavy nets first (one workgroup each), then waves of
-// 16-, 32- and 64-lane groups.
-__global__ __launch_bounds__(kBlock) void k_bwd_level(BwdArgs a, GroupRange rg, Slots sl) {
+// 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of the
+// first loads come first, as scalar parameters preloaded into scalar registers.
+template <int G0>
+__global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
+                                                      int w3, const int* __restrict__ net_off,
+                                                      const float4* __restrict__ rec, BwdArgs a0, Slots sl) {
   __shared__ float sh[kWavesPerBlock * N_ACC];
+  BwdArgs a = a0;
+  a.net_off = net_off;
+  a.rec = rec;
   GroupSlot gs;
-  if (!group_slot(rg, gs)) return;
+  if (!level_slot<G0>(nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
   if (gs.block || gs.G == 64) {
     bwd_net<64>(a, sl, gs, sh);
   } else if (gs.G == 32) {
@@ -962,13 +1004,13 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
     k_rc<<<range_grid(g->all_range), kBlock, 0, s>>>(ra);
   }
 
-  FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), d.rec_loc, g->N0, 0, gamma_ps,
-             smooth ? 1.0f / gamma_ps : 0.f, smooth ? 1 : 0};
+  const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, smooth ? 1.0f / gamma_ps : 0.f,
+                   smooth ? 1 : 0};
   for (int l = 1; l < g->L; ++l) {
     const Slots sl = level_slots(g, l);
     const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
-    k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, sl);
+    k_fwd_level<<<blocks, kBlock, 0, s>>>(sl.nc, sl.c0, sl.base, sl.F, g->N0, 0, d.ell, load, d.rec_loc, rec, fa);
   }
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
@@ -1025,10 +1067,25 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
              reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
   auto bwd_level = [&](int l) {
-    const unsigned blocks = range_grid(g->lvl_ranges[l]);
+    const GroupRange& r = g->lvl_ranges[l];
+    const unsigned blocks = range_grid(r);
     if (blocks == 0) return;
     LaunchTimer t(g, s, STA_K_BWD_LEVEL);
-    k_bwd_level<<<blocks, kBlock, 0, s>>>(ba, g->lvl_ranges[l], level_slots(g, l));
+    const int nh = r.cls_off[kNumClasses + 1] - r.cls_off[kNumClasses], h0 = r.cls_off[kNumClasses];
+    const int* c = r.cls_off;
+    const int* w = r.wave_off;
+    const Slots sl = level_slots(g, l);
+    switch (r.g0) {
+      case 4:
+        k_bwd_level<4><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        break;
+      case 5:
+        k_bwd_level<5><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        break;
+      default:
+        k_bwd_level<6><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        break;
+    }
   };
   if (g->ckpt_stride <= 0) {
     for (int l = g->L - 1; l >= 0; --l) bwd_level(l);
@@ -1036,8 +1093,8 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     // Segments last to first: rebuild the records the forward dropped (the kept ones are
     // left alone), then that segment's backward levels.  The recomputation needs the
     // smoothed arrival only where the gradient reads it.
-    FwdArgs fa{d.ell, wire, load, rec, d.lut_grid, d.lut_coef, lut_keys(g), d.rec_loc, g->N0, g->n_kept, gamma_ps,
-               grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
+    const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, grad ? 1.0f / gamma_ps : 0.f,
+                     grad ? 1 : 0};
     for (int j = (int)g->seg_lo.size() - 2; j >= 0; --j) {
       const int lo = g->seg_lo[j], hi = g->seg_lo[j + 1];
       for (int l = lo; l < hi; ++l) {
@@ -1045,7 +1102,8 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
         const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
         if (blocks == 0) continue;
         LaunchTimer t(g, s, STA_K_RECOMPUTE);
-        k_fwd_level<<<blocks, kBlock, 0, s>>>(fa, sl);
+        k_fwd_level<<<blocks, kBlock, 0, s>>>(sl.nc, sl.c0, sl.base, sl.F, g->N0, g->n_kept, d.ell, load,
+                                              d.rec_loc, rec, fa);
       }
       for (int l = hi - 1; l >= lo; --l) bwd_level(l);
     }
