@@ -430,19 +430,21 @@ def run_serve(args) -> dict:
         """Capacity: n requests of the same mix submitted at once, served with `slots` slots."""
         b = Server(200 << 30, max_slots=slots, queue_capacity=1 << 16)
         bid = [b.add_design(g, d.x, d.y) for g, d in zip(graphs, designs)]
-        for i in bid:
-            b.wait(b.submit(i, grad=True, x=jit[i][0][0], y=jit[i][0][1]))
+        def run_all():
+            tk = []
+            for r in range(n):
+                k = int(which[r])
+                if grad[r]:
+                    x, y = jit[k][r % n_jit]
+                    tk.append(b.submit(bid[k], grad=True, x=x, y=y))
+                else:
+                    tk.append(b.submit(bid[k], grad=False))
+            for q in tk:
+                b.wait(q)
+
+        run_all()                      # every slot captures its launch sequences
         t = time.perf_counter()
-        tk = []
-        for r in range(n):
-            k = int(which[r])
-            if grad[r]:
-                x, y = jit[k][r % n_jit]
-                tk.append(b.submit(bid[k], grad=True, x=x, y=y))
-            else:
-                tk.append(b.submit(bid[k], grad=False))
-        for q in tk:
-            b.wait(q)
+        run_all()
         dt = time.perf_counter() - t
         b.close()
         pp = float(sum(designs[int(which[r])].n_pins for r in range(n)))

@@ -261,16 +261,18 @@ sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int
 /* ---------------------------------------------------------------------------------------
  * Serving: timing queries of resident designs with continuous batching.
  *
- * A server owns a scheduler thread, `max_slots` HIP streams (one per slot) and a
- * stream-ordered device memory pool.  Designs are added once and stay resident in HBM
- * (topology, library tables and their placement coordinates).  Clients submit requests
- * from any thread; each request is one forward sweep (slack query: WNS, TNS and their
- * smoothed forms) or one forward + backward sweep (also d TNS_g / dx, dy), optionally on
- * new coordinates.  The scheduler admits queued requests in arrival order as soon as a slot
- * is free and the request's device memory fits the budget beside everything already
- * resident or in flight, so requests that arrive while others run start at once and their
- * levels overlap on the device.  Each request runs the same launch sequence as the plain
- * calls, so its result does not depend on what it ran beside.
+ * A server owns a scheduler thread and `max_slots` slots, each a HIP stream with a device
+ * buffer it keeps between requests (from a stream-ordered pool).  Designs are added once
+ * and stay resident in HBM (topology, library tables and their placement coordinates).
+ * Clients submit requests from any thread; each request is one forward sweep (slack query:
+ * WNS, TNS and their smoothed forms) or one forward + backward sweep (also d TNS_g / dx,
+ * dy), optionally on new coordinates.  The scheduler admits queued requests in arrival
+ * order as soon as a slot is free whose buffer holds the request, or can grow to hold it
+ * with the resident designs and every slot buffer within the budget; requests that arrive
+ * while others run start at once and their levels overlap on the device.  A slot captures
+ * the launch sequence of each (design, kind, coordinates, gamma) once into a hipGraph and
+ * replays it, so a request costs a few host calls.  It is the same launch sequence as the
+ * plain calls, so a result does not depend on what it ran beside.
  * ------------------------------------------------------------------------------------- */
 typedef struct sta_server sta_server;
 

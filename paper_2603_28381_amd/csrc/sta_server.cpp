@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -79,17 +80,30 @@ struct Ticket {
   double* hsc = nullptr; // pinned results
   float* hdx = nullptr;
   float* hdy = nullptr;
-  size_t need = 0;       // device bytes while on the device
-  void* dmem = nullptr;
+  size_t need = 0;       // device bytes of its buffers
   int slot = -1;
   Clock::time_point t_submit, t_admit, t_done;
 };
 
+// A slot runs one request at a time on its own stream, in a device buffer it keeps between
+// requests, with the launch sequence of each (design, kind, coordinates) captured once into
+// a hipGraph over that buffer and replayed afterwards.
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
   uint64_t ticket = 0;
   bool busy = false;
+  void* buf = nullptr;          // from the server's pool
+  size_t cap = 0;
+  std::map<std::tuple<int, int, int, uint32_t>, hipGraphExec_t> graphs;   // (design, kind, new x/y, gamma)
+};
+
+// Where a request's buffers sit inside its slot's buffer.
+struct Carve {
+  void* state;
+  double* sc;
+  void* ws;
+  float *dx, *dy, *x, *y;
 };
 
 }  // namespace
@@ -102,7 +116,7 @@ struct sta_server {
   std::vector<Slot> slots;
   std::vector<Design> designs;
   size_t resident = 0;        // bytes of designs (graph copies and coordinates)
-  size_t in_flight = 0;       // bytes of requests on the device
+  hipStream_t cap_stream = nullptr;   // captures the slots' launch sequences
   std::mutex mu;
   std::condition_variable wake;       // scheduler: new work or stop
   std::condition_variable finished;   // waiters: a ticket finished
@@ -120,68 +134,149 @@ struct sta_server {
     return b;
   }
 
-  // Issues a request's copies and sweeps on slot k's stream.  Called with mu held.  On a
-  // failure the request's memory goes back to the pool in stream order.
-  sta_status launch(uint64_t id, Ticket& t, int k) {
-    Slot& sl = slots[k];
-    hipError_t e = hipMallocFromPoolAsync(&t.dmem, t.need, pool, sl.s);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocFromPoolAsync");
-    sta_status st = enqueue(t, sl);
-    if (st != STA_OK) {
-      (void)hipFreeAsync(t.dmem, sl.s);
-      return st;
-    }
-    if ((e = hipFreeAsync(t.dmem, sl.s)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
-    if ((e = hipEventRecord(sl.done, sl.s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    sl.busy = true;
-    sl.ticket = id;
-    t.slot = k;
-    return STA_OK;
-  }
-
-  sta_status enqueue(Ticket& t, Slot& sl) {
-    const Design& d = designs[t.design];
-    hipError_t e;
-    char* p = static_cast<char*>(t.dmem);
-    auto carve = [&](size_t bytes) {
+  static Carve carve(void* base, const Design& d, int kind, bool new_xy) {
+    char* p = static_cast<char*>(base);
+    auto take = [&](size_t bytes) {
       char* r = p;
       p += align256(bytes);
       return r;
     };
-    void* state = carve(d.state_bytes);
-    double* sc = reinterpret_cast<double*>(carve(4 * sizeof(double)));
     const size_t fb = sizeof(float) * (size_t)d.P;
-    const float* x = d.x;
-    const float* y = d.y;
-    void* ws = nullptr;
-    float *dx = nullptr, *dy = nullptr;
-    if (t.kind == STA_REQ_FWD_BWD) {
-      ws = carve(d.work_bytes);
-      dx = reinterpret_cast<float*>(carve(fb));
-      dy = reinterpret_cast<float*>(carve(fb));
+    Carve c{};
+    c.state = take(d.state_bytes);
+    c.sc = reinterpret_cast<double*>(take(4 * sizeof(double)));
+    if (kind == STA_REQ_FWD_BWD) {
+      c.ws = take(d.work_bytes);
+      c.dx = reinterpret_cast<float*>(take(fb));
+      c.dy = reinterpret_cast<float*>(take(fb));
     }
-    if (t.hx) {
-      float* nx = reinterpret_cast<float*>(carve(fb));
-      float* ny = reinterpret_cast<float*>(carve(fb));
-      if ((e = hipMemcpyAsync(nx, t.hx, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(ny, t.hy, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess)
-        return hip_fail(e, "hipMemcpyAsync");
-      x = nx;
-      y = ny;
+    if (new_xy) {
+      c.x = reinterpret_cast<float*>(take(fb));
+      c.y = reinterpret_cast<float*>(take(fb));
     }
-    sta_fwd_out fo{state, nullptr, nullptr, nullptr, sc};
-    sta_status st = sta_forward(d.g, x, y, &fo, STA_SMOOTH, t.gamma, sl.s);
+    return c;
+  }
+
+  size_t held() const {
+    size_t b = 0;
+    for (const Slot& sl : slots) b += sl.cap;
+    return b;
+  }
+
+  void drop_graphs(Slot& sl) {
+    for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
+    sl.graphs.clear();
+  }
+
+  // Picks an idle slot for a request of `need` bytes and makes its buffer large enough,
+  // within the budget: an idle slot that already fits, else the idle slot with the largest
+  // buffer grown (to the largest request any resident design makes, when that fits the
+  // budget), releasing other idle slots' buffers if needed.  -1: wait for a slot to finish.
+  int pick_slot(size_t need) {
+    int fit = -1, grow = -1;
+    for (int i = 0; i < (int)slots.size(); ++i) {
+      const Slot& sl = slots[i];
+      if (sl.busy) continue;
+      if (sl.cap >= need && (fit < 0 || sl.cap < slots[fit].cap)) fit = i;
+      if (grow < 0 || sl.cap > slots[grow].cap) grow = i;
+    }
+    if (fit >= 0) return fit;
+    if (grow < 0) return -1;
+    const size_t budget = (size_t)cfg.hbm_budget_bytes;
+    size_t target = need;
+    for (const Design& d : designs) target = std::max(target, request_bytes(d, STA_REQ_FWD_BWD, true));
+    Slot& g = slots[grow];
+    auto others = [&] { return held() - g.cap; };
+    if (resident + others() + target > budget) target = need;
+    if (resident + others() + target > budget) {
+      for (Slot& sl : slots)                     // release idle buffers
+        if (&sl != &g && !sl.busy && sl.buf) {
+          drop_graphs(sl);
+          (void)hipFreeAsync(sl.buf, sl.s);
+          sl.buf = nullptr;
+          sl.cap = 0;
+        }
+      if (resident + others() + target > budget) return -1;
+    }
+    drop_graphs(g);
+    if (g.buf) (void)hipFreeAsync(g.buf, g.s);
+    g.buf = nullptr;
+    g.cap = 0;
+    hipError_t e = hipMallocFromPoolAsync(&g.buf, target, pool, g.s);
+    if (e != hipSuccess) {
+      g.buf = nullptr;
+      return -2;
+    }
+    g.cap = target;
+    return grow;
+  }
+
+  // The captured launch sequence of (design, kind, coordinates) over slot k's buffer.
+  sta_status graph_for(Slot& sl, const Ticket& t, hipGraphExec_t* out) {
+    uint32_t gb;
+    std::memcpy(&gb, &t.gamma, sizeof(gb));
+    const auto key = std::make_tuple(t.design, t.kind, t.hx ? 1 : 0, gb);
+    auto it = sl.graphs.find(key);
+    if (it != sl.graphs.end()) {
+      *out = it->second;
+      return STA_OK;
+    }
+    const Design& d = designs[t.design];
+    const Carve c = carve(sl.buf, d, t.kind, t.hx != nullptr);
+    const float* x = t.hx ? c.x : d.x;
+    const float* y = t.hx ? c.y : d.y;
+    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    sta_fwd_out fo{c.state, nullptr, nullptr, nullptr, c.sc};
+    sta_status st = sta_forward(d.g, x, y, &fo, STA_SMOOTH, t.gamma, cap_stream);
+    if (st == STA_OK && t.kind == STA_REQ_FWD_BWD) {
+      sta_bwd_out bo{c.ws, nullptr, nullptr, nullptr, nullptr, c.dx, c.dy, 1.0f, nullptr};
+      st = sta_backward(d.g, x, y, &fo, &bo, STA_GRAD, t.gamma, cap_stream);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap_stream, &graph);
+    if (st != STA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    sl.graphs.emplace(key, exec);
+    *out = exec;
+    return STA_OK;
+  }
+
+  // Issues a request on slot k: coordinates in, the captured sweeps, results out.  Called
+  // with mu held.
+  sta_status launch(uint64_t id, Ticket& t, int k) {
+    Slot& sl = slots[k];
+    const Design& d = designs[t.design];
+    const Carve c = carve(sl.buf, d, t.kind, t.hx != nullptr);
+    const size_t fb = sizeof(float) * (size_t)d.P;
+    hipError_t e;
+    hipGraphExec_t exec = nullptr;
+    sta_status st = graph_for(sl, t, &exec);
     if (st != STA_OK) return st;
-    if (t.kind == STA_REQ_FWD_BWD) {
-      sta_bwd_out bo{ws, nullptr, nullptr, nullptr, nullptr, dx, dy, 1.0f, nullptr};
-      st = sta_backward(d.g, x, y, &fo, &bo, STA_GRAD, t.gamma, sl.s);
-      if (st != STA_OK) return st;
-      if ((e = hipMemcpyAsync(t.hdx, dx, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(t.hdy, dy, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+    if (t.hx) {
+      if ((e = hipMemcpyAsync(c.x, t.hx, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess ||
+          (e = hipMemcpyAsync(c.y, t.hy, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     }
-    if ((e = hipMemcpyAsync(t.hsc, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+    if ((e = hipGraphLaunch(exec, sl.s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (t.kind == STA_REQ_FWD_BWD) {
+      if ((e = hipMemcpyAsync(t.hdx, c.dx, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
+          (e = hipMemcpyAsync(t.hdy, c.dy, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    }
+    if ((e = hipMemcpyAsync(t.hsc, c.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
       return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipEventRecord(sl.done, sl.s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    sl.busy = true;
+    sl.ticket = id;
+    t.slot = k;
     return STA_OK;
   }
 
@@ -215,23 +310,24 @@ struct sta_server {
           t.msg = sta_last_error();
           finish(t, kFailed);
         }
-        in_flight -= t.need;
         sl.busy = false;
         progress = true;
       }
       if (progress) finished.notify_all();
       // Admissions, in arrival order.
       while (!queue.empty()) {
-        int k = -1;
-        for (int i = 0; i < (int)slots.size(); ++i)
-          if (!slots[i].busy) {
-            k = i;
-            break;
-          }
-        if (k < 0) break;
         const uint64_t id = queue.front();
         Ticket& t = tickets[id];
-        if (resident + in_flight + t.need > (size_t)cfg.hbm_budget_bytes) break;
+        const int k = pick_slot(t.need);
+        if (k == -1) break;
+        if (k == -2) {
+          queue.pop_front();
+          t.err = fail(STA_E_NOMEM, "slot buffer allocation failed");
+          t.msg = sta_last_error();
+          finish(t, kFailed);
+          finished.notify_all();
+          continue;
+        }
         queue.pop_front();
         t.t_admit = Clock::now();
         t.st = kRunning;
@@ -243,7 +339,6 @@ struct sta_server {
           finished.notify_all();
           continue;
         }
-        in_flight += t.need;
         ++busy;
         progress = true;
       }
@@ -293,6 +388,8 @@ sta_status sta_server_create(const sta_server_config* cfg, sta_server** out) {
       st = hip_fail(e, "hipMemPoolSetAttribute");
   }
   if (st == STA_OK && (e = hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking)) != hipSuccess)
+    st = hip_fail(e, "hipStreamCreateWithFlags");
+  if (st == STA_OK && (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
     st = hip_fail(e, "hipStreamCreateWithFlags");
   s->slots.resize(cfg->max_slots);
   for (Slot& sl : s->slots) {
@@ -479,6 +576,11 @@ void sta_server_destroy(sta_server* s) {
   if (s->worker.joinable()) s->worker.join();
   for (Slot& sl : s->slots) {
     if (sl.s) (void)hipStreamSynchronize(sl.s);
+    s->drop_graphs(sl);
+    if (sl.buf) {
+      (void)hipFreeAsync(sl.buf, sl.s);
+      (void)hipStreamSynchronize(sl.s);
+    }
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.s) (void)hipStreamDestroy(sl.s);
   }
@@ -496,6 +598,7 @@ void sta_server_destroy(sta_server* s) {
     (void)hipFree(d.y);
   }
   if (s->setup_stream) (void)hipStreamDestroy(s->setup_stream);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->pool) (void)hipMemPoolDestroy(s->pool);
   delete s;
 }
