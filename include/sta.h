@@ -96,10 +96,11 @@ typedef struct sta_graph_info {
   int32_t n_levels;                /* net levels, 0 .. n_levels-1; 0 until levelized */
   int32_t n_pi_nets;               /* nets at level 0 */
   int32_t max_level_nets;          /* widest level */
-  int64_t fwd_state_bytes;         /* size of sta_fwd_out.state */
-  int64_t bwd_workspace_bytes;     /* size of sta_bwd_out.workspace */
+  int64_t fwd_state_bytes;         /* size of sta_fwd_out.state (all snapshots) */
+  int64_t bwd_workspace_bytes;     /* size of sta_bwd_out.workspace (all snapshots) */
   int64_t device_bytes;            /* graph data held on the device after upload */
   int32_t n_designs;               /* designs in the graph: 1, or the size of a batch */
+  int32_t n_snapshots;             /* placement snapshots swept per call (sta_set_snapshots) */
 } sta_graph_info;
 
 /* sta_forward / sta_backward flags */
@@ -207,6 +208,18 @@ sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Placement snapshots.  With n_snapshots = S > 1 every sta_forward / sta_backward call sweeps
+ * S placements of the same graph at once: the topology, library tables and launch plan are
+ * shared, and launches get a second grid dimension over snapshots.  Every per-call buffer
+ * then holds S copies back to back: x, y [S][n_pins]; at, slew, rat, slack [S][n_pins][4];
+ * atg [S][n_pins][2]; dx, dy [S][n_pins]; scalars [S][n_designs][4]; state and workspace
+ * S times their one-snapshot size (fwd_state_bytes and bwd_workspace_bytes report the
+ * total).  Snapshot s computes exactly what a call with S = 1 on its coordinates computes.
+ * Errors: STA_E_INVALID for S outside 1..65535.
+ * ------------------------------------------------------------------------------------- */
+sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
+
+/* ---------------------------------------------------------------------------------------
  * Lane-group schedule.  Nets are served by lane groups sized from their sink count: the
  * level kernels use groups of (1 << sweep_group_log2) lanes and doublings up to a wave
  * (16 lanes at least, since a cell step spreads 4 conditions x 4 arcs over 16 lanes), the
@@ -306,8 +319,8 @@ typedef struct sta_result {
 /* Creates a server on the current device.  Errors: STA_E_INVALID for out-of-range fields,
  * STA_E_DEVICE if the device lacks stream-ordered memory pools. */
 sta_status sta_server_create(const sta_server_config* cfg, sta_server** out);
-/* Makes a levelized graph resident (uploading it to the server's device if needed) with
- * host coordinates x, y [n_pins] by original pin id.  The caller keeps g alive until
+/* Makes a levelized graph with one snapshot resident (uploading it to the server's device
+ * if needed) with host coordinates x, y [n_pins] by original pin id.  The caller keeps g alive until
  * sta_server_destroy and makes no other calls on it meanwhile.  Errors: STA_E_STATE (not
  * levelized, or uploaded to another device), STA_E_NOMEM when the design does not fit the
  * budget. */

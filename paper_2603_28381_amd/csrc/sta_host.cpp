@@ -671,6 +671,14 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
   return STA_OK;
 }
 
+sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (n_snapshots < 1 || n_snapshots > 65535) return fail(STA_E_INVALID, "snapshot count out of range");
+  g->n_snap = n_snapshots;
+  drop_captured(g);
+  return STA_OK;
+}
+
 sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int32_t* record_slots,
                                  int32_t* kept_nets) {
   if (!g) return fail(STA_E_INVALID, "graph is NULL");
@@ -692,10 +700,11 @@ sta_status sta_graph_info_get(const sta_graph* g, sta_graph_info* info) {
   info->n_levels = g->levelized ? g->L : 0;
   info->n_pi_nets = g->levelized ? g->N0 : 0;
   info->max_level_nets = g->levelized ? g->max_level_nets : 0;
-  info->fwd_state_bytes = g->levelized ? (int64_t)g->state.total : 0;
-  info->bwd_workspace_bytes = g->levelized ? (int64_t)g->work.total : 0;
+  info->fwd_state_bytes = g->levelized ? (int64_t)g->state.total * g->n_snap : 0;
+  info->bwd_workspace_bytes = g->levelized ? (int64_t)g->work.total * g->n_snap : 0;
   info->device_bytes = g->uploaded ? (int64_t)g->dev.bytes : 0;
   info->n_designs = g->n_designs;
+  info->n_snapshots = g->n_snap;
   return STA_OK;
 }
 

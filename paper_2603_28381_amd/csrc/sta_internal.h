@@ -117,6 +117,7 @@ struct sta_graph {
   // level-0 nets at their own index, then the shared segment buffer), segment boundaries
   // seg_lo (levels [seg_lo[j], seg_lo[j+1])), and the endpoints' record slots.
   int ckpt_stride = 0, n_rec = 0, n_kept = 0;
+  int n_snap = 1;                              // placement snapshots per call (shared topology)
   std::vector<int> rec_loc, seg_lo, ep_rec;
   sta::StateLayout state{};
   sta::WorkLayout work{};

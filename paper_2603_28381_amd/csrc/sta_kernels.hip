@@ -25,6 +25,7 @@
 //  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "sta_internal.h"
 
@@ -36,6 +37,26 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kCellLanes = 16;   // lanes per cell: 4 conditions x 4 arcs
 constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
 constexpr int kRecChunks = 4;    // float4 chunks per arrival record, one per condition
+
+// Placement snapshots of one graph share its topology; snapshot blockIdx.y of a launch
+// works on its own copy of the per-call buffers, `state` / `work` bytes (state and
+// workspace) or `pins` / `scal` elements (per-pin arrays, scalars) after snapshot 0's.
+struct Snap {
+  size_t state, work, pins, scal;
+};
+
+// kSnap = false compiles the one-snapshot kernels, in which these offsets vanish.
+template <bool kSnap = true, class T>
+__device__ __forceinline__ T* snap_bytes(T* p, size_t stride) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  if (!kSnap) return p;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<C*>(p) + stride * blockIdx.y) : p;
+}
+template <bool kSnap = true, class T>
+__device__ __forceinline__ T* snap_elems(T* p, size_t stride) {
+  if (!kSnap) return p;
+  return p ? p + stride * blockIdx.y : p;
+}
 
 // ---------------------------------------------------------------------------- helpers
 // Table cell of v along an axis: upper_bound(axis, v) - 1 clamped to [0, 5], computed as
@@ -252,6 +273,7 @@ struct RcArgs {
   float4* __restrict__ rec;
   int N0;
   float r, c, pi_at, pi_slew;
+  Snap snap;
 };
 
 // RC net delay of every net (Sec. 3.1.1, Eq. 1-3, star nets): per sink the wire delay and
@@ -259,6 +281,11 @@ struct RcArgs {
 // are initialised here too.
 __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
   __shared__ float sh[kWavesPerBlock];
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
+  float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
   GroupSlot gs;
   if (!group_slot(a.range, gs)) return;
   const int n = gs.active ? a.sched[gs.entry] : 0;
@@ -268,14 +295,14 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     p0 = a.net_off[n];
     p1 = a.net_off[n + 1];
     const int q = a.io_perm ? a.io_perm[p0] : p0;
-    xd = a.x[q];
-    yd = a.y[q];
+    xd = xs[q];
+    yd = ys[q];
   }
   float sum = 0.f;
   for (int p = p0 + 1 + gs.gl; p < p1; p += gs.G) {
     const int q = a.io_perm ? a.io_perm[p] : p;
     const float cp = a.pin_cap[p];
-    const float len = fabsf(a.x[q] - xd) + fabsf(a.y[q] - yd);
+    const float len = fabsf(xs[q] - xd) + fabsf(ys[q] - yd);
     const float res = a.r * len;                 // Res(fa(u) -> u)
     const float cw = a.c * len;                  // wire capacitance, half at each end
     const float cap = fmaf(0.5f, cw, cp);        // Cap(u) of the sink node
@@ -283,15 +310,15 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     const float dly = 1e-3f * res * load;        // Eq. 2 (ohm * fF = 1e-3 ps)
     const float arg = 2.0f * (1e-3f * res * cap) * dly - dly * dly;   // Eq. 3
     const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
-    a.wire[p] = make_float2(dly, imp);
+    wire[p] = make_float2(dly, imp);
     sum += cp + cw;                              // the sink's Load plus the root half of the wire
   }
   sum = gs.block ? block_sum(sum, sh) : wave_group_sum(sum, gs.G);
   if (gs.active && gs.gl == 0) {
-    a.load[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
-    a.wire[p0] = make_float2(0.f, 0.f);
+    loads[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
+    wire[p0] = make_float2(0.f, 0.f);
     if (n < a.N0) {
-      float4* r = a.rec + kRecChunks * (size_t)n;
+      float4* r = rec + kRecChunks * (size_t)n;
       r[0] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
       r[1] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
       r[2] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
@@ -350,20 +377,25 @@ struct FwdArgs {
 // by max (late) / min (early), worst slew, and log-sum-exp of the late candidates (Eq. 4).
 // The values the first loads depend on come first, as scalar parameters, so that they are
 // preloaded into scalar registers at wave launch instead of read from the argument buffer:
-// the level's input slots (base, width, first cell, cell count), the level-0 net count,
-// the record slot map (NULL: slot = net) and the smallest slot recomputed (cells whose
-// net's record is below it are kept records and skipped).
-__global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int c0, int base, int F, int N0, int min_slot,
-                                                      const int4* __restrict__ ell, const float* __restrict__ loads,
-                                                      const int* __restrict__ loc, float4* __restrict__ rec,
+// the level's cell count, its first net, its input slots (base, width), the smallest
+// record slot recomputed (cells whose net's record lies below it are kept records and
+// skipped), the state bytes of one snapshot, the record slot map (NULL: slot = net) and
+// snapshot 0's load and record arrays.
+template <bool kSnap>
+__global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, int F, int min_slot, int snap_state,
+                                                      const int4* __restrict__ ell, const float* __restrict__ loads0,
+                                                      const int* __restrict__ loc, float4* __restrict__ rec0,
                                                       FwdArgs a) {
-  const Slots sl{base, F, c0, nc};
+  const Slots sl{base, F, 0, nc};
+  const float* loads = snap_bytes<kSnap>(loads0, (size_t)snap_state);
+  float4* rec = snap_bytes<kSnap>(rec0, (size_t)snap_state);
+  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state);
   const int gid = (int)(blockIdx.x * kBlock + threadIdx.x);
   const int kc = gid / kCellLanes;
   if (kc >= sl.nc) return;                     // uniform over the cell's 16 lanes
   const int lane = gid & (kCellLanes - 1);
   const int k = lane >> 2, jl = lane & 3, m = k >> 1, t = k & 1;
-  const int n = N0 + sl.c0 + kc;
+  const int n = n0 + kc;
   const int slot = loc ? loc[n] : n;
   if (slot < min_slot) return;                 // kept record, not recomputed
   const float load = loads[n];
@@ -416,7 +448,21 @@ struct EpArgs {
   int E, n_designs;
   float rat_late, hold, gamma, inv_gamma, scale;
   int smooth, wns_mode;
+  Snap snap;
 };
+
+// The endpoint arguments of snapshot blockIdx.y.
+__device__ __forceinline__ EpArgs ep_snap(const EpArgs& a0) {
+  EpArgs a = a0;
+  a.rec = snap_bytes(a.rec, a.snap.state);
+  a.wire = snap_bytes(a.wire, a.snap.state);
+  a.part = snap_bytes(a.part, a.snap.state);
+  a.fin = snap_bytes(a.fin, a.snap.state);
+  a.scalars = snap_elems(a.scalars, a.snap.scal);
+  a.ratp = snap_bytes(a.ratp, a.snap.work);
+  a.adjp = snap_bytes(a.adjp, a.snap.work);
+  return a;
+}
 
 struct EpVals {
   float worst;    // hard late slack, worst transition
@@ -462,8 +508,9 @@ __device__ __forceinline__ double block_reduce(double v, double* sh, bool is_max
 // Per-block partial sums over endpoints, in float64 and a fixed order: hard TNS, hard
 // worst slack, smoothed TNS terms, and a shifted sum of exponentials for smoothed WNS.
 // Each design's endpoints fill their own run of blocks.
-__global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
   __shared__ double sh[kBlock];
+  const EpArgs a = ep_snap(a0);
   int dsg = 0;
   while (dsg + 1 < a.n_designs && (int)blockIdx.x >= a.ep_blk_off[dsg + 1]) ++dsg;
   const int i = a.ep_design_off[dsg] + ((int)blockIdx.x - a.ep_blk_off[dsg]) * kBlock + (int)threadIdx.x;
@@ -495,8 +542,9 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a) {
 }
 
 // Scalars of design blockIdx.x from its partial blocks (fixed order).
-__global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a0) {
   __shared__ double sh[kBlock];
+  const EpArgs a = ep_snap(a0);
   const int dsg = blockIdx.x;
   const int b0 = a.ep_blk_off[dsg], b1 = a.ep_blk_off[dsg + 1];
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, mx = -__builtin_huge_val();
@@ -535,9 +583,10 @@ __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a) {
 
 // Seeds of the backward sweep at the endpoints: constrained required times, and the
 // adjoint of the smoothed objective with respect to each endpoint's smoothed arrival.
-__global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a) {
+__global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
   const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (i >= a.E) return;
+  if (i >= a0.E) return;
+  const EpArgs a = ep_snap(a0);
   const int e = a.ep_pin[i];
   a.ratp[e] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
   if (a.adjp) {
@@ -566,25 +615,31 @@ struct ExpandArgs {
   float4* at;
   float4* slew;
   float2* atg;
+  Snap snap;
 };
 
 // Per-pin arrival, slew and smoothed arrival from the net records (forward outputs).
 __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
+  const float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
+  const float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float4* at_out = snap_elems(a.at, a.snap.pins);
+  float4* slew_out = snap_elems(a.slew, a.snap.pins);
+  float2* atg_out = snap_elems(a.atg, a.snap.pins);
   GroupSlot gs;
   if (!group_slot(a.range, gs) || !gs.active) return;
   const int n = a.sched[gs.entry];
   const int p0 = a.net_off[n], p1 = a.net_off[n + 1];
-  const float4 c0 = a.rec[kRecChunks * (size_t)n], c1 = a.rec[kRecChunks * (size_t)n + 1],
-               c2 = a.rec[kRecChunks * (size_t)n + 2], c3 = a.rec[kRecChunks * (size_t)n + 3];
+  const float4 c0 = rec[kRecChunks * (size_t)n], c1 = rec[kRecChunks * (size_t)n + 1],
+               c2 = rec[kRecChunks * (size_t)n + 2], c3 = rec[kRecChunks * (size_t)n + 3];
   const float4 at = make_float4(c0.x, c1.x, c2.x, c3.x), sl = make_float4(c0.y, c1.y, c2.y, c3.y);
   const float2 ag = make_float2(c2.z, c3.z);
   for (int p = p0 + gs.gl; p < p1; p += gs.G) {
-    const float2 w = a.wire[p];
+    const float2 w = wire[p];
     const int q = a.io_perm ? a.io_perm[p] : p;
-    if (a.at) a.at[q] = make_float4(at.x + w.x, at.y + w.x, at.z + w.x, at.w + w.x);
-    if (a.slew)
-      a.slew[q] = make_float4(sink_slew(sl.x, w.y), sink_slew(sl.y, w.y), sink_slew(sl.z, w.y), sink_slew(sl.w, w.y));
-    if (a.atg) a.atg[q] = make_float2(ag.x + w.x, ag.y + w.x);
+    if (at_out) at_out[q] = make_float4(at.x + w.x, at.y + w.x, at.z + w.x, at.w + w.x);
+    if (slew_out)
+      slew_out[q] = make_float4(sink_slew(sl.x, w.y), sink_slew(sl.y, w.y), sink_slew(sl.z, w.y), sink_slew(sl.w, w.y));
+    if (atg_out) atg_out[q] = make_float2(ag.x + w.x, ag.y + w.x);
   }
 }
 
@@ -614,6 +669,7 @@ struct BwdArgs {
   int N0;
   float r, c, inv_gamma;
   int grad;
+  Snap snap;
 };
 
 // Accumulators of the net step (reduced over the group).
@@ -896,14 +952,26 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 // One level of backward propagation: heavy nets first (one workgroup each), then waves of
 // 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of the
 // first loads come first, as scalar parameters preloaded into scalar registers.
-template <int G0>
+template <int G0, bool kSnap>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
-                                                      int w3, const int* __restrict__ net_off,
+                                                      int w3, int snap_state, const int* __restrict__ net_off,
                                                       const float4* __restrict__ rec, BwdArgs a0, Slots sl) {
   __shared__ float sh[kWavesPerBlock * N_ACC];
   BwdArgs a = a0;
   a.net_off = net_off;
-  a.rec = rec;
+  a.rec = snap_bytes<kSnap>(rec, (size_t)snap_state);
+  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state);
+  a.load = snap_bytes<kSnap>(a.load, (size_t)snap_state);
+  a.ratp = snap_bytes<kSnap>(a.ratp, a.snap.work);
+  a.adjp = snap_bytes<kSnap>(a.adjp, a.snap.work);
+  a.x = snap_elems<kSnap>(a.x, a.snap.pins);
+  a.y = snap_elems<kSnap>(a.y, a.snap.pins);
+  a.at_out = snap_elems<kSnap>(a.at_out, a.snap.pins);
+  a.slew_out = snap_elems<kSnap>(a.slew_out, a.snap.pins);
+  a.rat_out = snap_elems<kSnap>(a.rat_out, a.snap.pins);
+  a.slack_out = snap_elems<kSnap>(a.slack_out, a.snap.pins);
+  a.dx = snap_elems<kSnap>(a.dx, a.snap.pins);
+  a.dy = snap_elems<kSnap>(a.dy, a.snap.pins);
   GroupSlot gs;
   if (!level_slot<G0>(nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
   if (gs.block || gs.G == 64) {
@@ -987,6 +1055,29 @@ using namespace sta;
 namespace sta {
 namespace {
 
+Snap snap_of(const sta_graph* g) {
+  return Snap{g->state.total, g->work.total, (size_t)g->P, 4 * (size_t)g->n_designs};
+}
+
+// Grid of a launch over all snapshots.  With several snapshots, the x extent is rounded up to
+// a multiple of the 8 XCDs (spare blocks exit at once): consecutive workgroups go to
+// consecutive XCDs, so every snapshot's copy of a block then runs on the same XCD and the
+// topology it reads is fetched into one L2.
+dim3 snap_grid(const sta_graph* g, unsigned blocks) {
+  if (g->n_snap > 1) blocks = (blocks + 7u) / 8u * 8u;
+  return dim3(blocks, (unsigned)g->n_snap, 1);
+}
+
+void fwd_level_launch(const sta_graph* g, unsigned blocks, hipStream_t s, const Slots& sl, int min_slot, int ss,
+                      const int4* ell, const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
+  const int n0 = g->N0 + sl.c0;
+  if (g->n_snap > 1)
+    k_fwd_level<true><<<snap_grid(g, blocks), kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc,
+                                                              rec, fa);
+  else
+    k_fwd_level<false><<<blocks, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+}
+
 sta_status launch_forward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
                           float gamma_ps, hipStream_t s) {
   const bool smooth = (flags & STA_SMOOTH) != 0;
@@ -997,11 +1088,12 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
   float* load = reinterpret_cast<float*>(sb + g->state.load);
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
+  const Snap sn = snap_of(g);
   RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0,
-            g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew};
+            g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn};
   {
     LaunchTimer t(g, s, STA_K_RC);
-    k_rc<<<range_grid(g->all_range), kBlock, 0, s>>>(ra);
+    k_rc<<<snap_grid(g, range_grid(g->all_range)), kBlock, 0, s>>>(ra);
   }
 
   const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, smooth ? 1.0f / gamma_ps : 0.f,
@@ -1010,27 +1102,27 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
     const Slots sl = level_slots(g, l);
     const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
-    k_fwd_level<<<blocks, kBlock, 0, s>>>(sl.nc, sl.c0, sl.base, sl.F, g->N0, 0, d.ell, load, d.rec_loc, rec, fa);
+    fwd_level_launch(g, blocks, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
   }
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
             nullptr, nullptr, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
-            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0};
+            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn};
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
-    k_ep_partials<<<g->n_ep_blocks, kBlock, 0, s>>>(ea);
+    k_ep_partials<<<dim3(g->n_ep_blocks, g->n_snap), kBlock, 0, s>>>(ea);
   }
   {
     LaunchTimer t(g, s, STA_K_EP_FINAL);
-    k_ep_finalize<<<g->n_designs, kBlock, 0, s>>>(ea);
+    k_ep_finalize<<<dim3(g->n_designs, g->n_snap), kBlock, 0, s>>>(ea);
   }
 
   if (out->at || out->slew || out->atg) {
     ExpandArgs xa{d.net_off, io, d.sched_all, g->all_range, rec, wire, reinterpret_cast<float4*>(out->at),
-                  reinterpret_cast<float4*>(out->slew), reinterpret_cast<float2*>(out->atg)};
+                  reinterpret_cast<float4*>(out->slew), reinterpret_cast<float2*>(out->atg), sn};
     LaunchTimer t(g, s, STA_K_EXPAND);
-    k_expand<<<range_grid(g->all_range), kBlock, 0, s>>>(xa);
+    k_expand<<<snap_grid(g, range_grid(g->all_range)), kBlock, 0, s>>>(xa);
   }
   if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
@@ -1055,17 +1147,18 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp,
             grad ? adjp : nullptr, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
             g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
-            (flags & STA_GRAD_WNS) ? 1 : 0};
+            (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g)};
   if (g->E > 0) {
     LaunchTimer t(g, s, STA_K_EP_SEED);
-    k_ep_seed<<<(g->E + kBlock - 1) / kBlock, kBlock, 0, s>>>(ea);
+    k_ep_seed<<<dim3((g->E + kBlock - 1) / kBlock, g->n_snap), kBlock, 0, s>>>(ea);
   }
 
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
              rec, wire, load, d.rec_loc, ratp, adjp, reinterpret_cast<float4*>(out->at),
              reinterpret_cast<float4*>(out->slew), reinterpret_cast<float4*>(out->rat),
              reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
-             g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0};
+             g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g)};
+  const int ss = (int)g->state.total;
   auto bwd_level = [&](int l) {
     const GroupRange& r = g->lvl_ranges[l];
     const unsigned blocks = range_grid(r);
@@ -1077,13 +1170,28 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     const Slots sl = level_slots(g, l);
     switch (r.g0) {
       case 4:
-        k_bwd_level<4><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        if (g->n_snap > 1)
+          k_bwd_level<4, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
+                                                                      ss, d.net_off, rec, ba, sl);
+        else
+          k_bwd_level<4, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
+                                                           d.net_off, rec, ba, sl);
         break;
       case 5:
-        k_bwd_level<5><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        if (g->n_snap > 1)
+          k_bwd_level<5, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
+                                                                      ss, d.net_off, rec, ba, sl);
+        else
+          k_bwd_level<5, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
+                                                           d.net_off, rec, ba, sl);
         break;
       default:
-        k_bwd_level<6><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], d.net_off, rec, ba, sl);
+        if (g->n_snap > 1)
+          k_bwd_level<6, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
+                                                                      ss, d.net_off, rec, ba, sl);
+        else
+          k_bwd_level<6, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
+                                                           d.net_off, rec, ba, sl);
         break;
     }
   };
@@ -1102,8 +1210,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
         const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
         if (blocks == 0) continue;
         LaunchTimer t(g, s, STA_K_RECOMPUTE);
-        k_fwd_level<<<blocks, kBlock, 0, s>>>(sl.nc, sl.c0, sl.base, sl.F, g->N0, g->n_kept, d.ell, load,
-                                              d.rec_loc, rec, fa);
+        fwd_level_launch(g, blocks, s, sl, g->n_kept, ss, d.ell, load, d.rec_loc, rec, fa);
       }
       for (int l = hi - 1; l >= lo; --l) bwd_level(l);
     }
@@ -1211,8 +1318,9 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   if (!(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t P = (size_t)g->P;
-  const size_t sizes[] = {g->state.total, g->work.total, 16 * P, 16 * P, 16 * P, 16 * P, 4 * P, 4 * P,
-                          32 * (size_t)g->n_designs};
+  const size_t S = (size_t)g->n_snap;
+  const size_t sizes[] = {S * g->state.total, S * g->work.total, S * 16 * P, S * 16 * P, S * 16 * P, S * 16 * P,
+                          S * 4 * P, S * 4 * P, S * 32 * (size_t)g->n_designs};
   void* buf[9] = {};
   for (int i = 0; i < 9; ++i) {
     hipError_t e = hipMalloc(&buf[i], sizes[i]);

@@ -416,6 +416,7 @@ sta_status sta_server_create(const sta_server_config* cfg, sta_server** out) {
 sta_status sta_server_add_design(sta_server* s, sta_graph* g, const float* x, const float* y, int32_t* id) {
   if (!s || !g || !x || !y || !id) return fail(STA_E_INVALID, "NULL argument");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (g->n_snap != 1) return fail(STA_E_INVALID, "served graphs sweep one snapshot per request");
   int cur = -1;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(s->device);

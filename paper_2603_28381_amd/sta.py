@@ -30,7 +30,7 @@ STA_REQ_FWD, STA_REQ_FWD_BWD = 0, 1
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
             "sta_forward", "sta_backward", "sta_get_schedule", "sta_set_schedule", "sta_tune",
-            "sta_set_checkpointing", "sta_get_checkpointing", "sta_server_create", "sta_server_add_design",
+            "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_server_create", "sta_server_add_design",
             "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
@@ -63,7 +63,7 @@ class StaGraphInfo(ctypes.Structure):
                 ("n_levels", ctypes.c_int32), ("n_pi_nets", ctypes.c_int32),
                 ("max_level_nets", ctypes.c_int32), ("fwd_state_bytes", ctypes.c_int64),
                 ("bwd_workspace_bytes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("n_designs", ctypes.c_int32)]
+                ("n_designs", ctypes.c_int32), ("n_snapshots", ctypes.c_int32)]
 
 
 class StaSchedule(ctypes.Structure):
@@ -142,6 +142,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_set_schedule.restype = S
     lib.sta_tune.argtypes = [_P, _P, _P, ctypes.c_float, ctypes.c_int32, ctypes.POINTER(StaSchedule), _P]
     lib.sta_tune.restype = S
+    lib.sta_set_snapshots.argtypes = [_P, ctypes.c_int32]
+    lib.sta_set_snapshots.restype = S
     lib.sta_set_checkpointing.argtypes = [_P, ctypes.c_int32]
     lib.sta_set_checkpointing.restype = S
     lib.sta_get_checkpointing.argtypes = [_P, _I32P, _I32P, _I32P]
@@ -328,6 +330,11 @@ class Graph:
                              _stream_handle(stream)))
         return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
 
+    def set_snapshots(self, n: int):
+        """Sweep n placement snapshots of this graph per call (per-call arrays gain a leading
+        snapshot dimension)."""
+        _check(_lib.sta_set_snapshots(self._h, int(n)))
+
     def set_checkpointing(self, stride_levels: int = -1):
         """Per-level checkpointing of the arrival state: 0 off, < 0 picks ceil(sqrt(L-1))."""
         _check(_lib.sta_set_checkpointing(self._h, int(stride_levels)))
@@ -359,18 +366,19 @@ class Graph:
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
-        P = self.n_pins
+        inf = self.info()
+        P, S, nd = self.n_pins, inf["n_snapshots"], inf["n_designs"]
+        lead = (S,) if S > 1 else ()
         state = self.new_state(dev) if state is None else state
         if scalars is None:
-            nd = self.info()["n_designs"]
-            scalars = torch.empty((nd, 4) if nd > 1 else 4, dtype=torch.float64, device=dev)
+            scalars = torch.empty(lead + ((nd, 4) if nd > 1 else (4,)), dtype=torch.float64, device=dev)
         at = slew = atg = None
         if out is not None:
             at, slew, atg = out.get("at"), out.get("slew"), out.get("atg")
         elif pins:
-            at = torch.empty((P, 4), dtype=torch.float32, device=dev)
-            slew = torch.empty((P, 4), dtype=torch.float32, device=dev)
-            atg = torch.empty((P, 2), dtype=torch.float32, device=dev) if smooth else None
+            at = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
+            slew = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
+            atg = torch.empty(lead + (P, 2), dtype=torch.float32, device=dev) if smooth else None
         fo = StaFwdOut(_ptr(state), _ptr(at), _ptr(slew), _ptr(atg), _ptr(scalars))
         flags = ((STA_SMOOTH if smooth else 0) | (STA_CANONICAL_IO if canonical else 0)
                  | (STA_GRAPH if capture else 0))
@@ -385,19 +393,20 @@ class Graph:
         dev = fwd.state.device
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
-        P = self.n_pins
+        P, S = self.n_pins, self.info()["n_snapshots"]
+        lead = (S,) if S > 1 else ()
         ws = self.new_workspace(dev) if workspace is None else workspace
         if out is None:
             out = {}
             if pins:
                 for k in ("at", "slew"):
-                    out[k] = torch.empty((P, 4), dtype=torch.float32, device=dev)
+                    out[k] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
             if rat:
-                out["rat"] = torch.empty((P, 4), dtype=torch.float32, device=dev)
-                out["slack"] = torch.empty((P, 4), dtype=torch.float32, device=dev)
+                out["rat"] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
+                out["slack"] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
             if grad:
-                out["dx"] = torch.empty(P, dtype=torch.float32, device=dev)
-                out["dy"] = torch.empty(P, dtype=torch.float32, device=dev)
+                out["dx"] = torch.empty(lead + (P,), dtype=torch.float32, device=dev)
+                out["dy"] = torch.empty(lead + (P,), dtype=torch.float32, device=dev)
         bo = StaBwdOut(_ptr(ws), _ptr(out.get("at")), _ptr(out.get("slew")), _ptr(out.get("rat")),
                        _ptr(out.get("slack")), _ptr(out.get("dx")), _ptr(out.get("dy")), float(grad_scale),
                        _ptr(grad_scale_dev))

@@ -361,3 +361,54 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
     again = _ckpt_run(g, d, wns)
     for key in plain:
         assert np.array_equal(again[key], plain[key], equal_nan=True), key
+
+
+@pytest.mark.parametrize("canonical", [False, True])
+def test_snapshots_equal_separate_calls_bitwise(canonical):
+    # Three placements swept together (shared topology) against three one-snapshot calls;
+    # also through a two-design batch and under checkpointing.
+    from gen.netlist import jitter
+    da = make_design(scaled_spec(25_000, cfg_id=49, box_um=600.0))
+    db = make_design(scaled_spec(8_000, cfg_id=50, box_um=300.0))
+    for members in ([da], [da, db]):
+        gs = [Graph.from_design(d) for d in members]
+        g = gs[0] if len(gs) == 1 else Graph.batch(gs)
+        g.levelize()
+        lev = g.levelization()
+        # original order of a batch: the members' pins one design after the other
+        base = [np.concatenate([d.x for d in members]), np.concatenate([d.y for d in members])]
+        snaps = []
+        for k in range(3):
+            xs, ys = (base[0], base[1]) if k == 0 else (base[0] + np.float32(3.0 * k), base[1] - np.float32(2.0 * k))
+            if k == 2:
+                xs = xs + np.random.default_rng(k).normal(0, 4.0, xs.shape).astype(np.float32)
+            if canonical:
+                xs, ys = xs[lev["pin_perm"]], ys[lev["pin_perm"]]
+            snaps.append((np.ascontiguousarray(xs, np.float32), np.ascontiguousarray(ys, np.float32)))
+        for ckpt in (0, -1):
+            g.set_checkpointing(ckpt)
+            g.set_snapshots(1)
+            alone = []
+            for xs, ys in snaps:
+                x, y = torch.tensor(xs, device="cuda"), torch.tensor(ys, device="cuda")
+                f = g.forward(x, y, gamma=GAMMA, canonical=canonical, pins=(ckpt == 0))
+                o = g.backward(x, y, f, rat=True, grad=True, pins=True)
+                torch.cuda.synchronize()
+                r = {k: v.cpu().numpy() for k, v in o.items()}
+                r["scalars"] = f.scalars.cpu().numpy()
+                if ckpt == 0:
+                    r["fwd_at"] = f.at.cpu().numpy()
+                alone.append(r)
+            g.set_snapshots(3)
+            x = torch.tensor(np.stack([s[0] for s in snaps]), device="cuda")
+            y = torch.tensor(np.stack([s[1] for s in snaps]), device="cuda")
+            f = g.forward(x, y, gamma=GAMMA, canonical=canonical, pins=(ckpt == 0))
+            o = g.backward(x, y, f, rat=True, grad=True, pins=True)
+            torch.cuda.synchronize()
+            for k in range(3):
+                for key in ("at", "slew", "rat", "slack", "dx", "dy"):
+                    assert np.array_equal(o[key][k].cpu().numpy(), alone[k][key], equal_nan=True), (len(members), ckpt, k, key)
+                assert np.array_equal(f.scalars[k].cpu().numpy(), alone[k]["scalars"]), (len(members), ckpt, k)
+                if ckpt == 0:
+                    assert np.array_equal(f.at[k].cpu().numpy(), alone[k]["fwd_at"], equal_nan=True)
+        g.set_snapshots(1)

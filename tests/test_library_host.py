@@ -246,3 +246,20 @@ def test_server_rejects_bad_configuration():
     assert lib.sta_poll(None, 1, None) == S.STA_E_INVALID
     assert lib.sta_release(None, 1) == S.STA_E_INVALID
     lib.sta_server_destroy(None)
+
+
+def test_snapshots_scale_per_call_buffers():
+    g = S.Graph.from_design(make_design(tiny_spec(20, 3, n_pi=3, seed=2)))
+    g.levelize()
+    one = g.info()
+    assert one["n_snapshots"] == 1
+    g.set_snapshots(5)
+    five = g.info()
+    assert five["n_snapshots"] == 5
+    assert five["fwd_state_bytes"] == 5 * one["fwd_state_bytes"]
+    assert five["bwd_workspace_bytes"] == 5 * one["bwd_workspace_bytes"]
+    for bad in (0, -1, 65536):
+        with pytest.raises(S.StaError) as e:
+            g.set_snapshots(bad)
+        assert e.value.code == S.STA_E_INVALID
+    g.close()
