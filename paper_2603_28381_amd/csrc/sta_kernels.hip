@@ -680,20 +680,41 @@ struct SinkKeep {     // what phase 3 needs of a sink, kept in registers
   int q;
 };
 
-// Net step of one sink: per-pin outputs and its contribution to the driver's reductions.
-__device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, int p, const float4& at_d, const float4& sl_d,
-                                              float xd, float yd, float (&acc)[N_ACC], bool write) {
-  const float4 rt = a.ratp[p];
-  const float2 w = a.wire[p];
-  const int q = a.io_perm ? a.io_perm[p] : p;
-  float4 aj = make_float4(0.f, 0.f, 0.f, 0.f);
-  float xs = 0.f, ys = 0.f, cp = 0.f;
-  if (a.grad) {
-    aj = a.adjp[p];
-    xs = a.x[q];
-    ys = a.y[q];
-    cp = a.pin_cap[p];
+// What the net step reads of one sink.  Loaded apart from its use, so that the loads of
+// a group's sinks are in flight while the cell step walks its own chain of loads.
+struct SinkIn {
+  float4 rt, aj;
+  float2 w;
+  float xs, ys, cp;
+  int q;
+};
+
+template <bool kCanon, bool kGrad>
+__device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p) {
+  SinkIn in;
+  in.rt = a.ratp[p];
+  in.w = a.wire[p];
+  in.q = kCanon ? p : a.io_perm[p];
+  in.aj = make_float4(0.f, 0.f, 0.f, 0.f);
+  in.xs = in.ys = in.cp = 0.f;
+  if (kGrad) {
+    in.aj = a.adjp[p];
+    in.xs = a.x[in.q];
+    in.ys = a.y[in.q];
+    in.cp = a.pin_cap[p];
   }
+  return in;
+}
+
+// Net step of one sink: per-pin outputs and its contribution to the driver's reductions.
+template <bool kGrad>
+__device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in, const float4& at_d,
+                                              const float4& sl_d, float xd, float yd, float (&acc)[N_ACC],
+                                              bool write) {
+  const float4 rt = in.rt, aj = in.aj;
+  const float2 w = in.w;
+  const int q = in.q;
+  const float xs = in.xs, ys = in.ys, cp = in.cp;
   const float4 ats = make_float4(at_d.x + w.x, at_d.y + w.x, at_d.z + w.x, at_d.w + w.x);
   const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
                                  sink_slew(sl_d.w, w.y));
@@ -708,7 +729,7 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, int p, const flo
   acc[R_L0] = fminf(acc[R_L0], rt.z - w.x);
   acc[R_L1] = fminf(acc[R_L1], rt.w - w.x);
   SinkKeep k{0.f, 0.f, 0.f, q};
-  if (a.grad) {
+  if (kGrad) {
     const float q0 = sls.z > 0.f ? aj.z / sls.z : 0.f;   // s_bar(s,t) / slew(s,late,t)
     const float q1 = sls.w > 0.f ? aj.w / sls.w : 0.f;
     acc[A_R] += aj.x;
@@ -758,6 +779,25 @@ __device__ __forceinline__ ArcBwd arc_backward(const BwdArgs& a, const Slots& sl
   return r;
 }
 
+// The cell-step lookup of an input already gathered: its table values at the input slew
+// and the root load.  The lookup runs for every lane (indices are valid for any entry), and
+// lanes without an arc come back invalid.
+__device__ __forceinline__ ArcBwd arc_from_input(const BwdArgs& a, const ArcIn& in, int t, float load) {
+  const LutVal v = lut_eval<true>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
+  ArcBwd r;
+  r.valid = in.valid;
+  r.pin = in.pin;
+  r.tp = in.tp;
+  r.d = in.valid ? v.d : 0.f;
+  r.s = in.valid ? v.s : 0.f;
+  r.xg = in.valid ? in.atg + v.d : -kInf;
+  r.ddx = in.valid ? v.ddx : 0.f;
+  r.ddy = in.valid ? v.ddy : 0.f;
+  r.dsx = in.valid ? v.dsx : 0.f;
+  r.dsy = in.valid ? v.dsy : 0.f;
+  return r;
+}
+
 // Group-wide reduction of the net-step accumulators (G = 16/32/64 wave groups, or a whole
 // workgroup when `block`).
 template <int G>
@@ -800,42 +840,63 @@ __device__ __forceinline__ void reduce_acc(float (&v)[N_ACC], bool block, float*
 //  3. Elmore adjoint: each sink's wire-length adjoint and d/dx, d/dy of every pin.
 // The cell step's loads and table lookups depend only on forward state, so they are issued
 // before the sink reduction they later combine with.
-template <int G>
+template <int G, bool kCanon, bool kGrad>
 __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const GroupSlot& gs, float* sh) {
   const int gl = gs.gl;
   const bool block = gs.block;
   const int n = gs.active ? gs.entry : 0;      // level ranges index canonical nets
-  int p0 = 0, p1 = 0;
+  // The loads are issued in three waves, each as soon as its addresses are known, with
+  // indices clamped to valid entries instead of branches so that the compiler keeps every
+  // wave's loads in flight together:
+  //  1. pin range, record slot, the cell input's slot entry, the root load;
+  //  2. the sinks' required times, adjoints, wires, coordinates and caps, the driver's
+  //     record and coordinates, and the input's source record and wire;
+  //  3. the table coefficients at the input slew.
+  const int lane16 = gl & (kCellLanes - 1);
+  const int k = lane16 >> 2, jl = lane16 & 3, m = k >> 1, t = k & 1;
+  const bool cell_lane = gs.active && n >= a.N0 && gl < kCellLanes;
+  const int kc = cell_lane ? n - a.N0 - sl.c0 : 0;   // position of the cell in its level
+  const size_t e_at = cell_lane ? (size_t)sl.base + (size_t)min(jl, sl.F - 1) * sl.nc + kc : 0;
+  const int p0 = a.net_off[n];
+  const int p1 = gs.active ? a.net_off[n + 1] : p0;
+  const int slot = a.loc ? a.loc[n] : n;
+  const int4 e = a.ell[e_at];
+  const float load = a.load[n];
+
+  const int s0 = p0 + 1 + gl;
+  const int gstride = block ? kBlock : G;
+  const bool has0 = s0 < p1;
+  const bool has1 = block && s0 + gstride < p1;
+  const SinkIn in0 = sink_load<kCanon, kGrad>(a, has0 ? s0 : p0);
+  SinkIn in1{};
+  if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0);
+  const float4* r = a.rec + kRecChunks * (size_t)slot;
+  const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
+  const float4 at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
+  const float4 sl_d = make_float4(c0.y, c1.y, c2.y, c3.y);
   float xd = 0.f, yd = 0.f;
-  float4 at_d = make_float4(0.f, 0.f, 0.f, 0.f), sl_d = at_d;
-  if (gs.active) {
-    p0 = a.net_off[n];
-    p1 = a.net_off[n + 1];
-    const int slot = a.loc ? a.loc[n] : n;
-    const float4* r = a.rec + kRecChunks * (size_t)slot;
-    const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
-    at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
-    sl_d = make_float4(c0.y, c1.y, c2.y, c3.y);
-    if (a.grad) {
-      const int q = a.io_perm ? a.io_perm[p0] : p0;
-      xd = a.x[q];
-      yd = a.y[q];
-    }
+  if (kGrad) {
+    const int q = kCanon ? p0 : a.io_perm[p0];
+    xd = a.x[q];
+    yd = a.y[q];
   }
 
   // 2a. Cell-step lookups: lane (k, jl) of the group's first 16 lanes takes arc jl.
-  const bool cell_net = gs.active && n >= a.N0;
-  const int lane16 = gl & (kCellLanes - 1);
-  const int k = lane16 >> 2, jl = lane16 & 3, m = k >> 1, t = k & 1;
-  const bool cell_lane = cell_net && gl < kCellLanes;
-  const int kc = n - a.N0 - sl.c0;             // position of the cell in its level
-  float load = 0.f;
-  if (cell_lane) load = a.load[n];
   ArcBwd arc0;
-  arc0.valid = false;
-  arc0.xg = -kInf;
-  arc0.s = -kInf;
-  if (cell_lane) arc0 = arc_backward(a, sl, kc, jl, m, t, load);
+  {
+    ArcIn in;
+    in.valid = cell_lane && jl < sl.F && e.x >= 0;
+    in.arc = e.z;
+    in.tp = e.w > 0 ? t : 1 - t;
+    in.pin = e.y;
+    const int kp = 2 * m + in.tp;
+    const float4 c = a.rec[kRecChunks * (size_t)max(e.x, 0) + kp];
+    const float2 w = a.wire[e.y];
+    in.at = c.x + w.x;
+    in.slew = sink_slew(c.y, w.y);
+    in.atg = c.z + w.x;
+    arc0 = arc_from_input(a, in, t, load);
+  }
   // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4).
   float xmax = quad_reduce<kMax>(arc0.valid ? arc0.xg : -kInf);
   float z = quad_reduce<kSum>(arc0.valid ? expf((arc0.xg - xmax) * a.inv_gamma) : 0.f);
@@ -858,18 +919,15 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
   }
 
-  // 1. Net step.  A lane holds at most one sink in a wave group and two in a workgroup;
-  //    sinks beyond that (nets over 512 sinks) are recomputed in phase 3.
+  // 1. Net step.  Sinks beyond the two a lane holds (nets over 512 sinks) are recomputed in
+  //    phase 3.
   float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   SinkKeep keep0{0.f, 0.f, 0.f, 0}, keep1{0.f, 0.f, 0.f, 0};
-  const int s0 = p0 + 1 + gl;
-  const int gstride = block ? kBlock : G;
-  const bool has0 = s0 < p1;
-  const bool has1 = block && s0 + gstride < p1;
-  if (has0) keep0 = sink_step(a, s0, at_d, sl_d, xd, yd, acc, true);
-  if (has1) keep1 = sink_step(a, s0 + gstride, at_d, sl_d, xd, yd, acc, true);
+  if (has0) keep0 = sink_step<kGrad>(a, in0, at_d, sl_d, xd, yd, acc, true);
+  if (has1) keep1 = sink_step<kGrad>(a, in1, at_d, sl_d, xd, yd, acc, true);
   if (block) {
-    for (int p = s0 + 2 * gstride; p < p1; p += gstride) sink_step(a, p, at_d, sl_d, xd, yd, acc, true);
+    for (int p = s0 + 2 * gstride; p < p1; p += gstride)
+      sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, acc, true);
   }
   reduce_acc<G>(acc, block, sh);
 
@@ -888,7 +946,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     if (cell_lane && v.valid) {
       // RAT(input, k') = RAT(output, k) - arc delay.
       reinterpret_cast<float*>(a.ratp + v.pin)[2 * m + v.tp] = rat_o - v.d;
-      if (a.grad && m == 1) {
+      if (kGrad && m == 1) {
         const float dbar = expf((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
         const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
         float* adj = reinterpret_cast<float*>(a.adjp + v.pin);
@@ -901,7 +959,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 
   // 3. Load adjoint of the root: arcs (quad sum) of late rise + late fall, lanes 8 and 12.
   float lbar = 0.f;
-  if (a.grad) {
+  if (kGrad) {
     lb = quad_reduce<kSum>(lb);
     if (!block) {
       const int base = (threadIdx.x & 63) & ~(G - 1);
@@ -915,7 +973,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
   }
   if (!gs.active) return;
-  if (a.grad && (a.dx || a.dy)) {
+  if (kGrad && (a.dx || a.dy)) {
     const float cl = a.c * lbar;
     if (has0) {
       if (a.dx) a.dx[keep0.q] = keep0.gx * (cl + keep0.rest);
@@ -928,20 +986,20 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     if (block) {
       for (int p = s0 + 2 * gstride; p < p1; p += gstride) {
         float scratch[N_ACC] = {};
-        const SinkKeep kk = sink_step(a, p, at_d, sl_d, xd, yd, scratch, false);
+        const SinkKeep kk = sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, scratch, false);
         if (a.dx) a.dx[kk.q] = kk.gx * (cl + kk.rest);
         if (a.dy) a.dy[kk.q] = kk.gy * (cl + kk.rest);
       }
     }
   }
   if (gl == 0) {
-    const int q = a.io_perm ? a.io_perm[p0] : p0;
+    const int q = kCanon ? p0 : a.io_perm[p0];
     if (a.at_out) a.at_out[q] = at_d;
     if (a.slew_out) a.slew_out[q] = sl_d;
     if (a.rat_out) a.rat_out[q] = make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]);
     if (a.slack_out)
       a.slack_out[q] = make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w);
-    if (a.grad) {
+    if (kGrad) {
       const float cl = a.c * lbar;
       if (a.dx) a.dx[q] = -(acc[X_RS] + cl * acc[X_N]);
       if (a.dy) a.dy[q] = -(acc[Y_RS] + cl * acc[Y_N]);
@@ -952,7 +1010,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 // One level of backward propagation: heavy nets first (one workgroup each), then waves of
 // 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of the
 // first loads come first, as scalar parameters preloaded into scalar registers.
-template <int G0, bool kSnap>
+template <int G0, bool kSnap, bool kCanon, bool kGrad>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
                                                       int w3, int snap_state, const int* __restrict__ net_off,
                                                       const float4* __restrict__ rec, BwdArgs a0, Slots sl) {
@@ -975,12 +1033,36 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   GroupSlot gs;
   if (!level_slot<G0>(nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
   if (gs.block || gs.G == 64) {
-    bwd_net<64>(a, sl, gs, sh);
+    bwd_net<64, kCanon, kGrad>(a, sl, gs, sh);
   } else if (gs.G == 32) {
-    bwd_net<32>(a, sl, gs, sh);
+    bwd_net<32, kCanon, kGrad>(a, sl, gs, sh);
   } else {
-    bwd_net<16>(a, sl, gs, sh);
+    bwd_net<16, kCanon, kGrad>(a, sl, gs, sh);
   }
+}
+
+// One backward level's launch, with the kernel compiled for its smallest group, snapshot
+// count, pin order and gradient flag.
+struct BwdLaunch {
+  int nh, h0, e0, e1, e2, e3, w1, w2, w3, ss;
+  const int* net_off;
+  const float4* rec;
+  BwdArgs ba;
+  Slots sl;
+};
+
+template <int G0, bool kSnap, bool kCanon, bool kGrad>
+void bwd_launch(dim3 grid, hipStream_t s, const BwdLaunch& L) {
+  k_bwd_level<G0, kSnap, kCanon, kGrad><<<grid, kBlock, 0, s>>>(L.nh, L.h0, L.e0, L.e1, L.e2, L.e3, L.w1, L.w2, L.w3,
+                                                                  L.ss, L.net_off, L.rec, L.ba, L.sl);
+}
+
+template <int G0, bool kSnap>
+void bwd_launch(dim3 grid, hipStream_t s, const BwdLaunch& L, bool canon, bool grad) {
+  if (canon)
+    grad ? bwd_launch<G0, kSnap, true, true>(grid, s, L) : bwd_launch<G0, kSnap, true, false>(grid, s, L);
+  else
+    grad ? bwd_launch<G0, kSnap, false, true>(grid, s, L) : bwd_launch<G0, kSnap, false, false>(grid, s, L);
 }
 
 Slots level_slots(const sta_graph* g, int l) {
@@ -1168,31 +1250,16 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     const int* c = r.cls_off;
     const int* w = r.wave_off;
     const Slots sl = level_slots(g, l);
-    switch (r.g0) {
-      case 4:
-        if (g->n_snap > 1)
-          k_bwd_level<4, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
-                                                                      ss, d.net_off, rec, ba, sl);
-        else
-          k_bwd_level<4, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
-                                                           d.net_off, rec, ba, sl);
-        break;
-      case 5:
-        if (g->n_snap > 1)
-          k_bwd_level<5, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
-                                                                      ss, d.net_off, rec, ba, sl);
-        else
-          k_bwd_level<5, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
-                                                           d.net_off, rec, ba, sl);
-        break;
-      default:
-        if (g->n_snap > 1)
-          k_bwd_level<6, true><<<snap_grid(g, blocks), kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3],
-                                                                      ss, d.net_off, rec, ba, sl);
-        else
-          k_bwd_level<6, false><<<blocks, kBlock, 0, s>>>(nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss,
-                                                           d.net_off, rec, ba, sl);
-        break;
+    const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss, d.net_off, rec, ba, sl};
+    const bool snap = g->n_snap > 1, canon = io == nullptr;
+    const dim3 grid = snap ? snap_grid(g, blocks) : dim3(blocks);
+    switch (r.g0 * 2 + (snap ? 1 : 0)) {
+      case 8: bwd_launch<4, false>(grid, s, L, canon, grad); break;
+      case 9: bwd_launch<4, true>(grid, s, L, canon, grad); break;
+      case 10: bwd_launch<5, false>(grid, s, L, canon, grad); break;
+      case 11: bwd_launch<5, true>(grid, s, L, canon, grad); break;
+      case 12: bwd_launch<6, false>(grid, s, L, canon, grad); break;
+      default: bwd_launch<6, true>(grid, s, L, canon, grad); break;
     }
   };
   if (g->ckpt_stride <= 0) {
