@@ -345,6 +345,28 @@ struct ArcIn {          // one cell input seen from one condition
 // inputs (j past the cell's fanin) read net 0 and come back invalid.
 __device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const Slots& sl, int kc, int j,
                                            const float4* __restrict__ rec, const float2* __restrict__ wire,
+                                           int m, int t);
+
+// The same from an input slot entry already loaded (entries of empty slots are valid
+// addresses: source -1 reads record 0, pin 0, arc 0).
+__device__ __forceinline__ ArcIn arc_input_entry(const int4 e, bool valid, const float4* __restrict__ rec,
+                                                 const float2* __restrict__ wire, int m, int t) {
+  ArcIn r;
+  r.valid = valid && e.x >= 0;
+  r.arc = e.z;
+  r.tp = e.w > 0 ? t : 1 - t;
+  r.pin = e.y;
+  const int kp = 2 * m + r.tp;
+  const float4 c = rec[kRecChunks * (size_t)max(e.x, 0) + kp];
+  const float2 w = wire[e.y];
+  r.at = c.x + w.x;
+  r.slew = sink_slew(c.y, w.y);
+  r.atg = c.z + w.x;
+  return r;
+}
+
+__device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const Slots& sl, int kc, int j,
+                                           const float4* __restrict__ rec, const float2* __restrict__ wire,
                                            int m, int t) {
   const int4 e = ell[sl.base + (size_t)min(j, sl.F - 1) * sl.nc + kc];
   ArcIn r;
@@ -396,17 +418,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
   const int lane = gid & (kCellLanes - 1);
   const int k = lane >> 2, jl = lane & 3, m = k >> 1, t = k & 1;
   const int n = n0 + kc;
+  // Loads in three waves, each issued as soon as its addresses are known: the first input
+  // slot entry and the root load; the source record and wire; the table coefficients.
+  const int4 e0 = ell[(size_t)sl.base + (size_t)min(jl, sl.F - 1) * sl.nc + kc];
+  const float load = loads[n];
   const int slot = loc ? loc[n] : n;
   if (slot < min_slot) return;                 // kept record, not recomputed
-  const float load = loads[n];
   float best_at = m ? -kInf : kInf;
   float best_sl = best_at;
   float lm = -kInf, ls = 0.f;
   for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
-    const ArcIn in = arc_input(ell, sl, kc, j0 + jl, rec, a.wire, m, t);
+    const ArcIn in = j0 == 0 ? arc_input_entry(e0, jl < sl.F, rec, a.wire, m, t)
+                             : arc_input(ell, sl, kc, j0 + jl, rec, a.wire, m, t);
+    const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
     float cand = m ? -kInf : kInf, s = cand, g = -kInf;
     if (in.valid) {
-      const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, t, in.slew, load);
       cand = in.at + v.d;
       s = v.s;
       g = in.atg + v.d;
