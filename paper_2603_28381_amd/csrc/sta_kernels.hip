@@ -884,18 +884,28 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const int kc = cell_lane ? n - a.N0 - sl.c0 : 0;   // position of the cell in its level
   const size_t e_at = cell_lane ? (size_t)sl.base + (size_t)min(jl, sl.F - 1) * sl.nc + kc : 0;
   const int p0 = a.net_off[n];
-  const int p1 = gs.active ? a.net_off[n + 1] : p0;
-  const int slot = a.loc ? a.loc[n] : n;
+  const int p1v = a.net_off[n + 1];
   const int4 e = a.ell[e_at];
   const float load = a.load[n];
+  const int slot = a.loc ? a.loc[n] : n;
+  const int p1 = gs.active ? p1v : p0;
 
-  const int s0 = p0 + 1 + gl;
-  const int gstride = block ? kBlock : G;
-  const bool has0 = s0 < p1;
-  const bool has1 = block && s0 + gstride < p1;
-  const SinkIn in0 = sink_load<kCanon, kGrad>(a, has0 ? s0 : p0);
-  SinkIn in1{};
-  if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0);
+  // Wave 2: the cell input's source record and wire first (the table lookup waits for
+  // them), then the driver's record and coordinates and the sinks, whose loads stay in
+  // flight through the lookup.
+  ArcIn ain;
+  {
+    ain.valid = cell_lane && jl < sl.F && e.x >= 0;
+    ain.arc = e.z;
+    ain.tp = e.w > 0 ? t : 1 - t;
+    ain.pin = e.y;
+    const int kp = 2 * m + ain.tp;
+    const float4 c = a.rec[kRecChunks * (size_t)max(e.x, 0) + kp];
+    const float2 w = a.wire[e.y];
+    ain.at = c.x + w.x;
+    ain.slew = sink_slew(c.y, w.y);
+    ain.atg = c.z + w.x;
+  }
   const float4* r = a.rec + kRecChunks * (size_t)slot;
   const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
   const float4 at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
@@ -906,23 +916,17 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     xd = a.x[q];
     yd = a.y[q];
   }
+  const int s0 = p0 + 1 + gl;
+  const int gstride = block ? kBlock : G;
+  const bool has0 = s0 < p1;
+  const bool has1 = block && s0 + gstride < p1;
+  const SinkIn in0 = sink_load<kCanon, kGrad>(a, has0 ? s0 : p0);
+  SinkIn in1{};
+  if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0);
+  __builtin_amdgcn_sched_barrier(0);          // keep wave 2 ahead of the lookup below
 
-  // 2a. Cell-step lookups: lane (k, jl) of the group's first 16 lanes takes arc jl.
-  ArcBwd arc0;
-  {
-    ArcIn in;
-    in.valid = cell_lane && jl < sl.F && e.x >= 0;
-    in.arc = e.z;
-    in.tp = e.w > 0 ? t : 1 - t;
-    in.pin = e.y;
-    const int kp = 2 * m + in.tp;
-    const float4 c = a.rec[kRecChunks * (size_t)max(e.x, 0) + kp];
-    const float2 w = a.wire[e.y];
-    in.at = c.x + w.x;
-    in.slew = sink_slew(c.y, w.y);
-    in.atg = c.z + w.x;
-    arc0 = arc_from_input(a, in, t, load);
-  }
+  // 2a. Cell-step lookups (wave 3): lane (k, jl) of the group's first 16 lanes takes arc jl.
+  ArcBwd arc0 = arc_from_input(a, ain, t, load);
   // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4).
   float xmax = quad_reduce<kMax>(arc0.valid ? arc0.xg : -kInf);
   float z = quad_reduce<kSum>(arc0.valid ? expf((arc0.xg - xmax) * a.inv_gamma) : 0.f);
