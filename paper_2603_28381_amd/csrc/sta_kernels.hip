@@ -669,6 +669,14 @@ __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
   }
 }
 
+// Streaming store of a per-pin output: written once, read by no later kernel of the sweep,
+// so it bypasses the cache instead of waiting in L2 for the end-of-kernel writeback.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_stream(float4* p, const float4 v) {
+  const f4v x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+}
+
 // ---------------------------------------------------------------------------- backward level
 struct BwdArgs {
   const int* __restrict__ net_off;
@@ -745,10 +753,10 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in
   const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
                                  sink_slew(sl_d.w, w.y));
   if (write) {
-    if (a.at_out) a.at_out[q] = ats;
-    if (a.slew_out) a.slew_out[q] = sls;
-    if (a.rat_out) a.rat_out[q] = rt;
-    if (a.slack_out) a.slack_out[q] = make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w);
+    if (a.at_out) store_stream(a.at_out + q, ats);
+    if (a.slew_out) store_stream(a.slew_out + q, sls);
+    if (a.rat_out) store_stream(a.rat_out + q, rt);
+    if (a.slack_out) store_stream(a.slack_out + q, make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w));
   }
   acc[R_E0] = fmaxf(acc[R_E0], rt.x - w.x);
   acc[R_E1] = fmaxf(acc[R_E1], rt.y - w.x);
@@ -1024,11 +1032,12 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   }
   if (gl == 0) {
     const int q = kCanon ? p0 : a.io_perm[p0];
-    if (a.at_out) a.at_out[q] = at_d;
-    if (a.slew_out) a.slew_out[q] = sl_d;
-    if (a.rat_out) a.rat_out[q] = make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]);
+    if (a.at_out) store_stream(a.at_out + q, at_d);
+    if (a.slew_out) store_stream(a.slew_out + q, sl_d);
+    if (a.rat_out) store_stream(a.rat_out + q, make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]));
     if (a.slack_out)
-      a.slack_out[q] = make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w);
+      store_stream(a.slack_out + q,
+                   make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w));
     if (kGrad) {
       const float cl = a.c * lbar;
       if (a.dx) a.dx[q] = -(acc[X_RS] + cl * acc[X_N]);
