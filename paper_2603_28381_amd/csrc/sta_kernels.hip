@@ -631,6 +631,20 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
 }
 
 // ---------------------------------------------------------------------------- outputs
+// Streaming store of a per-pin output: written once, read by no later kernel of the sweep,
+// so it bypasses the cache instead of waiting in L2 for the end-of-kernel writeback.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(float4* p, const float4 v) {
+  const f4v x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+}
+__device__ __forceinline__ void store_stream(float2* p, const float2 v) {
+  const f2v x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<f2v*>(p));
+}
+
+
 struct ExpandArgs {
   const int* __restrict__ net_off;
   const int* __restrict__ io_perm;
@@ -662,19 +676,12 @@ __global__ __launch_bounds__(kBlock) void k_expand(ExpandArgs a) {
   for (int p = p0 + gs.gl; p < p1; p += gs.G) {
     const float2 w = wire[p];
     const int q = a.io_perm ? a.io_perm[p] : p;
-    if (at_out) at_out[q] = make_float4(at.x + w.x, at.y + w.x, at.z + w.x, at.w + w.x);
+    if (at_out) store_stream(at_out + q, make_float4(at.x + w.x, at.y + w.x, at.z + w.x, at.w + w.x));
     if (slew_out)
-      slew_out[q] = make_float4(sink_slew(sl.x, w.y), sink_slew(sl.y, w.y), sink_slew(sl.z, w.y), sink_slew(sl.w, w.y));
-    if (atg_out) atg_out[q] = make_float2(ag.x + w.x, ag.y + w.x);
+      store_stream(slew_out + q,
+                   make_float4(sink_slew(sl.x, w.y), sink_slew(sl.y, w.y), sink_slew(sl.z, w.y), sink_slew(sl.w, w.y)));
+    if (atg_out) store_stream(atg_out + q, make_float2(ag.x + w.x, ag.y + w.x));
   }
-}
-
-// Streaming store of a per-pin output: written once, read by no later kernel of the sweep,
-// so it bypasses the cache instead of waiting in L2 for the end-of-kernel writeback.
-typedef float f4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void store_stream(float4* p, const float4 v) {
-  const f4v x = {v.x, v.y, v.z, v.w};
-  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
 }
 
 // ---------------------------------------------------------------------------- backward level
