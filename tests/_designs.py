@@ -84,3 +84,71 @@ def chain(n_gates: int, types, lib, L_um: float = 80.0, cpin: float = 2.0) -> De
 
 __all__ = ["build", "planar_library", "two_pin", "chain", "PIN_PI", "PIN_CELL_IN", "PIN_CELL_OUT",
            "PIN_FF_D", "PIN_PO"]
+
+
+def wide_library(seed: int = 0) -> Library:
+    """The default library plus two cell types of each fanin 5..8 (arcs appended)."""
+    base = make_library(seed_stream=seed)
+    rng = np.random.default_rng([seed, 23])
+    fanins = [5, 5, 6, 6, 7, 7, 8, 8]
+    n_new = sum(fanins)
+    off = list(base.arc_offsets)
+    for f in fanins:
+        off.append(off[-1] + f)
+    S = base.slew_axis.astype(np.float64)[:, None]
+    Ld = base.load_axis.astype(np.float64)[None, :]
+    tabs = np.empty((n_new, 4) + base.tables.shape[2:], np.float64)
+    for a in range(n_new):
+        for t in range(4):
+            if t < 2:
+                ca, cb, cc = rng.uniform(10, 30), rng.uniform(0.05, 0.3), rng.uniform(0.2, 1.0)
+            else:
+                ca, cb, cc = rng.uniform(3, 10), rng.uniform(0.02, 0.15), rng.uniform(0.5, 2.0)
+            tabs[a, t] = ca + cb * S + cc * Ld + rng.normal(0.0, 0.5, S.shape[:1] + Ld.shape[1:])
+    unate = np.concatenate([base.arc_unate, np.where(rng.random(n_new) < 0.5, 1, -1).astype(np.int8)])
+    return Library(base.n_cell_types + len(fanins), np.array(off, np.int32), unate, base.slew_axis,
+                   base.load_axis, np.concatenate([base.tables, tabs.astype(np.float32)]))
+
+
+def wide_dag(n_levels: int = 8, gates_per_level: int = 40, n_pi: int = 12, seed: int = 0,
+             box_um: float = 300.0) -> Design:
+    """A random levelized DAG whose gates have 1-8 inputs (most 5-8), on wide_library()."""
+    lib = wide_library(seed)
+    rng = np.random.default_rng([seed, 31])
+    fan_of_type = np.diff(lib.arc_offsets)
+    kinds, nets, cells, levels = [], [], [], []
+
+    def pin(kind):
+        kinds.append(kind)
+        return len(kinds) - 1
+
+    for _ in range(n_pi):
+        nets.append([pin(PIN_PI)])
+        levels.append(0)
+    for lv in range(1, n_levels + 1):
+        prev = [i for i, l in enumerate(levels) if l == lv - 1]
+        older = [i for i, l in enumerate(levels) if l < lv]
+        for _ in range(gates_per_level):
+            f = int(rng.choice([1, 2, 3, 4, 5, 6, 7, 8], p=[.05, .05, .05, .05, .2, .2, .2, .2]))
+            f = min(f, len(older))
+            typ = int(rng.choice(np.nonzero(fan_of_type == f)[0]))
+            srcs = [int(rng.choice(prev))]
+            rest = [n for n in older if n != srcs[0]]
+            srcs += [int(v) for v in rng.choice(rest, size=f - 1, replace=False)] if f > 1 else []
+            ins = []
+            for n in srcs:
+                p = pin(PIN_CELL_IN)
+                nets[n].append(p)
+                ins.append(p)
+            out = pin(PIN_CELL_OUT)
+            cells.append((typ, ins, out))
+            nets.append([out])
+            levels.append(lv)
+    for n in nets:
+        if len(n) == 1 or rng.random() < 0.2:
+            n.append(pin(PIN_PO if rng.random() < 0.5 else PIN_FF_D))
+    P = len(kinds)
+    caps = np.where(np.asarray(kinds) == PIN_CELL_OUT, 0.0, rng.uniform(1, 5, P))
+    caps = np.where(np.asarray(kinds) == PIN_PI, 0.0, caps)
+    return build(nets, cells, kinds, caps, rng.uniform(0, box_um, P), rng.uniform(0, box_um, P),
+                 lib=lib, name="wide")

@@ -412,3 +412,79 @@ def test_snapshots_equal_separate_calls_bitwise(canonical):
                 if ckpt == 0:
                     assert np.array_equal(f.at[k].cpu().numpy(), alone[k]["fwd_at"], equal_nan=True)
         g.set_snapshots(1)
+
+
+@pytest.mark.parametrize("wns", [False, True])
+def test_parity_wide_cells(wns):
+    # Cells of 5-8 inputs take the cell steps' second chunk of 4 arcs (merged log-sum-exp,
+    # arg max and softmax across chunks).
+    from tests._designs import wide_dag
+    d = wide_dag(n_levels=9, gates_per_level=60, n_pi=16, seed=3)
+    ref = O.run(d, gamma=GAMMA, grad="wns" if wns else "tns")
+    got = gpu_run(d, wns=wns)
+    check_values(d, got, ref)
+    check_grad(got, ref, 1e-3, 1e-6)
+
+
+@pytest.mark.slow
+def test_batched_workload_members_equal_alone_at_full_size():
+    # The batched workload at its real shape: 64 snapshots of the 806,509-pin design in one
+    # snapshot graph, and the 16 other designs in one batch graph; sampled members against
+    # the same sweeps run alone (the single sweep is oracle-checked at this size above).
+    from gen.netlist import CFG1, batch_designs, jitter
+    d1 = make_design(CFG1)
+    g1 = Graph.from_design(d1)
+    g1.levelize()
+    perm = g1.levelization()["pin_perm"]
+    snaps = [jitter(d1, 5.0, stream=s) for s in range(1, 65)]
+    g1.set_snapshots(64)
+    x = torch.tensor(np.stack([sx[perm] for sx, _ in snaps]), device="cuda")
+    y = torch.tensor(np.stack([sy[perm] for _, sy in snaps]), device="cuda")
+    f = g1.forward(x, y, gamma=GAMMA, canonical=True, capture=True)
+    o = g1.backward(x, y, f, rat=True, grad=True, pins=True, capture=True)
+    torch.cuda.synchronize()
+    picks = (0, 37, 63)
+    got = {s: ({k: o[k][s].cpu().numpy() for k in ("rat", "slack", "dx", "dy")}, f.scalars[s].cpu().numpy())
+           for s in picks}
+    del f, o, x, y
+    g1.set_snapshots(1)
+    for s in picks:
+        xs = torch.tensor(snaps[s][0][perm], device="cuda")
+        ys = torch.tensor(snaps[s][1][perm], device="cuda")
+        f1 = g1.forward(xs, ys, gamma=GAMMA, canonical=True)
+        o1 = g1.backward(xs, ys, f1, rat=True, grad=True, pins=True)
+        torch.cuda.synchronize()
+        for k in ("rat", "slack", "dx", "dy"):
+            assert np.array_equal(got[s][0][k], o1[k].cpu().numpy(), equal_nan=True), (s, k)
+        assert np.array_equal(got[s][1], f1.scalars.cpu().numpy()), s
+    others = batch_designs(16, 10_000, 400_000, cfg_id=3)
+    gs = [Graph.from_design(d) for d in others]
+    u = Graph.batch(gs)
+    u.levelize()
+    dsg, pin = u.batch_pin_map()
+    base = np.cumsum([0] + [d.n_pins for d in others])
+    src = base[dsg] + pin
+    xu = torch.tensor(np.concatenate([d.x for d in others])[src], device="cuda")
+    yu = torch.tensor(np.concatenate([d.y for d in others])[src], device="cuda")
+    fu = u.forward(xu, yu, gamma=GAMMA, canonical=True, capture=True)
+    ou = u.backward(xu, yu, fu, rat=True, grad=True, pins=True, capture=True)
+    torch.cuda.synchronize()
+    for i in (0, 7, 15):
+        g = gs[i]
+        g.levelize()
+        pm = g.levelization()["pin_perm"]
+        xs = torch.tensor(others[i].x[pm], device="cuda")
+        ys = torch.tensor(others[i].y[pm], device="cuda")
+        f1 = g.forward(xs, ys, gamma=GAMMA, canonical=True)
+        o1 = g.backward(xs, ys, f1, rat=True, grad=True, pins=True)
+        torch.cuda.synchronize()
+        sel = np.nonzero(dsg == i)[0]
+        # canonical pin j of the member sits at union canonical position sel[k] with pin[sel[k]]
+        # its original id; the member's own canonical order maps original -> canonical
+        inv = np.empty(others[i].n_pins, np.int64)
+        inv[pm] = np.arange(others[i].n_pins)
+        for k in ("dx", "slack"):
+            a = ou[k].cpu().numpy()[sel]
+            b = o1[k].cpu().numpy()[inv[pin[sel]]]
+            assert np.array_equal(a, b, equal_nan=True), (i, k)
+        assert np.array_equal(fu.scalars[i].cpu().numpy(), f1.scalars.cpu().numpy()), i

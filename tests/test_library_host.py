@@ -263,3 +263,8 @@ def test_snapshots_scale_per_call_buffers():
             g.set_snapshots(bad)
         assert e.value.code == S.STA_E_INVALID
     g.close()
+
+
+def test_levelization_bit_exact_wide_cells():
+    from tests._designs import wide_dag
+    _levelization_matches(wide_dag(seed=5))

@@ -387,3 +387,23 @@ def test_rounding_scales_bound_float32_perturbation(which):
             assert np.all(ref[k + "_scale"][fin] >= np.abs(r[fin]) * (1 - 1e-12)), k
             err = np.abs(v[fin] - r[fin])
             assert np.all(err <= 1.01 * u * ref[k + "_scale"][fin] + 1e-9), (k, np.max(err / (u * ref[k + "_scale"][fin])))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_wide_cells_match_path_enumeration(seed):
+    # Cells of 5-8 inputs: the same explicit enumeration over every path.
+    from tests._designs import wide_dag
+    d = wide_dag(n_levels=3, gates_per_level=5, n_pi=9, seed=seed)
+    lv = O.levelize(d)
+    out = O.run(d, grad=None, lv=lv)
+    sinks, drv_of, in_cell = _graph_maps(d, lv)
+    assert np.diff(d.cell_in_offsets).max() >= 5
+    for p in range(d.n_pins):
+        for k in range(4):
+            arr = _all_arrivals(d, lv, out, p, k, sinks, drv_of)
+            want = max(arr) if k >= 2 else min(arr)
+            assert out["at"][p, k] == pytest.approx(want, rel=1e-12, abs=1e-9)
+            req = _all_requireds(d, lv, out, p, k, sinks, in_cell)
+            if req:
+                want = min(req) if k >= 2 else max(req)
+                assert out["rat"][p, k] == pytest.approx(want, rel=1e-12, abs=1e-9)
