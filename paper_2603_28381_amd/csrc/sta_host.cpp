@@ -609,6 +609,10 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
     for (int l = 0; l < L; ++l) g->max_level_nets = std::max(g->max_level_nets, lcount[l + 1] - lcount[l]);
     build_schedule(g);
     compute_layouts(g);
+    // The kernels address arrays through 32-bit byte offsets from their bases.
+    const uint64_t lim = 1ull << 32;
+    if (16ull * (uint64_t)P >= lim || 64ull * (uint64_t)N >= lim || 16ull * (uint64_t)g->ell.size() >= lim)
+      return fail(STA_E_INVALID, "graph too large: a per-pin, per-net or per-input array reaches 4 GiB");
     g->levelized = true;
   } catch (const std::bad_alloc&) {
     return fail(STA_E_NOMEM, "host allocation failed");

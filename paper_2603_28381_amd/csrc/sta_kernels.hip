@@ -38,6 +38,19 @@ constexpr int kCellLanes = 16;   // lanes per cell: 4 conditions x 4 arcs
 constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
 constexpr int kRecChunks = 4;    // float4 chunks per arrival record, one per condition
 
+// Element i of an array through a 32-bit byte offset from its base.  The base is uniform,
+// so loads and stores take the scalar-base form with one 32-bit offset register instead of
+// a 64-bit address per lane.  The library rejects graphs with an array of 4 GiB or more.
+template <class T>
+__device__ __forceinline__ T* at32(T* base, uint32_t i) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<C*>(base) + (uint64_t)(i * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t i) {
+  return *at32(base, i);
+}
+
 // Placement snapshots of one graph share its topology; snapshot blockIdx.y of a launch
 // works on its own copy of the per-call buffers, `state` / `work` bytes (state and
 // workspace) or `pins` / `scal` elements (per-pin arrays, scalars) after snapshot 0's.
@@ -78,12 +91,12 @@ template <bool kPartials>
 __device__ __forceinline__ LutVal lut_eval(const float4* __restrict__ grid, const float4* __restrict__ coef,
                                            const LutKeys& keys, int arc, int tr, float xv, float yv) {
   const int cell = find_cell(xv, keys.x) * (STA_LUT_N - 1) + find_cell(yv, keys.y);
-  const float4 g = grid[cell];
+  const float4 g = ld(grid, (uint32_t)cell);
   const float tx = (xv - g.x) * g.y;
   const float ty = (yv - g.z) * g.w;
-  const float4* c = coef + ((size_t)(arc * 2 + tr) * kLutCells + cell) * 2;
-  const float4 cd = c[0];
-  const float4 cs = c[1];
+  const uint32_t ci = ((uint32_t)(arc * 2 + tr) * kLutCells + (uint32_t)cell) * 2;
+  const float4 cd = ld(coef, ci);
+  const float4 cs = ld(coef, ci + 1);
   const float bd = fmaf(cd.w, ty, cd.y);
   const float bs = fmaf(cs.w, ty, cs.y);
   LutVal r;
@@ -357,8 +370,8 @@ __device__ __forceinline__ ArcIn arc_input_entry(const int4 e, bool valid, const
   r.tp = e.w > 0 ? t : 1 - t;
   r.pin = e.y;
   const int kp = 2 * m + r.tp;
-  const float4 c = rec[kRecChunks * (size_t)max(e.x, 0) + kp];
-  const float2 w = wire[e.y];
+  const float4 c = ld(rec, (uint32_t)(kRecChunks * max(e.x, 0) + kp));
+  const float2 w = ld(wire, (uint32_t)e.y);
   r.at = c.x + w.x;
   r.slew = sink_slew(c.y, w.y);
   r.atg = c.z + w.x;
@@ -420,9 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
   const int n = n0 + kc;
   // Loads in three waves, each issued as soon as its addresses are known: the first input
   // slot entry and the root load; the source record and wire; the table coefficients.
-  const int4 e0 = ell[(size_t)sl.base + (size_t)min(jl, sl.F - 1) * sl.nc + kc];
-  const float load = loads[n];
-  const int slot = loc ? loc[n] : n;
+  const int4 e0 = ld(ell, (uint32_t)(sl.base + min(jl, sl.F - 1) * sl.nc + kc));
+  const float load = ld(loads, (uint32_t)n);
+  const int slot = loc ? ld(loc, (uint32_t)n) : n;
   if (slot < min_slot) return;                 // kept record, not recomputed
   float best_at = m ? -kInf : kInf;
   float best_sl = best_at;
@@ -452,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
   }
   if (jl == 0) {
     const float ag = m ? (a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("")) : 0.f;
-    rec[kRecChunks * (size_t)slot + k] = make_float4(best_at, best_sl, ag, 0.f);
+    *at32(rec, (uint32_t)(kRecChunks * slot + k)) = make_float4(best_at, best_sl, ag, 0.f);
   }
 }
 
@@ -733,16 +746,17 @@ struct SinkIn {
 template <bool kCanon, bool kGrad>
 __device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p) {
   SinkIn in;
-  in.rt = a.ratp[p];
-  in.w = a.wire[p];
-  in.q = kCanon ? p : a.io_perm[p];
+  const uint32_t u = (uint32_t)p;
+  in.rt = ld(a.ratp, u);
+  in.w = ld(a.wire, u);
+  in.q = kCanon ? p : ld(a.io_perm, u);
   in.aj = make_float4(0.f, 0.f, 0.f, 0.f);
   in.xs = in.ys = in.cp = 0.f;
   if (kGrad) {
-    in.aj = a.adjp[p];
-    in.xs = a.x[in.q];
-    in.ys = a.y[in.q];
-    in.cp = a.pin_cap[p];
+    in.aj = ld(a.adjp, u);
+    in.xs = ld(a.x, (uint32_t)in.q);
+    in.ys = ld(a.y, (uint32_t)in.q);
+    in.cp = ld(a.pin_cap, u);
   }
   return in;
 }
@@ -760,10 +774,12 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in
   const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
                                  sink_slew(sl_d.w, w.y));
   if (write) {
-    if (a.at_out) store_stream(a.at_out + q, ats);
-    if (a.slew_out) store_stream(a.slew_out + q, sls);
-    if (a.rat_out) store_stream(a.rat_out + q, rt);
-    if (a.slack_out) store_stream(a.slack_out + q, make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w));
+    const uint32_t uq = (uint32_t)q;
+    if (a.at_out) store_stream(at32(a.at_out, uq), ats);
+    if (a.slew_out) store_stream(at32(a.slew_out, uq), sls);
+    if (a.rat_out) store_stream(at32(a.rat_out, uq), rt);
+    if (a.slack_out)
+      store_stream(at32(a.slack_out, uq), make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w));
   }
   acc[R_E0] = fmaxf(acc[R_E0], rt.x - w.x);
   acc[R_E1] = fmaxf(acc[R_E1], rt.y - w.x);
@@ -897,12 +913,12 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const int k = lane16 >> 2, jl = lane16 & 3, m = k >> 1, t = k & 1;
   const bool cell_lane = gs.active && n >= a.N0 && gl < kCellLanes;
   const int kc = cell_lane ? n - a.N0 - sl.c0 : 0;   // position of the cell in its level
-  const size_t e_at = cell_lane ? (size_t)sl.base + (size_t)min(jl, sl.F - 1) * sl.nc + kc : 0;
-  const int p0 = a.net_off[n];
-  const int p1v = a.net_off[n + 1];
-  const int4 e = a.ell[e_at];
-  const float load = a.load[n];
-  const int slot = a.loc ? a.loc[n] : n;
+  const uint32_t e_at = cell_lane ? (uint32_t)(sl.base + min(jl, sl.F - 1) * sl.nc + kc) : 0u;
+  const int p0 = ld(a.net_off, (uint32_t)n);
+  const int p1v = ld(a.net_off, (uint32_t)n + 1u);
+  const int4 e = ld(a.ell, e_at);
+  const float load = ld(a.load, (uint32_t)n);
+  const int slot = a.loc ? ld(a.loc, (uint32_t)n) : n;
   const int p1 = gs.active ? p1v : p0;
 
   // Wave 2: the cell input's source record and wire first (the table lookup waits for
@@ -915,21 +931,21 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     ain.tp = e.w > 0 ? t : 1 - t;
     ain.pin = e.y;
     const int kp = 2 * m + ain.tp;
-    const float4 c = a.rec[kRecChunks * (size_t)max(e.x, 0) + kp];
-    const float2 w = a.wire[e.y];
+    const float4 c = ld(a.rec, (uint32_t)(kRecChunks * max(e.x, 0) + kp));
+    const float2 w = ld(a.wire, (uint32_t)e.y);
     ain.at = c.x + w.x;
     ain.slew = sink_slew(c.y, w.y);
     ain.atg = c.z + w.x;
   }
-  const float4* r = a.rec + kRecChunks * (size_t)slot;
+  const float4* r = at32(a.rec, (uint32_t)(kRecChunks * slot));
   const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
   const float4 at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
   const float4 sl_d = make_float4(c0.y, c1.y, c2.y, c3.y);
   float xd = 0.f, yd = 0.f;
   if (kGrad) {
-    const int q = kCanon ? p0 : a.io_perm[p0];
-    xd = a.x[q];
-    yd = a.y[q];
+    const int q = kCanon ? p0 : ld(a.io_perm, (uint32_t)p0);
+    xd = ld(a.x, (uint32_t)q);
+    yd = ld(a.y, (uint32_t)q);
   }
   const int s0 = p0 + 1 + gl;
   const int gstride = block ? kBlock : G;
@@ -990,11 +1006,11 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
     if (cell_lane && v.valid) {
       // RAT(input, k') = RAT(output, k) - arc delay.
-      reinterpret_cast<float*>(a.ratp + v.pin)[2 * m + v.tp] = rat_o - v.d;
+      *at32(reinterpret_cast<float*>(a.ratp), (uint32_t)(4 * v.pin + 2 * m + v.tp)) = rat_o - v.d;
       if (kGrad && m == 1) {
         const float dbar = expf((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
         const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
-        float* adj = reinterpret_cast<float*>(a.adjp + v.pin);
+        float* adj = reinterpret_cast<float*>(at32(a.adjp, (uint32_t)v.pin));
         adj[v.tp] = dbar;
         adj[2 + v.tp] = fmaf(dbar, v.ddx, s_j * v.dsx);
         lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
@@ -1021,12 +1037,12 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   if (kGrad && (a.dx || a.dy)) {
     const float cl = a.c * lbar;
     if (has0) {
-      if (a.dx) a.dx[keep0.q] = keep0.gx * (cl + keep0.rest);
-      if (a.dy) a.dy[keep0.q] = keep0.gy * (cl + keep0.rest);
+      if (a.dx) *at32(a.dx, (uint32_t)keep0.q) = keep0.gx * (cl + keep0.rest);
+      if (a.dy) *at32(a.dy, (uint32_t)keep0.q) = keep0.gy * (cl + keep0.rest);
     }
     if (has1) {
-      if (a.dx) a.dx[keep1.q] = keep1.gx * (cl + keep1.rest);
-      if (a.dy) a.dy[keep1.q] = keep1.gy * (cl + keep1.rest);
+      if (a.dx) *at32(a.dx, (uint32_t)keep1.q) = keep1.gx * (cl + keep1.rest);
+      if (a.dy) *at32(a.dy, (uint32_t)keep1.q) = keep1.gy * (cl + keep1.rest);
     }
     if (block) {
       for (int p = s0 + 2 * gstride; p < p1; p += gstride) {
@@ -1038,17 +1054,17 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
   }
   if (gl == 0) {
-    const int q = kCanon ? p0 : a.io_perm[p0];
-    if (a.at_out) store_stream(a.at_out + q, at_d);
-    if (a.slew_out) store_stream(a.slew_out + q, sl_d);
-    if (a.rat_out) store_stream(a.rat_out + q, make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]));
+    const uint32_t q = (uint32_t)(kCanon ? p0 : ld(a.io_perm, (uint32_t)p0));
+    if (a.at_out) store_stream(at32(a.at_out, q), at_d);
+    if (a.slew_out) store_stream(at32(a.slew_out, q), sl_d);
+    if (a.rat_out) store_stream(at32(a.rat_out, q), make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]));
     if (a.slack_out)
-      store_stream(a.slack_out + q,
+      store_stream(at32(a.slack_out, q),
                    make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w));
     if (kGrad) {
       const float cl = a.c * lbar;
-      if (a.dx) a.dx[q] = -(acc[X_RS] + cl * acc[X_N]);
-      if (a.dy) a.dy[q] = -(acc[Y_RS] + cl * acc[Y_N]);
+      if (a.dx) *at32(a.dx, q) = -(acc[X_RS] + cl * acc[X_N]);
+      if (a.dy) *at32(a.dy, q) = -(acc[Y_RS] + cl * acc[Y_N]);
     }
   }
 }
