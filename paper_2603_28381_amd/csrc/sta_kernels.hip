@@ -937,8 +937,8 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     ain.slew = sink_slew(c.y, w.y);
     ain.atg = c.z + w.x;
   }
-  const float4* r = at32(a.rec, (uint32_t)(kRecChunks * slot));
-  const float4 c0 = r[0], c1 = r[1], c2 = r[2], c3 = r[3];
+  const uint32_t rs = (uint32_t)(kRecChunks * slot);
+  const float4 c0 = ld(a.rec, rs), c1 = ld(a.rec, rs + 1), c2 = ld(a.rec, rs + 2), c3 = ld(a.rec, rs + 3);
   const float4 at_d = make_float4(c0.x, c1.x, c2.x, c3.x);
   const float4 sl_d = make_float4(c0.y, c1.y, c2.y, c3.y);
   float xd = 0.f, yd = 0.f;
@@ -1010,9 +1010,9 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
       if (kGrad && m == 1) {
         const float dbar = expf((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
         const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
-        float* adj = reinterpret_cast<float*>(at32(a.adjp, (uint32_t)v.pin));
-        adj[v.tp] = dbar;
-        adj[2 + v.tp] = fmaf(dbar, v.ddx, s_j * v.dsx);
+        float* adj = reinterpret_cast<float*>(a.adjp);
+        *at32(adj, (uint32_t)(4 * v.pin + v.tp)) = dbar;
+        *at32(adj, (uint32_t)(4 * v.pin + 2 + v.tp)) = fmaf(dbar, v.ddx, s_j * v.dsx);
         lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
       }
     }
