@@ -1149,6 +1149,9 @@ sta_status check_ready(sta_graph* g) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != g->dev.device) return fail(STA_E_STATE, "graph lives on another device than the current one");
+  // Snapshot offsets of the state reach the level kernels as 32-bit scalars.
+  if (g->n_snap > 1 && g->state.total > (size_t)INT32_MAX)
+    return fail(STA_E_INVALID, "forward state of one snapshot exceeds 2 GiB; sweep fewer pins per snapshot");
   return STA_OK;
 }
 
