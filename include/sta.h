@@ -201,7 +201,10 @@ sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out
  * TNS_g (or WNS_g with STA_GRAD_WNS) with respect to x, y.  x, y must hold the same
  * coordinates given to sta_forward, and fwd->state its result (computed with STA_SMOOTH
  * for STA_GRAD) on the same graph; flags must carry the same STA_CANONICAL_IO and gamma_ps
- * the same value as that call.
+ * the same value as that call.  Without checkpointing the backward only reads fwd->state,
+ * so several backward calls on one state (e.g. a required-time sweep and a gradient sweep
+ * on two streams, each with its own workspace) may run concurrently; with checkpointing
+ * it rebuilds records inside the state and calls on one state must not overlap.
  * Errors: STA_E_STATE (not levelized / not uploaded), STA_E_INVALID.
  * ------------------------------------------------------------------------------------- */
 sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,

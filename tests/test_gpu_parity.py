@@ -488,3 +488,41 @@ def test_batched_workload_members_equal_alone_at_full_size():
             b = o1[k].cpu().numpy()[inv[pin[sel]]]
             assert np.array_equal(a, b, equal_nan=True), (i, k)
         assert np.array_equal(fu.scalars[i].cpu().numpy(), f1.scalars.cpu().numpy()), i
+
+
+@pytest.mark.parametrize("wns", [False, True])
+def test_split_and_two_stream_passes_equal_fused_bitwise(wns):
+    # Operation fusion (Sec. 3.2): the fused backward sweep (required times and the adjoint
+    # in one pass) against the same work split into a required-time pass and a gradient
+    # pass, run one after the other on one stream and concurrently on two streams with
+    # their own workspaces.  Every output must be identical.
+    d = make_design(scaled_spec(60_000, cfg_id=43, box_um=400.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    x = torch.tensor(d.x, device="cuda")
+    y = torch.tensor(d.y, device="cuda")
+    fwd = g.forward(x, y, gamma=GAMMA)
+    fused = g.backward(x, y, fwd, rat=True, grad=True, wns=wns, pins=True)
+    torch.cuda.synchronize()
+    fused = {k: v.cpu().numpy() for k, v in fused.items()}
+
+    rat_only = g.backward(x, y, fwd, rat=True, grad=False, pins=True)
+    grad_only = g.backward(x, y, fwd, rat=False, grad=True, wns=wns, pins=False)
+    torch.cuda.synchronize()
+    assert set(rat_only) == {"at", "slew", "rat", "slack"} and set(grad_only) == {"dx", "dy"}
+
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ev = torch.cuda.Event()
+    ev.record()
+    s1.wait_event(ev)
+    s2.wait_event(ev)
+    two = {}
+    for _ in range(3):          # repeated so that the two sweeps overlap after the first
+        with torch.cuda.stream(s1):     # buffers allocated on the stream that uses them
+            two.update(g.backward(x, y, fwd, rat=True, grad=False, pins=True, stream=s1))
+        with torch.cuda.stream(s2):
+            two.update(g.backward(x, y, fwd, rat=False, grad=True, wns=wns, pins=False, stream=s2))
+    torch.cuda.synchronize()
+    for name, res in (("one stream", {**rat_only, **grad_only}), ("two streams", two)):
+        for k, v in res.items():
+            assert np.array_equal(v.cpu().numpy(), fused[k], equal_nan=True), (name, k)
