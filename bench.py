@@ -473,6 +473,61 @@ def run_fusion(args) -> dict:
                      "fused about 116%"}
 
 
+def run_rc(args) -> dict:
+    """RC-stage mapping ablation (Sec. 3.1.1, Alg. 1-2, Table 2 of the paper): the RC net delay
+    kernel and the whole forward+backward step with the RC stage mapped as lane groups per net
+    (the pin-based scheme), as Alg. 2's workgroup task pool (CTE), and one thread per net (the
+    mapping of earlier GPU timers); mid-size and 2.5M-pin designs, canonical order."""
+    import torch
+    from gen.netlist import CFG1, CFG2, make_design
+    from paper_2603_28381_amd import Graph
+
+    res = {}
+    for name, spec in (("cfg1", CFG1), ("cfg2", CFG2)):
+        d = make_design(spec)
+        g = Graph.from_design(d)
+        g.levelize()
+        g.upload()
+        lev = g.levelization()
+        alg = algorithmic_bytes(d, lev["level"])
+        P = d.n_pins
+        dev = torch.device("cuda")
+        perm = torch.from_numpy(lev["pin_perm"].astype(np.int64))
+        x = torch.from_numpy(d.x)[perm].contiguous().to(dev)
+        y = torch.from_numpy(d.y)[perm].contiguous().to(dev)
+        state, ws, scal, outs = step_buffers(g, P, dev)
+
+        def step():
+            f = g.forward(x, y, gamma=args.gamma, smooth=True, canonical=True, state=state, scalars=scal)
+            g.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs)
+
+        r = {"pins": P, "rc_alg_bytes": float(np.sum(alg["rc"]))}
+        for scheme in ("groups", "cte", "thread"):
+            g.set_schedule(4, 2, 64, scheme)
+            ms = timed(step, args.steps, args.warmup)[0]
+            g.profile(True)
+            for _ in range(args.steps):
+                step()
+            torch.cuda.synchronize()
+            n_rc, t_rc = g.profile_read()["rc"]
+            g.profile(False)
+            us = 1e3 * t_rc / n_rc
+            r[scheme] = {"rc_us": round(us, 2), "rc_gbs": round(r["rc_alg_bytes"] / (us * 1e-6) / 1e9, 1),
+                         "step_ms": round(ms, 4)}
+        r["groups_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["groups"]["rc_us"], 2)
+        r["cte_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["cte"]["rc_us"], 2)
+        res[name] = r
+        del state, ws, outs, g
+        torch.cuda.empty_cache()
+    c2 = res["cfg2"]
+    return {"metric": "RC net delay kernel speedup of lane groups over one thread per net", "value":
+            c2["groups_speedup_vs_thread"], "unit": "x", "ms_per_step": c2["groups"]["step_ms"], "dtype": "f32",
+            "config": {"workload": "RC mapping ablation: lane groups (pin-based), CTE task pool, one thread per net; "
+                                   "800k-pin and 2.5M-pin designs", "io": "canonical order, HBM resident"},
+            "variants": res,
+            "paper": "Table 2 (RTX 4090, whole STA): pin-based 236% and CTE 124% of GPU-Timer's speed"}
+
+
 def run_serve(args) -> dict:
     """Served workload: 12 resident designs of 5k-2.5M pins (log-uniform), an open-loop
     Poisson stream of requests (70% forward slack queries on resident coordinates, 30%
@@ -625,7 +680,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "fusion"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "fusion", "rc"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -651,7 +706,7 @@ def main(argv=None) -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"cfg3": run_batch, "cfg4": run_serve, "fusion": run_fusion}.get(args.workload, run_single)
+    run = {"cfg3": run_batch, "cfg4": run_serve, "fusion": run_fusion, "rc": run_rc}.get(args.workload, run_single)
     res = run(args)
     line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),

@@ -227,15 +227,23 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
  * level kernels use groups of (1 << sweep_group_log2) lanes and doublings up to a wave
  * (16 lanes at least, since a cell step spreads 4 conditions x 4 arcs over 16 lanes), the
  * one-pass kernels (RC, output expansion) groups from (1 << flat_group_log2) lanes, and
- * nets with more than heavy_sinks sinks take a whole 256-thread workgroup.  Defaults
- * {4, 2, 64}.  Setting a schedule rebuilds the launch plan (no result changes beyond
- * float summation order).  Errors: STA_E_INVALID for out-of-range fields, STA_E_STATE if
- * not levelized.
+ * nets with more than heavy_sinks sinks take a whole 256-thread workgroup.  rc_scheme
+ * picks the mapping of the RC net delay stage (Sec. 3.1.1): these lane groups (the
+ * pin-based scheme of Alg. 1), the CTE task pool of Alg. 2 (a workgroup pools the sinks of
+ * 256 nets and rebalances them over its threads), or one thread per net.  Defaults
+ * {4, 2, 64, STA_RC_GROUPS}.  Setting a schedule rebuilds the launch plan (no result
+ * changes beyond float summation order).  Errors: STA_E_INVALID for out-of-range fields,
+ * STA_E_STATE if not levelized.
  * ------------------------------------------------------------------------------------- */
+#define STA_RC_GROUPS 0   /* lane groups per net (Alg. 1) */
+#define STA_RC_CTE 1      /* workgroup task pool (Alg. 2) */
+#define STA_RC_THREAD 2   /* one thread per net */
+
 typedef struct sta_schedule {
   int32_t sweep_group_log2;   /* 4..6 */
   int32_t flat_group_log2;    /* 2..6 */
   int32_t heavy_sinks;        /* 1..64 */
+  int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */
 } sta_schedule;
 
 sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);

@@ -641,7 +641,8 @@ sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch) {
 sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   if (!g || !sch) return fail(STA_E_INVALID, "NULL argument");
   if (sch->sweep_group_log2 < 4 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
-      sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64)
+      sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64 || sch->rc_scheme < STA_RC_GROUPS ||
+      sch->rc_scheme > STA_RC_THREAD)
     return fail(STA_E_INVALID, "schedule out of range");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   g->sched_cfg = *sch;

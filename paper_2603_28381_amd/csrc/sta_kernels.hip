@@ -284,10 +284,44 @@ struct RcArgs {
   float2* __restrict__ wire;
   float* __restrict__ load;
   float4* __restrict__ rec;
-  int N0;
+  int N0, N;
   float r, c, pi_at, pi_slew;
   Snap snap;
 };
+
+// One sink p of a star net whose driver sits at (xd, yd): wire delay and impulse (Eq. 2-3)
+// to wire[p]; returns what the sink adds to the root load (Eq. 1): its pin cap plus the
+// whole wire, half of which sits at each end.
+__device__ __forceinline__ float rc_sink(const RcArgs& a, const float* __restrict__ xs, const float* __restrict__ ys,
+                                         float2* __restrict__ wire, int p, float xd, float yd) {
+  const int q = a.io_perm ? a.io_perm[p] : p;
+  const float cp = a.pin_cap[p];
+  const float len = fabsf(xs[q] - xd) + fabsf(ys[q] - yd);
+  const float res = a.r * len;                 // Res(fa(u) -> u)
+  const float cw = a.c * len;                  // wire capacitance, half at each end
+  const float cap = fmaf(0.5f, cw, cp);        // Cap(u) of the sink node
+  const float load = cap;                      // Eq. 1 at a leaf
+  const float dly = 1e-3f * res * load;        // Eq. 2 (ohm * fF = 1e-3 ps)
+  const float arg = 2.0f * (1e-3f * res * cap) * dly - dly * dly;   // Eq. 3
+  const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
+  wire[p] = make_float2(dly, imp);
+  return cp + cw;
+}
+
+// Root of net n (driver pin p0) once its sinks' contributions are summed: the root load,
+// a zero wire at the driver, and the arrival record of a primary-input net.
+__device__ __forceinline__ void rc_root(const RcArgs& a, float2* __restrict__ wire, float* __restrict__ loads,
+                                        float4* __restrict__ rec, int n, int p0, float sum) {
+  loads[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
+  wire[p0] = make_float2(0.f, 0.f);
+  if (n < a.N0) {
+    float4* r = rec + kRecChunks * (size_t)n;
+    r[0] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
+    r[1] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
+    r[2] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
+    r[3] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
+  }
+}
 
 // RC net delay of every net (Sec. 3.1.1, Eq. 1-3, star nets): per sink the wire delay and
 // impulse, per net the root load by a group reduction.  Level-0 (primary input) records
@@ -312,32 +346,103 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     yd = ys[q];
   }
   float sum = 0.f;
-  for (int p = p0 + 1 + gs.gl; p < p1; p += gs.G) {
-    const int q = a.io_perm ? a.io_perm[p] : p;
-    const float cp = a.pin_cap[p];
-    const float len = fabsf(xs[q] - xd) + fabsf(ys[q] - yd);
-    const float res = a.r * len;                 // Res(fa(u) -> u)
-    const float cw = a.c * len;                  // wire capacitance, half at each end
-    const float cap = fmaf(0.5f, cw, cp);        // Cap(u) of the sink node
-    const float load = cap;                      // Eq. 1 at a leaf
-    const float dly = 1e-3f * res * load;        // Eq. 2 (ohm * fF = 1e-3 ps)
-    const float arg = 2.0f * (1e-3f * res * cap) * dly - dly * dly;   // Eq. 3
-    const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
-    wire[p] = make_float2(dly, imp);
-    sum += cp + cw;                              // the sink's Load plus the root half of the wire
-  }
+  for (int p = p0 + 1 + gs.gl; p < p1; p += gs.G) sum += rc_sink(a, xs, ys, wire, p, xd, yd);
   sum = gs.block ? block_sum(sum, sh) : wave_group_sum(sum, gs.G);
-  if (gs.active && gs.gl == 0) {
-    loads[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
-    wire[p0] = make_float2(0.f, 0.f);
-    if (n < a.N0) {
-      float4* r = rec + kRecChunks * (size_t)n;
-      r[0] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
-      r[1] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
-      r[2] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
-      r[3] = make_float4(a.pi_at, a.pi_slew, a.pi_at, 0.f);
+  if (gs.active && gs.gl == 0) rc_root(a, wire, loads, rec, n, p0, sum);
+}
+
+// The same in the CTE scheme (Alg. 2): a workgroup takes 256 consecutive nets, one per
+// thread, and pools their sinks into one task list.  A work-efficient exclusive scan
+// (up-sweep, then down-sweep) over the per-net sink counts numbers the tasks; threads take
+// tasks with a stride of 256 and find a task's net by binary search for the last net whose
+// first task is not above it.  The model here is the same for the four timing conditions,
+// so a task is one sink rather than one (sink, condition) pair.  Root loads are summed in
+// task order from LDS, in chunks of kCteChunk tasks, by each net's own thread.
+constexpr int kCteChunk = 1024;
+__global__ __launch_bounds__(kBlock) void k_rc_cte(RcArgs a) {
+  __shared__ int pre[kBlock];
+  __shared__ int first[kBlock];
+  __shared__ float dx_[kBlock], dy_[kBlock];
+  __shared__ float part[kCteChunk];
+  __shared__ int total_sh;
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
+  float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
+  const int t = threadIdx.x;
+  const int n = (int)blockIdx.x * kBlock + t;
+  const bool own = n < a.N;
+  int p0 = 0, work = 0;
+  float xd = 0.f, yd = 0.f;
+  if (own) {
+    p0 = a.net_off[n];
+    work = a.net_off[n + 1] - p0 - 1;
+    const int q = a.io_perm ? a.io_perm[p0] : p0;
+    xd = xs[q];
+    yd = ys[q];
+  }
+  pre[t] = work;
+  first[t] = p0 + 1;
+  dx_[t] = xd;
+  dy_[t] = yd;
+  // Up-sweep: pre[t] becomes the sum of its subtree.
+  for (int d = 1; d < kBlock; d <<= 1) {
+    __syncthreads();
+    if (((t + 1) & (2 * d - 1)) == 0) pre[t] += pre[t - d];
+  }
+  __syncthreads();
+  if (t == kBlock - 1) {
+    total_sh = pre[t];
+    pre[t] = 0;
+  }
+  // Down-sweep: exclusive prefix sums.
+  for (int d = kBlock / 2; d >= 1; d >>= 1) {
+    __syncthreads();
+    if (((t + 1) & (2 * d - 1)) == 0) {
+      const int l = pre[t - d];
+      pre[t - d] = pre[t];
+      pre[t] += l;
     }
   }
+  __syncthreads();
+  const int total = total_sh;
+  const int my0 = pre[t], my1 = t + 1 < kBlock ? pre[t + 1] : total;
+  float sum = 0.f;
+  for (int c0 = 0; c0 < total; c0 += kCteChunk) {
+    const int c1 = min(total, c0 + kCteChunk);
+    for (int task = c0 + t; task < c1; task += kBlock) {
+      int lo = 0, hi = kBlock;                 // upper_bound(pre, task) - 1
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= task) lo = mid; else hi = mid;
+      }
+      const int p = first[lo] + (task - pre[lo]);
+      part[task - c0] = rc_sink(a, xs, ys, wire, p, dx_[lo], dy_[lo]);
+    }
+    __syncthreads();
+    for (int i = max(my0, c0); i < min(my1, c1); ++i) sum += part[i - c0];
+    __syncthreads();
+  }
+  if (own) rc_root(a, wire, loads, rec, n, p0, sum);
+}
+
+// The same with one thread per net walking its sinks in order (the net-per-thread mapping
+// of earlier GPU timers, kept as the baseline of the lane-group and CTE schemes).
+__global__ __launch_bounds__(kBlock) void k_rc_thread(RcArgs a) {
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
+  float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
+  const int n = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (n >= a.N) return;
+  const int p0 = a.net_off[n], p1 = a.net_off[n + 1];
+  const int q = a.io_perm ? a.io_perm[p0] : p0;
+  const float xd = xs[q], yd = ys[q];
+  float sum = 0.f;
+  for (int p = p0 + 1; p < p1; ++p) sum += rc_sink(a, xs, ys, wire, p, xd, yd);
+  rc_root(a, wire, loads, rec, n, p0, sum);
 }
 
 // ---------------------------------------------------------------------------- cell inputs
@@ -1236,11 +1341,17 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
   const Snap sn = snap_of(g);
-  RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0,
+  RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0, g->N,
             g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn};
   {
     LaunchTimer t(g, s, STA_K_RC);
-    k_rc<<<snap_grid(g, range_grid(g->all_range)), kBlock, 0, s>>>(ra);
+    const unsigned per_net = (unsigned)((g->N + kBlock - 1) / kBlock);
+    if (g->sched_cfg.rc_scheme == STA_RC_CTE)
+      k_rc_cte<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
+    else if (g->sched_cfg.rc_scheme == STA_RC_THREAD)
+      k_rc_thread<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
+    else
+      k_rc<<<snap_grid(g, range_grid(g->all_range)), kBlock, 0, s>>>(ra);
   }
 
   const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, smooth ? 1.0f / gamma_ps : 0.f,
@@ -1471,30 +1582,37 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
+  // Times one candidate and keeps it if it is the fastest so far.
+  auto try_schedule = [&](const sta_schedule& cand) {
+    st = sta_set_schedule(g, &cand);
+    for (int r = -1; r < reps && st == STA_OK; ++r) {
+      if (r == 0) (void)hipEventRecord(e0, s);
+      st = launch_forward(g, x, y, &fo, ff, gamma_ps, s);
+      if (st == STA_OK) st = launch_backward(g, x, y, &fo, &bo, bf, gamma_ps, s);
+    }
+    if (st != STA_OK) return;
+    (void)hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "hipEventSynchronize");
+      return;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_s = cand;
+    }
+  };
+  // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
+  // task pool, one thread per net) on the best of those.
   for (int sweep = 4; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
-      for (int heavy : {32, 64}) {
-        const sta_schedule cand{sweep, flat, heavy};
-        st = sta_set_schedule(g, &cand);
-        for (int r = -1; r < reps && st == STA_OK; ++r) {
-          if (r == 0) (void)hipEventRecord(e0, s);
-          st = launch_forward(g, x, y, &fo, ff, gamma_ps, s);
-          if (st == STA_OK) st = launch_backward(g, x, y, &fo, &bo, bf, gamma_ps, s);
-        }
-        if (st != STA_OK) break;
-        (void)hipEventRecord(e1, s);
-        hipError_t e = hipEventSynchronize(e1);
-        if (e != hipSuccess) {
-          st = hip_fail(e, "hipEventSynchronize");
-          break;
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best_s = cand;
-        }
-      }
+      for (int heavy : {32, 64})
+        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS});
+  const sta_schedule lanes = best_s;
+  for (int rc : {STA_RC_CTE, STA_RC_THREAD})
+    if (st == STA_OK) try_schedule(sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc});
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (void* p : buf) (void)hipFree(p);

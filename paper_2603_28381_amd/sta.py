@@ -26,6 +26,7 @@ STA_GRAD = 1 << 3
 STA_GRAD_WNS = 1 << 4
 STA_GRAPH = 1 << 5
 STA_REQ_FWD, STA_REQ_FWD_BWD = 0, 1
+STA_RC_GROUPS, STA_RC_CTE, STA_RC_THREAD = 0, 1, 2
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
@@ -68,7 +69,7 @@ class StaGraphInfo(ctypes.Structure):
 
 class StaSchedule(ctypes.Structure):
     _fields_ = [("sweep_group_log2", ctypes.c_int32), ("flat_group_log2", ctypes.c_int32),
-                ("heavy_sinks", ctypes.c_int32)]
+                ("heavy_sinks", ctypes.c_int32), ("rc_scheme", ctypes.c_int32)]
 
 
 class StaServerConfig(ctypes.Structure):
@@ -316,12 +317,17 @@ class Graph:
         _check(_lib.sta_get_schedule(self._h, ctypes.byref(sch)))
         return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
 
-    def set_schedule(self, sweep_group_log2: int, flat_group_log2: int, heavy_sinks: int):
-        sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks)
+    def set_schedule(self, sweep_group_log2: int, flat_group_log2: int, heavy_sinks: int,
+                     rc_scheme: int | str = 0):
+        """rc_scheme: 0 / "groups" (lane groups, Alg. 1), 1 / "cte" (task pool, Alg. 2),
+        2 / "thread" (one thread per net)."""
+        rc = {"groups": STA_RC_GROUPS, "cte": STA_RC_CTE, "thread": STA_RC_THREAD}.get(rc_scheme, rc_scheme)
+        sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks, int(rc))
         _check(_lib.sta_set_schedule(self._h, ctypes.byref(sch)))
 
     def tune(self, x, y, gamma: float = 10.0, reps: int = 3, stream=None) -> dict:
-        """Time the candidate lane-group schedules on these coordinates and keep the fastest."""
+        """Time the candidate schedules (lane groups, then the RC mappings) on these coordinates
+        and keep the fastest."""
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)

@@ -299,11 +299,17 @@ def test_graph_capture_replays_match_plain_calls():
 
 
 def test_schedules_agree_with_oracle():
-    # Every lane-group schedule sweeps the same arithmetic (summation order aside).
+    # Every schedule sweeps the same arithmetic (summation order aside): lane groups, and the
+    # RC stage as Alg. 2's task pool (pools of 256 nets that span several LDS chunks of
+    # sinks here) or one thread per net.
     d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
     ref = O.run(d, gamma=GAMMA, grad="tns")
     g = Graph.from_design(d)
-    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1)):
+    g.levelize()
+    sinks = (np.diff(d.net_offsets) - 1)[g.levelization()["net_perm"]]
+    pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
+    assert pools.max() > 2 * 1024, pools.max()
+    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread")):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
