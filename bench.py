@@ -528,6 +528,38 @@ def run_rc(args) -> dict:
             "paper": "Table 2 (RTX 4090, whole STA): pin-based 236% and CTE 124% of GPU-Timer's speed"}
 
 
+def run_place(args) -> dict:
+    """Synthetic timing-driven placement loop (Sec. 3.3): every iteration runs the smoothed
+    forward sweep and the fused gradient sweep of the mid-size design, gathers the pin gradients
+    to cells and takes one Adam step of the cells.  Reports iterations per second and the
+    timing before and after."""
+    import torch
+    from gen.netlist import CFG1, make_design
+    from paper_2603_28381_amd import Graph, TimingDescent
+
+    d = make_design(CFG1)
+    g = Graph.from_design(d)
+    g.levelize()
+    g.upload()
+    td = TimingDescent(g, d.x, d.y, d.cell_in_offsets, d.cell_in_pins, d.cell_out_pin, gamma=args.gamma, lr=1.0,
+                       anchor=1e-4)
+    iters = max(args.steps, 1) * 5
+    first = td.evaluate().cpu().numpy()
+    ms, _ = timed(td.step, iters, args.warmup)
+    last = td.evaluate().cpu().numpy()
+    x, y = td.coordinates()
+    disp = torch.sqrt((x - td.x0) ** 2 + (y - td.y0) ** 2)
+    names = ("wns", "tns", "wns_g", "tns_g")
+    return {"metric": "timing-driven placement iterations/sec (STA + TNS_g gradient + cell step)",
+            "value": round(1e3 / ms, 1), "unit": "iterations/s", "ms_per_step": round(ms, 4), "dtype": "f32",
+            "config": {"workload": f"placement loop: {d.n_pins}-pin design, {d.n_cells} movable cells, "
+                                   f"{iters + args.warmup} Adam steps of 1 um on cell x, y against TNS_g "
+                                   f"(gamma {args.gamma} ps) with a quadratic anchor", "pins": d.n_pins},
+            "timing_before": {k: float(v) for k, v in zip(names, first)},
+            "timing_after": {k: float(v) for k, v in zip(names, last)},
+            "mean_displacement_um": round(float(disp.mean()), 3), "max_displacement_um": round(float(disp.max()), 3)}
+
+
 def run_serve(args) -> dict:
     """Served workload: 12 resident designs of 5k-2.5M pins (log-uniform), an open-loop
     Poisson stream of requests (70% forward slack queries on resident coordinates, 30%
@@ -680,7 +712,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "fusion", "rc"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2", "cfg3", "cfg4", "fusion", "rc", "place"])
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -706,7 +738,8 @@ def main(argv=None) -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"cfg3": run_batch, "cfg4": run_serve, "fusion": run_fusion, "rc": run_rc}.get(args.workload, run_single)
+    run = {"cfg3": run_batch, "cfg4": run_serve, "fusion": run_fusion, "rc": run_rc,
+           "place": run_place}.get(args.workload, run_single)
     res = run(args)
     line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),

@@ -14,7 +14,7 @@ def test_more_than_one_gpu_exits_with_message(capsys):
 
 
 def test_every_workload_has_a_runner():
-    for name in ("run_single", "run_batch", "run_serve", "run_fusion", "run_rc", "checkpoint_comparison"):
+    for name in ("run_single", "run_batch", "run_serve", "run_fusion", "run_rc", "run_place", "checkpoint_comparison"):
         assert callable(getattr(bench, name))
 
 

@@ -273,3 +273,30 @@ def test_snapshots_scale_per_call_buffers():
 def test_levelization_bit_exact_wide_cells():
     from tests._designs import wide_dag
     _levelization_matches(wide_dag(seed=5))
+
+
+def test_placement_loop_pin_cell_maps():
+    # The placement loop's gather of pin gradients to cells (built on the host).
+    import torch
+    from paper_2603_28381_amd import TimingDescent
+    d = make_design(tiny_spec(40, 5, n_pi=4, seed=7))
+    g = S.Graph.from_design(d)
+    g.levelize()
+    td = TimingDescent(g, d.x, d.y, d.cell_in_offsets, d.cell_in_pins, d.cell_out_pin, device="cpu")
+    idx, cell = td.idx.numpy(), td.cell.numpy()
+    P, C = d.n_pins, d.n_cells
+    for c in range(C):
+        pins = [d.cell_out_pin[c]] + list(d.cell_in_pins[d.cell_in_offsets[c]:d.cell_in_offsets[c + 1]])
+        assert sorted(p for p in idx[c] if p != P) == sorted(pins)
+        assert all(cell[p] == c for p in pins)
+    owned = np.zeros(P, bool)
+    owned[d.cell_out_pin] = True
+    owned[d.cell_in_pins] = True
+    assert np.all(cell[~owned] == C)
+    # pin gradients gathered per cell equal a plain loop
+    gp = torch.arange(P, dtype=torch.float32) * 0.5 + 1.0
+    got = torch.cat([gp, torch.zeros(1)])[td.idx].sum(1).numpy()
+    for c in range(C):
+        pins = [d.cell_out_pin[c]] + list(d.cell_in_pins[d.cell_in_offsets[c]:d.cell_in_offsets[c + 1]])
+        assert got[c] == pytest.approx(float(sum(gp[p] for p in pins)))
+    g.close()
