@@ -23,7 +23,7 @@ Original pin, net and cell ids are random permutations, so the canonical
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 import math
 
 import numpy as np
@@ -121,6 +121,7 @@ class Design:
     cons: Constraints
     gen_net_level: np.ndarray    # int32 [N], level the generator built each (original) net at
     stats: dict = field(default_factory=dict)
+    pin_parent: np.ndarray | None = None   # int32 [P]: RC tree parent pin (-1 at drivers); None: stars
 
     @property
     def n_arcs(self) -> int:
@@ -337,3 +338,28 @@ def tiny_spec(n_gates: int, n_levels: int, n_pi: int = 4, seed: int = 0, box_um:
     """Small designs for brute-force checks (a few gates, a few levels)."""
     return Spec(f"tiny{seed}", 500 + seed, n_gates, n_pi, n_levels, min(2, n_pi), "geom",
                 box_um, geom_p=fanout_p, geom_cap=fanout_cap)
+
+
+def heap_trees(d: Design) -> Design:
+    """The same design with an RC tree on every net instead of a star.
+
+    Per net, the driver and then the sinks sorted by Manhattan distance from the driver
+    (ties in net order) fill a binary heap: the k-th pin of that order hangs off the
+    (k - 1) // 2-th, so trees branch in two and are about log2(pins) deep.
+    """
+    off = d.net_offsets.astype(np.int64)
+    pins = d.net_pins.astype(np.int64)
+    cnt = np.diff(off)
+    net = np.repeat(np.arange(d.n_nets), cnt)
+    pos = np.arange(len(pins)) - off[net]
+    drv = pins[off[:-1]][net]
+    x, y = d.x.astype(np.float64), d.y.astype(np.float64)
+    dist = np.abs(x[pins] - x[drv]) + np.abs(y[pins] - y[drv])
+    dist[pos == 0] = -1.0                       # the driver first
+    order = np.lexsort((pos, dist, net))
+    sp, sn = pins[order], net[order]
+    rank = np.arange(len(pins)) - off[sn]
+    sink = rank >= 1
+    parent = np.full(d.n_pins, -1, np.int64)
+    parent[sp[sink]] = sp[off[sn[sink]] + (rank[sink] - 1) // 2]
+    return replace(d, pin_parent=parent.astype(np.int32))

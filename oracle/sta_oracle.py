@@ -38,6 +38,16 @@ Readings of what the paper leaves open (each used below):
   R10 only the late max merge is smoothed, using the hard-path arc delays and slews;
       smoothed slack s_e = -LSE(-slack_rise, -slack_fall), TNS_g = -sum_e LSE(0, -s_e),
       WNS_g = -LSE({0} u {-s_e}).
+  R11 a design may instead give every net an RC tree over its own pins (each sink's
+      parent pin, the driver at the root; one segment per sink, Manhattan length).
+      Eq. 1 then sums Loads over children recursively, Eq. 2 gains the parent's delay,
+      Delay(u) = Delay(fa(u)) + Res(fa(u) -> u) * Load(u) (the paper's Eq. 2 omits it,
+      which is exact for the depth-1 trees of R1), and the impulse of Eq. 3 takes the
+      second moment of the TAU 2015 model the paper cites for Eq. 1-3:
+      LDelay(u) = Cap(u) * Delay(u) + sum over children of LDelay(v),
+      Beta(u) = Beta(fa(u)) + Res(fa(u) -> u) * LDelay(u),
+      Impulse(u) = sqrt(2 * Beta(u) - Delay(u)^2), clamped at 0.  On a star, Beta(u) =
+      Res(u) * Cap(u) * Delay(u) and this is Eq. 3.
 """
 from __future__ import annotations
 
@@ -152,8 +162,11 @@ def rc(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor):
     """Per-pin wire length, node capacitance, Load (Eq. 1), Delay (Eq. 2), Impulse (Eq. 3).
 
     Returns dict of float64 tensors indexed by original pin id; Load is also given per net
-    (the root load of the net, which is the load a driving cell sees).
+    (the root load of the net, which is the load a driving cell sees).  Designs with RC
+    trees (d.pin_parent) go through rc_tree (reading R11).
     """
+    if getattr(d, "pin_parent", None) is not None:
+        return rc_tree(d, lv, x, y)
     P, N = d.n_pins, d.n_nets
     r, c = float(d.cons.r_per_um), float(d.cons.c_per_um)
     net = torch.from_numpy(lv.net_of_pin)
@@ -176,6 +189,67 @@ def rc(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor):
     pos = arg > 0
     imp = torch.where(pos, torch.sqrt(torch.where(pos, arg, torch.ones((), dtype=F64))), torch.zeros((), dtype=F64))
     return dict(length=length, cap_node=cap_node, load_root=load_root, delay=delay, imp=imp)
+
+
+def tree_depth(parent: np.ndarray) -> np.ndarray:
+    """Depth of every pin in its net's RC tree (0 at the driver), by following parents."""
+    P = len(parent)
+    depth = np.full(P, -1, np.int64)
+    depth[parent < 0] = 0
+    for _ in range(P + 1):
+        todo = depth < 0
+        if not todo.any():
+            return depth
+        ready = todo & (depth[np.where(parent >= 0, parent, 0)] >= 0) & (parent >= 0)
+        if not ready.any():
+            raise ValueError("pin_parent has a cycle")
+        depth[ready] = depth[parent[ready]] + 1
+    raise ValueError("pin_parent has a cycle")
+
+
+def rc_tree(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor):
+    """Eq. 1-3 on RC trees (reading R11): segment u runs from pin fa(u) to pin u.
+
+    Children are summed depth by depth, deepest first (Load, LDelay); delays and second
+    moments accumulate from the root down (Delay, Beta).
+    """
+    N = d.n_nets
+    r, c = float(d.cons.r_per_um), float(d.cons.c_per_um)
+    parent = np.asarray(d.pin_parent, np.int64)
+    depth = tree_depth(parent)
+    zero = torch.zeros((), dtype=F64)
+    nonroot = torch.from_numpy(parent >= 0)
+    fa = torch.from_numpy(np.where(parent >= 0, parent, np.arange(len(parent))))
+    cpin = torch.from_numpy(d.pin_cap.astype(np.float64))
+    length = torch.where(nonroot, (x - x[fa]).abs() + (y - y[fa]).abs(), zero)
+    res = r * length                                            # Res(fa(u) -> u), ohm
+    cwire = c * length
+    # Node capacitance: the pin, half of the segment into it, half of each segment out of it (R2).
+    half = torch.where(nonroot, 0.5 * cwire, zero)
+    cap = cpin + half + torch.zeros_like(cpin).index_add(0, fa[nonroot], half[nonroot])
+    levels = [torch.from_numpy(np.nonzero(depth == k)[0]) for k in range(int(depth.max()) + 1)]
+    # Eq. 1: Load(u) = Cap(u) + sum of the children's Loads, deepest level first.
+    load = cap
+    for nodes in reversed(levels[1:]):
+        load = load.index_add(0, fa[nodes], load[nodes])
+    # Eq. 2 with the parent's delay: Delay(u) = Delay(fa(u)) + Res(fa(u) -> u) * Load(u).
+    delay = torch.zeros_like(cap)
+    for nodes in levels[1:]:
+        delay = delay.index_put((nodes,), delay[fa[nodes]] + 1e-3 * res[nodes] * load[nodes])
+    # Second moment: LDelay bottom-up, Beta top-down.
+    ldelay = cap * delay
+    for nodes in reversed(levels[1:]):
+        ldelay = ldelay.index_add(0, fa[nodes], ldelay[nodes])
+    beta = torch.zeros_like(cap)
+    for nodes in levels[1:]:
+        beta = beta.index_put((nodes,), beta[fa[nodes]] + 1e-3 * res[nodes] * ldelay[nodes])
+    arg = 2.0 * beta - delay * delay
+    pos = arg > 0
+    imp = torch.where(pos, torch.sqrt(torch.where(pos, arg, torch.ones((), dtype=F64))), zero)
+    drv = torch.from_numpy(lv.driver.astype(np.int64))
+    load_root = load[drv]
+    return dict(length=length, cap_node=torch.where(nonroot, cap, zero), load_root=load_root,
+                delay=torch.where(nonroot, delay, zero), imp=imp, beta=beta)
 
 
 # --------------------------------------------------------------------------------------
@@ -458,8 +532,12 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
     rows = torch.from_numpy(plan.row)
     st = allst[rows]
     if want_decisions:
-        decisions.append(np.sign((x - x[torch.from_numpy(lv.driver)[net_of_pin]]).detach().numpy()))
-        decisions.append(np.sign((y - y[torch.from_numpy(lv.driver)[net_of_pin]]).detach().numpy()))
+        # the sign of each wire segment's extent (to the driver, or to the parent pin of R11)
+        pp = getattr(d, "pin_parent", None)
+        ref = (torch.from_numpy(np.where(pp >= 0, pp, np.arange(P)).astype(np.int64)) if pp is not None
+               else torch.from_numpy(lv.driver)[net_of_pin])
+        decisions.append(np.sign((x - x[ref]).detach().numpy()))
+        decisions.append(np.sign((y - y[ref]).detach().numpy()))
     out = dict(at=st[:, 0:4], slew=st[:, 4:8], atg=st[:, 8:10], arc_delay=arc_delay, rc=rcr,
                plan=plan, decisions=decisions if want_decisions else None)
     if want_scales:

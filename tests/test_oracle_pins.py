@@ -407,3 +407,110 @@ def test_wide_cells_match_path_enumeration(seed):
             if req:
                 want = min(req) if k >= 2 else max(req)
                 assert out["rat"][p, k] == pytest.approx(want, rel=1e-12, abs=1e-9)
+
+
+# ----------------------------------------------------------------------------- RC trees (R11)
+def _tree_moments_by_path_resistance(d, net):
+    """Elmore delay and second moment of every pin of one net from the path-resistance
+    form: Delay(u) = sum_k Rc(u, k) C_k and Beta(u) = sum_k Rc(u, k) C_k Delay(k), where
+    Rc(u, k) is the resistance shared by the root-to-u and root-to-k paths and C_k the
+    node capacitance (pin plus half of every segment touching it)."""
+    pins = list(d.net_pins[d.net_offsets[net]:d.net_offsets[net + 1]])
+    par = {p: int(d.pin_parent[p]) for p in pins}
+    seg = {p: abs(float(d.x[p]) - float(d.x[par[p]])) + abs(float(d.y[p]) - float(d.y[par[p]]))
+           for p in pins if par[p] >= 0}
+    cap = {p: float(d.pin_cap[p]) for p in pins}
+    for p, L in seg.items():
+        cap[p] += 0.5 * C * L
+        cap[par[p]] += 0.5 * C * L
+
+    def path(p):
+        out = []
+        while par[p] >= 0:
+            out.append(p)
+            p = par[p]
+        return set(out)
+    paths = {p: path(p) for p in pins}
+    rc = {(u, k): sum(R * seg[s] for s in paths[u] & paths[k]) for u in pins for k in pins}
+    delay = {u: 1e-3 * sum(rc[u, k] * cap[k] for k in pins) for u in pins}
+    beta = {u: 1e-3 * sum(rc[u, k] * cap[k] * delay[k] for k in pins) for u in pins}
+    return pins, delay, beta, sum(cap.values())
+
+
+def _tree_design(seed):
+    from gen.netlist import heap_trees
+    return heap_trees(make_design(tiny_spec(30, 4, n_pi=3, seed=seed, box_um=120.0, fanout_p=0.25,
+                                            fanout_cap=12)))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tree_elmore_matches_path_resistance_form(seed):
+    d = _tree_design(seed)
+    lv = O.levelize(d)
+    x = torch.from_numpy(d.x.astype(np.float64))
+    y = torch.from_numpy(d.y.astype(np.float64))
+    rcr = O.rc(d, lv, x, y)
+    deep = 0
+    for net in range(d.n_nets):
+        pins, delay, beta, total = _tree_moments_by_path_resistance(d, net)
+        assert float(rcr["load_root"][net]) == pytest.approx(total, rel=1e-12)   # Eq. 1 at the root
+        for u in pins[1:]:
+            assert float(rcr["delay"][u]) == pytest.approx(delay[u], rel=1e-11, abs=1e-15)
+            assert float(rcr["beta"][u]) == pytest.approx(beta[u], rel=1e-11, abs=1e-18)
+            arg = 2 * beta[u] - delay[u] ** 2
+            assert float(rcr["imp"][u]) == pytest.approx(math.sqrt(max(arg, 0.0)), rel=1e-9, abs=1e-12)
+        deep = max(deep, int(O.tree_depth(d.pin_parent.astype(np.int64))[pins].max()))
+    assert deep >= 3                                   # trees deeper than a star were exercised
+
+
+def test_tree_three_pin_chain_closed_form():
+    # Driver -> a (40 um) -> b (60 um): Delay(b) = R1 (C_a + C_b) + R2 C_b with lumped node caps,
+    # Delay(a) = R1 (C_a + C_b).
+    from dataclasses import replace
+    d = build([[0, 1, 2]], [], [PIN_PI, PIN_PO, PIN_FF_D], [0.5, 1.5, 3.0], [0.0, 40.0, 40.0],
+              [0.0, 0.0, 60.0])
+    d = replace(d, pin_parent=np.array([-1, 0, 1], np.int32))
+    out = O.run(d, grad=None)
+    R1, R2 = R * 40.0, R * 60.0
+    Ca = 1.5 + 0.5 * C * 40.0 + 0.5 * C * 60.0
+    Cb = 3.0 + 0.5 * C * 60.0
+    assert out["delay"][1] == pytest.approx(1e-3 * R1 * (Ca + Cb), rel=1e-12)
+    assert out["delay"][2] == pytest.approx(1e-3 * (R1 * (Ca + Cb) + R2 * Cb), rel=1e-12)
+    assert out["load_root"][0] == pytest.approx(0.5 + C * 100.0 + 1.5 + 3.0, rel=1e-12)
+
+
+def test_tree_of_depth_one_is_the_star():
+    from dataclasses import replace
+    d = make_design(CFG0)
+    lv = O.levelize(d)
+    star_tree = replace(d, pin_parent=np.where(lv.driver[lv.net_of_pin] == np.arange(d.n_pins), -1,
+                                               lv.driver[lv.net_of_pin]).astype(np.int32))
+    a = O.run(d, grad="tns")
+    b = O.run(star_tree, grad="tns")
+    for k in ("delay", "imp", "load_root", "at", "slew", "dx", "dy"):
+        assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-12, equal_nan=True), k
+    assert b["tns"] == pytest.approx(a["tns"], rel=1e-12)
+
+
+def test_tree_gradient_matches_central_differences():
+    d = _tree_design(2)
+    lv = O.levelize(d)
+    plan = O._Plan(d, lv)
+    g = 10.0
+    out = O.run(d, grad="tns", gamma=g, lv=lv, plan=plan)
+    x0, y0 = d.x.astype(np.float64), d.y.astype(np.float64)
+    h = 1e-3
+    checked = 0
+    for p in range(d.n_pins):
+        for axis in (0, 1):
+            xp, yp, xm, ym = x0.copy(), y0.copy(), x0.copy(), y0.copy()
+            (xp if axis == 0 else yp)[p] += h
+            (xm if axis == 0 else ym)[p] -= h
+            fp, dp = O.objective_at(d, lv, plan, xp, yp, g)
+            fm, dm = O.objective_at(d, lv, plan, xm, ym, g)
+            if any(not np.array_equal(u, v) for u, v in zip(dp, dm)):
+                continue
+            an = out["dx" if axis == 0 else "dy"][p]
+            assert abs((fp - fm) / (2 * h) - an) <= 1e-4 * abs(an) + 1e-3, (p, axis)
+            checked += 1
+    assert checked >= 40
