@@ -299,6 +299,9 @@ def run_single(args) -> dict:
     spec = {"cfg0": CFG0, "cfg1": CFG1, "cfg2": CFG2}[args.workload]
     t0 = time.time()
     d = make_design(spec)
+    if args.trees:
+        from gen.netlist import heap_trees
+        d = heap_trees(d)
     g = Graph.from_design(d)
     n_levels = g.levelize()
     g.upload()
@@ -329,7 +332,7 @@ def run_single(args) -> dict:
         prof = g.profile_read()
         g.profile(False)
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
-        if args.workload == "cfg2":
+        if args.workload == "cfg2" and not args.trees:
             roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
 
     ckpt = None
@@ -355,7 +358,8 @@ def run_single(args) -> dict:
         "dtype": "f32",
         "config": {"workload": f"{args.workload}: {P} pins, {d.n_nets} nets, {d.n_cells} cells, "
                                f"{n_levels} net levels, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps"
-                               + (", hipGraph-captured" if args.capture else ""),
+                               + (", hipGraph-captured" if args.capture else "")
+                               + (", an RC tree per net (binary heaps by distance)" if args.trees else ""),
                    "pins": P, "levels": n_levels, "io": "canonical order, HBM resident"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -725,6 +729,8 @@ def main(argv=None) -> int:
                     help="first run one plain device copy of this size (a reference for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
+    ap.add_argument("--trees", action="store_true",
+                    help="cfg0-2 with an RC tree per net (binary heaps by distance) instead of stars")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the STA sweep of one design runs on a single device "

@@ -69,6 +69,13 @@ typedef struct sta_netlist {
   const int32_t* cell_out_pin;     /* [n_cells] */
   const float* pin_cap;            /* [n_pins], pin capacitance, fF */
   const int8_t* pin_kind;          /* [n_pins], STA_PIN_* */
+  const int32_t* pin_parent;       /* [n_pins] or NULL.  NULL: every net is a star (each sink
+                                      wired straight to its driver).  Otherwise the RC tree of
+                                      each net: the pin of the same net whose wire segment feeds
+                                      this pin, -1 at drivers; following parents must reach the
+                                      driver.  Trees use the recursive Eq. 1, the parent's delay
+                                      in Eq. 2 and the second moment of the impulse (TAU 2015
+                                      model cited for Eq. 1-3); a star gives the same values. */
 } sta_netlist;
 
 /* NLDM cell library (Sec. 3.1.2: cell arc delay by table interpolation).  One arc per
@@ -366,7 +373,8 @@ void sta_server_destroy(sta_server* s);
 #define STA_K_EP_SEED 5      /* backward seeds */
 #define STA_K_BWD_LEVEL 6    /* one backward level (RAT, slack, adjoint) */
 #define STA_K_RECOMPUTE 7    /* one forward level recomputed from a checkpoint */
-#define STA_K_COUNT 8
+#define STA_K_RC_ADJOINT 8   /* Elmore adjoint through RC trees (graphs with pin_parent) */
+#define STA_K_COUNT 9
 sta_status sta_profile_enable(sta_graph* g, int32_t on);
 sta_status sta_profile_read(sta_graph* g, int64_t* launches, double* total_ms);
 

@@ -42,12 +42,16 @@ void compute_layouts(sta_graph* g) {
   g->state.rec = take(sizeof(float4) * 4 * (size_t)std::max(1, g->n_rec));
   g->state.wire = take(sizeof(float2) * (size_t)g->P);
   g->state.load = take(sizeof(float) * (size_t)g->N);
+  const bool tree = !g->c_parent.empty();
+  g->state.tree = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
   g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
   g->state.fin = take(sizeof(double) * 8 * (size_t)g->n_designs);
   g->state.total = off;
   off = 0;
   g->work.ratp = take(sizeof(float4) * (size_t)g->P);
   g->work.adjp = take(sizeof(float4) * (size_t)g->P);
+  g->work.tree_adj = take(tree ? sizeof(float2) * (size_t)g->P : 0);
+  g->work.tree_bar = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
   g->work.total = off;
 }
 
@@ -331,6 +335,31 @@ sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib, const 
       if (nl->pin_kind[p] == STA_PIN_CELL_IN || nl->pin_kind[p] == STA_PIN_CELL_OUT)
         return fail(STA_E_INVALID, "cell pin without cells");
   }
+  // RC trees: a parent inside the pin's own net, none at the driver, no cycle.
+  if (nl->pin_parent) {
+    std::vector<int> depth(P, -1);
+    std::vector<int> stack;
+    for (int n = 0; n < N; ++n) {
+      const int b = nl->net_offsets[n], e = nl->net_offsets[n + 1];
+      if (nl->pin_parent[nl->net_pins[b]] != -1) return fail(STA_E_INVALID, "pin_parent of a driver must be -1");
+      depth[nl->net_pins[b]] = 0;
+      for (int i = b + 1; i < e; ++i) {
+        const int p = nl->net_pins[i], q = nl->pin_parent[p];
+        if (q < 0 || q >= P || net_of_pin[q] != n || q == p)
+          return fail(STA_E_INVALID, "pin_parent must be another pin of the same net");
+      }
+      for (int i = b + 1; i < e; ++i) {        // walk up to a pin of known depth
+        int p = nl->net_pins[i];
+        stack.clear();
+        while (depth[p] < 0) {
+          stack.push_back(p);
+          if ((int)stack.size() > e - b) return fail(STA_E_INVALID, "pin_parent has a cycle");
+          p = nl->pin_parent[p];
+        }
+        for (int j = (int)stack.size() - 1; j >= 0; --j) depth[stack[j]] = depth[nl->pin_parent[stack[j]]] + 1;
+      }
+    }
+  }
   if (!(std::isfinite(cons->t_clk) && std::isfinite(cons->pi_slew) && cons->pi_slew >= 0 &&
         cons->r_per_um >= 0 && cons->c_per_um >= 0))
     return fail(STA_E_INVALID, "bad constraints");
@@ -344,6 +373,7 @@ sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib, const 
     g->net_pins.assign(nl->net_pins, nl->net_pins + P);
     g->pin_cap.assign(nl->pin_cap, nl->pin_cap + P);
     g->pin_kind.assign(nl->pin_kind, nl->pin_kind + P);
+    if (nl->pin_parent) g->pin_parent.assign(nl->pin_parent, nl->pin_parent + P);
     if (C > 0) {
       g->cell_type.assign(nl->cell_type, nl->cell_type + C);
       g->cell_in_off.assign(nl->cell_in_offsets, nl->cell_in_offsets + C + 1);
@@ -417,6 +447,8 @@ sta_status sta_batch_create(sta_graph* const* graphs, int32_t n, sta_graph** out
       u->n_arcs += h->n_arcs;
     }
     // Netlists, ids offset design by design.
+    bool any_tree = false;
+    for (int d = 0; d < n; ++d) any_tree = any_tree || !graphs[d]->pin_parent.empty();
     u->net_off.assign(1, 0);
     u->cell_in_off.assign(1, 0);
     for (int d = 0; d < n; ++d) {
@@ -433,6 +465,14 @@ sta_status sta_batch_create(sta_graph* const* graphs, int32_t n, sta_graph** out
         u->cell_out_pin.push_back(pb + h->cell_out_pin[c]);
       }
       for (int i = 0; i < h->A; ++i) u->cell_in_pins.push_back(pb + h->cell_in_pins[i]);
+      if (any_tree) {                           // star members join as depth-one trees
+        for (int q = 0; q < h->P; ++q) u->pin_parent.push_back(-1);
+        for (int i = 0; i < h->N; ++i)
+          for (int q = h->net_off[i] + 1; q < h->net_off[i + 1]; ++q) {
+            const int p = h->net_pins[q];
+            u->pin_parent[pb + p] = pb + (h->pin_parent.empty() ? h->net_pins[h->net_off[i]] : h->pin_parent[p]);
+          }
+      }
       u->P += h->P;
       u->N += h->N;
       u->C += h->C;
@@ -544,6 +584,33 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
     g->c_net_off[N] = P;
     g->c_pin_cap.resize(P);
     for (int i = 0; i < P; ++i) g->c_pin_cap[i] = g->pin_cap[g->pin_perm[i]];
+    // RC trees in canonical ids, and each net's pins in breadth-first order from its driver.
+    g->c_parent.clear();
+    g->c_tree_order.clear();
+    if (!g->pin_parent.empty()) {
+      g->c_parent.resize(P);
+      for (int q = 0; q < P; ++q) {
+        const int pp = g->pin_parent[g->pin_perm[q]];
+        g->c_parent[q] = pp < 0 ? -1 : pin_new[pp];
+      }
+      g->c_tree_order.resize(P);
+      std::vector<int> child_off, child;
+      for (int i = 0; i < N; ++i) {
+        const int b = g->c_net_off[i], e = g->c_net_off[i + 1];
+        child_off.assign(e - b + 1, 0);
+        for (int q = b + 1; q < e; ++q) ++child_off[g->c_parent[q] - b + 1];
+        for (int j = 0; j < e - b; ++j) child_off[j + 1] += child_off[j];
+        child.assign(e - b, 0);
+        std::vector<int> fill(child_off.begin(), child_off.end() - 1);
+        for (int q = b + 1; q < e; ++q) child[fill[g->c_parent[q] - b]++] = q;
+        int head = b, tail = b;
+        g->c_tree_order[tail++] = b;
+        while (head < tail) {
+          const int u = g->c_tree_order[head++];
+          for (int j = child_off[u - b]; j < child_off[u - b + 1]; ++j) g->c_tree_order[tail++] = child[j];
+        }
+      }
+    }
     // Level 0 holds exactly the PI-driven nets; every later net is driven by a cell.
     const int N0 = lcount[1];
     for (int i = 0; i < N; ++i) {
@@ -761,6 +828,7 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
       (s = up(d.sched_all, g->sched_all)) || (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
+      (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)))) ||
       (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
     free_device(g);
     return s;

@@ -52,6 +52,8 @@ struct StateLayout {
                    // (late k; 0 for early k), 0}
   size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
   size_t load;     // float[N]: root load of each net (Eq. 1)
+  size_t tree;     // RC trees only, float4[2 * P]: per pin {length, Cap, Load, Delay} and
+                   // {LDelay, Beta, Impulse, 0} of the tree passes
   size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
   size_t fin;      // double[n_designs * 8]: finished scalars and the WNS_g normaliser per design
   size_t total;
@@ -60,6 +62,9 @@ struct StateLayout {
 struct WorkLayout {
   size_t ratp;     // float4[P]: required time of each sink, by condition
   size_t adjp;     // float4[P]: adjoint of each sink {a_rise, a_fall, s_rise, s_fall}
+  size_t tree_adj; // RC trees only, float2[P]: adjoints of each sink's {Delay, Impulse} and
+                   // of each net's root load (at its driver), from the backward sweep
+  size_t tree_bar; // RC trees only, float4[2 * P]: adjoint scratch of the tree passes
   size_t total;
 };
 
@@ -77,6 +82,8 @@ struct DeviceGraph {
   int* pin_perm = nullptr;     // [P] original id of each canonical pin
   int* sched_all = nullptr;    // [N] all nets ordered by class
   int* rec_loc = nullptr;      // [N] record slot of each net (checkpointing only)
+  int* parent = nullptr;       // [P] RC trees only: canonical parent pin, -1 at drivers
+  int* tree_order = nullptr;   // [P] RC trees only: each net's pins in breadth-first order
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
   size_t bytes = 0;
@@ -90,6 +97,7 @@ struct sta_graph {
   std::vector<int> net_off, net_pins, cell_type, cell_in_off, cell_in_pins, cell_out_pin;
   std::vector<float> pin_cap;
   std::vector<int8_t> pin_kind;
+  std::vector<int> pin_parent;                 // RC tree parent pin (original ids), empty: stars
   std::vector<int> arc_off;
   std::vector<int8_t> unate;
   std::vector<float> slew_axis, load_axis, tables;
@@ -110,6 +118,8 @@ struct sta_graph {
   std::vector<int> ep_design, ep_design_off, ep_blk_off;
   std::vector<int4> ell;                       // padded per-level cell-input slots
   std::vector<int> ell_base, ell_slots;        // per level: first entry, slots per cell
+  std::vector<int> c_parent, c_tree_order;     // RC trees: canonical parent pin (-1 at the
+                                               // driver); each net's pins in breadth-first order
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
   sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS};

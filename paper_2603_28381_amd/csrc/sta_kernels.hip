@@ -287,6 +287,9 @@ struct RcArgs {
   int N0, N;
   float r, c, pi_at, pi_slew;
   Snap snap;
+  const int* __restrict__ parent;       // RC trees: canonical parent pin, -1 at drivers
+  const int* __restrict__ tree_order;   // RC trees: each net's pins in breadth-first order
+  float4* __restrict__ tree;            // RC trees: pass values, two float4 per pin
 };
 
 // One sink p of a star net whose driver sits at (xd, yd): wire delay and impulse (Eq. 2-3)
@@ -311,8 +314,8 @@ __device__ __forceinline__ float rc_sink(const RcArgs& a, const float* __restric
 // Root of net n (driver pin p0) once its sinks' contributions are summed: the root load,
 // a zero wire at the driver, and the arrival record of a primary-input net.
 __device__ __forceinline__ void rc_root(const RcArgs& a, float2* __restrict__ wire, float* __restrict__ loads,
-                                        float4* __restrict__ rec, int n, int p0, float sum) {
-  loads[n] = a.pin_cap[p0] + sum;             // Eq. 1 at the root
+                                        float4* __restrict__ rec, int n, int p0, float sum, bool is_total = false) {
+  loads[n] = is_total ? sum : a.pin_cap[p0] + sum;   // Eq. 1 at the root
   wire[p0] = make_float2(0.f, 0.f);
   if (n < a.N0) {
     float4* r = rec + kRecChunks * (size_t)n;
@@ -443,6 +446,156 @@ __global__ __launch_bounds__(kBlock) void k_rc_thread(RcArgs a) {
   float sum = 0.f;
   for (int p = p0 + 1; p < p1; ++p) sum += rc_sink(a, xs, ys, wire, p, xd, yd);
   rc_root(a, wire, loads, rec, n, p0, sum);
+}
+
+// RC net delay on RC trees, one thread per net walking its pins in breadth-first order
+// (parents before children).  Segment u runs from parent pin fa(u) to pin u; Cap(u) holds the
+// pin and half of every segment touching it.  Load sums the children's Loads bottom-up
+// (Eq. 1), Delay adds the parent's delay top-down (Eq. 2 on a tree), and the impulse takes
+// the second moment: LDelay(u) = Cap(u) Delay(u) + the children's LDelay bottom-up,
+// Beta(u) = Beta(fa(u)) + Res(fa(u) -> u) LDelay(u) top-down, Impulse = sqrt(2 Beta - Delay^2)
+// (Eq. 3 on a star).  The pass values stay in `tree` for the adjoint (k_rc_tree_adjoint).
+__global__ __launch_bounds__(kBlock) void k_rc_tree(RcArgs a) {
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
+  float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
+  float4* __restrict__ T = snap_bytes(a.tree, a.snap.state);
+  const int n = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (n >= a.N) return;
+  const int b = a.net_off[n], e = a.net_off[n + 1];
+  const float kr = 1e-3f * a.r, hc = 0.5f * a.c;   // ohm * fF = 1e-3 ps
+  // Lengths and own caps ({length, Cap, Load, Delay}, {LDelay, Beta, Impulse, 0} per pin).
+  for (int q = b; q < e; ++q) {
+    float len = 0.f;
+    if (q > b) {
+      const int f = a.parent[q];
+      const int qo = a.io_perm ? a.io_perm[q] : q, fo = a.io_perm ? a.io_perm[f] : f;
+      len = fabsf(xs[qo] - xs[fo]) + fabsf(ys[qo] - ys[fo]);
+    }
+    T[2 * (size_t)q] = make_float4(len, fmaf(hc, len, a.pin_cap[q]), 0.f, 0.f);
+  }
+  for (int q = b + 1; q < e; ++q) T[2 * (size_t)a.parent[q]].y += hc * T[2 * (size_t)q].x;   // segments out of a pin
+  for (int q = b; q < e; ++q) T[2 * (size_t)q].z = T[2 * (size_t)q].y;
+  for (int j = e - 1; j > b; --j) {                 // Load, children first
+    const int u = a.tree_order[j];
+    T[2 * (size_t)a.parent[u]].z += T[2 * (size_t)u].z;
+  }
+  for (int j = b + 1; j < e; ++j) {                 // Delay, parents first
+    const int u = a.tree_order[j];
+    const float4 t = T[2 * (size_t)u];
+    T[2 * (size_t)u].w = T[2 * (size_t)a.parent[u]].w + kr * t.x * t.z;
+  }
+  for (int q = b; q < e; ++q) T[2 * (size_t)q + 1] = make_float4(T[2 * (size_t)q].y * T[2 * (size_t)q].w, 0.f, 0.f, 0.f);
+  for (int j = e - 1; j > b; --j) {                 // LDelay, children first
+    const int u = a.tree_order[j];
+    T[2 * (size_t)a.parent[u] + 1].x += T[2 * (size_t)u + 1].x;
+  }
+  for (int j = b + 1; j < e; ++j) {                 // Beta and the impulse, parents first
+    const int u = a.tree_order[j];
+    const float4 t = T[2 * (size_t)u];
+    const float beta = T[2 * (size_t)a.parent[u] + 1].y + kr * t.x * T[2 * (size_t)u + 1].x;
+    const float arg = 2.0f * beta - t.w * t.w;
+    const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
+    T[2 * (size_t)u + 1].y = beta;
+    T[2 * (size_t)u + 1].z = imp;
+    wire[u] = make_float2(t.w, imp);
+  }
+  rc_root(a, wire, loads, rec, n, b, T[2 * (size_t)b].z, true);
+}
+
+// Adjoint of k_rc_tree for one net per thread: from the backward sweep's adjoints of each
+// sink's Delay and Impulse and of the root Load (tree_adj), back through the four passes in
+// reverse (Beta and Delay children-first, LDelay and Load parents-first), to the segment
+// lengths, Cap and Res, and through |dx| + |dy| to the pins' coordinates.
+struct TreeAdjArgs {
+  const int* __restrict__ net_off;
+  const int* __restrict__ parent;
+  const int* __restrict__ tree_order;
+  const int* __restrict__ io_perm;
+  const float* __restrict__ x;
+  const float* __restrict__ y;
+  const float4* __restrict__ tree;      // forward pass values (state)
+  const float2* __restrict__ tree_adj;  // per sink {d/dDelay, d/dImpulse}, at the driver {d/dLoad, 0}
+  float4* __restrict__ bar;             // scratch, two float4 per pin
+  float* __restrict__ dx;
+  float* __restrict__ dy;
+  int N;
+  float r, c;
+  Snap snap;
+};
+
+__global__ __launch_bounds__(kBlock) void k_rc_tree_adjoint(TreeAdjArgs a) {
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  const float4* __restrict__ T = snap_bytes(a.tree, a.snap.state);
+  const float2* __restrict__ A = snap_bytes(a.tree_adj, a.snap.work);
+  float4* __restrict__ B = snap_bytes(a.bar, a.snap.work);   // {dDelay, dBeta, dLDelay, dLoad}, {dCap, dlen, gx, gy}
+  float* __restrict__ dx = snap_elems(a.dx, a.snap.pins);
+  float* __restrict__ dy = snap_elems(a.dy, a.snap.pins);
+  const int n = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (n >= a.N) return;
+  const int b = a.net_off[n], e = a.net_off[n + 1];
+  const float kr = 1e-3f * a.r, hc = 0.5f * a.c;
+  for (int q = b; q < e; ++q) {                     // seeds: the impulse into Beta and Delay
+    float dd = 0.f, db = 0.f, dl = 0.f;
+    if (q == b) {
+      dl = A[q].x;
+    } else {
+      const float2 g = A[q];
+      const float dly = T[2 * (size_t)q].w, imp = T[2 * (size_t)q + 1].z;
+      dd = g.x;
+      if (imp > 0.f) {
+        db = g.y / imp;
+        dd -= g.y * dly / imp;
+      }
+    }
+    B[2 * (size_t)q] = make_float4(dd, db, 0.f, dl);
+    B[2 * (size_t)q + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int j = e - 1; j > b; --j) {                 // Beta, children first
+    const int u = a.tree_order[j];
+    const float bb = B[2 * (size_t)u].y;
+    B[2 * (size_t)a.parent[u]].y += bb;
+    B[2 * (size_t)u + 1].y += kr * T[2 * (size_t)u + 1].x * bb;
+    B[2 * (size_t)u].z += kr * T[2 * (size_t)u].x * bb;
+  }
+  for (int j = b; j < e; ++j) {                     // LDelay, parents first
+    const int u = a.tree_order[j];
+    if (j > b) B[2 * (size_t)u].z += B[2 * (size_t)a.parent[u]].z;
+    const float ld = B[2 * (size_t)u].z;
+    B[2 * (size_t)u + 1].x += ld * T[2 * (size_t)u].w;
+    B[2 * (size_t)u].x += ld * T[2 * (size_t)u].y;
+  }
+  for (int j = e - 1; j > b; --j) {                 // Delay, children first
+    const int u = a.tree_order[j];
+    const float dd = B[2 * (size_t)u].x;
+    const float4 t = T[2 * (size_t)u];
+    B[2 * (size_t)a.parent[u]].x += dd;
+    B[2 * (size_t)u + 1].y += kr * t.z * dd;
+    B[2 * (size_t)u].w += kr * t.x * dd;
+  }
+  for (int j = b; j < e; ++j) {                     // Load, parents first
+    const int u = a.tree_order[j];
+    if (j > b) B[2 * (size_t)u].w += B[2 * (size_t)a.parent[u]].w;
+    B[2 * (size_t)u + 1].x += B[2 * (size_t)u].w;
+  }
+  for (int q = b + 1; q < e; ++q) {                 // Cap and Res to lengths, lengths to x, y
+    const int f = a.parent[q];
+    const float lb = B[2 * (size_t)q + 1].y + hc * (B[2 * (size_t)q + 1].x + B[2 * (size_t)f + 1].x);
+    const int qo = a.io_perm ? a.io_perm[q] : q, fo = a.io_perm ? a.io_perm[f] : f;
+    const float gx = lb * sgnf(xs[qo] - xs[fo]), gy = lb * sgnf(ys[qo] - ys[fo]);
+    B[2 * (size_t)q + 1].z += gx;
+    B[2 * (size_t)q + 1].w += gy;
+    B[2 * (size_t)f + 1].z -= gx;
+    B[2 * (size_t)f + 1].w -= gy;
+  }
+  for (int q = b; q < e; ++q) {
+    const int qo = a.io_perm ? a.io_perm[q] : q;
+    if (dx) dx[qo] = B[2 * (size_t)q + 1].z;
+    if (dy) dy[qo] = B[2 * (size_t)q + 1].w;
+  }
 }
 
 // ---------------------------------------------------------------------------- cell inputs
@@ -829,6 +982,7 @@ struct BwdArgs {
   float r, c, inv_gamma;
   int grad;
   Snap snap;
+  float2* tree_adj;   // RC trees: the Elmore adjoint is left to k_rc_tree_adjoint (else NULL)
 };
 
 // Accumulators of the net step (reduced over the group).
@@ -870,7 +1024,7 @@ __device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p) {
 template <bool kGrad>
 __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in, const float4& at_d,
                                               const float4& sl_d, float xd, float yd, float (&acc)[N_ACC],
-                                              bool write) {
+                                              bool write, int pc) {
   const float4 rt = in.rt, aj = in.aj;
   const float2 w = in.w;
   const int q = in.q;
@@ -900,6 +1054,7 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in
     acc[S_F] += q1 * sl_d.w;
     const float dbar = aj.x + aj.y;                      // adjoint of the wire delay
     const float ibar = (q0 + q1) * w.y;                  // adjoint of the impulse
+    if (a.tree_adj && write) *at32(a.tree_adj, (uint32_t)pc) = make_float2(dbar, ibar);
     const float len = fabsf(xs - xd) + fabsf(ys - yd);
     // d Delay / d len = d Impulse / d len = 1e-3 r (Cpin + c len) for a star sink.
     k.rest = (dbar + ibar) * (1e-3f * a.r * fmaf(a.c, len, cp));
@@ -1089,11 +1244,11 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   //    phase 3.
   float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   SinkKeep keep0{0.f, 0.f, 0.f, 0}, keep1{0.f, 0.f, 0.f, 0};
-  if (has0) keep0 = sink_step<kGrad>(a, in0, at_d, sl_d, xd, yd, acc, true);
-  if (has1) keep1 = sink_step<kGrad>(a, in1, at_d, sl_d, xd, yd, acc, true);
+  if (has0) keep0 = sink_step<kGrad>(a, in0, at_d, sl_d, xd, yd, acc, true, s0);
+  if (has1) keep1 = sink_step<kGrad>(a, in1, at_d, sl_d, xd, yd, acc, true, s0 + gstride);
   if (block) {
     for (int p = s0 + 2 * gstride; p < p1; p += gstride)
-      sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, acc, true);
+      sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, acc, true, p);
   }
   reduce_acc<G>(acc, block, sh);
 
@@ -1139,7 +1294,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
   }
   if (!gs.active) return;
-  if (kGrad && (a.dx || a.dy)) {
+  if (kGrad && (a.dx || a.dy) && !a.tree_adj) {
     const float cl = a.c * lbar;
     if (has0) {
       if (a.dx) *at32(a.dx, (uint32_t)keep0.q) = keep0.gx * (cl + keep0.rest);
@@ -1152,7 +1307,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     if (block) {
       for (int p = s0 + 2 * gstride; p < p1; p += gstride) {
         float scratch[N_ACC] = {};
-        const SinkKeep kk = sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, scratch, false);
+        const SinkKeep kk = sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, scratch, false, p);
         if (a.dx) a.dx[kk.q] = kk.gx * (cl + kk.rest);
         if (a.dy) a.dy[kk.q] = kk.gy * (cl + kk.rest);
       }
@@ -1166,7 +1321,9 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     if (a.slack_out)
       store_stream(at32(a.slack_out, q),
                    make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w));
-    if (kGrad) {
+    if (kGrad && a.tree_adj) {
+      *at32(a.tree_adj, (uint32_t)p0) = make_float2(lbar, 0.f);
+    } else if (kGrad) {
       const float cl = a.c * lbar;
       if (a.dx) *at32(a.dx, q) = -(acc[X_RS] + cl * acc[X_N]);
       if (a.dy) *at32(a.dy, q) = -(acc[Y_RS] + cl * acc[Y_N]);
@@ -1197,6 +1354,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   a.slack_out = snap_elems<kSnap>(a.slack_out, a.snap.pins);
   a.dx = snap_elems<kSnap>(a.dx, a.snap.pins);
   a.dy = snap_elems<kSnap>(a.dy, a.snap.pins);
+  a.tree_adj = snap_bytes<kSnap>(a.tree_adj, a.snap.work);
   GroupSlot gs;
   if (!level_slot<G0>(nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
   if (gs.block || gs.G == 64) {
@@ -1341,12 +1499,16 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
   const Snap sn = snap_of(g);
+  const bool tree = !g->c_parent.empty();
   RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0, g->N,
-            g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn};
+            g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn, d.parent, d.tree_order,
+            tree ? reinterpret_cast<float4*>(sb + g->state.tree) : nullptr};
   {
     LaunchTimer t(g, s, STA_K_RC);
     const unsigned per_net = (unsigned)((g->N + kBlock - 1) / kBlock);
-    if (g->sched_cfg.rc_scheme == STA_RC_CTE)
+    if (tree)
+      k_rc_tree<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
+    else if (g->sched_cfg.rc_scheme == STA_RC_CTE)
       k_rc_cte<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
     else if (g->sched_cfg.rc_scheme == STA_RC_THREAD)
       k_rc_thread<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
@@ -1411,11 +1573,13 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     k_ep_seed<<<dim3((g->E + kBlock - 1) / kBlock, g->n_snap), kBlock, 0, s>>>(ea);
   }
 
+  const bool tree = !g->c_parent.empty();
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
              rec, wire, load, d.rec_loc, ratp, adjp, reinterpret_cast<float4*>(out->at),
              reinterpret_cast<float4*>(out->slew), reinterpret_cast<float4*>(out->rat),
              reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
-             g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g)};
+             g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g),
+             (grad && tree) ? reinterpret_cast<float2*>(wb + g->work.tree_adj) : nullptr};
   const int ss = (int)g->state.total;
   auto bwd_level = [&](int l) {
     const GroupRange& r = g->lvl_ranges[l];
@@ -1458,6 +1622,16 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
       for (int l = hi - 1; l >= lo; --l) bwd_level(l);
     }
     bwd_level(0);
+  }
+  if (grad && tree && (out->dx || out->dy)) {
+    // The Elmore adjoint through each net's tree, from the sweep's per-sink adjoints.
+    const TreeAdjArgs ta{d.net_off, d.parent, d.tree_order, io, x, y,
+                         reinterpret_cast<const float4*>(sb + g->state.tree),
+                         reinterpret_cast<const float2*>(wb + g->work.tree_adj),
+                         reinterpret_cast<float4*>(wb + g->work.tree_bar), out->dx, out->dy, g->N,
+                         g->cons.r_per_um, g->cons.c_per_um, snap_of(g)};
+    LaunchTimer t(g, s, STA_K_RC_ADJOINT);
+    k_rc_tree_adjoint<<<snap_grid(g, (unsigned)((g->N + kBlock - 1) / kBlock)), kBlock, 0, s>>>(ta);
   }
   if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();

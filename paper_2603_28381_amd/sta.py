@@ -36,7 +36,8 @@ EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_grap
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
-KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level", "recompute"]
+KERNELS = ["rc", "fwd_level", "ep_partial", "ep_final", "expand", "ep_seed", "bwd_level", "recompute",
+           "rc_adjoint"]
 
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -45,7 +46,7 @@ _I32P = ctypes.POINTER(ctypes.c_int32)
 class StaNetlist(ctypes.Structure):
     _fields_ = [("n_pins", ctypes.c_int32), ("n_nets", ctypes.c_int32), ("n_cells", ctypes.c_int32),
                 ("net_offsets", _P), ("net_pins", _P), ("cell_type", _P), ("cell_in_offsets", _P),
-                ("cell_in_pins", _P), ("cell_out_pin", _P), ("pin_cap", _P), ("pin_kind", _P)]
+                ("cell_in_pins", _P), ("cell_out_pin", _P), ("pin_cap", _P), ("pin_kind", _P), ("pin_parent", _P)]
 
 
 class StaLibrary(ctypes.Structure):
@@ -227,7 +228,8 @@ class Graph:
                         arr(netlist["net_offsets"], np.int32), arr(netlist["net_pins"], np.int32),
                         arr(netlist["cell_type"], np.int32), arr(netlist["cell_in_offsets"], np.int32),
                         arr(netlist["cell_in_pins"], np.int32), arr(netlist["cell_out_pin"], np.int32),
-                        arr(netlist["pin_cap"], np.float32), arr(netlist["pin_kind"], np.int8))
+                        arr(netlist["pin_cap"], np.float32), arr(netlist["pin_kind"], np.int8),
+                        None if netlist.get("pin_parent") is None else arr(netlist["pin_parent"], np.int32))
         lb = StaLibrary(int(library["n_cell_types"]), arr(library["arc_offsets"], np.int32),
                         arr(library["arc_unate"], np.int8), arr(library["slew_axis"], np.float32),
                         arr(library["load_axis"], np.float32), arr(library["tables"], np.float32))
@@ -245,7 +247,7 @@ class Graph:
         nl = dict(n_pins=d.n_pins, n_nets=d.n_nets, n_cells=d.n_cells, net_offsets=d.net_offsets,
                   net_pins=d.net_pins, cell_type=d.cell_type, cell_in_offsets=d.cell_in_offsets,
                   cell_in_pins=d.cell_in_pins, cell_out_pin=d.cell_out_pin, pin_cap=d.pin_cap,
-                  pin_kind=d.pin_kind)
+                  pin_kind=d.pin_kind, pin_parent=getattr(d, "pin_parent", None))
         lb = dict(n_cell_types=d.lib.n_cell_types, arc_offsets=d.lib.arc_offsets, arc_unate=d.lib.arc_unate,
                   slew_axis=d.lib.slew_axis, load_axis=d.lib.load_axis, tables=d.lib.tables)
         c = d.cons

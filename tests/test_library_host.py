@@ -300,3 +300,40 @@ def test_placement_loop_pin_cell_maps():
         pins = [d.cell_out_pin[c]] + list(d.cell_in_pins[d.cell_in_offsets[c]:d.cell_in_offsets[c + 1]])
         assert got[c] == pytest.approx(float(sum(gp[p] for p in pins)))
     g.close()
+
+
+def test_rc_tree_parents_validated():
+    from dataclasses import replace
+    from gen.netlist import heap_trees
+    d = heap_trees(make_design(tiny_spec(30, 4, n_pi=3, seed=5, fanout_p=0.25, fanout_cap=8)))
+    g = S.Graph.from_design(d)          # a valid tree per net
+    g.levelize()
+    star = S.Graph.from_design(replace(d, pin_parent=None))
+    star.levelize()
+    # the tree passes keep 32 bytes per pin in the state and 40 in the workspace
+    assert g.info()["fwd_state_bytes"] >= star.info()["fwd_state_bytes"] + 32 * d.n_pins
+    assert g.info()["bwd_workspace_bytes"] >= star.info()["bwd_workspace_bytes"] + 40 * d.n_pins
+    g.close()
+    star.close()
+    off, pins = d.net_offsets, d.net_pins
+    big = int(np.argmax(np.diff(off)))
+    drv, s1, s2 = pins[off[big]], pins[off[big] + 1], pins[off[big] + 2]
+    other = pins[off[(big + 1) % d.n_nets] + 1]
+    for what, edit in (("driver with a parent", {drv: s1}), ("parent in another net", {s1: other}),
+                       ("self parent", {s1: s1}), ("cycle", {s1: s2, s2: s1}), ("out of range", {s1: d.n_pins})):
+        pp = d.pin_parent.copy()
+        for k, v in edit.items():
+            pp[k] = v
+        with pytest.raises(S.StaError) as e:
+            S.Graph.from_design(replace(d, pin_parent=pp))
+        assert e.value.code == S.STA_E_INVALID, what
+
+
+def test_rc_tree_batch_with_star_member_levelizes():
+    from gen.netlist import heap_trees
+    a = heap_trees(make_design(tiny_spec(30, 4, n_pi=3, seed=6)))
+    b = make_design(tiny_spec(20, 3, n_pi=2, seed=7))
+    g = S.Graph.batch([S.Graph.from_design(a), S.Graph.from_design(b)])
+    g.levelize()
+    assert g.info()["n_designs"] == 2
+    g.close()
