@@ -108,7 +108,8 @@ def kernel_table(prof: dict, alg: dict, steps: int) -> tuple[dict, dict]:
         kernels[k] = dict(launches_per_step=n // steps, avg_us=1e3 * tot / n, ms_per_step=tot / steps,
                           alg_bytes_per_step=per_step,
                           gbs=(per_step * steps / (tot * 1e-3) / 1e9) if per_step else None)
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    # the dominant kernel among those the byte model covers
+    dom = max((k for k in kernels if kernels[k]["gbs"] is not None), key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
     achieved = kd["gbs"]
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",

@@ -610,6 +610,53 @@ sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out) {
           for (int j = child_off[u - b]; j < child_off[u - b + 1]; ++j) g->c_tree_order[tail++] = child[j];
         }
       }
+      // Per pin: depth, and its children as a run of breadth-first positions.
+      g->c_tree_node.assign(P, make_int4(0, 0, 0, 0));
+      for (int i = 0; i < N; ++i) {
+        const int b = g->c_net_off[i], e = g->c_net_off[i + 1];
+        int next = b + 1;                        // children of the j-th pin in order follow
+        for (int j = b; j < e; ++j) {
+          const int u = g->c_tree_order[j];
+          int4& t = g->c_tree_node[u];
+          t.x = u == b ? 0 : g->c_tree_node[g->c_parent[u]].x + 1;
+          t.y = next;
+          while (next < e && g->c_parent[g->c_tree_order[next]] == u) ++next;
+          t.z = next - t.y;
+        }
+      }
+      // Chunks of whole nets for the LDS kernels (depth -1: a net too big for one, left to the
+      // fallback kernel).
+      g->tree_blk_net.assign(1, 0);
+      g->tree_blk_depth.clear();
+      g->tree_big.clear();
+      int pins = 0, depth = 0;
+      for (int i = 0; i < N; ++i) {
+        const int np = g->c_net_off[i + 1] - g->c_net_off[i];
+        int dn = 0;
+        for (int q = g->c_net_off[i]; q < g->c_net_off[i + 1]; ++q) dn = std::max(dn, g->c_tree_node[q].x);
+        if (np > kTreeChunk) {
+          if (i > g->tree_blk_net.back()) {
+            g->tree_blk_depth.push_back(depth);
+            g->tree_blk_net.push_back(i);
+          }
+          g->tree_big.push_back(i);
+          g->tree_blk_depth.push_back(-1);
+          g->tree_blk_net.push_back(i + 1);
+          pins = depth = 0;
+          continue;
+        }
+        if (pins + np > kTreeChunk) {
+          g->tree_blk_depth.push_back(depth);
+          g->tree_blk_net.push_back(i);
+          pins = depth = 0;
+        }
+        pins += np;
+        depth = std::max(depth, dn);
+      }
+      if (N > g->tree_blk_net.back()) {
+        g->tree_blk_depth.push_back(depth);
+        g->tree_blk_net.push_back(N);
+      }
     }
     // Level 0 holds exactly the PI-driven nets; every later net is driven by a cell.
     const int N0 = lcount[1];
@@ -828,7 +875,9 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
       (s = up(d.sched_all, g->sched_all)) || (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
-      (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)))) ||
+      (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)) ||
+                                (s = up(d.tree_node, g->c_tree_node)) || (s = up(d.tree_blk_net, g->tree_blk_net)) ||
+                                (s = up(d.tree_blk_depth, g->tree_blk_depth)) || (s = up(d.tree_big, g->tree_big)))) ||
       (s = up(d.lut_grid, grid)) || (s = up(d.lut_coef, coef))) {
     free_device(g);
     return s;

@@ -18,6 +18,7 @@ constexpr int kHeavy = kNumClasses;  // class of nets served by a whole workgrou
 constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
 constexpr int kFlatG0Default = 2;    // flat kernels (RC, outputs): smallest group 4 lanes
 constexpr int kSweepG0Default = 4;   // level kernels: smallest group 16 lanes (4 conditions x 4 arcs)
+constexpr int kTreeChunk = 1024;     // RC trees: pins of whole nets swept by one workgroup in LDS
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0
 // lanes: the smallest wave group (doubling from 1 << g0) in which every lane holds at most
@@ -84,6 +85,10 @@ struct DeviceGraph {
   int* rec_loc = nullptr;      // [N] record slot of each net (checkpointing only)
   int* parent = nullptr;       // [P] RC trees only: canonical parent pin, -1 at drivers
   int* tree_order = nullptr;   // [P] RC trees only: each net's pins in breadth-first order
+  int4* tree_node = nullptr;   // [P] RC trees only: {depth, first child position, children, 0}
+  int* tree_blk_net = nullptr;    // RC trees only: chunk net ranges
+  int* tree_blk_depth = nullptr;  // RC trees only: deepest depth of each chunk
+  int* tree_big = nullptr;        // RC trees only: nets over the chunk size
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
   size_t bytes = 0;
@@ -120,6 +125,11 @@ struct sta_graph {
   std::vector<int> ell_base, ell_slots;        // per level: first entry, slots per cell
   std::vector<int> c_parent, c_tree_order;     // RC trees: canonical parent pin (-1 at the
                                                // driver); each net's pins in breadth-first order
+  std::vector<int4> c_tree_node;               // RC trees, per canonical pin: {depth, breadth-first
+                                               // position of the first child, children, 0}
+  std::vector<int> tree_blk_net, tree_blk_depth;  // RC trees: chunks of whole nets of at most
+                                               // kTreeChunk pins (net ranges, deepest depth)
+  std::vector<int> tree_big;                   // RC trees: nets over kTreeChunk pins
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
   sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS};

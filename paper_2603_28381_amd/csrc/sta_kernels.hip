@@ -290,6 +290,12 @@ struct RcArgs {
   const int* __restrict__ parent;       // RC trees: canonical parent pin, -1 at drivers
   const int* __restrict__ tree_order;   // RC trees: each net's pins in breadth-first order
   float4* __restrict__ tree;            // RC trees: pass values, two float4 per pin
+  const int4* __restrict__ tree_node;   // RC trees: {depth, first child position, children, 0}
+  const int* __restrict__ chunk_net;    // RC trees: net ranges of the LDS chunks
+  const int* __restrict__ chunk_depth;  // RC trees: deepest depth per chunk (-1: skipped)
+  const int* __restrict__ net_list;     // RC trees: the nets of the fallback kernel
+  int n_list;
+  int n_chunks;
 };
 
 // One sink p of a star net whose driver sits at (xd, yd): wire delay and impulse (Eq. 2-3)
@@ -449,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_thread(RcArgs a) {
 }
 
 // RC net delay on RC trees, one thread per net walking its pins in breadth-first order
-// (parents before children).  Segment u runs from parent pin fa(u) to pin u; Cap(u) holds the
+// (parents before children), for nets too big for the LDS chunks of k_rc_tree_chunk.  Segment u runs from parent pin fa(u) to pin u; Cap(u) holds the
 // pin and half of every segment touching it.  Load sums the children's Loads bottom-up
 // (Eq. 1), Delay adds the parent's delay top-down (Eq. 2 on a tree), and the impulse takes
 // the second moment: LDelay(u) = Cap(u) Delay(u) + the children's LDelay bottom-up,
@@ -462,8 +468,9 @@ __global__ __launch_bounds__(kBlock) void k_rc_tree(RcArgs a) {
   float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
   float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
   float4* __restrict__ T = snap_bytes(a.tree, a.snap.state);
-  const int n = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (n >= a.N) return;
+  const int k = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (k >= a.n_list) return;
+  const int n = a.net_list[k];
   const int b = a.net_off[n], e = a.net_off[n + 1];
   const float kr = 1e-3f * a.r, hc = 0.5f * a.c;   // ohm * fF = 1e-3 ps
   // Lengths and own caps ({length, Cap, Load, Delay}, {LDelay, Beta, Impulse, 0} per pin).
@@ -505,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_tree(RcArgs a) {
   rc_root(a, wire, loads, rec, n, b, T[2 * (size_t)b].z, true);
 }
 
-// Adjoint of k_rc_tree for one net per thread: from the backward sweep's adjoints of each
+// Adjoint of the tree passes for one net per thread (nets too big for k_rc_tree_adjoint_chunk): from the backward sweep's adjoints of each
 // sink's Delay and Impulse and of the root Load (tree_adj), back through the four passes in
 // reverse (Beta and Delay children-first, LDelay and Load parents-first), to the segment
 // lengths, Cap and Res, and through |dx| + |dy| to the pins' coordinates.
@@ -524,6 +531,12 @@ struct TreeAdjArgs {
   int N;
   float r, c;
   Snap snap;
+  const int4* __restrict__ tree_node;
+  const int* __restrict__ chunk_net;
+  const int* __restrict__ chunk_depth;
+  const int* __restrict__ net_list;
+  int n_list;
+  int n_chunks;
 };
 
 __global__ __launch_bounds__(kBlock) void k_rc_tree_adjoint(TreeAdjArgs a) {
@@ -534,8 +547,9 @@ __global__ __launch_bounds__(kBlock) void k_rc_tree_adjoint(TreeAdjArgs a) {
   float4* __restrict__ B = snap_bytes(a.bar, a.snap.work);   // {dDelay, dBeta, dLDelay, dLoad}, {dCap, dlen, gx, gy}
   float* __restrict__ dx = snap_elems(a.dx, a.snap.pins);
   float* __restrict__ dy = snap_elems(a.dy, a.snap.pins);
-  const int n = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (n >= a.N) return;
+  const int k = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (k >= a.n_list) return;
+  const int n = a.net_list[k];
   const int b = a.net_off[n], e = a.net_off[n + 1];
   const float kr = 1e-3f * a.r, hc = 0.5f * a.c;
   for (int q = b; q < e; ++q) {                     // seeds: the impulse into Beta and Delay
@@ -595,6 +609,301 @@ __global__ __launch_bounds__(kBlock) void k_rc_tree_adjoint(TreeAdjArgs a) {
     const int qo = a.io_perm ? a.io_perm[q] : q;
     if (dx) dx[qo] = B[2 * (size_t)q + 1].z;
     if (dy) dy[qo] = B[2 * (size_t)q + 1].w;
+  }
+}
+
+// The RC tree passes for a chunk of whole nets (at most kTreeChunk pins) per workgroup, in LDS:
+// each thread holds kTreePer pins, and the passes run depth by depth with a barrier between
+// depths - Load and LDelay from the deepest depth up, each node summing its children (a run
+// of breadth-first positions) in order; Delay and Beta from the root down, each node reading
+// its parent.  Same values as k_rc_tree, kept in `tree` for the adjoint.
+constexpr int kTreePer = kTreeChunk / kBlock;
+static_assert(kTreePer * kBlock == kTreeChunk, "chunk must be a multiple of the workgroup");
+
+__global__ __launch_bounds__(kBlock) void k_rc_tree_chunk(RcArgs a) {
+  __shared__ float Llen[kTreeChunk], Lcap[kTreeChunk], Lload[kTreeChunk], Ldly[kTreeChunk], Lld[kTreeChunk],
+      Lbeta[kTreeChunk];
+  if ((int)blockIdx.x >= a.n_chunks) return;              // padding blocks of a snapshot grid
+  const int maxd = a.chunk_depth[blockIdx.x];
+  if (maxd < 0) return;                                   // a net left to the fallback kernel
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  float2* __restrict__ wire = snap_bytes(a.wire, a.snap.state);
+  float* __restrict__ loads = snap_bytes(a.load, a.snap.state);
+  float4* __restrict__ rec = snap_bytes(a.rec, a.snap.state);
+  float4* __restrict__ T = snap_bytes(a.tree, a.snap.state);
+  const int n_lo = a.chunk_net[blockIdx.x], n_hi = a.chunk_net[blockIdx.x + 1];
+  const int p_lo = a.net_off[n_lo], np = a.net_off[n_hi] - p_lo;
+  const float kr = 1e-3f * a.r, hc = 0.5f * a.c;
+  int dep[kTreePer], par[kTreePer], fc[kTreePer], nch[kTreePer];
+  float len[kTreePer];
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    dep[k] = -1;
+    par[k] = -1;
+    fc[k] = nch[k] = 0;
+    len[k] = 0.f;
+    if (i < np) {
+      const int q = p_lo + i;
+      const int4 t = a.tree_node[q];
+      dep[k] = t.x;
+      fc[k] = t.y;
+      nch[k] = t.z;
+      const int f = a.parent[q];
+      if (f >= 0) {
+        par[k] = f - p_lo;
+        const int qo = a.io_perm ? a.io_perm[q] : q, fo = a.io_perm ? a.io_perm[f] : f;
+        len[k] = fabsf(xs[qo] - xs[fo]) + fabsf(ys[qo] - ys[fo]);
+      }
+      Llen[i] = len[k];
+      Lcap[i] = fmaf(hc, len[k], a.pin_cap[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {                    // half of every segment out of a pin
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (nch[k] > 0) {
+      float c = Lcap[i];
+      for (int j = 0; j < nch[k]; ++j) c = fmaf(hc, Llen[a.tree_order[fc[k] + j] - p_lo], c);
+      Lcap[i] = c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] >= 0) Lload[i] = Lcap[i];
+  }
+  for (int d = maxd - 1; d >= 0; --d) {                   // Load (Eq. 1), deepest first
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d && nch[k] > 0) {
+        float v = Lload[i];
+        for (int j = 0; j < nch[k]; ++j) v += Lload[a.tree_order[fc[k] + j] - p_lo];
+        Lload[i] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k)
+    if (dep[k] == 0) Ldly[(int)threadIdx.x + k * kBlock] = 0.f;
+  for (int d = 1; d <= maxd; ++d) {                       // Delay, from the root down
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d) Ldly[i] = Ldly[par[k]] + kr * len[k] * Lload[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] >= 0) Lld[i] = Lcap[i] * Ldly[i];
+  }
+  for (int d = maxd - 1; d >= 0; --d) {                   // LDelay, deepest first
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d && nch[k] > 0) {
+        float v = Lld[i];
+        for (int j = 0; j < nch[k]; ++j) v += Lld[a.tree_order[fc[k] + j] - p_lo];
+        Lld[i] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k)
+    if (dep[k] == 0) Lbeta[(int)threadIdx.x + k * kBlock] = 0.f;
+  for (int d = 1; d <= maxd; ++d) {                       // Beta, from the root down
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d) Lbeta[i] = Lbeta[par[k]] + kr * len[k] * Lld[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] < 0) continue;
+    const int q = p_lo + i;
+    const float dly = Ldly[i], beta = Lbeta[i];
+    const float arg = 2.0f * beta - dly * dly;
+    const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
+    if (dep[k] > 0) wire[q] = make_float2(dly, imp);
+    T[2 * (size_t)q] = make_float4(len[k], Lcap[i], Lload[i], dly);
+    T[2 * (size_t)q + 1] = make_float4(Lld[i], beta, imp, 0.f);
+  }
+  for (int n = n_lo + (int)threadIdx.x; n < n_hi; n += kBlock) {
+    const int p0 = a.net_off[n];
+    rc_root(a, wire, loads, rec, n, p0, Lload[p0 - p_lo], true);
+  }
+}
+
+// Adjoint of the tree passes for a chunk of nets per workgroup in LDS (see k_rc_tree_chunk):
+// seeds from the sweep (the impulse into Beta and Delay), then Beta and Delay totals summed
+// over children from the deepest depth up, LDelay and Load totals passed down from parents,
+// Cap and Res to segment lengths, and lengths to the coordinates of both segment ends.
+__global__ __launch_bounds__(kBlock) void k_rc_tree_adjoint_chunk(TreeAdjArgs a) {
+  __shared__ float Db[kTreeChunk], Bb[kTreeChunk], LDb[kTreeChunk], Lb[kTreeChunk], Cb[kTreeChunk],
+      Gx[kTreeChunk], Gy[kTreeChunk];
+  if ((int)blockIdx.x >= a.n_chunks) return;
+  const int maxd = a.chunk_depth[blockIdx.x];
+  if (maxd < 0) return;
+  const float* __restrict__ xs = snap_elems(a.x, a.snap.pins);
+  const float* __restrict__ ys = snap_elems(a.y, a.snap.pins);
+  const float4* __restrict__ T = snap_bytes(a.tree, a.snap.state);
+  const float2* __restrict__ A = snap_bytes(a.tree_adj, a.snap.work);
+  float* __restrict__ dx = snap_elems(a.dx, a.snap.pins);
+  float* __restrict__ dy = snap_elems(a.dy, a.snap.pins);
+  const int n_lo = a.chunk_net[blockIdx.x], n_hi = a.chunk_net[blockIdx.x + 1];
+  const int p_lo = a.net_off[n_lo], np = a.net_off[n_hi] - p_lo;
+  const float kr = 1e-3f * a.r, hc = 0.5f * a.c;
+  int dep[kTreePer], par[kTreePer], fc[kTreePer], nch[kTreePer];
+  float len[kTreePer], cap[kTreePer], load[kTreePer], dly[kTreePer], ld[kTreePer], lenb[kTreePer];
+  float sx[kTreePer], sy[kTreePer];
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    dep[k] = -1;
+    par[k] = -1;
+    fc[k] = nch[k] = 0;
+    len[k] = cap[k] = load[k] = dly[k] = ld[k] = lenb[k] = sx[k] = sy[k] = 0.f;
+    if (i < np) {
+      const int q = p_lo + i;
+      const int4 t = a.tree_node[q];
+      dep[k] = t.x;
+      fc[k] = t.y;
+      nch[k] = t.z;
+      const int f = a.parent[q];
+      const float4 t0 = T[2 * (size_t)q], t1 = T[2 * (size_t)q + 1];
+      len[k] = t0.x;
+      cap[k] = t0.y;
+      load[k] = t0.z;
+      dly[k] = t0.w;
+      ld[k] = t1.x;
+      float dd = 0.f, db = 0.f, dl = 0.f;
+      const float2 g = A[q];
+      if (f < 0) {
+        dl = g.x;                                          // the root load's adjoint
+      } else {
+        par[k] = f - p_lo;
+        const int qo = a.io_perm ? a.io_perm[q] : q, fo = a.io_perm ? a.io_perm[f] : f;
+        sx[k] = sgnf(xs[qo] - xs[fo]);
+        sy[k] = sgnf(ys[qo] - ys[fo]);
+        dd = g.x;
+        if (t1.z > 0.f) {                                  // Impulse = sqrt(2 Beta - Delay^2)
+          db = g.y / t1.z;
+          dd -= g.y * t0.w / t1.z;
+        }
+      }
+      Db[i] = dd;
+      Bb[i] = db;
+      Lb[i] = dl;
+      Cb[i] = 0.f;
+    }
+  }
+  for (int d = maxd - 1; d >= 0; --d) {                   // Beta totals, deepest first
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d && nch[k] > 0) {
+        float v = Bb[i];
+        for (int j = 0; j < nch[k]; ++j) v += Bb[a.tree_order[fc[k] + j] - p_lo];
+        Bb[i] = v;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] < 0) continue;
+    lenb[k] = kr * ld[k] * Bb[i];
+    LDb[i] = kr * len[k] * Bb[i];
+  }
+  for (int d = 1; d <= maxd; ++d) {                       // LDelay totals, from the root down
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d) LDb[i] += LDb[par[k]];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] < 0) continue;
+    Cb[i] += LDb[i] * dly[k];
+    Db[i] += LDb[i] * cap[k];
+  }
+  for (int d = maxd - 1; d >= 0; --d) {                   // Delay totals, deepest first
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d && nch[k] > 0) {
+        float v = Db[i];
+        for (int j = 0; j < nch[k]; ++j) v += Db[a.tree_order[fc[k] + j] - p_lo];
+        Db[i] = v;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] <= 0) continue;
+    lenb[k] += kr * load[k] * Db[i];
+    Lb[i] += kr * len[k] * Db[i];
+  }
+  for (int d = 1; d <= maxd; ++d) {                       // Load totals, from the root down
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTreePer; ++k) {
+      const int i = (int)threadIdx.x + k * kBlock;
+      if (dep[k] == d) Lb[i] += Lb[par[k]];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] >= 0) Cb[i] += Lb[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {                    // Cap: half of the segment at each end
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] < 0) continue;
+    if (dep[k] > 0) lenb[k] += hc * (Cb[i] + Cb[par[k]]);
+    Gx[i] = lenb[k] * sx[k];
+    Gy[i] = lenb[k] * sy[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kTreePer; ++k) {                    // both ends of every segment
+    const int i = (int)threadIdx.x + k * kBlock;
+    if (dep[k] < 0) continue;
+    float gx = Gx[i], gy = Gy[i];
+    for (int j = 0; j < nch[k]; ++j) {
+      const int c = a.tree_order[fc[k] + j] - p_lo;
+      gx -= Gx[c];
+      gy -= Gy[c];
+    }
+    const int q = p_lo + i;
+    const int qo = a.io_perm ? a.io_perm[q] : q;
+    if (dx) dx[qo] = gx;
+    if (dy) dy[qo] = gy;
   }
 }
 
@@ -1500,15 +1809,18 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
 
   const Snap sn = snap_of(g);
   const bool tree = !g->c_parent.empty();
+  const int n_chunks = (int)g->tree_blk_depth.size(), n_big = (int)g->tree_big.size();
   RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0, g->N,
             g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn, d.parent, d.tree_order,
-            tree ? reinterpret_cast<float4*>(sb + g->state.tree) : nullptr};
+            tree ? reinterpret_cast<float4*>(sb + g->state.tree) : nullptr, d.tree_node, d.tree_blk_net,
+            d.tree_blk_depth, d.tree_big, n_big, n_chunks};
   {
     LaunchTimer t(g, s, STA_K_RC);
     const unsigned per_net = (unsigned)((g->N + kBlock - 1) / kBlock);
-    if (tree)
-      k_rc_tree<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
-    else if (g->sched_cfg.rc_scheme == STA_RC_CTE)
+    if (tree) {
+      if (n_chunks > 0) k_rc_tree_chunk<<<snap_grid(g, (unsigned)n_chunks), kBlock, 0, s>>>(ra);
+      if (n_big > 0) k_rc_tree<<<snap_grid(g, (unsigned)((n_big + kBlock - 1) / kBlock)), kBlock, 0, s>>>(ra);
+    } else if (g->sched_cfg.rc_scheme == STA_RC_CTE)
       k_rc_cte<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
     else if (g->sched_cfg.rc_scheme == STA_RC_THREAD)
       k_rc_thread<<<snap_grid(g, per_net), kBlock, 0, s>>>(ra);
@@ -1629,9 +1941,12 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
                          reinterpret_cast<const float4*>(sb + g->state.tree),
                          reinterpret_cast<const float2*>(wb + g->work.tree_adj),
                          reinterpret_cast<float4*>(wb + g->work.tree_bar), out->dx, out->dy, g->N,
-                         g->cons.r_per_um, g->cons.c_per_um, snap_of(g)};
+                         g->cons.r_per_um, g->cons.c_per_um, snap_of(g), d.tree_node, d.tree_blk_net,
+                         d.tree_blk_depth, d.tree_big, (int)g->tree_big.size(), (int)g->tree_blk_depth.size()};
     LaunchTimer t(g, s, STA_K_RC_ADJOINT);
-    k_rc_tree_adjoint<<<snap_grid(g, (unsigned)((g->N + kBlock - 1) / kBlock)), kBlock, 0, s>>>(ta);
+    if (ta.n_chunks > 0) k_rc_tree_adjoint_chunk<<<snap_grid(g, (unsigned)ta.n_chunks), kBlock, 0, s>>>(ta);
+    if (ta.n_list > 0)
+      k_rc_tree_adjoint<<<snap_grid(g, (unsigned)((ta.n_list + kBlock - 1) / kBlock)), kBlock, 0, s>>>(ta);
   }
   if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
