@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gen.netlist import CFG0, jitter, make_design, scaled_spec
+from gen.netlist import CFG0, heap_trees, jitter, make_design, scaled_spec
 from oracle import sta_oracle as O
 from paper_2603_28381_amd import Graph, Server, StaError
 from paper_2603_28381_amd import sta as S
@@ -17,8 +17,10 @@ GAMMA = 10.0
 
 
 def _designs():
+    # the last design carries an RC tree per net (served like the star designs)
     ds = [make_design(CFG0), make_design(scaled_spec(20_000, cfg_id=46, box_um=700.0)),
-          make_design(scaled_spec(5_000, cfg_id=47, box_um=300.0))]
+          make_design(scaled_spec(5_000, cfg_id=47, box_um=300.0)),
+          heap_trees(make_design(scaled_spec(8_000, cfg_id=58, box_um=400.0)))]
     gs = []
     for d in ds:
         g = Graph.from_design(d)
