@@ -75,7 +75,9 @@ typedef struct sta_netlist {
                                       this pin, -1 at drivers; following parents must reach the
                                       driver.  Trees use the recursive Eq. 1, the parent's delay
                                       in Eq. 2 and the second moment of the impulse (TAU 2015
-                                      model cited for Eq. 1-3); a star gives the same values. */
+                                      model cited for Eq. 1-3); a star gives the same values.
+                                      Trees add 32 bytes per pin to the forward state and 40 to
+                                      the backward workspace. */
 } sta_netlist;
 
 /* NLDM cell library (Sec. 3.1.2: cell arc delay by table interpolation).  One arc per
@@ -225,7 +227,8 @@ sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_
  * atg [S][n_pins][2]; dx, dy [S][n_pins]; scalars [S][n_designs][4]; state and workspace
  * S times their one-snapshot size (fwd_state_bytes and bwd_workspace_bytes report the
  * total).  Snapshot s computes exactly what a call with S = 1 on its coordinates computes.
- * Errors: STA_E_INVALID for S outside 1..65535.
+ * Errors: STA_E_INVALID for S outside 1..65535; sta_forward / sta_backward return
+ * STA_E_INVALID when one snapshot's state would exceed 2 GiB.
  * ------------------------------------------------------------------------------------- */
 sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
 
