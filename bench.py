@@ -131,6 +131,32 @@ def step_buffers(g, P, dev, n_designs=1, snaps=1):
     return state, ws, scal, outs
 
 
+def launch_floor_us(dev, n: int, reps: int = 200) -> float:
+    """Average time of back-to-back dependent launches of a trivial kernel (one float add per
+    thread), replayed from a captured graph so that host-side dispatch does not pace them."""
+    import torch
+    t = torch.zeros(n, device=dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            t.add_(1.0)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(reps):
+            t.add_(1.0)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return 1e3 * e0.elapsed_time(e1) / (3 * reps)
+
+
 def timed(step, steps: int, warmup: int) -> tuple[float, float]:
     """(ms per step from events on the current stream, wall seconds)."""
     import torch
@@ -335,6 +361,9 @@ def run_single(args) -> dict:
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
         if args.workload == "cfg2" and not args.trees:
             roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
+        # The per-launch floor of this machine for comparison: back-to-back dependent launches of
+        # a trivial elementwise kernel over as many threads as a level launch has.
+        roofline["launch_floor_us"] = round(launch_floor_us(dev, 256 * 450), 2)
 
     ckpt = None
     if args.ckpt_compare:
