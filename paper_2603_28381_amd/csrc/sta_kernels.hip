@@ -113,19 +113,27 @@ __device__ __forceinline__ LutVal lut_eval(const float4* __restrict__ grid, cons
   return r;
 }
 
+// Hardware approximations (about 1 ulp) of exp, log, square root and reciprocal: one
+// instruction each instead of the correctly rounded library sequences, in the level kernels'
+// per-lane arithmetic, whose times are compared with the oracle within 1e-4 relative.
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Slew at a sink: the driver slew combined with the wire's impulse.
 __device__ __forceinline__ float sink_slew(float drv_slew, float imp) {
-  return sqrtf(fmaf(drv_slew, drv_slew, imp * imp));
+  return fsqrt(fmaf(drv_slew, drv_slew, imp * imp));
 }
 
 // Merges log-sum-exp partials (m, s) <- (m, s) + (m2, s2), each meaning m + gamma*log(s)
 // (Eq. 4 with the maximum as the shift).
 __device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2, float inv_gamma) {
   if (m2 > m) {
-    s = fmaf(s, expf((m - m2) * inv_gamma), s2);
+    s = fmaf(s, fexp((m - m2) * inv_gamma), s2);
     m = m2;
   } else if (s2 > 0.f) {
-    s = fmaf(s2, expf((m2 - m) * inv_gamma), s);
+    s = fmaf(s2, fexp((m2 - m) * inv_gamma), s);
   }
 }
 
@@ -1022,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
       best_sl = fmaxf(best_sl, quad_reduce<kMax>(s));
       if (a.smooth) {
         const float gm = quad_reduce<kMax>(g);
-        const float gs = quad_reduce<kSum>(in.valid ? expf((g - gm) * a.inv_gamma) : 0.f);
+        const float gs = quad_reduce<kSum>(in.valid ? fexp((g - gm) * a.inv_gamma) : 0.f);
         lse_merge(lm, ls, gm, gs, a.inv_gamma);
       }
     } else {
@@ -1031,7 +1039,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
     }
   }
   if (jl == 0) {
-    const float ag = m ? (a.smooth ? fmaf(a.gamma, logf(ls), lm) : __builtin_nanf("")) : 0.f;
+    const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls), lm) : __builtin_nanf("")) : 0.f;
     *at32(rec, (uint32_t)(kRecChunks * slot + k)) = make_float4(best_at, best_sl, ag, 0.f);
   }
 }
@@ -1355,8 +1363,8 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in
   acc[R_L1] = fminf(acc[R_L1], rt.w - w.x);
   SinkKeep k{0.f, 0.f, 0.f, q};
   if (kGrad) {
-    const float q0 = sls.z > 0.f ? aj.z / sls.z : 0.f;   // s_bar(s,t) / slew(s,late,t)
-    const float q1 = sls.w > 0.f ? aj.w / sls.w : 0.f;
+    const float q0 = sls.z > 0.f ? aj.z * frcp(sls.z) : 0.f;   // s_bar(s,t) / slew(s,late,t)
+    const float q1 = sls.w > 0.f ? aj.w * frcp(sls.w) : 0.f;
     acc[A_R] += aj.x;
     acc[A_F] += aj.y;
     acc[S_R] += q0 * sl_d.z;
@@ -1529,7 +1537,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   ArcBwd arc0 = arc_from_input(a, ain, t, load);
   // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4).
   float xmax = quad_reduce<kMax>(arc0.valid ? arc0.xg : -kInf);
-  float z = quad_reduce<kSum>(arc0.valid ? expf((arc0.xg - xmax) * a.inv_gamma) : 0.f);
+  float z = quad_reduce<kSum>(arc0.valid ? fexp((arc0.xg - xmax) * a.inv_gamma) : 0.f);
   float smax = arc0.valid ? arc0.s : -kInf;
   int jstar = arc0.valid ? jl : STA_MAX_FANIN;
   quad_argmax(smax, jstar);
@@ -1538,7 +1546,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     v.valid = false;
     if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl, m, t, load);
     const float cm = quad_reduce<kMax>(v.valid ? v.xg : -kInf);
-    const float cz = quad_reduce<kSum>(v.valid ? expf((v.xg - cm) * a.inv_gamma) : 0.f);
+    const float cz = quad_reduce<kSum>(v.valid ? fexp((v.xg - cm) * a.inv_gamma) : 0.f);
     lse_merge(xmax, z, cm, cz, a.inv_gamma);
     float s2 = v.valid ? v.s : -kInf;
     int j2 = v.valid ? j0 + jl : STA_MAX_FANIN;
@@ -1565,7 +1573,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const float rat_o = k == 0 ? acc[R_E0] : (k == 1 ? acc[R_E1] : (k == 2 ? acc[R_L0] : acc[R_L1]));
   const float abar = t ? acc[A_F] : acc[A_R];
   const float sbar = t ? acc[S_F] : acc[S_R];
-  const float inv_z = 1.0f / z;
+  const float inv_z = frcp(z);
   float lb = 0.f;
   for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
     ArcBwd v = arc0;
@@ -1577,7 +1585,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
       // RAT(input, k') = RAT(output, k) - arc delay.
       *at32(reinterpret_cast<float*>(a.ratp), (uint32_t)(4 * v.pin + 2 * m + v.tp)) = rat_o - v.d;
       if (kGrad && m == 1) {
-        const float dbar = expf((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
+        const float dbar = fexp((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
         const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
         float* adj = reinterpret_cast<float*>(a.adjp);
         *at32(adj, (uint32_t)(4 * v.pin + v.tp)) = dbar;
