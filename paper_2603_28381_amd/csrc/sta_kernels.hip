@@ -1103,20 +1103,31 @@ __device__ __forceinline__ EpVals endpoint_values(const EpArgs& a, int i) {
   return v;
 }
 
-template <int NT>
-__device__ __forceinline__ double block_reduce(double v, double* sh, bool is_max) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const double b = sh[threadIdx.x + o];
-      sh[threadIdx.x] = is_max ? fmax(sh[threadIdx.x], b) : sh[threadIdx.x] + b;
+// Sums and maxima of K doubles at once over the 256 threads of a workgroup: xor butterflies
+// inside each wave (symmetric, so every lane ends with the same bits), then the four wave
+// results in wave order through LDS.  `sh` holds 4 * K doubles.
+template <int K>
+__device__ __forceinline__ void block_reduce(double (&v)[K], const bool (&is_max)[K], double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double w = __shfl_xor(v[k], o);
+      v[k] = is_max[k] ? fmax(v[k], w) : v[k] + w;
     }
-    __syncthreads();
   }
-  const double r = sh[0];
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[(threadIdx.x >> 6) * K + k] = v[k];
+  }
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double r = sh[k];
+    for (int q = 1; q < kWavesPerBlock; ++q) r = is_max[k] ? fmax(r, sh[q * K + k]) : r + sh[q * K + k];
+    v[k] = r;
+  }
+  __syncthreads();
 }
 
 // Per-block partial sums over endpoints, in float64 and a fixed order: hard TNS, hard
@@ -1139,12 +1150,15 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
     tnsg = -(fmax(0.0, -s) + g * log1p(exp(-fabs(s) / g)));
     v = -s;
   }
-  tns = block_reduce<kBlock>(tns, sh, false);
-  wmin = -block_reduce<kBlock>(-wmin, sh, true);
-  tnsg = block_reduce<kBlock>(tnsg, sh, false);
-  const double mb = block_reduce<kBlock>(v, sh, true);
-  const double ex = act ? exp((v - mb) / (double)a.gamma) : 0.0;
-  const double sb = block_reduce<kBlock>(ex, sh, false);
+  double r4[4] = {tns, -wmin, tnsg, v};
+  block_reduce<4>(r4, {false, true, false, true}, sh);
+  tns = r4[0];
+  wmin = -r4[1];
+  tnsg = r4[2];
+  const double mb = r4[3];
+  double r1[1] = {act ? exp((v - mb) / (double)a.gamma) : 0.0};
+  block_reduce<1>(r1, {false}, sh);
+  const double sb = r1[0];
   if (threadIdx.x == 0) {
     double* p = a.part + 5 * (size_t)blockIdx.x;
     p[0] = tns;
@@ -1169,16 +1183,20 @@ __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a0) {
     tnsg += p[2];
     mx = fmax(mx, p[3]);
   }
-  tns = block_reduce<kBlock>(tns, sh, false);
-  wmin = -block_reduce<kBlock>(-wmin, sh, true);
-  tnsg = block_reduce<kBlock>(tnsg, sh, false);
-  const double M = fmax(0.0, block_reduce<kBlock>(mx, sh, true));   // {0} joins the WNS_g set
+  double r4[4] = {tns, -wmin, tnsg, mx};
+  block_reduce<4>(r4, {false, true, false, true}, sh);
+  tns = r4[0];
+  wmin = -r4[1];
+  tnsg = r4[2];
+  const double M = fmax(0.0, r4[3]);   // {0} joins the WNS_g set
   double tot = 0.0;
   for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
     const double* p = a.part + 5 * (size_t)b;
     if (p[4] > 0.0) tot += p[4] * exp((p[3] - M) / (double)a.gamma);
   }
-  tot = block_reduce<kBlock>(tot, sh, false);
+  double r1[1] = {tot};
+  block_reduce<1>(r1, {false}, sh);
+  tot = r1[0];
   if (threadIdx.x == 0) {
     tot += exp(-M / (double)a.gamma);
     const double lse_all = M + (double)a.gamma * log(tot);
