@@ -46,6 +46,7 @@ void compute_layouts(sta_graph* g) {
   g->state.tree = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
   g->state.part = take(sizeof(double) * 5 * (size_t)std::max(1, g->n_ep_blocks));
   g->state.fin = take(sizeof(double) * 8 * (size_t)g->n_designs);
+  g->state.epv = take(sizeof(float4) * (size_t)std::max(1, g->E));
   g->state.total = off;
   off = 0;
   g->work.ratp = take(sizeof(float4) * (size_t)g->P);

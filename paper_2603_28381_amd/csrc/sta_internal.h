@@ -57,6 +57,7 @@ struct StateLayout {
                    // {LDelay, Beta, Impulse, 0} of the tree passes
   size_t part;     // double[n_ep_blocks * 5]: endpoint partial sums
   size_t fin;      // double[n_designs * 8]: finished scalars and the WNS_g normaliser per design
+  size_t epv;      // float4[E]: per endpoint {smoothed slack s_e, d s_e / d slack_g (rise, fall), 0}
   size_t total;
 };
 

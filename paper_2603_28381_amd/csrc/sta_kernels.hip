@@ -1063,6 +1063,7 @@ struct EpArgs {
   float rat_late, hold, gamma, inv_gamma, scale;
   int smooth, wns_mode;
   Snap snap;
+  float4* epv;        // per endpoint {s_e, w_rise, w_fall, 0}: written by the partials, read by the seeds
 };
 
 // The endpoint arguments of snapshot blockIdx.y.
@@ -1075,6 +1076,7 @@ __device__ __forceinline__ EpArgs ep_snap(const EpArgs& a0) {
   a.scalars = snap_elems(a.scalars, a.snap.scal);
   a.ratp = snap_bytes(a.ratp, a.snap.work);
   a.adjp = snap_bytes(a.adjp, a.snap.work);
+  a.epv = snap_bytes(a.epv, a.snap.state);
   return a;
 }
 
@@ -1143,6 +1145,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, v = -__builtin_huge_val();
   if (act) {
     const EpVals ev = endpoint_values(a, i);
+    a.epv[i] = make_float4(ev.sg, ev.w0, ev.w1, 0.f);   // kept for the backward's seeds
     tns = fmin(0.0, (double)ev.worst);
     wmin = ev.worst;
     const double s = ev.sg, g = a.gamma;
@@ -1222,7 +1225,12 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
   const int e = a.ep_pin[i];
   a.ratp[e] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
   if (a.adjp) {
-    const EpVals ev = endpoint_values(a, i);
+    // s_e and its weights as the forward computed them (same coordinates and gamma).
+    const float4 q = a.epv[i];
+    EpVals ev;
+    ev.sg = q.x;
+    ev.w0 = q.y;
+    ev.w1 = q.z;
     float coef;
     if (a.wns_mode) {
       const double lse_all = a.fin[8 * (size_t)a.ep_design[i] + 4];
@@ -1866,7 +1874,8 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
             nullptr, nullptr, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
-            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn};
+            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn,
+            reinterpret_cast<float4*>(sb + g->state.epv)};
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
     k_ep_partials<<<dim3(g->n_ep_blocks, g->n_snap), kBlock, 0, s>>>(ea);
@@ -1905,7 +1914,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp,
             grad ? adjp : nullptr, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
             g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
-            (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g)};
+            (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g), reinterpret_cast<float4*>(sb + g->state.epv)};
   if (g->E > 0) {
     LaunchTimer t(g, s, STA_K_EP_SEED);
     k_ep_seed<<<dim3((g->E + kBlock - 1) / kBlock, g->n_snap), kBlock, 0, s>>>(ea);
