@@ -39,8 +39,9 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict
                  (+40 record write for level-0 nets); per sink 8 x,y + 4 cap + 8 wire write
       fwd_level  per cell 16 (type, offset, arc base, load) + 40 record write; per cell
                  input 9 (source net, pin, unateness) + 8 wire + 40 source record
-      ep_partial per endpoint 28 (pin, net, late AT 8, smoothed AT 8, wire delay 4)
-      ep_seed    per endpoint 28 + 32 (required-time and adjoint seeds)
+      ep_partial per endpoint 28 (pin, net, late AT 8, smoothed AT 8, wire delay 4) + 16
+                 (its smoothed slack and weights, kept for the seeds)
+      ep_seed    per endpoint 4 pin + 16 kept values + 32 (required-time and adjoint seeds)
       bwd_level  per net 4 sched + 4 offset + 32 record + 8 driver x,y; per cell 16; per
                  cell input 9 + 8 wire + 24 source slew/smoothed AT + 32 seed writes;
                  per sink 16 RAT + 16 adjoint + 8 wire + 8 x,y + 4 cap; per pin 72 output
@@ -66,8 +67,8 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict
     out = {}
     out["rc"] = np.array([float(N * 24 + n0 * 40 + sinks.sum() * 20)])
     out["fwd_level"] = np.array([float(cells_l[l] * 56 + ins_l[l] * 57) for l in range(1, L)])
-    out["ep_partial"] = np.array([float(E * 28)])
-    out["ep_seed"] = np.array([float(E * 60)])
+    out["ep_partial"] = np.array([float(E * 44)])
+    out["ep_seed"] = np.array([float(E * 52)])
     out["bwd_level"] = np.array([float(nets_l[l] * 48 + cells_l[l] * 16 + ins_l[l] * 73 + sinks_l[l] * 52
                                        + pins_l[l] * 72) for l in range(L - 1, -1, -1)])
     return out
