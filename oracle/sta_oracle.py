@@ -38,7 +38,7 @@ Readings of what the paper leaves open (each used below):
   R10 only the late max merge is smoothed, using the hard-path arc delays and slews;
       smoothed slack s_e = -LSE(-slack_rise, -slack_fall), TNS_g = -sum_e LSE(0, -s_e),
       WNS_g = -LSE({0} u {-s_e}).
-  R11 a design may instead give every net an RC tree over its own pins (each sink's
+  R13 a design may instead give every net an RC tree over its own pins (each sink's
       parent pin, the driver at the root; one segment per sink, Manhattan length).
       Eq. 1 then sums Loads over children recursively, Eq. 2 gains the parent's delay,
       Delay(u) = Delay(fa(u)) + Res(fa(u) -> u) * Load(u) (the paper's Eq. 2 omits it,
@@ -163,7 +163,7 @@ def rc(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor):
 
     Returns dict of float64 tensors indexed by original pin id; Load is also given per net
     (the root load of the net, which is the load a driving cell sees).  Designs with RC
-    trees (d.pin_parent) go through rc_tree (reading R11).
+    trees (d.pin_parent) go through rc_tree (reading R13).
     """
     if getattr(d, "pin_parent", None) is not None:
         return rc_tree(d, lv, x, y)
@@ -208,7 +208,7 @@ def tree_depth(parent: np.ndarray) -> np.ndarray:
 
 
 def rc_tree(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor):
-    """Eq. 1-3 on RC trees (reading R11): segment u runs from pin fa(u) to pin u.
+    """Eq. 1-3 on RC trees (reading R13): segment u runs from pin fa(u) to pin u.
 
     Children are summed depth by depth, deepest first (Load, LDelay); delays and second
     moments accumulate from the root down (Delay, Beta).
@@ -532,7 +532,7 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
     rows = torch.from_numpy(plan.row)
     st = allst[rows]
     if want_decisions:
-        # the sign of each wire segment's extent (to the driver, or to the parent pin of R11)
+        # the sign of each wire segment's extent (to the driver, or to the parent pin of R13)
         pp = getattr(d, "pin_parent", None)
         ref = (torch.from_numpy(np.where(pp >= 0, pp, np.arange(P)).astype(np.int64)) if pp is not None
                else torch.from_numpy(lv.driver)[net_of_pin])

@@ -409,7 +409,7 @@ def test_wide_cells_match_path_enumeration(seed):
                 assert out["rat"][p, k] == pytest.approx(want, rel=1e-12, abs=1e-9)
 
 
-# ----------------------------------------------------------------------------- RC trees (R11)
+# ----------------------------------------------------------------------------- RC trees (R13)
 def _tree_moments_by_path_resistance(d, net):
     """Elmore delay and second moment of every pin of one net from the path-resistance
     form: Delay(u) = sum_k Rc(u, k) C_k and Beta(u) = sum_k Rc(u, k) C_k Delay(k), where
