@@ -49,8 +49,7 @@ void compute_layouts(sta_graph* g) {
   g->state.epv = take(sizeof(float4) * (size_t)std::max(1, g->E));
   g->state.total = off;
   off = 0;
-  g->work.ratp = take(sizeof(float4) * (size_t)g->P);
-  g->work.adjp = take(sizeof(float4) * (size_t)g->P);
+  g->work.sink = take(2 * sizeof(float4) * (size_t)g->P);
   g->work.tree_adj = take(tree ? sizeof(float2) * (size_t)g->P : 0);
   g->work.tree_bar = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
   g->work.total = off;

@@ -62,8 +62,9 @@ struct StateLayout {
 };
 
 struct WorkLayout {
-  size_t ratp;     // float4[P]: required time of each sink, by condition
-  size_t adjp;     // float4[P]: adjoint of each sink {a_rise, a_fall, s_rise, s_fall}
+  size_t sink;     // float4[2 * P]: per sink its required time by condition, then its adjoint
+                   // {a_rise, a_fall, s_rise, s_fall}; interleaved, so that the scattered
+                   // writes of one sink fill one aligned 32-byte segment
   size_t tree_adj; // RC trees only, float2[P]: adjoints of each sink's {Delay, Impulse} and
                    // of each net's root load (at its driver), from the backward sweep
   size_t tree_bar; // RC trees only, float4[2 * P]: adjoint scratch of the tree passes

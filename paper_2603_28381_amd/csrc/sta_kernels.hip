@@ -121,6 +121,13 @@ __device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x)
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Positions (in float4) of a sink's required times and adjoint in the backward workspace:
+// the two are interleaved per sink.
+__device__ __forceinline__ uint32_t rat_at(uint32_t p) { return 2u * p; }
+__device__ __forceinline__ uint32_t adj_at(uint32_t p) { return 2u * p + 1u; }
+__device__ __forceinline__ int rat_at(int p) { return 2 * p; }
+__device__ __forceinline__ int adj_at(int p) { return 2 * p + 1; }
+
 // Slew at a sink: the driver slew combined with the wire's impulse.
 __device__ __forceinline__ float sink_slew(float drv_slew, float imp) {
   return fsqrt(fmaf(drv_slew, drv_slew, imp * imp));
@@ -1056,8 +1063,8 @@ struct EpArgs {
   double* part;        // [blocks][5]
   double* fin;         // [designs][8]
   double* scalars;     // [designs][4] or NULL
-  float4* ratp;
-  float4* adjp;
+  float4* sink;        // per sink {RAT}, {adjoint} (see rat_at / adj_at)
+  int seed_adj;        // also seed the adjoint
   const double* scale_dev;
   int E, n_designs;
   float rat_late, hold, gamma, inv_gamma, scale;
@@ -1074,8 +1081,7 @@ __device__ __forceinline__ EpArgs ep_snap(const EpArgs& a0) {
   a.part = snap_bytes(a.part, a.snap.state);
   a.fin = snap_bytes(a.fin, a.snap.state);
   a.scalars = snap_elems(a.scalars, a.snap.scal);
-  a.ratp = snap_bytes(a.ratp, a.snap.work);
-  a.adjp = snap_bytes(a.adjp, a.snap.work);
+  a.sink = snap_bytes(a.sink, a.snap.work);
   a.epv = snap_bytes(a.epv, a.snap.state);
   return a;
 }
@@ -1223,8 +1229,8 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
   if (i >= a0.E) return;
   const EpArgs a = ep_snap(a0);
   const int e = a.ep_pin[i];
-  a.ratp[e] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
-  if (a.adjp) {
+  a.sink[rat_at(e)] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
+  if (a.seed_adj) {
     // s_e and its weights as the forward computed them (same coordinates and gamma).
     const float4 q = a.epv[i];
     EpVals ev;
@@ -1240,7 +1246,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
     }
     // d s_e / d atg(e, t) = -w_t; the objective's adjoint scales by `scale`.
     const float sc = a.scale_dev ? a.scale * (float)a.scale_dev[0] : a.scale;
-    a.adjp[e] = make_float4(-sc * coef * ev.w0, -sc * coef * ev.w1, 0.f, 0.f);
+    a.sink[adj_at(e)] = make_float4(-sc * coef * ev.w0, -sc * coef * ev.w1, 0.f, 0.f);
   }
 }
 
@@ -1313,8 +1319,7 @@ struct BwdArgs {
   const float2* __restrict__ wire;
   const float* __restrict__ load;
   const int* __restrict__ loc;       // record slot of each net, NULL: slot = net
-  float4* ratp;
-  float4* adjp;
+  float4* sink;                      // per sink {RAT}, {adjoint} (see rat_at / adj_at)
   float4* __restrict__ at_out;
   float4* __restrict__ slew_out;
   float4* __restrict__ rat_out;
@@ -1349,13 +1354,13 @@ template <bool kCanon, bool kGrad>
 __device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p) {
   SinkIn in;
   const uint32_t u = (uint32_t)p;
-  in.rt = ld(a.ratp, u);
+  in.rt = ld(a.sink, rat_at(u));
   in.w = ld(a.wire, u);
   in.q = kCanon ? p : ld(a.io_perm, u);
   in.aj = make_float4(0.f, 0.f, 0.f, 0.f);
   in.xs = in.ys = in.cp = 0.f;
   if (kGrad) {
-    in.aj = ld(a.adjp, u);
+    in.aj = ld(a.sink, adj_at(u));
     in.xs = ld(a.x, (uint32_t)in.q);
     in.ys = ld(a.y, (uint32_t)in.q);
     in.cp = ld(a.pin_cap, u);
@@ -1609,13 +1614,14 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     }
     if (cell_lane && v.valid) {
       // RAT(input, k') = RAT(output, k) - arc delay.
-      *at32(reinterpret_cast<float*>(a.ratp), (uint32_t)(4 * v.pin + 2 * m + v.tp)) = rat_o - v.d;
+      float* sw = reinterpret_cast<float*>(a.sink);
+      *at32(sw, 4 * rat_at((uint32_t)v.pin) + (uint32_t)(2 * m + v.tp)) = rat_o - v.d;
       if (kGrad && m == 1) {
         const float dbar = fexp((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
         const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
-        float* adj = reinterpret_cast<float*>(a.adjp);
-        *at32(adj, (uint32_t)(4 * v.pin + v.tp)) = dbar;
-        *at32(adj, (uint32_t)(4 * v.pin + 2 + v.tp)) = fmaf(dbar, v.ddx, s_j * v.dsx);
+        const uint32_t aj = 4 * adj_at((uint32_t)v.pin);
+        *at32(sw, aj + (uint32_t)v.tp) = dbar;
+        *at32(sw, aj + 2u + (uint32_t)v.tp) = fmaf(dbar, v.ddx, s_j * v.dsx);
         lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
       }
     }
@@ -1687,8 +1693,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   a.rec = snap_bytes<kSnap>(rec, (size_t)snap_state);
   a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state);
   a.load = snap_bytes<kSnap>(a.load, (size_t)snap_state);
-  a.ratp = snap_bytes<kSnap>(a.ratp, a.snap.work);
-  a.adjp = snap_bytes<kSnap>(a.adjp, a.snap.work);
+  a.sink = snap_bytes<kSnap>(a.sink, a.snap.work);
   a.x = snap_elems<kSnap>(a.x, a.snap.pins);
   a.y = snap_elems<kSnap>(a.y, a.snap.pins);
   a.at_out = snap_elems<kSnap>(a.at_out, a.snap.pins);
@@ -1873,7 +1878,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
-            nullptr, nullptr, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
+            nullptr, 0, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
             smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn,
             reinterpret_cast<float4*>(sb + g->state.epv)};
   if (g->n_ep_blocks > 0) {
@@ -1906,13 +1911,12 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
   float4* rec = reinterpret_cast<float4*>(sb + g->state.rec);
   float2* wire = reinterpret_cast<float2*>(sb + g->state.wire);
   float* load = reinterpret_cast<float*>(sb + g->state.load);
-  float4* ratp = reinterpret_cast<float4*>(wb + g->work.ratp);
-  float4* adjp = reinterpret_cast<float4*>(wb + g->work.adjp);
+  float4* sink = reinterpret_cast<float4*>(wb + g->work.sink);
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
-            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, ratp,
-            grad ? adjp : nullptr, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
+            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, sink,
+            grad ? 1 : 0, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
             g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
             (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g), reinterpret_cast<float4*>(sb + g->state.epv)};
   if (g->E > 0) {
@@ -1922,7 +1926,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
 
   const bool tree = !g->c_parent.empty();
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
-             rec, wire, load, d.rec_loc, ratp, adjp, reinterpret_cast<float4*>(out->at),
+             rec, wire, load, d.rec_loc, sink, reinterpret_cast<float4*>(out->at),
              reinterpret_cast<float4*>(out->slew), reinterpret_cast<float4*>(out->rat),
              reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g),
