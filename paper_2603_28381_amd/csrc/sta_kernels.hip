@@ -70,6 +70,39 @@ __device__ __forceinline__ T* snap_elems(T* p, size_t stride) {
   if (!kSnap) return p;
   return p ? p + stride * blockIdx.y : p;
 }
+// The same for an explicit snapshot index.
+template <bool kSnap = true, class T>
+__device__ __forceinline__ T* snap_bytes(T* p, size_t stride, int sn) {
+  using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  if (!kSnap) return p;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<C*>(p) + stride * (size_t)sn) : p;
+}
+template <bool kSnap = true, class T>
+__device__ __forceinline__ T* snap_elems(T* p, size_t stride, int sn) {
+  if (!kSnap) return p;
+  return p ? p + stride * (size_t)sn : p;
+}
+
+// Block and snapshot a workgroup of a level launch works on.  Workgroups go to the 8 XCDs
+// round-robin in launch order.  When the snapshot count is a multiple of 8, workgroup b
+// takes snapshot (b mod 8) + 8 * floor((b / 8) / X) and block (b / 8) mod X of the X blocks
+// of one snapshot, a bijection under which every snapshot runs on one XCD: the records,
+// wires and sink state that a level gathers at random of that snapshot then meet in one
+// L2, and the scattered stores to a line are merged there.  Otherwise snapshot blockIdx.y
+// takes block blockIdx.x (the x extent is padded to a multiple of 8, so that the copies of
+// a block share an XCD and its topology lines).
+struct SnapBlock {
+  int x, s;
+};
+template <bool kSnap>
+__device__ __forceinline__ SnapBlock snap_block() {
+  if (!kSnap) return SnapBlock{(int)blockIdx.x, 0};
+  const uint32_t X = gridDim.x, S = gridDim.y;
+  if (S % 8u != 0u) return SnapBlock{(int)blockIdx.x, (int)blockIdx.y};
+  const uint32_t b = blockIdx.y * X + blockIdx.x;
+  const uint32_t r = b >> 3;
+  return SnapBlock{(int)(r % X), (int)((b & 7u) + 8u * (r / X))};
+}
 
 // ---------------------------------------------------------------------------- helpers
 // Table cell of v along an axis: upper_bound(axis, v) - 1 clamped to [0, 5], computed as
@@ -244,18 +277,18 @@ __device__ __forceinline__ bool group_slot(const GroupRange& r, GroupSlot& s) {
 // heavy nets [h0, h0 + nh), class c entries [e_c, e_{c+1}) on waves [w_c, w_{c+1}) with
 // w_0 = 0 - and the class is found without indexing an array.
 template <int G0>
-__device__ __forceinline__ bool level_slot(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2, int w3,
-                                           GroupSlot& s) {
-  if ((int)blockIdx.x < nh) {
+__device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
+                                           int w3, GroupSlot& s) {
+  if (bx < nh) {
     s.block = true;
     s.G = kBlock;
     s.gl = threadIdx.x;
-    s.entry = h0 + (int)blockIdx.x;
+    s.entry = h0 + bx;
     s.active = true;
     return true;
   }
   s.block = false;
-  const int wave = ((int)blockIdx.x - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
+  const int wave = (bx - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= w3) return false;
   const int c = (wave >= w1) + (wave >= w2);
@@ -1004,10 +1037,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
                                                       const int* __restrict__ loc, float4* __restrict__ rec0,
                                                       FwdArgs a) {
   const Slots sl{base, F, 0, nc};
-  const float* loads = snap_bytes<kSnap>(loads0, (size_t)snap_state);
-  float4* rec = snap_bytes<kSnap>(rec0, (size_t)snap_state);
-  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state);
-  const int gid = (int)(blockIdx.x * kBlock + threadIdx.x);
+  const SnapBlock sb = snap_block<kSnap>();
+  const float* loads = snap_bytes<kSnap>(loads0, (size_t)snap_state, sb.s);
+  float4* rec = snap_bytes<kSnap>(rec0, (size_t)snap_state, sb.s);
+  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state, sb.s);
+  const int gid = sb.x * kBlock + (int)threadIdx.x;
   const int kc = gid / kCellLanes;
   if (kc >= sl.nc) return;                     // uniform over the cell's 16 lanes
   const int lane = gid & (kCellLanes - 1);
@@ -1690,21 +1724,22 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   __shared__ float sh[kWavesPerBlock * N_ACC];
   BwdArgs a = a0;
   a.net_off = net_off;
-  a.rec = snap_bytes<kSnap>(rec, (size_t)snap_state);
-  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state);
-  a.load = snap_bytes<kSnap>(a.load, (size_t)snap_state);
-  a.sink = snap_bytes<kSnap>(a.sink, a.snap.work);
-  a.x = snap_elems<kSnap>(a.x, a.snap.pins);
-  a.y = snap_elems<kSnap>(a.y, a.snap.pins);
-  a.at_out = snap_elems<kSnap>(a.at_out, a.snap.pins);
-  a.slew_out = snap_elems<kSnap>(a.slew_out, a.snap.pins);
-  a.rat_out = snap_elems<kSnap>(a.rat_out, a.snap.pins);
-  a.slack_out = snap_elems<kSnap>(a.slack_out, a.snap.pins);
-  a.dx = snap_elems<kSnap>(a.dx, a.snap.pins);
-  a.dy = snap_elems<kSnap>(a.dy, a.snap.pins);
-  a.tree_adj = snap_bytes<kSnap>(a.tree_adj, a.snap.work);
+  const SnapBlock sb = snap_block<kSnap>();
+  a.rec = snap_bytes<kSnap>(rec, (size_t)snap_state, sb.s);
+  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state, sb.s);
+  a.load = snap_bytes<kSnap>(a.load, (size_t)snap_state, sb.s);
+  a.sink = snap_bytes<kSnap>(a.sink, a.snap.work, sb.s);
+  a.x = snap_elems<kSnap>(a.x, a.snap.pins, sb.s);
+  a.y = snap_elems<kSnap>(a.y, a.snap.pins, sb.s);
+  a.at_out = snap_elems<kSnap>(a.at_out, a.snap.pins, sb.s);
+  a.slew_out = snap_elems<kSnap>(a.slew_out, a.snap.pins, sb.s);
+  a.rat_out = snap_elems<kSnap>(a.rat_out, a.snap.pins, sb.s);
+  a.slack_out = snap_elems<kSnap>(a.slack_out, a.snap.pins, sb.s);
+  a.dx = snap_elems<kSnap>(a.dx, a.snap.pins, sb.s);
+  a.dy = snap_elems<kSnap>(a.dy, a.snap.pins, sb.s);
+  a.tree_adj = snap_bytes<kSnap>(a.tree_adj, a.snap.work, sb.s);
   GroupSlot gs;
-  if (!level_slot<G0>(nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
+  if (!level_slot<G0>(sb.x, nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
   if (gs.block || gs.G == 64) {
     bwd_net<64, kCanon, kGrad>(a, sl, gs, sh);
   } else if (gs.G == 32) {
@@ -1826,11 +1861,18 @@ dim3 snap_grid(const sta_graph* g, unsigned blocks) {
   return dim3(blocks, (unsigned)g->n_snap, 1);
 }
 
+// Grid of a level launch over all snapshots: with a multiple of 8 snapshots the level
+// kernels place each snapshot on one XCD (snap_block) and need no padding.
+dim3 level_grid(const sta_graph* g, unsigned blocks) {
+  if (g->n_snap % 8 == 0) return dim3(blocks, (unsigned)g->n_snap, 1);
+  return snap_grid(g, blocks);
+}
+
 void fwd_level_launch(const sta_graph* g, unsigned blocks, hipStream_t s, const Slots& sl, int min_slot, int ss,
                       const int4* ell, const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
   const int n0 = g->N0 + sl.c0;
   if (g->n_snap > 1)
-    k_fwd_level<true><<<snap_grid(g, blocks), kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc,
+    k_fwd_level<true><<<level_grid(g, blocks), kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc,
                                                               rec, fa);
   else
     k_fwd_level<false><<<blocks, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
@@ -1943,7 +1985,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     const Slots sl = level_slots(g, l);
     const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss, d.net_off, rec, ba, sl};
     const bool snap = g->n_snap > 1, canon = io == nullptr;
-    const dim3 grid = snap ? snap_grid(g, blocks) : dim3(blocks);
+    const dim3 grid = snap ? level_grid(g, blocks) : dim3(blocks);
     switch (r.g0 * 2 + (snap ? 1 : 0)) {
       case 8: bwd_launch<4, false>(grid, s, L, canon, grad); break;
       case 9: bwd_launch<4, true>(grid, s, L, canon, grad); break;

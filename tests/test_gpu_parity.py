@@ -369,10 +369,11 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
         assert np.array_equal(again[key], plain[key], equal_nan=True), key
 
 
-@pytest.mark.parametrize("canonical", [False, True])
-def test_snapshots_equal_separate_calls_bitwise(canonical):
-    # Three placements swept together (shared topology) against three one-snapshot calls;
-    # also through a two-design batch and under checkpointing.
+@pytest.mark.parametrize("canonical,n_snap", [(False, 3), (True, 3), (True, 8)])
+def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap):
+    # Placements swept together (shared topology) against one-snapshot calls; also through a
+    # two-design batch and under checkpointing.  Eight snapshots take the level kernels'
+    # one-XCD-per-snapshot block mapping, three the padded one.
     from gen.netlist import jitter
     da = make_design(scaled_spec(25_000, cfg_id=49, box_um=600.0))
     db = make_design(scaled_spec(8_000, cfg_id=50, box_um=300.0))
@@ -384,9 +385,9 @@ def test_snapshots_equal_separate_calls_bitwise(canonical):
         # original order of a batch: the members' pins one design after the other
         base = [np.concatenate([d.x for d in members]), np.concatenate([d.y for d in members])]
         snaps = []
-        for k in range(3):
+        for k in range(n_snap):
             xs, ys = (base[0], base[1]) if k == 0 else (base[0] + np.float32(3.0 * k), base[1] - np.float32(2.0 * k))
-            if k == 2:
+            if k >= 2:
                 xs = xs + np.random.default_rng(k).normal(0, 4.0, xs.shape).astype(np.float32)
             if canonical:
                 xs, ys = xs[lev["pin_perm"]], ys[lev["pin_perm"]]
@@ -405,13 +406,13 @@ def test_snapshots_equal_separate_calls_bitwise(canonical):
                 if ckpt == 0:
                     r["fwd_at"] = f.at.cpu().numpy()
                 alone.append(r)
-            g.set_snapshots(3)
+            g.set_snapshots(n_snap)
             x = torch.tensor(np.stack([s[0] for s in snaps]), device="cuda")
             y = torch.tensor(np.stack([s[1] for s in snaps]), device="cuda")
             f = g.forward(x, y, gamma=GAMMA, canonical=canonical, pins=(ckpt == 0))
             o = g.backward(x, y, f, rat=True, grad=True, pins=True)
             torch.cuda.synchronize()
-            for k in range(3):
+            for k in range(n_snap):
                 for key in ("at", "slew", "rat", "slack", "dx", "dy"):
                     assert np.array_equal(o[key][k].cpu().numpy(), alone[k][key], equal_nan=True), (len(members), ckpt, k, key)
                 assert np.array_equal(f.scalars[k].cpu().numpy(), alone[k]["scalars"]), (len(members), ckpt, k)
