@@ -84,10 +84,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counted_traffic(kernel: str) -> float | None:
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary of the 2.5M-pin sweep, or None when the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", "sta_sweep_2p5Mpins_hbm_counters.md")
+def counted_traffic(kernel: str, summary: str = "sta_sweep_2p5Mpins_hbm_counters.md") -> float | None:
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (by default the 2.5M-pin sweep's), or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     want = kernel_source_hash()
@@ -284,6 +284,7 @@ def run_batch(args) -> dict:
         alg = {k: 64 * v for k, v in algorithmic_bytes(d1, g1.levelization()["level"]).items()}
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
+        roofline["traffic"] = counted_traffic("k_" + roofline["kernel"], "sta_batched_64snap_kernel_stats.md")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -347,6 +348,7 @@ def snapshot_graph_only(args, g1, d1, x1, y1, dev, best1, t_setup) -> dict:
         alg = {k: 64 * v for k, v in algorithmic_bytes(d1, g1.levelization()["level"]).items()}
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
+        roofline["traffic"] = counted_traffic("k_" + roofline["kernel"], "sta_batched_64snap_kernel_stats.md")
     P = 64 * d1.n_pins
     return {
         "metric": "STA fwd+bwd pins/sec, 64 placement snapshots in one sweep",
