@@ -34,7 +34,8 @@ namespace {
 
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kCellLanes = 16;   // lanes per cell: 4 conditions x 4 arcs
+constexpr int kCellLanes = 16;   // backward cell step: lanes per cell, 4 conditions x 4 arcs
+constexpr int kFwdCellLanes = 4; // forward level: lanes per cell, one per condition
 constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
 constexpr int kRecChunks = 4;    // float4 chunks per arrival record, one per condition
 
@@ -1085,6 +1086,80 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
   }
 }
 
+// The same level with 4 lanes per cell, lane k for condition k: the lane looks up every arc
+// of the cell (the loads of 4 arcs are issued together) and merges them in registers, with
+// the same arguments and results up to the order of the log-sum-exp terms.  A quarter of
+// the waves of k_fwd_level, for launches over many snapshots.
+template <bool kSnap>
+__global__ __launch_bounds__(kBlock) void k_fwd_level4(int nc, int n0, int base, int F, int min_slot, int snap_state,
+                                                      const int4* __restrict__ ell, const float* __restrict__ loads0,
+                                                      const int* __restrict__ loc, float4* __restrict__ rec0,
+                                                      FwdArgs a) {
+  const Slots sl{base, F, 0, nc};
+  const SnapBlock sb = snap_block<kSnap>();
+  const float* loads = snap_bytes<kSnap>(loads0, (size_t)snap_state, sb.s);
+  float4* rec = snap_bytes<kSnap>(rec0, (size_t)snap_state, sb.s);
+  a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state, sb.s);
+  const int gid = sb.x * kBlock + (int)threadIdx.x;
+  const int kc = gid / kFwdCellLanes;
+  if (kc >= sl.nc) return;                     // uniform over the cell's 4 lanes
+  const int k = gid & (kFwdCellLanes - 1), m = k >> 1, t = k & 1;
+  const int n = n0 + kc;
+  // Loads in three waves, each issued as soon as its addresses are known: the input slot
+  // entries and the root load; the source records and wires; the table coefficients.
+  int4 e[kArcLanes];
+#pragma unroll
+  for (int j = 0; j < kArcLanes; ++j) e[j] = ld(ell, (uint32_t)(sl.base + min(j, sl.F - 1) * sl.nc + kc));
+  const float load = ld(loads, (uint32_t)n);
+  const int slot = loc ? ld(loc, (uint32_t)n) : n;
+  if (slot < min_slot) return;                 // kept record, not recomputed
+  float best_at = m ? -kInf : kInf;
+  float best_sl = best_at;
+  float lm = -kInf, ls = 0.f;
+  for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
+    ArcIn in[kArcLanes];
+#pragma unroll
+    for (int j = 0; j < kArcLanes; ++j)
+      in[j] = j0 == 0 ? arc_input_entry(e[j], j < sl.F, rec, a.wire, m, t)
+                      : arc_input(ell, sl, kc, j0 + j, rec, a.wire, m, t);
+    LutVal v[kArcLanes];
+#pragma unroll
+    for (int j = 0; j < kArcLanes; ++j) v[j] = lut_eval<false>(a.grid, a.coef, a.keys, in[j].arc, t, in[j].slew, load);
+    const float neutral = m ? -kInf : kInf;
+    float g[kArcLanes];
+    float cm = neutral, sm = neutral, gm = -kInf;
+#pragma unroll
+    for (int j = 0; j < kArcLanes; ++j) {
+      const float cand = in[j].valid ? in[j].at + v[j].d : neutral;
+      const float s = in[j].valid ? v[j].s : neutral;
+      g[j] = in[j].valid ? in[j].atg + v[j].d : -kInf;
+      if (m) {
+        cm = fmaxf(cm, cand);
+        sm = fmaxf(sm, s);
+        gm = fmaxf(gm, g[j]);
+      } else {
+        cm = fminf(cm, cand);
+        sm = fminf(sm, s);
+      }
+    }
+    if (m) {
+      best_at = fmaxf(best_at, cm);
+      best_sl = fmaxf(best_sl, sm);
+      if (a.smooth) {
+        float gs = 0.f;
+#pragma unroll
+        for (int j = 0; j < kArcLanes; ++j) gs += in[j].valid ? fexp((g[j] - gm) * a.inv_gamma) : 0.f;
+        lse_merge(lm, ls, gm, gs, a.inv_gamma);
+      }
+    } else {
+      best_at = fminf(best_at, cm);
+      best_sl = fminf(best_sl, sm);
+    }
+  }
+  const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls), lm) : __builtin_nanf("")) : 0.f;
+  *at32(rec, (uint32_t)(kRecChunks * slot + k)) = make_float4(best_at, best_sl, ag, 0.f);
+}
+
 // ---------------------------------------------------------------------------- endpoints
 struct EpArgs {
   const int* __restrict__ ep_pin;
@@ -1868,14 +1943,25 @@ dim3 level_grid(const sta_graph* g, unsigned blocks) {
   return snap_grid(g, blocks);
 }
 
-void fwd_level_launch(const sta_graph* g, unsigned blocks, hipStream_t s, const Slots& sl, int min_slot, int ss,
-                      const int4* ell, const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
+// One forward level with the schedule's lanes per cell (16: k_fwd_level, 4: k_fwd_level4).
+void fwd_level_launch(const sta_graph* g, hipStream_t s, const Slots& sl, int min_slot, int ss, const int4* ell,
+                      const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
+  const int lanes = g->sched_cfg.fwd_cell_lanes == 4 ? kFwdCellLanes : kCellLanes;
+  const unsigned blocks = (unsigned)(((size_t)lanes * sl.nc + kBlock - 1) / kBlock);
+  if (blocks == 0) return;
   const int n0 = g->N0 + sl.c0;
-  if (g->n_snap > 1)
-    k_fwd_level<true><<<level_grid(g, blocks), kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc,
-                                                              rec, fa);
-  else
-    k_fwd_level<false><<<blocks, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  const bool snap = g->n_snap > 1;
+  const dim3 grid = snap ? level_grid(g, blocks) : dim3(blocks);
+  if (lanes == kFwdCellLanes) {
+    if (snap)
+      k_fwd_level4<true><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+    else
+      k_fwd_level4<false><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  } else if (snap) {
+    k_fwd_level<true><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  } else {
+    k_fwd_level<false><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  }
 }
 
 sta_status launch_forward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
@@ -1913,9 +1999,9 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
                    smooth ? 1 : 0};
   for (int l = 1; l < g->L; ++l) {
     const Slots sl = level_slots(g, l);
-    const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
+    if (sl.nc == 0) continue;
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
-    fwd_level_launch(g, blocks, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
+    fwd_level_launch(g, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
   }
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
@@ -2007,10 +2093,9 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
       const int lo = g->seg_lo[j], hi = g->seg_lo[j + 1];
       for (int l = lo; l < hi; ++l) {
         const Slots sl = level_slots(g, l);
-        const unsigned blocks = (unsigned)((kCellLanes * sl.nc + kBlock - 1) / kBlock);
-        if (blocks == 0) continue;
+        if (sl.nc == 0) continue;
         LaunchTimer t(g, s, STA_K_RECOMPUTE);
-        fwd_level_launch(g, blocks, s, sl, g->n_kept, ss, d.ell, load, d.rec_loc, rec, fa);
+        fwd_level_launch(g, s, sl, g->n_kept, ss, d.ell, load, d.rec_loc, rec, fa);
       }
       for (int l = hi - 1; l >= lo; --l) bwd_level(l);
     }
@@ -2175,14 +2260,18 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
     }
   };
   // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
-  // task pool, one thread per net) on the best of those.
+  // task pool, one thread per net) on the best of those, then 4 lanes per forward cell.
   for (int sweep = 4; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
-        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS});
+        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16});
   const sta_schedule lanes = best_s;
   for (int rc : {STA_RC_CTE, STA_RC_THREAD})
-    if (st == STA_OK) try_schedule(sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc});
+    if (st == STA_OK)
+      try_schedule(sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16});
+  sta_schedule fwd4 = best_s;
+  fwd4.fwd_cell_lanes = 4;
+  if (st == STA_OK) try_schedule(fwd4);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (void* p : buf) (void)hipFree(p);

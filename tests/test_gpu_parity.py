@@ -299,9 +299,9 @@ def test_graph_capture_replays_match_plain_calls():
 
 
 def test_schedules_agree_with_oracle():
-    # Every schedule sweeps the same arithmetic (summation order aside): lane groups, and the
-    # RC stage as Alg. 2's task pool (pools of 256 nets that span several LDS chunks of
-    # sinks here) or one thread per net.
+    # Every schedule sweeps the same arithmetic (summation order aside): lane groups, the RC
+    # stage as Alg. 2's task pool (pools of 256 nets that span several LDS chunks of sinks
+    # here) or one thread per net, and 4 lanes per forward cell.
     d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
     ref = O.run(d, gamma=GAMMA, grad="tns")
     g = Graph.from_design(d)
@@ -309,7 +309,7 @@ def test_schedules_agree_with_oracle():
     sinks = (np.diff(d.net_offsets) - 1)[g.levelization()["net_perm"]]
     pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
     assert pools.max() > 2 * 1024, pools.max()
-    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread")):
+    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4)):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
@@ -369,11 +369,11 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
         assert np.array_equal(again[key], plain[key], equal_nan=True), key
 
 
-@pytest.mark.parametrize("canonical,n_snap", [(False, 3), (True, 3), (True, 8)])
-def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap):
+@pytest.mark.parametrize("canonical,n_snap,fwd_lanes", [(False, 3, 16), (True, 3, 16), (True, 8, 16), (True, 8, 4)])
+def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
     # Placements swept together (shared topology) against one-snapshot calls; also through a
     # two-design batch and under checkpointing.  Eight snapshots take the level kernels'
-    # one-XCD-per-snapshot block mapping, three the padded one.
+    # one-XCD-per-snapshot block mapping, three the padded one; both forward cell mappings.
     from gen.netlist import jitter
     da = make_design(scaled_spec(25_000, cfg_id=49, box_um=600.0))
     db = make_design(scaled_spec(8_000, cfg_id=50, box_um=300.0))
@@ -381,6 +381,7 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap):
         gs = [Graph.from_design(d) for d in members]
         g = gs[0] if len(gs) == 1 else Graph.batch(gs)
         g.levelize()
+        g.set_schedule(4, 2, 64, "groups", fwd_lanes)
         lev = g.levelization()
         # original order of a batch: the members' pins one design after the other
         base = [np.concatenate([d.x for d in members]), np.concatenate([d.y for d in members])]
@@ -421,14 +422,17 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap):
         g.set_snapshots(1)
 
 
-@pytest.mark.parametrize("wns", [False, True])
-def test_parity_wide_cells(wns):
+@pytest.mark.parametrize("wns,fwd_lanes", [(False, 16), (True, 16), (False, 4), (True, 4)])
+def test_parity_wide_cells(wns, fwd_lanes):
     # Cells of 5-8 inputs take the cell steps' second chunk of 4 arcs (merged log-sum-exp,
-    # arg max and softmax across chunks).
+    # arg max and softmax across chunks), in both forward cell mappings.
     from tests._designs import wide_dag
     d = wide_dag(n_levels=9, gates_per_level=60, n_pi=16, seed=3)
     ref = O.run(d, gamma=GAMMA, grad="wns" if wns else "tns")
-    got = gpu_run(d, wns=wns)
+    g = Graph.from_design(d)
+    g.levelize()
+    g.set_schedule(4, 2, 64, "groups", fwd_lanes)
+    got = gpu_run(d, wns=wns, graph=g)
     check_values(d, got, ref)
     check_grad(got, ref, 1e-3, 1e-6)
 

@@ -132,19 +132,24 @@ def test_schedule_roundtrip_and_validation():
         g.set_schedule(4, 2, 64)
     assert e.value.code == S.STA_E_STATE          # not levelized yet
     g.levelize()
-    assert g.schedule() == dict(sweep_group_log2=4, flat_group_log2=2, heavy_sinks=64, rc_scheme=S.STA_RC_GROUPS)
+    assert g.schedule() == dict(sweep_group_log2=4, flat_group_log2=2, heavy_sinks=64, rc_scheme=S.STA_RC_GROUPS,
+                                fwd_cell_lanes=16)
     g.set_schedule(5, 3, 32)
-    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_GROUPS)
+    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_GROUPS,
+                                fwd_cell_lanes=16)
+    g.set_schedule(5, 3, 32, "groups", 4)
+    assert g.schedule()["fwd_cell_lanes"] == 4
     g.set_schedule(5, 3, 32, "cte")
     assert g.schedule()["rc_scheme"] == S.STA_RC_CTE
     g.set_schedule(5, 3, 32, "thread")
     assert g.schedule()["rc_scheme"] == S.STA_RC_THREAD
     for bad in ((3, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65), (4, 2, 64, 3),
-                (4, 2, 64, -1)):
+                (4, 2, 64, -1), (4, 2, 64, 0, 8), (4, 2, 64, 0, 0), (4, 2, 64, 0, 32)):
         with pytest.raises(S.StaError) as e:
             g.set_schedule(*bad)
         assert e.value.code == S.STA_E_INVALID
-    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_THREAD)
+    assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_THREAD,
+                                fwd_cell_lanes=16)
     g.close()
 
 
