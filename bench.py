@@ -380,6 +380,8 @@ def run_single(args) -> dict:
         d = heap_trees(d)
     g = Graph.from_design(d)
     n_levels = g.levelize()
+    if args.fwd_cell_lanes != 16:
+        g.set_schedule(4, 2, 64, "groups", args.fwd_cell_lanes)
     g.upload()
     lev = g.levelization()
     t_setup = time.time() - t0
@@ -408,7 +410,7 @@ def run_single(args) -> dict:
         prof = g.profile_read()
         g.profile(False)
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
-        if args.workload == "cfg2" and not args.trees:
+        if args.workload == "cfg2" and not args.trees and args.fwd_cell_lanes == 16:
             roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
         # The per-launch floor of this machine for comparison: back-to-back dependent launches of
         # a trivial elementwise kernel over as many threads as a level launch has.
@@ -438,7 +440,8 @@ def run_single(args) -> dict:
         "config": {"workload": f"{args.workload}: {P} pins, {d.n_nets} nets, {d.n_cells} cells, "
                                f"{n_levels} net levels, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps"
                                + (", hipGraph-captured" if args.capture else "")
-                               + (", an RC tree per net (binary heaps by distance)" if args.trees else ""),
+                               + (", an RC tree per net (binary heaps by distance)" if args.trees else "")
+                               + (f", {args.fwd_cell_lanes} lanes per forward cell" if args.fwd_cell_lanes != 16 else ""),
                    "pins": P, "levels": n_levels, "io": "canonical order, HBM resident"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -812,6 +815,8 @@ def main(argv=None) -> int:
                     help="first run one plain device copy of this size (a reference for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
+    ap.add_argument("--fwd-cell-lanes", type=int, default=16, choices=[16, 8, 4],
+                    help="cfg0-2: lanes per cell of the forward level kernel (the schedule's fwd_cell_lanes)")
     ap.add_argument("--trees", action="store_true",
                     help="cfg0-2 with an RC tree per net (binary heaps by distance) instead of stars")
     args = ap.parse_args(argv)

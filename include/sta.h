@@ -242,9 +242,10 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
  * pin-based scheme of Alg. 1), the CTE task pool of Alg. 2 (a workgroup pools the sinks of
  * 256 nets and rebalances them over its threads), or one thread per net.  fwd_cell_lanes
  * is the number of lanes per cell in the forward level kernel: 16 (one per condition and
- * arc, merged across lanes) or 4 (one per condition, each lane looking up all of the cell's
- * arcs): 4 launches a quarter of the waves, which pays when many snapshots fill the chip,
- * while one design's short levels favour 16.  Defaults {4, 2, 64, STA_RC_GROUPS, 16}.
+ * arc, merged across lanes), 8 (two per condition, two arcs each) or 4 (one per condition,
+ * each lane looking up all of the cell's arcs): fewer lanes launch fewer waves, which pays
+ * when many snapshots fill the chip, while one design's short levels favour 16.  Defaults
+ * {4, 2, 64, STA_RC_GROUPS, 16}.
  * Setting a schedule rebuilds the launch plan (no result changes beyond float summation
  * order).  Errors: STA_E_INVALID for out-of-range fields,
  * STA_E_STATE if not levelized.
@@ -258,7 +259,7 @@ typedef struct sta_schedule {
   int32_t flat_group_log2;    /* 2..6 */
   int32_t heavy_sinks;        /* 1..64 */
   int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */
-  int32_t fwd_cell_lanes;     /* 16 or 4 */
+  int32_t fwd_cell_lanes;     /* 16, 8 or 4 */
 } sta_schedule;
 
 sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);

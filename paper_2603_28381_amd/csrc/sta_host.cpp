@@ -756,7 +756,8 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   if (!g || !sch) return fail(STA_E_INVALID, "NULL argument");
   if (sch->sweep_group_log2 < 4 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
       sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64 || sch->rc_scheme < STA_RC_GROUPS ||
-      sch->rc_scheme > STA_RC_THREAD || (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 4))
+      sch->rc_scheme > STA_RC_THREAD ||
+      (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4))
     return fail(STA_E_INVALID, "schedule out of range");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   g->sched_cfg = *sch;

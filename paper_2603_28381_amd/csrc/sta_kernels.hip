@@ -35,7 +35,6 @@ namespace {
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kCellLanes = 16;   // backward cell step: lanes per cell, 4 conditions x 4 arcs
-constexpr int kFwdCellLanes = 4; // forward level: lanes per cell, one per condition
 constexpr int kArcLanes = 4;     // arcs handled at once per condition; wider cells loop
 constexpr int kRecChunks = 4;    // float4 chunks per arrival record, one per condition
 
@@ -1086,30 +1085,49 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level(int nc, int n0, int base, 
   }
 }
 
-// The same level with 4 lanes per cell, lane k for condition k: the lane looks up every arc
-// of the cell (the loads of 4 arcs are issued together) and merges them in registers, with
-// the same arguments and results up to the order of the log-sum-exp terms.  A quarter of
-// the waves of k_fwd_level, for launches over many snapshots.
-template <bool kSnap>
-__global__ __launch_bounds__(kBlock) void k_fwd_level4(int nc, int n0, int base, int F, int min_slot, int snap_state,
-                                                      const int4* __restrict__ ell, const float* __restrict__ loads0,
-                                                      const int* __restrict__ loc, float4* __restrict__ rec0,
-                                                      FwdArgs a) {
+// The same level with 4 * L lanes per cell, L = 1 or 2 lanes per condition k: lane (k, jl)
+// looks up arcs jl, jl + L, ... of each chunk of 4 (their loads issued together), merges
+// them in registers and then, for L = 2, with the other lane of its pair.  Same arguments
+// and results up to the order of the log-sum-exp terms; a quarter (L = 1) or half (L = 2)
+// of the waves of k_fwd_level, at the price of serial lookups in each lane.
+template <int L>
+__device__ __forceinline__ float pair_reduce_max(float v) {
+  return L == 2 ? fmaxf(v, dpp<kDppQuadX1>(v)) : v;
+}
+template <int L>
+__device__ __forceinline__ float pair_reduce_min(float v) {
+  return L == 2 ? fminf(v, dpp<kDppQuadX1>(v)) : v;
+}
+template <int L>
+__device__ __forceinline__ float pair_reduce_sum(float v) {
+  return L == 2 ? v + dpp<kDppQuadX1>(v) : v;
+}
+
+template <bool kSnap, int L>
+__global__ __launch_bounds__(kBlock) void k_fwd_level_narrow(int nc, int n0, int base, int F, int min_slot,
+                                                             int snap_state, const int4* __restrict__ ell,
+                                                             const float* __restrict__ loads0,
+                                                             const int* __restrict__ loc, float4* __restrict__ rec0,
+                                                             FwdArgs a) {
+  constexpr int kLanes = 4 * L;                // lanes per cell
+  constexpr int kArcs = kArcLanes / L;         // arcs per lane in a chunk of 4
   const Slots sl{base, F, 0, nc};
   const SnapBlock sb = snap_block<kSnap>();
   const float* loads = snap_bytes<kSnap>(loads0, (size_t)snap_state, sb.s);
   float4* rec = snap_bytes<kSnap>(rec0, (size_t)snap_state, sb.s);
   a.wire = snap_bytes<kSnap>(a.wire, (size_t)snap_state, sb.s);
   const int gid = sb.x * kBlock + (int)threadIdx.x;
-  const int kc = gid / kFwdCellLanes;
-  if (kc >= sl.nc) return;                     // uniform over the cell's 4 lanes
-  const int k = gid & (kFwdCellLanes - 1), m = k >> 1, t = k & 1;
+  const int kc = gid / kLanes;
+  if (kc >= sl.nc) return;                     // uniform over the cell's lanes
+  const int lane = gid & (kLanes - 1);
+  const int k = lane / L, jl = lane % L, m = k >> 1, t = k & 1;
   const int n = n0 + kc;
   // Loads in three waves, each issued as soon as its addresses are known: the input slot
   // entries and the root load; the source records and wires; the table coefficients.
-  int4 e[kArcLanes];
+  int4 e[kArcs];
 #pragma unroll
-  for (int j = 0; j < kArcLanes; ++j) e[j] = ld(ell, (uint32_t)(sl.base + min(j, sl.F - 1) * sl.nc + kc));
+  for (int i = 0; i < kArcs; ++i)
+    e[i] = ld(ell, (uint32_t)(sl.base + min(jl + L * i, sl.F - 1) * sl.nc + kc));
   const float load = ld(loads, (uint32_t)n);
   const int slot = loc ? ld(loc, (uint32_t)n) : n;
   if (slot < min_slot) return;                 // kept record, not recomputed
@@ -1117,47 +1135,52 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level4(int nc, int n0, int base,
   float best_sl = best_at;
   float lm = -kInf, ls = 0.f;
   for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
-    ArcIn in[kArcLanes];
+    ArcIn in[kArcs];
 #pragma unroll
-    for (int j = 0; j < kArcLanes; ++j)
-      in[j] = j0 == 0 ? arc_input_entry(e[j], j < sl.F, rec, a.wire, m, t)
-                      : arc_input(ell, sl, kc, j0 + j, rec, a.wire, m, t);
-    LutVal v[kArcLanes];
+    for (int i = 0; i < kArcs; ++i) {
+      const int j = j0 + jl + L * i;
+      in[i] = j0 == 0 ? arc_input_entry(e[i], j < sl.F, rec, a.wire, m, t)
+                      : arc_input(ell, sl, kc, j, rec, a.wire, m, t);
+    }
+    LutVal v[kArcs];
 #pragma unroll
-    for (int j = 0; j < kArcLanes; ++j) v[j] = lut_eval<false>(a.grid, a.coef, a.keys, in[j].arc, t, in[j].slew, load);
+    for (int i = 0; i < kArcs; ++i) v[i] = lut_eval<false>(a.grid, a.coef, a.keys, in[i].arc, t, in[i].slew, load);
     const float neutral = m ? -kInf : kInf;
-    float g[kArcLanes];
+    float g[kArcs];
     float cm = neutral, sm = neutral, gm = -kInf;
 #pragma unroll
-    for (int j = 0; j < kArcLanes; ++j) {
-      const float cand = in[j].valid ? in[j].at + v[j].d : neutral;
-      const float s = in[j].valid ? v[j].s : neutral;
-      g[j] = in[j].valid ? in[j].atg + v[j].d : -kInf;
+    for (int i = 0; i < kArcs; ++i) {
+      const float cand = in[i].valid ? in[i].at + v[i].d : neutral;
+      const float s = in[i].valid ? v[i].s : neutral;
+      g[i] = in[i].valid ? in[i].atg + v[i].d : -kInf;
       if (m) {
         cm = fmaxf(cm, cand);
         sm = fmaxf(sm, s);
-        gm = fmaxf(gm, g[j]);
+        gm = fmaxf(gm, g[i]);
       } else {
         cm = fminf(cm, cand);
         sm = fminf(sm, s);
       }
     }
     if (m) {
-      best_at = fmaxf(best_at, cm);
-      best_sl = fmaxf(best_sl, sm);
+      best_at = fmaxf(best_at, pair_reduce_max<L>(cm));
+      best_sl = fmaxf(best_sl, pair_reduce_max<L>(sm));
       if (a.smooth) {
+        gm = pair_reduce_max<L>(gm);
         float gs = 0.f;
 #pragma unroll
-        for (int j = 0; j < kArcLanes; ++j) gs += in[j].valid ? fexp((g[j] - gm) * a.inv_gamma) : 0.f;
-        lse_merge(lm, ls, gm, gs, a.inv_gamma);
+        for (int i = 0; i < kArcs; ++i) gs += in[i].valid ? fexp((g[i] - gm) * a.inv_gamma) : 0.f;
+        lse_merge(lm, ls, gm, pair_reduce_sum<L>(gs), a.inv_gamma);
       }
     } else {
-      best_at = fminf(best_at, cm);
-      best_sl = fminf(best_sl, sm);
+      best_at = fminf(best_at, pair_reduce_min<L>(cm));
+      best_sl = fminf(best_sl, pair_reduce_min<L>(sm));
     }
   }
-  const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls), lm) : __builtin_nanf("")) : 0.f;
-  *at32(rec, (uint32_t)(kRecChunks * slot + k)) = make_float4(best_at, best_sl, ag, 0.f);
+  if (jl == 0) {
+    const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls), lm) : __builtin_nanf("")) : 0.f;
+    *at32(rec, (uint32_t)(kRecChunks * slot + k)) = make_float4(best_at, best_sl, ag, 0.f);
+  }
 }
 
 // ---------------------------------------------------------------------------- endpoints
@@ -1943,20 +1966,30 @@ dim3 level_grid(const sta_graph* g, unsigned blocks) {
   return snap_grid(g, blocks);
 }
 
-// One forward level with the schedule's lanes per cell (16: k_fwd_level, 4: k_fwd_level4).
+// One forward level with the schedule's lanes per cell (16: k_fwd_level, 8 or 4:
+// k_fwd_level_narrow).
+template <int L>
+void fwd_narrow_launch(dim3 grid, bool snap, hipStream_t s, const Slots& sl, int n0, int min_slot, int ss,
+                       const int4* ell, const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
+  if (snap)
+    k_fwd_level_narrow<true, L><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  else
+    k_fwd_level_narrow<false, L><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec,
+                                                         fa);
+}
+
 void fwd_level_launch(const sta_graph* g, hipStream_t s, const Slots& sl, int min_slot, int ss, const int4* ell,
                       const float* load, const int* loc, float4* rec, const FwdArgs& fa) {
-  const int lanes = g->sched_cfg.fwd_cell_lanes == 4 ? kFwdCellLanes : kCellLanes;
+  const int lanes = g->sched_cfg.fwd_cell_lanes;
   const unsigned blocks = (unsigned)(((size_t)lanes * sl.nc + kBlock - 1) / kBlock);
   if (blocks == 0) return;
   const int n0 = g->N0 + sl.c0;
   const bool snap = g->n_snap > 1;
   const dim3 grid = snap ? level_grid(g, blocks) : dim3(blocks);
-  if (lanes == kFwdCellLanes) {
-    if (snap)
-      k_fwd_level4<true><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
-    else
-      k_fwd_level4<false><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
+  if (lanes == 4) {
+    fwd_narrow_launch<1>(grid, snap, s, sl, n0, min_slot, ss, ell, load, loc, rec, fa);
+  } else if (lanes == 8) {
+    fwd_narrow_launch<2>(grid, snap, s, sl, n0, min_slot, ss, ell, load, loc, rec, fa);
   } else if (snap) {
     k_fwd_level<true><<<grid, kBlock, 0, s>>>(sl.nc, n0, sl.base, sl.F, min_slot, ss, ell, load, loc, rec, fa);
   } else {
@@ -2260,7 +2293,7 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
     }
   };
   // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
-  // task pool, one thread per net) on the best of those, then 4 lanes per forward cell.
+  // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell.
   for (int sweep = 4; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
@@ -2269,9 +2302,12 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   for (int rc : {STA_RC_CTE, STA_RC_THREAD})
     if (st == STA_OK)
       try_schedule(sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16});
-  sta_schedule fwd4 = best_s;
-  fwd4.fwd_cell_lanes = 4;
-  if (st == STA_OK) try_schedule(fwd4);
+  const sta_schedule wide = best_s;
+  for (int fl : {8, 4}) {
+    sta_schedule narrow = wide;
+    narrow.fwd_cell_lanes = fl;
+    if (st == STA_OK) try_schedule(narrow);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (void* p : buf) (void)hipFree(p);

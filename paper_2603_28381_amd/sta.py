@@ -323,15 +323,15 @@ class Graph:
     def set_schedule(self, sweep_group_log2: int, flat_group_log2: int, heavy_sinks: int,
                      rc_scheme: int | str = 0, fwd_cell_lanes: int = 16):
         """rc_scheme: 0 / "groups" (lane groups, Alg. 1), 1 / "cte" (task pool, Alg. 2),
-        2 / "thread" (one thread per net).  fwd_cell_lanes: 16 or 4 lanes per cell in the
+        2 / "thread" (one thread per net).  fwd_cell_lanes: 16, 8 or 4 lanes per cell in the
         forward level kernel."""
         rc = {"groups": STA_RC_GROUPS, "cte": STA_RC_CTE, "thread": STA_RC_THREAD}.get(rc_scheme, rc_scheme)
         sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks, int(rc), int(fwd_cell_lanes))
         _check(_lib.sta_set_schedule(self._h, ctypes.byref(sch)))
 
     def tune(self, x, y, gamma: float = 10.0, reps: int = 3, stream=None) -> dict:
-        """Time the candidate schedules (lane groups, then the RC mappings, then 4 lanes per
-        forward cell) on these coordinates and keep the fastest."""
+        """Time the candidate schedules (lane groups, then the RC mappings, then 8 and 4 lanes
+        per forward cell) on these coordinates and keep the fastest."""
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)

@@ -309,7 +309,8 @@ def test_schedules_agree_with_oracle():
     sinks = (np.diff(d.net_offsets) - 1)[g.levelization()["net_perm"]]
     pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
     assert pools.max() > 2 * 1024, pools.max()
-    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4)):
+    for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
+                (5, 3, 32, "groups", 8)):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
@@ -369,7 +370,8 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
         assert np.array_equal(again[key], plain[key], equal_nan=True), key
 
 
-@pytest.mark.parametrize("canonical,n_snap,fwd_lanes", [(False, 3, 16), (True, 3, 16), (True, 8, 16), (True, 8, 4)])
+@pytest.mark.parametrize("canonical,n_snap,fwd_lanes",
+                         [(False, 3, 16), (True, 3, 16), (True, 8, 16), (True, 8, 4), (True, 3, 8)])
 def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
     # Placements swept together (shared topology) against one-snapshot calls; also through a
     # two-design batch and under checkpointing.  Eight snapshots take the level kernels'
@@ -422,7 +424,7 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
         g.set_snapshots(1)
 
 
-@pytest.mark.parametrize("wns,fwd_lanes", [(False, 16), (True, 16), (False, 4), (True, 4)])
+@pytest.mark.parametrize("wns,fwd_lanes", [(False, 16), (True, 16), (False, 8), (True, 4)])
 def test_parity_wide_cells(wns, fwd_lanes):
     # Cells of 5-8 inputs take the cell steps' second chunk of 4 arcs (merged log-sum-exp,
     # arg max and softmax across chunks), in both forward cell mappings.
