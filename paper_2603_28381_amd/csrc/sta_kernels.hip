@@ -217,13 +217,30 @@ __device__ __forceinline__ void quad_argmax(float& v, int& j) {
   if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
 }
 
-// Reduction over an aligned group of G lanes (G = 16, 32 or 64) of a wave.
+// The arc lanes of one condition in a backward cell step: 4 (a quad) or 2 (a pair).
+template <int OP, int AL>
+__device__ __forceinline__ float arc_reduce(float v) {
+  v = red2<OP>(v, dpp<kDppQuadX1>(v));
+  return AL == 4 ? red2<OP>(v, dpp<kDppQuadX2>(v)) : v;
+}
+template <int AL>
+__device__ __forceinline__ void arc_argmax(float& v, int& j) {
+  if (AL == 4) {
+    quad_argmax(v, j);
+    return;
+  }
+  const float v2 = dpp<kDppQuadX1>(v);
+  const int j2 = dpp_i<kDppQuadX1>(j);
+  if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
+}
+
+// Reduction over an aligned group of G lanes (G = 8, 16, 32 or 64) of a wave.
 template <int OP, int G>
 __device__ __forceinline__ float wave_group_reduce(float v) {
   v = red2<OP>(v, dpp<kDppQuadX1>(v));
   v = red2<OP>(v, dpp<kDppQuadX2>(v));
   v = red2<OP>(v, dpp<kDppHalfMirror>(v));
-  v = red2<OP>(v, dpp<kDppMirror>(v));
+  if (G >= 16) v = red2<OP>(v, dpp<kDppMirror>(v));
   if (G >= 32) v = red2<OP>(v, __shfl_xor(v, 16));
   if (G >= 64) v = red2<OP>(v, __shfl_xor(v, 32));
   return v;
@@ -272,13 +289,13 @@ __device__ __forceinline__ bool group_slot(const GroupRange& r, GroupSlot& s) {
   return true;
 }
 
-// The same mapping for a level kernel, whose smallest group is 2^G0 >= 16 lanes, so that at
-// most three wave classes (16/32/64 lanes) exist.  The level's ranges arrive as scalars -
+// The same mapping for a level kernel, whose smallest group is 2^G0 >= 8 lanes, so that at
+// most four wave classes (8/16/32/64 lanes) exist.  The level's ranges arrive as scalars -
 // heavy nets [h0, h0 + nh), class c entries [e_c, e_{c+1}) on waves [w_c, w_{c+1}) with
 // w_0 = 0 - and the class is found without indexing an array.
 template <int G0>
-__device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
-                                           int w3, GroupSlot& s) {
+__device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e1, int e2, int e3, int e4, int w1,
+                                           int w2, int w3, int w4, GroupSlot& s) {
   if (bx < nh) {
     s.block = true;
     s.G = kBlock;
@@ -290,11 +307,13 @@ __device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e
   s.block = false;
   const int wave = (bx - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (wave >= w3) return false;
-  const int c = (wave >= w1) + (wave >= w2);
-  const int eb = c == 0 ? e0 : (c == 1 ? e1 : e2);
-  const int ee = c == 0 ? e1 : (c == 1 ? e2 : e3);
-  const int wb = c == 0 ? 0 : (c == 1 ? w1 : w2);
+  // Groups of 16 lanes and more have three classes at most (e4 = e3, w4 = w3), and then e4
+  // and w4, which are not preloaded, are not read.
+  if (wave >= (G0 >= 4 ? w3 : w4)) return false;
+  const int c = (wave >= w1) + (wave >= w2) + (G0 >= 4 ? 0 : (wave >= w3));
+  const int eb = c == 0 ? e0 : (c == 1 ? e1 : (c == 2 ? e2 : e3));
+  const int ee = c == 0 ? e1 : (c == 1 ? e2 : (c == 2 ? e3 : e4));
+  const int wb = c == 0 ? 0 : (c == 1 ? w1 : (c == 2 ? w2 : w3));
   const int lg = G0 + c;
   s.G = 1 << lg;
   s.gl = lane & (s.G - 1);
@@ -1649,14 +1668,22 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   //  2. the sinks' required times, adjoints, wires, coordinates and caps, the driver's
   //     record and coordinates, and the input's source record and wire;
   //  3. the table coefficients at the input slew.
-  const int lane16 = gl & (kCellLanes - 1);
-  const int k = lane16 >> 2, jl = lane16 & 3, m = k >> 1, t = k & 1;
-  const bool cell_lane = gs.active && n >= a.N0 && gl < kCellLanes;
+  // The cell step spreads the 4 conditions over the group's first 16 lanes (4 arc lanes per
+  // condition, one arc each per chunk of 4), or over 8 lanes in 8-lane groups (2 arc lanes,
+  // two arcs each).
+  constexpr int AL = G == 8 ? 2 : kArcLanes;   // arc lanes per condition
+  constexpr int NA = kArcLanes / AL;           // arcs per lane in a chunk of 4
+  constexpr int CL = 4 * AL;                   // cell lanes
+  const int lanec = gl & (CL - 1);
+  const int k = lanec / AL, jl = lanec % AL, m = k >> 1, t = k & 1;
+  const bool cell_lane = gs.active && n >= a.N0 && gl < CL;
   const int kc = cell_lane ? n - a.N0 - sl.c0 : 0;   // position of the cell in its level
-  const uint32_t e_at = cell_lane ? (uint32_t)(sl.base + min(jl, sl.F - 1) * sl.nc + kc) : 0u;
   const int p0 = ld(a.net_off, (uint32_t)n);
   const int p1v = ld(a.net_off, (uint32_t)n + 1u);
-  const int4 e = ld(a.ell, e_at);
+  int4 e[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i)
+    e[i] = ld(a.ell, cell_lane ? (uint32_t)(sl.base + min(jl + AL * i, sl.F - 1) * sl.nc + kc) : 0u);
   const float load = ld(a.load, (uint32_t)n);
   const int slot = a.loc ? ld(a.loc, (uint32_t)n) : n;
   const int p1 = gs.active ? p1v : p0;
@@ -1664,18 +1691,19 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   // Wave 2: the cell input's source record and wire first (the table lookup waits for
   // them), then the driver's record and coordinates and the sinks, whose loads stay in
   // flight through the lookup.
-  ArcIn ain;
-  {
-    ain.valid = cell_lane && jl < sl.F && e.x >= 0;
-    ain.arc = e.z;
-    ain.tp = e.w > 0 ? t : 1 - t;
-    ain.pin = e.y;
-    const int kp = 2 * m + ain.tp;
-    const float4 c = ld(a.rec, (uint32_t)(kRecChunks * max(e.x, 0) + kp));
-    const float2 w = ld(a.wire, (uint32_t)e.y);
-    ain.at = c.x + w.x;
-    ain.slew = sink_slew(c.y, w.y);
-    ain.atg = c.z + w.x;
+  ArcIn ain[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    ain[i].valid = cell_lane && jl + AL * i < sl.F && e[i].x >= 0;
+    ain[i].arc = e[i].z;
+    ain[i].tp = e[i].w > 0 ? t : 1 - t;
+    ain[i].pin = e[i].y;
+    const int kp = 2 * m + ain[i].tp;
+    const float4 c = ld(a.rec, (uint32_t)(kRecChunks * max(e[i].x, 0) + kp));
+    const float2 w = ld(a.wire, (uint32_t)e[i].y);
+    ain[i].at = c.x + w.x;
+    ain[i].slew = sink_slew(c.y, w.y);
+    ain[i].atg = c.z + w.x;
   }
   const uint32_t rs = (uint32_t)(kRecChunks * slot);
   const float4 c0 = ld(a.rec, rs), c1 = ld(a.rec, rs + 1), c2 = ld(a.rec, rs + 2), c3 = ld(a.rec, rs + 3);
@@ -1696,24 +1724,59 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0);
   __builtin_amdgcn_sched_barrier(0);          // keep wave 2 ahead of the lookup below
 
-  // 2a. Cell-step lookups (wave 3): lane (k, jl) of the group's first 16 lanes takes arc jl.
-  ArcBwd arc0 = arc_from_input(a, ain, t, load);
-  // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4).
-  float xmax = quad_reduce<kMax>(arc0.valid ? arc0.xg : -kInf);
-  float z = quad_reduce<kSum>(arc0.valid ? fexp((arc0.xg - xmax) * a.inv_gamma) : 0.f);
-  float smax = arc0.valid ? arc0.s : -kInf;
-  int jstar = arc0.valid ? jl : STA_MAX_FANIN;
-  quad_argmax(smax, jstar);
+  // 2a. Cell-step lookups (wave 3): lane (k, jl) of the cell lanes takes arcs jl + AL * i.
+  ArcBwd arc0[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) arc0[i] = arc_from_input(a, ain[i], t, load);
+  // Softmax normaliser and arg-max slew over the condition's arcs (all chunks of 4): the
+  // lane's own arcs first, then across the condition's arc lanes.
+  float xmax, z, smax;
+  int jstar;
+  if constexpr (NA == 1) {
+    xmax = arc_reduce<kMax, AL>(arc0[0].valid ? arc0[0].xg : -kInf);
+    z = arc_reduce<kSum, AL>(arc0[0].valid ? fexp((arc0[0].xg - xmax) * a.inv_gamma) : 0.f);
+    smax = arc0[0].valid ? arc0[0].s : -kInf;
+    jstar = arc0[0].valid ? jl : STA_MAX_FANIN;
+  } else {
+    xmax = -kInf;
+    z = 0.f;
+    smax = -kInf;
+    jstar = STA_MAX_FANIN;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      xmax = fmaxf(xmax, arc0[i].valid ? arc0[i].xg : -kInf);
+      const bool take = arc0[i].valid && (jstar == STA_MAX_FANIN || arc0[i].s > smax);
+      smax = take ? arc0[i].s : smax;
+      jstar = take ? jl + AL * i : jstar;
+    }
+    xmax = arc_reduce<kMax, AL>(xmax);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) z += arc0[i].valid ? fexp((arc0[i].xg - xmax) * a.inv_gamma) : 0.f;
+    z = arc_reduce<kSum, AL>(z);
+  }
+  arc_argmax<AL>(smax, jstar);
   for (int j0 = kArcLanes; j0 < sl.F; j0 += kArcLanes) {    // cells wider than 4 inputs
-    ArcBwd v;
-    v.valid = false;
-    if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl, m, t, load);
-    const float cm = quad_reduce<kMax>(v.valid ? v.xg : -kInf);
-    const float cz = quad_reduce<kSum>(v.valid ? fexp((v.xg - cm) * a.inv_gamma) : 0.f);
+    ArcBwd v[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      v[i].valid = false;
+      if (cell_lane) v[i] = arc_backward(a, sl, kc, j0 + jl + AL * i, m, t, load);
+    }
+    float cm = -kInf, cz = 0.f, s2 = -kInf;
+    int j2 = STA_MAX_FANIN;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      cm = fmaxf(cm, v[i].valid ? v[i].xg : -kInf);
+      const bool take = v[i].valid && (j2 == STA_MAX_FANIN || v[i].s > s2);
+      s2 = take ? v[i].s : s2;
+      j2 = take ? j0 + jl + AL * i : j2;
+    }
+    cm = arc_reduce<kMax, AL>(cm);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) cz += v[i].valid ? fexp((v[i].xg - cm) * a.inv_gamma) : 0.f;
+    cz = arc_reduce<kSum, AL>(cz);
     lse_merge(xmax, z, cm, cz, a.inv_gamma);
-    float s2 = v.valid ? v.s : -kInf;
-    int j2 = v.valid ? j0 + jl : STA_MAX_FANIN;
-    quad_argmax(s2, j2);
+    arc_argmax<AL>(s2, j2);
     if (s2 > smax) {
       smax = s2;
       jstar = j2;
@@ -1739,36 +1802,40 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const float inv_z = frcp(z);
   float lb = 0.f;
   for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
-    ArcBwd v = arc0;
-    if (j0 > 0) {
-      v.valid = false;
-      if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl, m, t, load);
-    }
-    if (cell_lane && v.valid) {
-      // RAT(input, k') = RAT(output, k) - arc delay.
-      float* sw = reinterpret_cast<float*>(a.sink);
-      *at32(sw, 4 * rat_at((uint32_t)v.pin) + (uint32_t)(2 * m + v.tp)) = rat_o - v.d;
-      if (kGrad && m == 1) {
-        const float dbar = fexp((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
-        const float s_j = (j0 + jl) == jstar ? sbar : 0.f;
-        const uint32_t aj = 4 * adj_at((uint32_t)v.pin);
-        *at32(sw, aj + (uint32_t)v.tp) = dbar;
-        *at32(sw, aj + 2u + (uint32_t)v.tp) = fmaf(dbar, v.ddx, s_j * v.dsx);
-        lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      ArcBwd v = arc0[i];
+      if (j0 > 0) {
+        v.valid = false;
+        if (cell_lane) v = arc_backward(a, sl, kc, j0 + jl + AL * i, m, t, load);
+      }
+      if (cell_lane && v.valid) {
+        // RAT(input, k') = RAT(output, k) - arc delay.
+        float* sw = reinterpret_cast<float*>(a.sink);
+        *at32(sw, 4 * rat_at((uint32_t)v.pin) + (uint32_t)(2 * m + v.tp)) = rat_o - v.d;
+        if (kGrad && m == 1) {
+          const float dbar = fexp((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
+          const float s_j = (j0 + jl + AL * i) == jstar ? sbar : 0.f;
+          const uint32_t aj = 4 * adj_at((uint32_t)v.pin);
+          *at32(sw, aj + (uint32_t)v.tp) = dbar;
+          *at32(sw, aj + 2u + (uint32_t)v.tp) = fmaf(dbar, v.ddx, s_j * v.dsx);
+          lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
+        }
       }
     }
   }
 
-  // 3. Load adjoint of the root: arcs (quad sum) of late rise + late fall, lanes 8 and 12.
+  // 3. Load adjoint of the root: arcs summed over the arc lanes of late rise + late fall
+  //    (cell lanes 2 * AL and 3 * AL).
   float lbar = 0.f;
   if (kGrad) {
-    lb = quad_reduce<kSum>(lb);
+    lb = arc_reduce<kSum, AL>(lb);
     if (!block) {
       const int base = (threadIdx.x & 63) & ~(G - 1);
-      lbar = __shfl(lb, base + 8) + __shfl(lb, base + 12);
+      lbar = __shfl(lb, base + 2 * AL) + __shfl(lb, base + 3 * AL);
     } else {
-      if (threadIdx.x == 8) sh[0] = lb;
-      if (threadIdx.x == 12) sh[1] = lb;
+      if (threadIdx.x == 2 * AL) sh[0] = lb;
+      if (threadIdx.x == 3 * AL) sh[1] = lb;
       __syncthreads();
       lbar = sh[0] + sh[1];
       __syncthreads();
@@ -1813,12 +1880,14 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 }
 
 // One level of backward propagation: heavy nets first (one workgroup each), then waves of
-// 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of the
-// first loads come first, as scalar parameters preloaded into scalar registers.
+// 8-, 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of
+// the first loads come first, as scalar parameters preloaded into scalar registers (14
+// dwords are); the fourth class's range (8-lane groups only) follows them.
 template <int G0, bool kSnap, bool kCanon, bool kGrad>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
                                                       int w3, int snap_state, const int* __restrict__ net_off,
-                                                      const float4* __restrict__ rec, BwdArgs a0, Slots sl) {
+                                                      const float4* __restrict__ rec, int e4, int w4, BwdArgs a0,
+                                                      Slots sl) {
   __shared__ float sh[kWavesPerBlock * N_ACC];
   BwdArgs a = a0;
   a.net_off = net_off;
@@ -1837,20 +1906,22 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   a.dy = snap_elems<kSnap>(a.dy, a.snap.pins, sb.s);
   a.tree_adj = snap_bytes<kSnap>(a.tree_adj, a.snap.work, sb.s);
   GroupSlot gs;
-  if (!level_slot<G0>(sb.x, nh, h0, e0, e1, e2, e3, w1, w2, w3, gs)) return;
+  if (!level_slot<G0>(sb.x, nh, h0, e0, e1, e2, e3, e4, w1, w2, w3, w4, gs)) return;
   if (gs.block || gs.G == 64) {
     bwd_net<64, kCanon, kGrad>(a, sl, gs, sh);
   } else if (gs.G == 32) {
     bwd_net<32, kCanon, kGrad>(a, sl, gs, sh);
-  } else {
+  } else if (G0 >= 4 || gs.G == 16) {
     bwd_net<16, kCanon, kGrad>(a, sl, gs, sh);
+  } else {
+    if constexpr (G0 == 3) bwd_net<8, kCanon, kGrad>(a, sl, gs, sh);
   }
 }
 
 // One backward level's launch, with the kernel compiled for its smallest group, snapshot
 // count, pin order and gradient flag.
 struct BwdLaunch {
-  int nh, h0, e0, e1, e2, e3, w1, w2, w3, ss;
+  int nh, h0, e0, e1, e2, e3, e4, w1, w2, w3, w4, ss;
   const int* net_off;
   const float4* rec;
   BwdArgs ba;
@@ -1860,7 +1931,7 @@ struct BwdLaunch {
 template <int G0, bool kSnap, bool kCanon, bool kGrad>
 void bwd_launch(dim3 grid, hipStream_t s, const BwdLaunch& L) {
   k_bwd_level<G0, kSnap, kCanon, kGrad><<<grid, kBlock, 0, s>>>(L.nh, L.h0, L.e0, L.e1, L.e2, L.e3, L.w1, L.w2, L.w3,
-                                                                  L.ss, L.net_off, L.rec, L.ba, L.sl);
+                                                                  L.ss, L.net_off, L.rec, L.e4, L.w4, L.ba, L.sl);
 }
 
 template <int G0, bool kSnap>
@@ -2102,10 +2173,12 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     const int* c = r.cls_off;
     const int* w = r.wave_off;
     const Slots sl = level_slots(g, l);
-    const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], w[1], w[2], w[3], ss, d.net_off, rec, ba, sl};
+    const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], c[4], w[1], w[2], w[3], w[4], ss, d.net_off, rec, ba, sl};
     const bool snap = g->n_snap > 1, canon = io == nullptr;
     const dim3 grid = snap ? level_grid(g, blocks) : dim3(blocks);
     switch (r.g0 * 2 + (snap ? 1 : 0)) {
+      case 6: bwd_launch<3, false>(grid, s, L, canon, grad); break;
+      case 7: bwd_launch<3, true>(grid, s, L, canon, grad); break;
       case 8: bwd_launch<4, false>(grid, s, L, canon, grad); break;
       case 9: bwd_launch<4, true>(grid, s, L, canon, grad); break;
       case 10: bwd_launch<5, false>(grid, s, L, canon, grad); break;
@@ -2294,7 +2367,7 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   };
   // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
   // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell.
-  for (int sweep = 4; sweep <= 6 && st == STA_OK; ++sweep)
+  for (int sweep = 3; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
         if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16});

@@ -310,7 +310,7 @@ def test_schedules_agree_with_oracle():
     pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
     assert pools.max() > 2 * 1024, pools.max()
     for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
-                (5, 3, 32, "groups", 8)):
+                (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4)):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
@@ -370,9 +370,9 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
         assert np.array_equal(again[key], plain[key], equal_nan=True), key
 
 
-@pytest.mark.parametrize("canonical,n_snap,fwd_lanes",
-                         [(False, 3, 16), (True, 3, 16), (True, 8, 16), (True, 8, 4), (True, 3, 8)])
-def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
+@pytest.mark.parametrize("canonical,n_snap,fwd_lanes,sweep",
+                         [(False, 3, 16, 4), (True, 3, 16, 4), (True, 8, 16, 4), (True, 8, 4, 3), (True, 3, 8, 3)])
+def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes, sweep):
     # Placements swept together (shared topology) against one-snapshot calls; also through a
     # two-design batch and under checkpointing.  Eight snapshots take the level kernels'
     # one-XCD-per-snapshot block mapping, three the padded one; both forward cell mappings.
@@ -383,7 +383,7 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
         gs = [Graph.from_design(d) for d in members]
         g = gs[0] if len(gs) == 1 else Graph.batch(gs)
         g.levelize()
-        g.set_schedule(4, 2, 64, "groups", fwd_lanes)
+        g.set_schedule(sweep, 2, 64, "groups", fwd_lanes)
         lev = g.levelization()
         # original order of a batch: the members' pins one design after the other
         base = [np.concatenate([d.x for d in members]), np.concatenate([d.y for d in members])]
@@ -424,16 +424,17 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes):
         g.set_snapshots(1)
 
 
-@pytest.mark.parametrize("wns,fwd_lanes", [(False, 16), (True, 16), (False, 8), (True, 4)])
-def test_parity_wide_cells(wns, fwd_lanes):
+@pytest.mark.parametrize("wns,fwd_lanes,sweep", [(False, 16, 4), (True, 16, 4), (False, 8, 3), (True, 4, 3)])
+def test_parity_wide_cells(wns, fwd_lanes, sweep):
     # Cells of 5-8 inputs take the cell steps' second chunk of 4 arcs (merged log-sum-exp,
-    # arg max and softmax across chunks), in both forward cell mappings.
+    # arg max and softmax across chunks), in every forward cell mapping and in backward
+    # groups of 16 lanes and of 8 (two arcs per lane).
     from tests._designs import wide_dag
     d = wide_dag(n_levels=9, gates_per_level=60, n_pi=16, seed=3)
     ref = O.run(d, gamma=GAMMA, grad="wns" if wns else "tns")
     g = Graph.from_design(d)
     g.levelize()
-    g.set_schedule(4, 2, 64, "groups", fwd_lanes)
+    g.set_schedule(sweep, 2, 64, "groups", fwd_lanes)
     got = gpu_run(d, wns=wns, graph=g)
     check_values(d, got, ref)
     check_grad(got, ref, 1e-3, 1e-6)
