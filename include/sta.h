@@ -235,8 +235,8 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
 /* ---------------------------------------------------------------------------------------
  * Lane-group schedule.  Nets are served by lane groups sized from their sink count: the
  * level kernels use groups of (1 << sweep_group_log2) lanes and doublings up to a wave
- * (8 lanes at least: a backward cell step spreads 4 conditions x 4 arcs over 16 lanes, or
- * over 8 lanes with two arcs each in 8-lane groups), the
+ * (4 lanes at least: a backward cell step spreads 4 conditions x 4 arcs over 16 lanes, over
+ * 8 lanes with two arcs each in 8-lane groups, or over 4 lanes with all arcs in each), the
  * one-pass kernels (RC, output expansion) groups from (1 << flat_group_log2) lanes, and
  * nets with more than heavy_sinks sinks take a whole 256-thread workgroup.  rc_scheme
  * picks the mapping of the RC net delay stage (Sec. 3.1.1): these lane groups (the
@@ -256,7 +256,7 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
 #define STA_RC_THREAD 2   /* one thread per net */
 
 typedef struct sta_schedule {
-  int32_t sweep_group_log2;   /* 3..6 */
+  int32_t sweep_group_log2;   /* 2..6 */
   int32_t flat_group_log2;    /* 2..6 */
   int32_t heavy_sinks;        /* 1..64 */
   int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */

@@ -754,7 +754,7 @@ sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch) {
 
 sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   if (!g || !sch) return fail(STA_E_INVALID, "NULL argument");
-  if (sch->sweep_group_log2 < 3 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
+  if (sch->sweep_group_log2 < 2 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
       sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64 || sch->rc_scheme < STA_RC_GROUPS ||
       sch->rc_scheme > STA_RC_THREAD ||
       (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4))

@@ -217,10 +217,10 @@ __device__ __forceinline__ void quad_argmax(float& v, int& j) {
   if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
 }
 
-// The arc lanes of one condition in a backward cell step: 4 (a quad) or 2 (a pair).
+// The arc lanes of one condition in a backward cell step: 4 (a quad), 2 (a pair) or 1.
 template <int OP, int AL>
 __device__ __forceinline__ float arc_reduce(float v) {
-  v = red2<OP>(v, dpp<kDppQuadX1>(v));
+  if (AL >= 2) v = red2<OP>(v, dpp<kDppQuadX1>(v));
   return AL == 4 ? red2<OP>(v, dpp<kDppQuadX2>(v)) : v;
 }
 template <int AL>
@@ -229,17 +229,18 @@ __device__ __forceinline__ void arc_argmax(float& v, int& j) {
     quad_argmax(v, j);
     return;
   }
+  if (AL == 1) return;
   const float v2 = dpp<kDppQuadX1>(v);
   const int j2 = dpp_i<kDppQuadX1>(j);
   if (v2 > v || (v2 == v && j2 < j)) { v = v2; j = j2; }
 }
 
-// Reduction over an aligned group of G lanes (G = 8, 16, 32 or 64) of a wave.
+// Reduction over an aligned group of G lanes (G = 4, 8, 16, 32 or 64) of a wave.
 template <int OP, int G>
 __device__ __forceinline__ float wave_group_reduce(float v) {
   v = red2<OP>(v, dpp<kDppQuadX1>(v));
   v = red2<OP>(v, dpp<kDppQuadX2>(v));
-  v = red2<OP>(v, dpp<kDppHalfMirror>(v));
+  if (G >= 8) v = red2<OP>(v, dpp<kDppHalfMirror>(v));
   if (G >= 16) v = red2<OP>(v, dpp<kDppMirror>(v));
   if (G >= 32) v = red2<OP>(v, __shfl_xor(v, 16));
   if (G >= 64) v = red2<OP>(v, __shfl_xor(v, 32));
@@ -289,13 +290,13 @@ __device__ __forceinline__ bool group_slot(const GroupRange& r, GroupSlot& s) {
   return true;
 }
 
-// The same mapping for a level kernel, whose smallest group is 2^G0 >= 8 lanes, so that at
-// most four wave classes (8/16/32/64 lanes) exist.  The level's ranges arrive as scalars -
+// The same mapping for a level kernel, whose smallest group is 2^G0 >= 4 lanes, so that at
+// most five wave classes (4/8/16/32/64 lanes) exist.  The level's ranges arrive as scalars -
 // heavy nets [h0, h0 + nh), class c entries [e_c, e_{c+1}) on waves [w_c, w_{c+1}) with
 // w_0 = 0 - and the class is found without indexing an array.
 template <int G0>
-__device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e1, int e2, int e3, int e4, int w1,
-                                           int w2, int w3, int w4, GroupSlot& s) {
+__device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e1, int e2, int e3, int e4, int e5,
+                                           int w1, int w2, int w3, int w4, int w5, GroupSlot& s) {
   if (bx < nh) {
     s.block = true;
     s.G = kBlock;
@@ -307,13 +308,13 @@ __device__ __forceinline__ bool level_slot(int bx, int nh, int h0, int e0, int e
   s.block = false;
   const int wave = (bx - nh) * kWavesPerBlock + (int)(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // Groups of 16 lanes and more have three classes at most (e4 = e3, w4 = w3), and then e4
-  // and w4, which are not preloaded, are not read.
-  if (wave >= (G0 >= 4 ? w3 : w4)) return false;
-  const int c = (wave >= w1) + (wave >= w2) + (G0 >= 4 ? 0 : (wave >= w3));
-  const int eb = c == 0 ? e0 : (c == 1 ? e1 : (c == 2 ? e2 : e3));
-  const int ee = c == 0 ? e1 : (c == 1 ? e2 : (c == 2 ? e3 : e4));
-  const int wb = c == 0 ? 0 : (c == 1 ? w1 : (c == 2 ? w2 : w3));
+  // Groups of 16 lanes and more have three classes at most (e4 = e3, w4 = w3), and then e4,
+  // e5, w4 and w5, which are not preloaded, are not read; 8-lane groups have four.
+  if (wave >= (G0 >= 4 ? w3 : (G0 == 3 ? w4 : w5))) return false;
+  const int c = (wave >= w1) + (wave >= w2) + (G0 <= 3 ? (wave >= w3) : 0) + (G0 <= 2 ? (wave >= w4) : 0);
+  const int eb = c == 0 ? e0 : (c == 1 ? e1 : (c == 2 ? e2 : (c == 3 ? e3 : e4)));
+  const int ee = c == 0 ? e1 : (c == 1 ? e2 : (c == 2 ? e3 : (c == 3 ? e4 : e5)));
+  const int wb = c == 0 ? 0 : (c == 1 ? w1 : (c == 2 ? w2 : (c == 3 ? w3 : w4)));
   const int lg = G0 + c;
   s.G = 1 << lg;
   s.gl = lane & (s.G - 1);
@@ -1669,9 +1670,9 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   //     record and coordinates, and the input's source record and wire;
   //  3. the table coefficients at the input slew.
   // The cell step spreads the 4 conditions over the group's first 16 lanes (4 arc lanes per
-  // condition, one arc each per chunk of 4), or over 8 lanes in 8-lane groups (2 arc lanes,
-  // two arcs each).
-  constexpr int AL = G == 8 ? 2 : kArcLanes;   // arc lanes per condition
+  // condition, one arc each per chunk of 4), over 8 lanes in 8-lane groups (2 arc lanes, two
+  // arcs each) or over 4 lanes in 4-lane groups (one lane, all four arcs).
+  constexpr int AL = G == 4 ? 1 : (G == 8 ? 2 : kArcLanes);   // arc lanes per condition
   constexpr int NA = kArcLanes / AL;           // arcs per lane in a chunk of 4
   constexpr int CL = 4 * AL;                   // cell lanes
   const int lanec = gl & (CL - 1);
@@ -1880,14 +1881,15 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 }
 
 // One level of backward propagation: heavy nets first (one workgroup each), then waves of
-// 8-, 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of
+// 4-, 8-, 16-, 32- and 64-lane groups.  The level's ranges (see level_slot) and the pointers of
 // the first loads come first, as scalar parameters preloaded into scalar registers (14
-// dwords are); the fourth class's range (8-lane groups only) follows them.
+// dwords are); the ranges of the fourth and fifth classes (groups of 8 and 4 lanes only)
+// come last.
 template <int G0, bool kSnap, bool kCanon, bool kGrad>
 __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, int e1, int e2, int e3, int w1, int w2,
                                                       int w3, int snap_state, const int* __restrict__ net_off,
-                                                      const float4* __restrict__ rec, int e4, int w4, BwdArgs a0,
-                                                      Slots sl) {
+                                                      const float4* __restrict__ rec, BwdArgs a0, Slots sl, int e4,
+                                                      int w4, int e5, int w5) {
   __shared__ float sh[kWavesPerBlock * N_ACC];
   BwdArgs a = a0;
   a.net_off = net_off;
@@ -1906,22 +1908,24 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level(int nh, int h0, int e0, in
   a.dy = snap_elems<kSnap>(a.dy, a.snap.pins, sb.s);
   a.tree_adj = snap_bytes<kSnap>(a.tree_adj, a.snap.work, sb.s);
   GroupSlot gs;
-  if (!level_slot<G0>(sb.x, nh, h0, e0, e1, e2, e3, e4, w1, w2, w3, w4, gs)) return;
+  if (!level_slot<G0>(sb.x, nh, h0, e0, e1, e2, e3, e4, e5, w1, w2, w3, w4, w5, gs)) return;
   if (gs.block || gs.G == 64) {
     bwd_net<64, kCanon, kGrad>(a, sl, gs, sh);
   } else if (gs.G == 32) {
     bwd_net<32, kCanon, kGrad>(a, sl, gs, sh);
   } else if (G0 >= 4 || gs.G == 16) {
     bwd_net<16, kCanon, kGrad>(a, sl, gs, sh);
+  } else if (G0 == 3 || gs.G == 8) {
+    if constexpr (G0 <= 3) bwd_net<8, kCanon, kGrad>(a, sl, gs, sh);
   } else {
-    if constexpr (G0 == 3) bwd_net<8, kCanon, kGrad>(a, sl, gs, sh);
+    if constexpr (G0 == 2) bwd_net<4, kCanon, kGrad>(a, sl, gs, sh);
   }
 }
 
 // One backward level's launch, with the kernel compiled for its smallest group, snapshot
 // count, pin order and gradient flag.
 struct BwdLaunch {
-  int nh, h0, e0, e1, e2, e3, e4, w1, w2, w3, w4, ss;
+  int nh, h0, e0, e1, e2, e3, e4, e5, w1, w2, w3, w4, w5, ss;
   const int* net_off;
   const float4* rec;
   BwdArgs ba;
@@ -1931,7 +1935,8 @@ struct BwdLaunch {
 template <int G0, bool kSnap, bool kCanon, bool kGrad>
 void bwd_launch(dim3 grid, hipStream_t s, const BwdLaunch& L) {
   k_bwd_level<G0, kSnap, kCanon, kGrad><<<grid, kBlock, 0, s>>>(L.nh, L.h0, L.e0, L.e1, L.e2, L.e3, L.w1, L.w2, L.w3,
-                                                                  L.ss, L.net_off, L.rec, L.e4, L.w4, L.ba, L.sl);
+                                                                  L.ss, L.net_off, L.rec, L.ba, L.sl, L.e4, L.w4, L.e5,
+                                                                  L.w5);
 }
 
 template <int G0, bool kSnap>
@@ -2173,10 +2178,12 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     const int* c = r.cls_off;
     const int* w = r.wave_off;
     const Slots sl = level_slots(g, l);
-    const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], c[4], w[1], w[2], w[3], w[4], ss, d.net_off, rec, ba, sl};
+    const BwdLaunch L{nh, h0, c[0], c[1], c[2], c[3], c[4], c[5], w[1], w[2], w[3], w[4], w[5], ss, d.net_off, rec, ba, sl};
     const bool snap = g->n_snap > 1, canon = io == nullptr;
     const dim3 grid = snap ? level_grid(g, blocks) : dim3(blocks);
     switch (r.g0 * 2 + (snap ? 1 : 0)) {
+      case 4: bwd_launch<2, false>(grid, s, L, canon, grad); break;
+      case 5: bwd_launch<2, true>(grid, s, L, canon, grad); break;
       case 6: bwd_launch<3, false>(grid, s, L, canon, grad); break;
       case 7: bwd_launch<3, true>(grid, s, L, canon, grad); break;
       case 8: bwd_launch<4, false>(grid, s, L, canon, grad); break;
@@ -2367,7 +2374,7 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   };
   // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
   // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell.
-  for (int sweep = 3; sweep <= 6 && st == STA_OK; ++sweep)
+  for (int sweep = 2; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
         if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16});

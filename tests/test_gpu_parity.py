@@ -310,7 +310,7 @@ def test_schedules_agree_with_oracle():
     pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
     assert pools.max() > 2 * 1024, pools.max()
     for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
-                (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4)):
+                (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4), (2, 2, 64, "cte", 4)):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
@@ -371,7 +371,8 @@ def test_checkpointed_backward_equals_plain_bitwise(wns):
 
 
 @pytest.mark.parametrize("canonical,n_snap,fwd_lanes,sweep",
-                         [(False, 3, 16, 4), (True, 3, 16, 4), (True, 8, 16, 4), (True, 8, 4, 3), (True, 3, 8, 3)])
+                         [(False, 3, 16, 4), (True, 3, 16, 4), (True, 8, 16, 4), (True, 8, 4, 3), (True, 3, 8, 3),
+                          (True, 8, 4, 2)])
 def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes, sweep):
     # Placements swept together (shared topology) against one-snapshot calls; also through a
     # two-design batch and under checkpointing.  Eight snapshots take the level kernels'
@@ -424,11 +425,11 @@ def test_snapshots_equal_separate_calls_bitwise(canonical, n_snap, fwd_lanes, sw
         g.set_snapshots(1)
 
 
-@pytest.mark.parametrize("wns,fwd_lanes,sweep", [(False, 16, 4), (True, 16, 4), (False, 8, 3), (True, 4, 3)])
+@pytest.mark.parametrize("wns,fwd_lanes,sweep", [(False, 16, 4), (True, 16, 4), (False, 8, 3), (True, 4, 3), (True, 4, 2)])
 def test_parity_wide_cells(wns, fwd_lanes, sweep):
     # Cells of 5-8 inputs take the cell steps' second chunk of 4 arcs (merged log-sum-exp,
     # arg max and softmax across chunks), in every forward cell mapping and in backward
-    # groups of 16 lanes and of 8 (two arcs per lane).
+    # groups of 16 lanes, of 8 (two arcs per lane) and of 4 (four arcs per lane).
     from tests._designs import wide_dag
     d = wide_dag(n_levels=9, gates_per_level=60, n_pi=16, seed=3)
     ref = O.run(d, gamma=GAMMA, grad="wns" if wns else "tns")

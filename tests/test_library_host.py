@@ -145,7 +145,7 @@ def test_schedule_roundtrip_and_validation():
     assert g.schedule()["rc_scheme"] == S.STA_RC_CTE
     g.set_schedule(5, 3, 32, "thread")
     assert g.schedule()["rc_scheme"] == S.STA_RC_THREAD
-    for bad in ((2, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65), (4, 2, 64, 3),
+    for bad in ((1, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65), (4, 2, 64, 3),
                 (4, 2, 64, -1), (4, 2, 64, 0, 2), (4, 2, 64, 0, 0), (4, 2, 64, 0, 12), (4, 2, 64, 0, 32)):
         with pytest.raises(S.StaError) as e:
             g.set_schedule(*bad)
