@@ -380,8 +380,8 @@ def run_single(args) -> dict:
         d = heap_trees(d)
     g = Graph.from_design(d)
     n_levels = g.levelize()
-    if args.fwd_cell_lanes != 16:
-        g.set_schedule(4, 2, 64, "groups", args.fwd_cell_lanes)
+    if args.fwd_cell_lanes != 16 or args.sweep_group_log2 != 2:
+        g.set_schedule(args.sweep_group_log2, 2, 64, "groups", args.fwd_cell_lanes)
     g.upload()
     lev = g.levelization()
     t_setup = time.time() - t0
@@ -410,7 +410,7 @@ def run_single(args) -> dict:
         prof = g.profile_read()
         g.profile(False)
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
-        if args.workload == "cfg2" and not args.trees and args.fwd_cell_lanes == 16:
+        if args.workload == "cfg2" and not args.trees and args.fwd_cell_lanes == 16 and args.sweep_group_log2 == 2:
             roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
         # The per-launch floor of this machine for comparison: back-to-back dependent launches of
         # a trivial elementwise kernel over as many threads as a level launch has.
@@ -441,7 +441,9 @@ def run_single(args) -> dict:
                                f"{n_levels} net levels, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps"
                                + (", hipGraph-captured" if args.capture else "")
                                + (", an RC tree per net (binary heaps by distance)" if args.trees else "")
-                               + (f", {args.fwd_cell_lanes} lanes per forward cell" if args.fwd_cell_lanes != 16 else ""),
+                               + (f", {args.fwd_cell_lanes} lanes per forward cell" if args.fwd_cell_lanes != 16 else "")
+                               + (f", backward groups from {1 << args.sweep_group_log2} lanes"
+                                  if args.sweep_group_log2 != 2 else ""),
                    "pins": P, "levels": n_levels, "io": "canonical order, HBM resident"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -589,7 +591,7 @@ def run_rc(args) -> dict:
 
         r = {"pins": P, "rc_alg_bytes": float(np.sum(alg["rc"]))}
         for scheme in ("groups", "cte", "thread"):
-            g.set_schedule(4, 2, 64, scheme)
+            g.set_schedule(2, 2, 64, scheme)
             ms = timed(step, args.steps, args.warmup)[0]
             g.profile(True)
             for _ in range(args.steps):
@@ -817,6 +819,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed roofline pass")
     ap.add_argument("--fwd-cell-lanes", type=int, default=16, choices=[16, 8, 4],
                     help="cfg0-2: lanes per cell of the forward level kernel (the schedule's fwd_cell_lanes)")
+    ap.add_argument("--sweep-group-log2", type=int, default=2, choices=[2, 3, 4, 5, 6],
+                    help="cfg0-2: log2 of the smallest backward lane group (the schedule's sweep_group_log2)")
     ap.add_argument("--trees", action="store_true",
                     help="cfg0-2 with an RC tree per net (binary heaps by distance) instead of stars")
     args = ap.parse_args(argv)

@@ -246,7 +246,7 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
  * arc, merged across lanes), 8 (two per condition, two arcs each) or 4 (one per condition,
  * each lane looking up all of the cell's arcs): fewer lanes launch fewer waves, which pays
  * when many snapshots fill the chip, while one design's short levels favour 16.  Defaults
- * {4, 2, 64, STA_RC_GROUPS, 16}.
+ * {2, 2, 64, STA_RC_GROUPS, 16}.
  * Setting a schedule rebuilds the launch plan (no result changes beyond float summation
  * order).  Errors: STA_E_INVALID for out-of-range fields,
  * STA_E_STATE if not levelized.

@@ -17,7 +17,7 @@ constexpr int kNumClasses = 5;       // wave lane groups of 4, 8, 16, 32, 64 lan
 constexpr int kHeavy = kNumClasses;  // class of nets served by a whole workgroup
 constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
 constexpr int kFlatG0Default = 2;    // flat kernels (RC, outputs): smallest group 4 lanes
-constexpr int kSweepG0Default = 4;   // level kernels: smallest group 16 lanes (4 conditions x 4 arcs)
+constexpr int kSweepG0Default = 2;   // level kernels: smallest backward group 4 lanes (one per condition)
 constexpr int kTreeChunk = 1024;     // RC trees: pins of whole nets swept by one workgroup in LDS
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0

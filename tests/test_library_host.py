@@ -132,7 +132,7 @@ def test_schedule_roundtrip_and_validation():
         g.set_schedule(4, 2, 64)
     assert e.value.code == S.STA_E_STATE          # not levelized yet
     g.levelize()
-    assert g.schedule() == dict(sweep_group_log2=4, flat_group_log2=2, heavy_sinks=64, rc_scheme=S.STA_RC_GROUPS,
+    assert g.schedule() == dict(sweep_group_log2=2, flat_group_log2=2, heavy_sinks=64, rc_scheme=S.STA_RC_GROUPS,
                                 fwd_cell_lanes=16)
     g.set_schedule(5, 3, 32)
     assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_GROUPS,
