@@ -43,3 +43,11 @@ def test_traffic_is_reported_only_for_matching_kernel_sources(tmp_path, monkeypa
     assert bench.counted_traffic("k_bwd_level") == 1234.0
     f.write_text("traffic_bytes_per_launch k_bwd_level 1234 kernel_source 0000000000000000\n")
     assert bench.counted_traffic("k_bwd_level") is None
+
+
+def test_schedule_flags_reject_unsupported_values():
+    import pytest
+    for argv in (["--fwd-cell-lanes", "12"], ["--sweep-group-log2", "1"]):
+        with pytest.raises(SystemExit):
+            bench.main(argv)
+    assert callable(bench.snapshot_graph_only)
