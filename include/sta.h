@@ -268,7 +268,10 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
 
 /* Autotuner: times one forward+backward (smoothed, gradient, canonical IO, every per-pin
  * output) of g on the given coordinates for each candidate schedule, `reps` times after a
- * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Allocates
+ * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Candidates:
+ * sweep_group_log2 2..6 x flat_group_log2 2..4 x heavy_sinks {32, 64} with lane-group RC
+ * and 16 forward lanes, then on the best of those the CTE and thread RC mappings, then 8
+ * and 4 forward lanes.  Allocates
  * and frees its own device buffers; synchronizes the stream.  Errors: as sta_forward. */
 sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
                     sta_schedule* best, sta_stream stream);
