@@ -310,7 +310,8 @@ def test_schedules_agree_with_oracle():
     pools = np.add.reduceat(sinks, np.arange(0, len(sinks), 256))
     assert pools.max() > 2 * 1024, pools.max()
     for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
-                (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4), (2, 2, 64, "cte", 4)):
+                (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4), (2, 2, 64, "cte", 4),
+                (2, 2, 1, "thread", 8)):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
