@@ -154,8 +154,10 @@ sta_status sta_build_graph(const sta_netlist* nl, const sta_library* lib,
 
 /* Levelization (Sec. 2.1 stage 2; Sec. 3.1.2): a net's level is 0 if a primary input
  * drives it, else 1 + the deepest level among the nets feeding its driving cell.  Builds
- * the canonical order: nets sorted by (level, original id); pins renumbered net by net,
- * driver first, then sinks in input order; cells ordered like the nets they drive.
+ * the canonical order: nets sorted by (level, pin count, original id) - the pin count key
+ * makes the nets of one lane-group size class contiguous inside each level, so a level
+ * launch maps each wave to one class; pins renumbered net by net, driver first, then
+ * sinks in input order; cells ordered like the nets they drive.
  * Host only, idempotent.  Errors: STA_E_CYCLE for a combinational loop. */
 sta_status sta_levelize(sta_graph* g, int32_t* n_levels_out);
 
@@ -214,7 +216,9 @@ sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out
  * so several backward calls on one state (e.g. a required-time sweep and a gradient sweep
  * on two streams, each with its own workspace) may run concurrently; with checkpointing
  * it rebuilds records inside the state and calls on one state must not overlap.
- * Errors: STA_E_STATE (not levelized / not uploaded), STA_E_INVALID.
+ * Errors: STA_E_STATE (not levelized / not uploaded; with STA_GRAD also a state that the
+ * latest of this graph's sta_forward calls into it did not compute with STA_SMOOTH and the
+ * same gamma_ps, or that no sta_forward on this graph produced), STA_E_INVALID.
  * ------------------------------------------------------------------------------------- */
 sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);

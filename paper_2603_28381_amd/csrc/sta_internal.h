@@ -159,6 +159,13 @@ struct sta_graph {
   Captured cap_fwd, cap_bwd;
   hipStream_t cap_stream = nullptr;
 
+  // The smoothing flag and gamma of the latest sta_forward into each state buffer (most
+  // recent last, at most kFwdSeen entries), so that sta_backward can refuse a gradient
+  // against a state computed without the smoothed arrival or with another gamma.
+  struct FwdSeen { const void* state; bool smooth; float gamma; };
+  static constexpr size_t kFwdSeen = 256;
+  std::vector<FwdSeen> fwd_seen;
+
   // Event timing of launches (sta_profile_enable).
   bool profiling = false;
   // A run of consecutive launches of one kind, bracketed by one event pair.

@@ -2283,6 +2283,31 @@ sta_status run_maybe_captured(sta_graph* g, sta_graph::Captured& cap, bool use_g
 
 uint64_t ptr(const void* p) { return (uint64_t)(uintptr_t)p; }
 
+// Remembers how the forward into `state` was run (see sta_graph::fwd_seen).
+void note_forward(sta_graph* g, const void* state, bool smooth, float gamma) {
+  auto& v = g->fwd_seen;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].state == state) {
+      v.erase(v.begin() + (long)i);
+      break;
+    }
+  if (v.size() >= sta_graph::kFwdSeen) v.erase(v.begin());
+  v.push_back(sta_graph::FwdSeen{state, smooth, gamma});
+}
+
+// A gradient needs the smoothed arrivals of a forward with the same gamma on this graph.
+sta_status check_grad_state(const sta_graph* g, const void* state, float gamma) {
+  for (auto it = g->fwd_seen.rbegin(); it != g->fwd_seen.rend(); ++it) {
+    if (it->state != state) continue;
+    if (!it->smooth)
+      return fail(STA_E_STATE, "the gradient needs a forward state computed with STA_SMOOTH");
+    if (bits(it->gamma) != bits(gamma))
+      return fail(STA_E_STATE, "the gradient's gamma differs from the gamma of the forward state");
+    return STA_OK;
+  }
+  return fail(STA_E_STATE, "the forward state was not produced by sta_forward on this graph");
+}
+
 }  // namespace
 }  // namespace sta
 
@@ -2300,8 +2325,10 @@ extern "C" sta_status sta_forward(sta_graph* g, const float* x, const float* y, 
   const std::vector<uint64_t> key{ptr(x), ptr(y), ptr(out->state), ptr(out->at), ptr(out->slew), ptr(out->atg),
                                   ptr(out->scalars), flags, bits(gamma_ps)};
   const sta_fwd_out o = *out;
-  return run_maybe_captured(g, g->cap_fwd, (flags & STA_GRAPH) != 0, key, reinterpret_cast<hipStream_t>(stream),
-                            [&](hipStream_t s) { return launch_forward(g, x, y, &o, flags, gamma_ps, s); });
+  st = run_maybe_captured(g, g->cap_fwd, (flags & STA_GRAPH) != 0, key, reinterpret_cast<hipStream_t>(stream),
+                          [&](hipStream_t s) { return launch_forward(g, x, y, &o, flags, gamma_ps, s); });
+  if (st == STA_OK) note_forward(g, out->state, (flags & STA_SMOOTH) != 0, gamma_ps);
+  return st;
 }
 
 extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
@@ -2312,6 +2339,10 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   const bool grad = (flags & STA_GRAD) != 0;
   if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
   if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  if (grad) {
+    st = check_grad_state(g, fwd->state, gamma_ps);
+    if (st != STA_OK) return st;
+  }
   const std::vector<uint64_t> key{ptr(x), ptr(y), ptr(fwd->state), ptr(out->workspace), ptr(out->at), ptr(out->slew),
                                   ptr(out->rat), ptr(out->slack), ptr(out->dx), ptr(out->dy), bits(out->grad_scale),
                                   ptr(out->grad_scale_dev), flags, bits(gamma_ps)};

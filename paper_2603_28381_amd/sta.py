@@ -505,6 +505,9 @@ class SmoothedSlack(torch.autograd.Function):
 
     forward returns the float64 scalar TNS_g (WNS_g with which="wns"); backward runs the
     fused backward sweep of libsta and returns d/dx, d/dy scaled by the incoming gradient.
+    On a batch of designs or several placement snapshots the scalar is the sum of the
+    per-design (per-snapshot) objectives: the backward seeds every design and snapshot with
+    the same incoming gradient, which is the gradient of that sum.
     """
 
     @staticmethod
@@ -512,7 +515,7 @@ class SmoothedSlack(torch.autograd.Function):
         fwd = graph.forward(x, y, gamma=gamma, smooth=True)
         ctx.graph, ctx.fwd, ctx.which = graph, fwd, which
         ctx.save_for_backward(x, y)
-        return fwd.scalars[3 if which == "tns" else 2].clone()
+        return fwd.scalars[..., 3 if which == "tns" else 2].sum()
 
     @staticmethod
     def backward(ctx, g):
