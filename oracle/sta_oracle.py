@@ -369,37 +369,23 @@ class _Plan:
         self.endpoints = np.nonzero((kind == PIN_FF_D) | (kind == PIN_PO))[0]
 
 
-def fp32_rounding_noise(seed: int):
-    """A perturbation that multiplies each value by (1 + e), e uniform in +-2^-24: the size of
-    one float32 rounding.  Used to measure how far float32 arithmetic can move an exact result
-    (the conditioning of the timing problem at float32 resolution); off by default."""
-    gen = torch.Generator().manual_seed(seed)
-    rng = np.random.default_rng([seed, 24])
-    u = 2.0 ** -24
-
-    def p(v):
-        if isinstance(v, np.ndarray):
-            return v * (1 + rng.uniform(-u, u, v.shape))
-        e = (torch.rand(v.shape, generator=gen, dtype=F64) * 2 - 1) * u
-        return v * (1 + e)
-    return p
-
-
 def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float = 10.0,
-            plan: _Plan | None = None, want_decisions: bool = False, perturb=None, want_scales: bool = False):
+            plan: _Plan | None = None, want_decisions: bool = False, perturb=None, base=None,
+            start_level: int = 0):
     """Arrival time, slew and smoothed late arrival time for every pin.
 
     x, y: float64 tensors [P] by original pin id (may require grad).
-    perturb: None, or a function applied to each table-lookup result and each propagated
-    arrival and slew (see fp32_rounding_noise).
-    want_scales: also return at_scale[P,4], slew_scale[P,4], atg_scale[P,2]: a first-order
-    running bound on float rounding (Wilkinson): each value's scale is the sum, over the
-    operations that produce it, of |partial derivative| x (scale of the operand) plus
-    |result|, with one unit of rounding per operation; the float error of a value is then at
-    most a small multiple of (unit roundoff x scale).  Merges (max/min) take the largest.
+    perturb: None (the default, exact float64), or a function applied to each wire delay,
+    impulse and root load and to the result of each table lookup and of each propagated
+    arrival, slew and smoothed arrival; the rounding experiments of oracle/sta_rounding.py
+    use it.
+    base, start_level: levels below start_level are taken from `base`, an earlier result of
+    this function on the same design and plan, instead of being recomputed.  That is exact
+    when x, y changed only in nets of level start_level or above (a net's coordinates reach
+    its own level first), and is how finite differences avoid redoing the whole sweep.
     Returns dict with at[P,4], slew[P,4], atg[P,2] (torch, by original pin id),
     arc_delay[P,4] (numpy; delay of the arc entered at each cell-input pin, for each
-    output condition k), and the RC results.
+    output condition k), the RC results, and the level-ordered state blocks.
     """
     plan = plan or _Plan(d, lv)
     pt = perturb or (lambda v: v)
@@ -407,16 +393,19 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
     xa = torch.from_numpy(lib.slew_axis.astype(np.float64))
     ya = torch.from_numpy(lib.load_axis.astype(np.float64))
     tables = torch.from_numpy(lib.tables.astype(np.float64))       # [arcs, 4, 7, 7]
-    rcr = rc(d, lv, x, y)
+    rcr = dict(rc(d, lv, x, y))
+    for k in ("delay", "imp", "load_root"):
+        rcr[k] = pt(rcr[k])
     delay, imp, load_root = rcr["delay"], rcr["imp"], rcr["load_root"]
     net_of_pin = torch.from_numpy(lv.net_of_pin)
     P = d.n_pins
-    arc_delay = np.full((P, 4), np.nan)
-    arc_sigma = np.full((P, 4), np.nan)
+    arc_delay = np.full((P, 4), np.nan) if base is None else base["arc_delay"].copy()
     decisions = []
     blocks = []           # level-ordered pin states [rows, 10]: at(4) slew(4) atg(2)
-    sblocks = []          # matching term-magnitude scales [rows, 6] (want_scales)
     for l in range(plan.L):
+        if l < start_level:
+            blocks.append(base["blocks"][l])
+            continue
         drv = plan.drv[l]
         n_d = len(drv)
         if l == 0:
@@ -436,7 +425,6 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
             load_o = load_root[net_of_pin[torch.from_numpy(drv)]]  # [nc]
             cols = []
             late_delay = {}
-            scale_inputs, arc_sigma_pending = {}, {}
             for k in range(4):
                 m, t = k // 2, k % 2
                 tp = np.where(unate > 0, t, 1 - t)                  # input transition t'
@@ -455,7 +443,7 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
                     am = torch.argmax(sm, dim=1)                   # first max: ties to lowest arc
                     slew_o = torch.gather(sm, 1, am.unsqueeze(1)).squeeze(1)
                     atg_in = torch.gather(src[:, :, 8:10], 2, torch.from_numpy(tp).unsqueeze(-1)).squeeze(-1)
-                    late_delay[t] = (atg_in + dval, mask)
+                    late_delay[t] = (pt(atg_in + dval), mask)
                     if want_decisions:
                         decisions.append(am.numpy().copy())
                 else:
@@ -467,58 +455,11 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
                 ad = dval.detach().numpy()
                 pm = plan.in_mask[l]
                 arc_delay[pins[pm], k] = ad[pm]
-                if want_scales:
-                    sdx, sdy = lut_partials(tables[arc, t], xa, ya, slew_in.detach(), lo.detach())
-                    ssx, ssy = lut_partials(tables[arc, 2 + t], xa, ya, slew_in.detach(), lo.detach())
-                    scale_inputs[k] = (sdx.numpy(), sdy.numpy(), ssx.numpy(), ssy.numpy(), ad,
-                                       sval.detach().numpy(), cand.detach().numpy())
             atg_cols = []
             for t in range(2):
                 vals, mask_t = late_delay[t]
-                atg_cols.append(lse(torch.where(mask_t, vals, torch.tensor(-math.inf, dtype=F64)), gamma, dim=1))
+                atg_cols.append(pt(lse(torch.where(mask_t, vals, torch.tensor(-math.inf, dtype=F64)), gamma, dim=1)))
             drv_state = torch.stack([c[0] for c in cols] + [c[1] for c in cols] + atg_cols, dim=1)
-        # Rounding-error scales (want_scales), in float64 numpy, outside the autograd graph.
-        if want_scales:
-            if l == 0:
-                drv_sc = np.concatenate([np.full((n_d, 4), abs(cons.pi_at)), np.full((n_d, 4), abs(cons.pi_slew)),
-                                         np.full((n_d, 2), abs(cons.pi_at))], axis=1)
-            else:
-                ssrc = np.concatenate(sblocks)[np.where(plan.in_mask[l], plan.row[plan.in_pins[l]], 0)]
-                mask_np = plan.in_mask[l]
-                un_np = plan.in_unate[l]
-                lo_np = np.abs(load_o.detach().numpy())[:, None]
-                cols_at, cols_sl, cols_g = [], [], []
-                for k in range(4):
-                    m, t = k // 2, k % 2
-                    tp = np.where(un_np > 0, t, 1 - t)
-                    kp = 2 * m + tp
-                    sd_dx, sd_dy, ss_dx, ss_dy, dv, sv, cv = scale_inputs[k]
-                    s_at = np.take_along_axis(ssrc[:, :, 0:4], kp[:, :, None], 2)[:, :, 0]
-                    s_sl = np.take_along_axis(ssrc[:, :, 4:8], kp[:, :, None], 2)[:, :, 0]
-                    sig_d = np.abs(sd_dx) * s_sl + np.abs(sd_dy) * lo_np + np.abs(dv)
-                    sig_s = np.abs(ss_dx) * s_sl + np.abs(ss_dy) * lo_np + np.abs(sv)
-                    arc_sigma_pending[k] = sig_d
-                    cols_at.append(np.where(mask_np, s_at + sig_d + np.abs(cv), 0.0).max(axis=1))
-                    cols_sl.append(np.where(mask_np, sig_s, 0.0).max(axis=1))
-                    if m == 1:
-                        s_g = np.take_along_axis(ssrc[:, :, 8:10], tp[:, :, None], 2)[:, :, 0]
-                        gv = np.abs(late_delay[t][0].detach().numpy())
-                        cols_g.append(np.where(mask_np, s_g + sig_d + gv, 0.0).max(axis=1)
-                                      + np.abs(atg_cols[t].detach().numpy()))
-                drv_sc = np.stack(cols_at + cols_sl + cols_g, axis=1)
-                pm = plan.in_mask[l]
-                for k in range(4):
-                    arc_sigma[plan.in_pins[l][pm], k] = arc_sigma_pending[k][pm]
-            sk = torch.from_numpy(plan.sinks[l])
-            wv = np.abs(delay[sk].detach().numpy())[:, None]
-            iv = np.abs(imp[sk].detach().numpy())[:, None]
-            dsc = drv_sc[plan.sink_drv[l]]
-            dst = drv_state.detach().numpy()[plan.sink_drv[l]]
-            sl_s = np.sqrt(dst[:, 4:8] ** 2 + iv ** 2)
-            sig_sl = np.where(sl_s > 0, (np.abs(dst[:, 4:8]) * dsc[:, 4:8] + iv * iv) / np.where(sl_s > 0, sl_s, 1), 0) + sl_s
-            sink_sc = np.concatenate([dsc[:, 0:4] + wv + np.abs(dst[:, 0:4] + wv), sig_sl,
-                                      dsc[:, 8:10] + wv + np.abs(dst[:, 8:10] + wv)], axis=1)
-            sblocks.append(np.concatenate([drv_sc, sink_sc]))
         # Net step: sinks take the driver's arrival plus the wire (R4 for the slew).
         sinks = torch.from_numpy(plan.sinks[l])
         sd = torch.from_numpy(plan.sink_drv[l])
@@ -538,13 +479,8 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
                else torch.from_numpy(lv.driver)[net_of_pin])
         decisions.append(np.sign((x - x[ref]).detach().numpy()))
         decisions.append(np.sign((y - y[ref]).detach().numpy()))
-    out = dict(at=st[:, 0:4], slew=st[:, 4:8], atg=st[:, 8:10], arc_delay=arc_delay, rc=rcr,
-               plan=plan, decisions=decisions if want_decisions else None)
-    if want_scales:
-        sc = np.concatenate(sblocks)[plan.row]
-        out["at_scale"], out["slew_scale"], out["atg_scale"] = sc[:, 0:4], sc[:, 4:8], sc[:, 8:10]
-        out["arc_sigma"] = arc_sigma
-    return out
+    return dict(at=st[:, 0:4], slew=st[:, 4:8], atg=st[:, 8:10], arc_delay=arc_delay, rc=rcr,
+                plan=plan, decisions=decisions if want_decisions else None, blocks=blocks)
 
 
 # --------------------------------------------------------------------------------------
@@ -553,8 +489,8 @@ def forward(d, lv: Levelization, x: torch.Tensor, y: torch.Tensor, gamma: float 
 def backward(d, lv: Levelization, fwd, perturb=None) -> dict:
     """Required arrival time, slack, WNS and TNS (readings R8, R9). numpy float64.
 
-    perturb: None, or a function applied to each propagated required time (see
-    fp32_rounding_noise)."""
+    perturb: None (exact), or a function applied to each propagated required time (see
+    forward)."""
     pt = perturb or (lambda v: v)
     plan = fwd["plan"]
     cons = d.cons
@@ -568,18 +504,8 @@ def backward(d, lv: Levelization, fwd, perturb=None) -> dict:
     ep = plan.endpoints
     rat[ep, 0:2] = cons.hold
     rat[ep, 2:4] = cons.t_clk - cons.setup
-    want_scales = "at_scale" in fwd
-    if want_scales:      # term magnitudes of each required time (see forward)
-        rsc = np.zeros((P, 4))
-        rsc[ep] = np.abs(rat[ep])
     for l in range(plan.L - 1, -1, -1):
         drv, sinks, sd = plan.drv[l], plan.sinks[l], plan.sink_drv[l]
-        if want_scales:
-            sv = rsc[sinks] + np.abs(delay[sinks])[:, None] + np.abs(np.nan_to_num(rat[sinks] - delay[sinks][:, None],
-                                                                                    posinf=0, neginf=0))
-            rd_sc = np.zeros((len(drv), 4))
-            np.maximum.at(rd_sc, sd, sv)
-            rsc[drv] = rd_sc
         # Net step: the driver needs its tightest sink, less the wire delay.
         req = pt(rat[sinks] - delay[sinks][:, None])
         rd = np.empty((len(drv), 4))
@@ -598,21 +524,13 @@ def backward(d, lv: Levelization, fwd, perturb=None) -> dict:
             kp = 2 * m + tp
             val = pt(rat[drv, k][:, None] - ad[pins, k])
             rat[pins[mask], kp[mask]] = val[mask]
-            if want_scales:
-                vs = (rsc[drv, k][:, None] + np.nan_to_num(fwd["arc_sigma"][pins, k])
-                      + np.abs(np.nan_to_num(val, posinf=0, neginf=0)))
-                rsc[pins[mask], kp[mask]] = vs[mask]
     slack = np.empty((P, 4))
     slack[:, 2:4] = rat[:, 2:4] - at[:, 2:4]
     slack[:, 0:2] = at[:, 0:2] - rat[:, 0:2]
     worst = np.minimum(slack[ep, 2], slack[ep, 3])
     wns = min(0.0, float(worst.min())) if len(ep) else 0.0
     tns = math.fsum(np.minimum(0.0, worst).tolist())
-    out = dict(rat=rat, slack=slack, wns=wns, tns=tns, endpoint_slack=worst, endpoints=ep)
-    if want_scales:
-        out["rat_scale"] = rsc
-        out["slack_scale"] = rsc + fwd["at_scale"] + np.abs(np.nan_to_num(slack, posinf=0, neginf=0))
-    return out
+    return dict(rat=rat, slack=slack, wns=wns, tns=tns, endpoint_slack=worst, endpoints=ep)
 
 
 # --------------------------------------------------------------------------------------
@@ -629,8 +547,7 @@ def smoothed_objective(d, fwd, gamma: float) -> dict:
     return dict(tns_g=tns_g, wns_g=wns_g, s=s)
 
 
-def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=None, plan=None, perturb=None,
-        scales: bool = False):
+def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=None, plan=None, perturb=None):
     """Full oracle: forward, backward, smoothed objective and (optionally) its gradient.
 
     Returns numpy float64 arrays by original pin id.
@@ -638,7 +555,7 @@ def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=Non
     lv = lv or levelize(d)
     xt = torch.tensor(np.asarray(d.x if x is None else x, np.float64), requires_grad=grad is not None)
     yt = torch.tensor(np.asarray(d.y if y is None else y, np.float64), requires_grad=grad is not None)
-    fwd = forward(d, lv, xt, yt, gamma, plan=plan, perturb=perturb, want_scales=scales)
+    fwd = forward(d, lv, xt, yt, gamma, plan=plan, perturb=perturb)
     bwd = backward(d, lv, fwd, perturb=perturb)
     obj = smoothed_objective(d, fwd, gamma)
     out = dict(at=fwd["at"].detach().numpy(), slew=fwd["slew"].detach().numpy(),
@@ -647,11 +564,6 @@ def run(d, x=None, y=None, gamma: float = 10.0, grad: str | None = "tns", lv=Non
                delay=fwd["rc"]["delay"].detach().numpy(), imp=fwd["rc"]["imp"].detach().numpy(),
                load_root=fwd["rc"]["load_root"].detach().numpy(), arc_delay=fwd["arc_delay"],
                endpoints=bwd["endpoints"], endpoint_slack=bwd["endpoint_slack"], lv=lv, plan=fwd["plan"])
-    if scales:
-        for k in ("at_scale", "slew_scale", "atg_scale"):
-            out[k] = fwd[k]
-        for k in ("rat_scale", "slack_scale"):
-            out[k] = bwd[k]
     if grad is not None:
         target = obj["tns_g"] if grad == "tns" else obj["wns_g"]
         gx, gy = torch.autograd.grad(target, (xt, yt), allow_unused=True)

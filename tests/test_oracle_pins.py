@@ -17,6 +17,7 @@ from scipy.special import logsumexp
 
 from gen.netlist import CFG0, Constraints, make_design, make_library, tiny_spec
 from oracle import sta_oracle as O
+from oracle import sta_rounding as RB
 from tests._designs import (PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D, PIN_PI, PIN_PO, build, chain,
                             planar_library, two_pin)
 
@@ -363,30 +364,153 @@ def test_fp32_noise_envelope_small_on_cfg0():
     d = make_design(CFG0)
     lv = O.levelize(d)
     ref = O.run(d, grad=None, lv=lv)
-    r = O.run(d, grad=None, lv=lv, perturb=O.fp32_rounding_noise(0))
+    r = O.run(d, grad=None, lv=lv, perturb=RB.fp32_rounding_noise(0))
     assert np.max(np.abs(r["at"] - ref["at"]) / np.maximum(np.abs(ref["at"]), 1.0)) < 1e-6
     assert not np.array_equal(r["at"], ref["at"])      # the perturbation is live
 
 
+FAR = dict(cfg_id=77, box_um=4000.0)   # loads far past the table edge
+
+
 @pytest.mark.parametrize("which", ["cfg0", "far_extrapolation"])
 def test_rounding_scales_bound_float32_perturbation(which):
-    # sigma is a first-order bound: one rounding of relative size <= u at every operation
-    # moves each value by at most u * sigma (up to second-order terms).
+    # Lower pin: sigma is a first-order bound, so one rounding of relative size <= u at
+    # every operation moves each value by at most u * sigma (up to second-order terms).
     from gen.netlist import scaled_spec
-    d = make_design(CFG0 if which == "cfg0" else scaled_spec(20_000, cfg_id=77, box_um=4000.0))
+    d = make_design(CFG0 if which == "cfg0" else scaled_spec(20_000, **FAR))
     lv = O.levelize(d)
     plan = O._Plan(d, lv)
-    ref = O.run(d, grad=None, lv=lv, plan=plan, scales=True)
-    u = 2.0 ** -24
+    ref = O.run(d, grad=None, lv=lv, plan=plan)
+    sc = RB.rounding_scales(d, ref)
+    u = RB.U32
     for seed in range(3):
-        p = O.run(d, grad=None, lv=lv, plan=plan, perturb=O.fp32_rounding_noise(seed))
+        p = O.run(d, grad=None, lv=lv, plan=plan, perturb=RB.fp32_rounding_noise(seed))
         for k in ("at", "slew", "atg", "rat", "slack"):
             r, v = ref[k], p[k]
             fin = np.isfinite(r)
             assert np.array_equal(fin, np.isfinite(v)), k
-            assert np.all(ref[k + "_scale"][fin] >= np.abs(r[fin]) * (1 - 1e-12)), k
             err = np.abs(v[fin] - r[fin])
-            assert np.all(err <= 1.01 * u * ref[k + "_scale"][fin] + 1e-9), (k, np.max(err / (u * ref[k + "_scale"][fin])))
+            assert np.all(err <= 1.01 * u * sc[k + "_scale"][fin] + 1e-9), (k, np.max(err / (u * sc[k + "_scale"][fin])))
+
+
+@pytest.mark.parametrize("which", ["cfg0", "far_extrapolation"])
+def test_rounding_scales_reached_by_signed_rounding(which):
+    # Upper pin: rounding every forward result down and every required time up by one
+    # float32 unit (all errors of one sign) is a rounding pattern float32 could produce; it
+    # moves the median value by about half its bound and the top percentile to it, so sigma
+    # is not inflated.  A sigma with a spurious term (a doubled partial, a term counted
+    # twice) would put these ratios near or below 0.5 and 0.25.
+    from gen.netlist import scaled_spec
+    d = make_design(CFG0 if which == "cfg0" else scaled_spec(20_000, **FAR))
+    ref = O.run(d, grad=None)
+    sc = RB.rounding_scales(d, ref)
+    sg = RB.run_signed(d, lv=ref["lv"], plan=ref["plan"])
+    for k in ("at", "slew", "atg", "rat", "slack"):
+        s = sc[k + "_scale"]
+        fin = np.isfinite(ref[k]) & (s > 0)
+        ratio = np.abs(sg[k][fin] - ref[k][fin]) / (RB.U32 * s[fin])
+        assert ratio.max() <= 1.0 + 1e-6, k                    # and it stays a bound
+        assert np.median(ratio) >= 0.4 and np.quantile(ratio, 0.99) >= 0.8, (k, np.median(ratio))
+
+
+def _gain_library(gain: float) -> "Library":
+    """Planar tables without load dependence: delay = a + b slew, slew = a_s + gain * slew,
+    the same for both output transitions, all coefficients dyadic so that every entry is
+    exact in float32."""
+    from gen.netlist import Library
+    base = planar_library(seed=5)
+    xa = base.slew_axis.astype(np.float64)
+    rng = np.random.default_rng(9)
+    tabs = np.empty(base.tables.shape, np.float64)
+    for a in range(tabs.shape[0]):          # rise and fall alike, so all conditions share values
+        tabs[a, 0:2] = rng.integers(8, 64) / 2.0 + rng.integers(1, 20) / 64.0 * xa[:, None]
+        tabs[a, 2:4] = rng.integers(4, 16) / 2.0 + gain * xa[:, None]
+    assert np.array_equal(tabs.astype(np.float32).astype(np.float64), tabs)
+    return Library(base.n_cell_types, base.arc_offsets, base.arc_unate, base.slew_axis, base.load_axis,
+                   tabs.astype(np.float32))
+
+
+def test_rounding_scales_exact_on_amplifying_chain():
+    # A chain of 12 single-input gates whose tables have slew gain 1.5 (slews run from 10 ps
+    # to about 3e3 ps, far past the 500 ps axis end), co-located pins (no wire) and no load
+    # dependence: every partial derivative is positive, so signed rounding reaches the
+    # first-order bound exactly, and the slew bound has the closed form of a linear
+    # recurrence: sigma(s_j) = gain * sigma(s'_(j-1)) + s_j at the gate output,
+    # sigma(s'_j) = sigma(s_j) + s'_j at the next input (the sink slew's own rounding).
+    gain = 1.5
+    lib = _gain_library(gain)
+    n = 12
+    d = chain(n, [0, 1, 2, 3, 4, 5] * 2, lib, L_um=0.0, cpin=2.0)
+    ref = O.run(d, grad=None)
+    sc = RB.rounding_scales(d, ref)
+    sg = RB.run_signed(d, lv=ref["lv"], plan=ref["plan"])
+    for k in ("at", "slew", "atg", "rat"):
+        s = sc[k + "_scale"]
+        fin = np.isfinite(ref[k]) & (s > 0)
+        ratio = np.abs(sg[k][fin] - ref[k][fin]) / (RB.U32 * s[fin])
+        assert np.all(np.abs(ratio - 1.0) < 1e-5), (k, ratio.min(), ratio.max())
+    fin = np.isfinite(ref["slack"])
+    sl = np.abs(np.where(fin, ref["slack"], 0))
+    ratio = np.abs(sg["slack"][fin] - ref["slack"][fin]) / (RB.U32 * (sc["slack_scale"][fin] - sl[fin]))
+    assert np.all(np.abs(ratio - 1.0) < 1e-5)     # the final subtraction is not perturbed
+    # Closed form of the slew bound along the chain (late rise of the primary output).
+    po = d.n_pins - 1
+    sig_in, s_in = 10.0, 10.0                      # PI sink: sqrt(10^2 + 0) rounded once
+    sl_gate = ref["slew"]
+    outs = d.cell_out_pin
+    for j in range(n):
+        s_out = sl_gate[outs[j], 2]
+        kp_src = 2 if lib.arc_unate[lib.arc_offsets[d.cell_type[j]]] > 0 else 3
+        assert np.isclose(s_in, ref["slew"][d.cell_in_pins[j], kp_src])
+        sig_out = gain * sig_in + s_out
+        sig_in, s_in = sig_out + s_out, s_out
+    assert ref["slew"][po, 2] > 500.0 * 5                       # far past the table edge
+    assert sc["slew_scale"][po, 2] == pytest.approx(sig_in, rel=1e-12)
+    assert sig_in / ref["slew"][po, 2] > 2.5                    # amplified: sigma/slew ~ 1/(1-1/gain)
+
+
+def test_wns_smoothed_counts_the_zero_member():
+    # WNS_g = -LSE({0} u {-s_e}): with every endpoint's slack positive, the zero member is
+    # the largest term.  A PI -> buffer -> FF design with the clock at 40 ps puts the
+    # smoothed endpoint slack s at a few ps, so WNS_g = -gamma log(1 + exp(-s/gamma)), a
+    # small negative number, where dropping {0} would give s itself (positive).
+    lib = planar_library(seed=3)
+    d = chain(1, [0], lib, L_um=30.0, cpin=2.0)
+    d.pin_kind[-1] = PIN_FF_D
+    d.cons = type(d.cons)(**{**d.cons.__dict__, "t_clk": 40.0})
+    g = 10.0
+    out = O.run(d, gamma=g, grad="wns")
+    sl = out["slack"][d.n_pins - 1, 2:4]                         # late rise, fall slack at the FF
+    assert np.all(sl > 0)
+    s = -g * np.log(np.exp(-sl[0] / g) + np.exp(-sl[1] / g))     # soft worst of rise and fall
+    assert 0 < s < 40
+    assert out["wns_g"] == pytest.approx(-g * np.log1p(np.exp(-s / g)), rel=1e-12)
+    assert out["wns"] == 0.0 and out["tns"] == 0.0
+    # Two endpoints: both positive, WNS_g = -gamma log(1 + sum exp(-s_e / gamma)).
+    d2 = chain(2, [0, 1], lib, L_um=30.0, cpin=2.0)
+    d2 = _add_endpoint(d2, net_driver=int(d2.cell_out_pin[0]))
+    d2.cons = type(d2.cons)(**{**d2.cons.__dict__, "t_clk": 80.0})
+    out2 = O.run(d2, gamma=g, grad=None)
+    ep = out2["endpoints"]
+    sle = out2["slack"][ep][:, 2:4]
+    assert len(ep) == 2 and np.all(sle > 0)
+    se = -g * np.log(np.exp(-sle[:, 0] / g) + np.exp(-sle[:, 1] / g))
+    assert out2["wns_g"] == pytest.approx(-g * np.log1p(np.exp(-se / g).sum()), rel=1e-12)
+
+
+def _add_endpoint(d, net_driver: int):
+    """Adds a flop D sink, co-located with the driver, to the net that `net_driver` drives."""
+    from tests._designs import build
+    nets = [list(d.net_pins[d.net_offsets[n]:d.net_offsets[n + 1]]) for n in range(d.n_nets)]
+    new = d.n_pins
+    for n in nets:
+        if n[0] == net_driver:
+            n.append(new)
+    cells = [(int(d.cell_type[c]), list(d.cell_in_pins[d.cell_in_offsets[c]:d.cell_in_offsets[c + 1]]),
+              int(d.cell_out_pin[c])) for c in range(d.n_cells)]
+    kinds = list(d.pin_kind) + [PIN_FF_D]
+    return build(nets, cells, kinds, list(d.pin_cap) + [2.0], list(d.x) + [float(d.x[net_driver])],
+                 list(d.y) + [float(d.y[net_driver])], lib=d.lib, cons=d.cons)
 
 
 @pytest.mark.parametrize("seed", range(3))
