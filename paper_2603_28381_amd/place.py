@@ -68,6 +68,7 @@ class TimingDescent:
         self.g.backward(x, y, f, rat=False, grad=True, pins=False, workspace=self.ws, out=self.grads)
         gx = torch.cat([self.grads["dx"], self.zero])[self.idx].sum(1)   # d TNS_g / d cell x
         gy = torch.cat([self.grads["dy"], self.zero])[self.idx].sum(1)
+        self.cell_grad = (gx, gy)        # of this step's placement, kept for inspection
         C = self.idx.shape[0]
         self.dxc.grad = torch.cat([2.0 * self.anchor * self.dxc[:C] - gx, self.zero])
         self.dyc.grad = torch.cat([2.0 * self.anchor * self.dyc[:C] - gy, self.zero])

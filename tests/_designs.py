@@ -152,3 +152,31 @@ def wide_dag(n_levels: int = 8, gates_per_level: int = 40, n_pi: int = 12, seed:
     caps = np.where(np.asarray(kinds) == PIN_PI, 0.0, caps)
     return build(nets, cells, kinds, caps, rng.uniform(0, box_um, P), rng.uniform(0, box_um, P),
                  lib=lib, name="wide")
+
+
+def fanout_design(n_sinks=1300, n_buf=100, seed=3, via_cell=False):
+    """A primary input driving one net of n_sinks sinks (n_buf of them 1-input cells whose
+    outputs each drive a flop), placed at random: a net too big for one LDS chunk.  With
+    via_cell the big net is driven by a 1-input cell fed by the primary input (the big net
+    then sits at level 1, behind a cell step)."""
+    lib = make_library()
+    one_in = int(np.nonzero(np.diff(lib.arc_offsets) == 1)[0][0])
+    rng = np.random.default_rng(seed)
+    if via_cell:
+        kinds, nets, cells = [PIN_PI, PIN_CELL_IN, PIN_CELL_OUT], [[0, 1], [2]], [(one_in, [1], 2)]
+    else:
+        kinds, nets, cells = [PIN_PI], [[0]], []
+    big = nets[-1]
+    for i in range(n_sinks):
+        p = len(kinds)
+        big.append(p)
+        if i < n_buf:
+            kinds += [PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D]
+            cells.append((one_in, [p], p + 1))
+            nets.append([p + 1, p + 2])
+        else:
+            kinds.append(PIN_PO)
+    P = len(kinds)
+    caps = np.where(np.isin(kinds, [PIN_PI, PIN_CELL_OUT]), 0.0, rng.uniform(1, 5, P)) if via_cell \
+        else rng.uniform(1, 5, P)
+    return build(nets, cells, kinds, caps, rng.uniform(0, 3000, P), rng.uniform(0, 3000, P), lib=lib)

@@ -43,3 +43,31 @@ def test_descent_improves_timing_moves_cells_rigidly_and_repeats():
     assert np.abs(mx).max() > 0.1              # cells did move
     hist2, x2, _ = _loop(d, 40)                # the loop is deterministic
     assert np.array_equal(hist, hist2) and np.array_equal(x, x2)
+
+
+def test_descent_cell_gradient_matches_oracle():
+    # The per-cell gradient a step follows (sum of d TNS_g / dx, dy over the cell's pins)
+    # against the oracle's gradient at the same placement, gathered over the same pins: at
+    # the start and after a few steps, once cells have moved.
+    from oracle import sta_oracle as O
+    d = make_design(scaled_spec(20_000, cfg_id=61, box_um=800.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    td = TimingDescent(g, d.x, d.y, d.cell_in_offsets, d.cell_in_pins, d.cell_out_pin, gamma=10.0, lr=1.0,
+                       anchor=1e-4)
+    off = d.cell_in_offsets
+    pins = [np.concatenate([[d.cell_out_pin[c]], d.cell_in_pins[off[c]:off[c + 1]]]) for c in range(d.n_cells)]
+    for it in range(6):
+        x, y = (t.cpu().numpy() for t in td.coordinates())
+        td.step()
+        if it not in (0, 5):
+            continue
+        ref = O.run(d, x=x, y=y, gamma=10.0, grad="tns")
+        for k, got in zip(("dx", "dy"), td.cell_grad):
+            got = got.cpu().numpy().astype(np.float64)
+            r = np.array([ref[k][p].sum() for p in pins])
+            # each pin's entry is held to 1e-3 |g| + 1e-6 max|g|; a cell sums its pins' bounds
+            tol = np.array([(1e-3 * np.abs(ref[k][p]) + 1e-6 * np.abs(ref[k]).max()).sum() for p in pins])
+            bad = np.abs(got - r) > tol
+            print(f"step {it} {k}: max |cell grad| {np.abs(r).max():.4g}, worst {np.max(np.abs(got - r) / tol):.3g}x tol")
+            assert not bad.any(), f"step {it} {k}: {bad.sum()} cells outside tolerance"

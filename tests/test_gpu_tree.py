@@ -11,6 +11,7 @@ import torch
 from gen.netlist import heap_trees, make_design, scaled_spec
 from oracle import sta_oracle as O
 from paper_2603_28381_amd import Graph
+from tests._designs import fanout_design
 from tests.test_gpu_parity import GAMMA, check_grad, check_values, gpu_run
 
 pytestmark = pytest.mark.gpu
@@ -105,31 +106,8 @@ def test_tree_batch_checkpointing_and_snapshots_bitwise():
     check_grad({"dx": plain["dx"][:P_a], "dy": plain["dy"][:P_a]}, ref, 1e-3, 1e-6)
 
 
-def _fanout_design(n_sinks=1300, n_buf=100, seed=3):
-    """A primary input driving one net of n_sinks sinks (n_buf of them 1-input cells whose
-    outputs each drive a flop), placed at random: a net too big for one LDS chunk."""
-    from gen.netlist import make_library
-    from tests._designs import PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D, PIN_PI, PIN_PO, build
-    lib = make_library()
-    one_in = int(np.nonzero(np.diff(lib.arc_offsets) == 1)[0][0])
-    rng = np.random.default_rng(seed)
-    kinds, nets, cells = [PIN_PI], [[0]], []
-    for i in range(n_sinks):
-        p = len(kinds)
-        nets[0].append(p)
-        if i < n_buf:
-            kinds += [PIN_CELL_IN, PIN_CELL_OUT, PIN_FF_D]
-            cells.append((one_in, [p], p + 1))
-            nets.append([p + 1, p + 2])
-        else:
-            kinds.append(PIN_PO)
-    P = len(kinds)
-    return build(nets, cells, kinds, rng.uniform(1, 5, P), rng.uniform(0, 3000, P), rng.uniform(0, 3000, P),
-                 lib=lib)
-
-
 def test_tree_net_over_one_chunk_uses_the_fallback_kernels():
-    d = heap_trees(_fanout_design())
+    d = heap_trees(fanout_design())
     assert np.diff(d.net_offsets).max() > 1024
     ref = O.run(d, gamma=GAMMA, grad="tns")
     got = gpu_run(d)
