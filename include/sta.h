@@ -224,6 +224,30 @@ sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Backward sweep that allocates nothing, for callers that cannot allocate device memory:
+ * code under hipGraph stream capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same sweep, arguments, results and errors as sta_backward (the same kernels), except:
+ *  - out->workspace must be NULL.  The workspace is a fixed array of
+ *    STA_NOALLOC_WORKSPACE_BYTES inside the library, one per device, held from the library's
+ *    first use of that device until the process ends.  Its address is looked up once per
+ *    device, on the first call there; nothing is allocated or freed by any call.
+ *  - the graph must already be uploaded to the current device (sta_graph_upload, or a
+ *    sta_forward on it): uploading allocates.  STA_E_STATE otherwise, and while profiling
+ *    (sta_profile_enable) is on, since that creates events.
+ *  - STA_GRAPH is refused (STA_E_INVALID): capturing and instantiating a graph allocates.
+ *    The call may itself be recorded by a caller's stream capture.
+ *  - every call on one device shares that device's array, which keeps the last call's
+ *    contents (the sweep writes every entry it reads, so nothing needs clearing).  Calls
+ *    that overlap on one device race: serialize them, for example on one stream.
+ * Errors: STA_E_NOMEM when the graph's bwd_workspace_bytes (all snapshots) exceed
+ * STA_NOALLOC_WORKSPACE_BYTES, with the sizes in the message; STA_E_DEVICE when the array's
+ * device address cannot be obtained; otherwise as sta_backward.
+ * ------------------------------------------------------------------------------------- */
+#define STA_NOALLOC_WORKSPACE_BYTES (96ll << 20)   /* 96 MiB: star designs of 3.1M pins */
+sta_status sta_backward_noalloc(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                                sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);
+
+/* ---------------------------------------------------------------------------------------
  * Placement snapshots.  With n_snapshots = S > 1 every sta_forward / sta_backward call sweeps
  * S placements of the same graph at once: the topology, library tables and launch plan are
  * shared, and launches get a second grid dimension over snapshots.  Every per-call buffer

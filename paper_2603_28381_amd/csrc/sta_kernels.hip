@@ -25,6 +25,8 @@
 //  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "sta_internal.h"
@@ -2350,6 +2352,68 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   const sta_bwd_out o = *out;
   return run_maybe_captured(g, g->cap_bwd, (flags & STA_GRAPH) != 0, key, reinterpret_cast<hipStream_t>(stream),
                             [&](hipStream_t s) { return launch_backward(g, x, y, &f, &o, flags, gamma_ps, s); });
+}
+
+namespace sta {
+namespace {
+
+// Backward workspace of sta_backward_noalloc: a fixed array in device memory, one copy per
+// device, held from the code object's load until the process ends.  Host code never passes
+// its name to a kernel (on the host it names a stand-in, not device memory): it takes the
+// device address once per device from hipGetSymbolAddress and uses that.
+constexpr size_t kNoallocBytes = (size_t)STA_NOALLOC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+sta_status scratch_on(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(STA_E_DEVICE, "device id beyond the library's table");
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(STA_E_DEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return STA_OK;
+}
+
+}  // namespace
+}  // namespace sta
+
+extern "C" sta_status sta_backward_noalloc(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                                           sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  // Uploading allocates: the graph must already be on the device.
+  if (!g->uploaded) return fail(STA_E_STATE, "graph is not uploaded; call sta_graph_upload first");
+  if (flags & STA_GRAPH) return fail(STA_E_INVALID, "STA_GRAPH captures a hipGraph, which allocates");
+  if (g->profiling) return fail(STA_E_STATE, "profiling creates events; disable it for this call");
+  sta_status st = check_ready(g);
+  if (st != STA_OK) return st;
+  if (!fwd || !fwd->state || !out) return fail(STA_E_INVALID, "state and outputs are required");
+  if (out->workspace) return fail(STA_E_INVALID, "workspace must be NULL: the library's own array is used");
+  const size_t need = (size_t)g->n_snap * g->work.total;
+  if (need > kNoallocBytes)
+    return fail(STA_E_NOMEM, "backward workspace of " + std::to_string(need) + " bytes exceeds the " +
+                                 std::to_string(kNoallocBytes) + "-byte fixed array of sta_backward_noalloc");
+  const bool grad = (flags & STA_GRAD) != 0;
+  if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
+  if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  if (grad) {
+    st = check_grad_state(g, fwd->state, gamma_ps);
+    if (st != STA_OK) return st;
+  }
+  void* ws = nullptr;
+  st = scratch_on(g->dev.device, &ws);
+  if (st != STA_OK) return st;
+  sta_bwd_out o = *out;
+  o.workspace = ws;
+  return launch_backward(g, x, y, fwd, &o, flags, gamma_ps, reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,

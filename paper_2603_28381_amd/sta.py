@@ -30,7 +30,7 @@ STA_RC_GROUPS, STA_RC_CTE, STA_RC_THREAD = 0, 1, 2
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
-            "sta_forward", "sta_backward", "sta_get_schedule", "sta_set_schedule", "sta_tune",
+            "sta_forward", "sta_backward", "sta_backward_noalloc", "sta_get_schedule", "sta_set_schedule", "sta_tune",
             "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_server_create", "sta_server_add_design",
             "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
@@ -135,6 +135,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_backward.argtypes = [_P, _P, _P, ctypes.POINTER(StaFwdOut), ctypes.POINTER(StaBwdOut),
                                  ctypes.c_uint32, ctypes.c_float, _P]
     lib.sta_backward.restype = S
+    lib.sta_backward_noalloc.argtypes = lib.sta_backward.argtypes
+    lib.sta_backward_noalloc.restype = S
     lib.sta_batch_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)]
     lib.sta_batch_create.restype = S
     lib.sta_batch_pin_map.argtypes = [_P, _P, _P]
@@ -399,13 +401,17 @@ class Graph:
     def backward(self, x, y, fwd: Forward, rat: bool = True, grad: bool = True, wns: bool = False,
                  pins: bool = True, grad_scale: float = 1.0, grad_scale_dev: torch.Tensor | None = None,
                  workspace: torch.Tensor | None = None, out: dict | None = None, stream=None,
-                 capture: bool = False) -> dict:
+                 capture: bool = False, noalloc: bool = False) -> dict:
+        """noalloc: run sta_backward_noalloc, whose workspace is the library's fixed device
+        array (no workspace tensor; outputs still come from `out` or are allocated here)."""
         dev = fwd.state.device
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
         P, S = self.n_pins, self.info()["n_snapshots"]
         lead = (S,) if S > 1 else ()
-        ws = self.new_workspace(dev) if workspace is None else workspace
+        if noalloc and (workspace is not None or capture):
+            raise ValueError("noalloc takes neither a workspace nor capture")
+        ws = None if noalloc else (self.new_workspace(dev) if workspace is None else workspace)
         if out is None:
             out = {}
             if pins:
@@ -423,8 +429,9 @@ class Graph:
         fo = StaFwdOut(_ptr(fwd.state), None, None, None, None)
         flags = ((STA_RAT if rat else 0) | (STA_GRAD if grad else 0) | (STA_GRAD_WNS if wns else 0)
                  | (STA_CANONICAL_IO if fwd.canonical else 0) | (STA_GRAPH if capture else 0))
-        _check(_lib.sta_backward(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), ctypes.byref(bo), flags,
-                                 float(fwd.gamma), _stream_handle(stream)))
+        call = _lib.sta_backward_noalloc if noalloc else _lib.sta_backward
+        _check(call(self._h, _ptr(x), _ptr(y), ctypes.byref(fo), ctypes.byref(bo), flags, float(fwd.gamma),
+                    _stream_handle(stream)))
         return out
 
 
