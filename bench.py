@@ -74,6 +74,81 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict
     return out
 
 
+def survey_bytes(d) -> dict:
+    """The per-step byte model of the sweep as a whole, written per pin (P pins, N nets,
+    S = P - N sinks, C cells, A cell inputs; float32 values, int32 indices):
+      forward   8P x,y + 4S cap + 4N offsets + 8C type and input offset + 4A input pin ids
+                + 40A gathers (4 AT, 4 slew, 2 smoothed AT per cell input) + 40P writes of
+                the same per pin + the library tables once
+      backward  topology 4N + 8C + 4A, RC inputs again 8P + 4S, 40P state read, 16P RAT and
+                16P slack writes, 32P adjoint scratch written and read, 8P dx, dy
+    Unlike algorithmic_bytes it does not follow where the kernels actually move each value
+    (here the per-pin AT and slew are written by the backward sweep)."""
+    P, N, C = d.n_pins, d.n_nets, d.n_cells
+    S, A = P - N, int(d.cell_in_offsets[-1])
+    tables = int(d.lib.tables.size) * 4
+    fwd = 8 * P + 4 * S + 4 * N + 8 * C + 4 * A + 40 * A + 40 * P + tables
+    bwd = (4 * N + 8 * C + 4 * A) + (8 * P + 4 * S) + 40 * P + 16 * P + 16 * P + 32 * P + 8 * P
+    return {"forward": float(fwd), "backward": float(bwd)}
+
+
+def survey_roofline(d, kernels: dict, ms_step: float) -> dict:
+    """Fractions of HBM peak under survey_bytes: the backward level kernel (the whole backward
+    sweep's bytes over its summed launch time), the forward sweep (RC, levels, endpoint
+    scalars) and the whole step."""
+    b = survey_bytes(d)
+    fwd_ms = sum(kernels[k]["ms_per_step"] for k in ("rc", "fwd_level", "ep_partial", "ep_final") if k in kernels)
+    bl = kernels["bwd_level"]
+    out = {"model": "survey_bytes (whole-sweep byte model per pin)",
+           "bwd_level": {"bytes_per_launch": round(b["backward"] / bl["launches_per_step"], 1),
+                         "avg_launch_us": round(bl["avg_us"], 3)},
+           "forward_sweep": {"bytes": b["forward"], "ms": round(fwd_ms, 4)},
+           "step": {"bytes": b["forward"] + b["backward"], "ms": round(ms_step, 4)}}
+    gbs = b["backward"] / (bl["ms_per_step"] * 1e-3) / 1e9
+    out["bwd_level"].update(achieved_gbs=round(gbs, 2), frac=round(gbs / HBM_PEAK_GBS, 5))
+    for k in ("forward_sweep", "step"):
+        gb = out[k]["bytes"] / (out[k]["ms"] * 1e-3) / 1e9
+        out[k].update(achieved_gbs=round(gb, 2), frac=round(gb / HBM_PEAK_GBS, 5))
+    return out
+
+
+def cpu_host() -> dict:
+    """The host CPU the oracle ran on: model name, logical CPUs, and those this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def time_oracle(d, gamma: float, threads: int, x=None, y=None) -> float:
+    """Seconds of one FP64 oracle forward+backward+gradient of d (levelization excluded) on
+    `threads` host threads (torch and BLAS pools limited to that)."""
+    import torch
+    from threadpoolctl import threadpool_limits
+    from oracle import sta_oracle as O
+    lv = O.levelize(d)
+    plan = O._Plan(d, lv)
+    prev = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    try:
+        with threadpool_limits(threads):
+            c0 = time.perf_counter()
+            O.run(d, x=x, y=y, gamma=gamma, grad="tns", lv=lv, plan=plan)
+            return time.perf_counter() - c0
+    finally:
+        torch.set_num_threads(prev)
+
+
 def kernel_source_hash() -> str:
     """First 16 hex digits of the SHA-256 of the kernel sources (kernels and their shared header)."""
     import hashlib
@@ -235,19 +310,21 @@ def run_batch(args) -> dict:
     ms, wall = timed(step_shared, args.steps, args.warmup)
     value = P / (ms * 1e-3)
 
-    # union: one batch graph of all 80 members
-    gu = Graph.batch([Graph.from_design(d1)] * 64 + [Graph.from_design(d) for d in others])
-    gu.levelize()
-    gu.upload()
-    dsg, pin = gu.batch_pin_map()
-    base = np.cumsum([0] + [m[0].n_pins for m in members])
-    src = base[dsg] + pin
-    xu = torch.from_numpy(np.concatenate([m[1] for m in members])[src]).to(dev)
-    yu = torch.from_numpy(np.concatenate([m[2] for m in members])[src]).to(dev)
-    bu = step_buffers(gu, P, dev, 80)
-    ms_u, _ = timed(lambda: sweep(gu, xu, yu, bu, None), max(1, args.steps // 2), 1)
-    del bu, xu, yu
-    gu.close()
+    ms_u = None
+    if not getattr(args, "lean", False):
+        # union: one batch graph of all 80 members
+        gu = Graph.batch([Graph.from_design(d1)] * 64 + [Graph.from_design(d) for d in others])
+        gu.levelize()
+        gu.upload()
+        dsg, pin = gu.batch_pin_map()
+        base = np.cumsum([0] + [m[0].n_pins for m in members])
+        src = base[dsg] + pin
+        xu = torch.from_numpy(np.concatenate([m[1] for m in members])[src]).to(dev)
+        yu = torch.from_numpy(np.concatenate([m[2] for m in members])[src]).to(dev)
+        bu = step_buffers(gu, P, dev, 80)
+        ms_u, _ = timed(lambda: sweep(gu, xu, yu, bu, None), max(1, args.steps // 2), 1)
+        del bu, xu, yu
+        gu.close()
 
     # plain: the same 80 sweeps as plain call pairs, each member in its own canonical order
     gp1 = Graph.from_design(d1)
@@ -287,7 +364,7 @@ def run_batch(args) -> dict:
         roofline["traffic"] = counted_traffic("k_" + roofline["kernel"], "sta_batched_64snap_kernel_stats.md")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not getattr(args, "lean", False):
         from oracle import sta_oracle as O
         c0 = time.perf_counter()
         done = 0
@@ -311,9 +388,9 @@ def run_batch(args) -> dict:
                                + ("launched directly" if args.no_batch_capture else "both hipGraph-captured"),
                    "pins": P, "members": 80, "schedule_snapshots": best1, "schedule_designs": best16,
                    "io": "canonical order, HBM resident"},
-        "union": {"value": round(P / (ms_u * 1e-3), 1), "unit": "pins/s", "ms_per_step": round(ms_u, 4),
-                  "note": "one batch graph of all 80 members"
-                          + ("" if args.no_batch_capture else ", captured")},
+        "union": None if ms_u is None else {
+            "value": round(P / (ms_u * 1e-3), 1), "unit": "pins/s", "ms_per_step": round(ms_u, 4),
+            "note": "one batch graph of all 80 members" + ("" if args.no_batch_capture else ", captured")},
         "plain_sequential": {"value": round(P / (ms_seq * 1e-3), 1), "unit": "pins/s",
                              "ms_per_step": round(ms_seq, 4), "calls": 2 * len(plain),
                              "speedup_batched": round(ms_seq / ms, 3)},
@@ -415,6 +492,8 @@ def run_single(args) -> dict:
         # The per-launch floor of this machine for comparison: back-to-back dependent launches of
         # a trivial elementwise kernel over as many threads as a level launch has.
         roofline["launch_floor_us"] = round(launch_floor_us(dev, 256 * 450), 2)
+        if not args.trees:
+            roofline["survey_model"] = survey_roofline(d, kernels, ms)
 
     ckpt = None
     if args.ckpt_compare:
@@ -422,15 +501,14 @@ def run_single(args) -> dict:
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import sta_oracle as O
-        lv = O.levelize(d)
-        plan = O._Plan(d, lv)
-        c0 = time.perf_counter()
-        O.run(d, gamma=args.gamma, grad="tns", lv=lv, plan=plan)
-        ct = time.perf_counter() - c0
-        cpu = dict(value=round(P / ct, 1), unit="pins/s", cores=int(torch.get_num_threads()), kind="oracle",
+        host = cpu_host()
+        ct = time_oracle(d, args.gamma, 1)
+        cpu = dict(value=round(P / ct, 1), unit="pins/s", cores=1, kind="oracle",
                    sample=f"one full FP64 forward+backward+gradient of the same {P}-pin design "
-                          f"(levelization excluded), {ct:.1f} s")
+                          f"(levelization excluded) on one host thread, {ct:.1f} s", **host)
+        nt = min(16, host["usable_cpus"] or 1)
+        ctm = time_oracle(d, args.gamma, nt)
+        cpu["multithread"] = dict(value=round(P / ctm, 1), unit="pins/s", cores=nt, seconds=round(ctm, 2))
     return {
         "metric": "STA fwd+bwd pins/sec @2.5M pins",
         "value": round(value, 1),
@@ -736,6 +814,16 @@ def run_serve(args) -> dict:
         pp = float(sum(designs[int(which[r])].n_pins for r in range(n)))
         return {"slots": slots, "requests": n, "s": round(dt, 4), "pins_per_s": round(pp / dt, 1)}
 
+    if getattr(args, "served_samples", ""):
+        # every 100th result with what regenerates its inputs, for check_served on the host
+        rs = list(range(0, n_req, sample_every))
+        dx = [results[r][3][0] if grad[r] else np.zeros(0, np.float32) for r in rs]
+        dy = [results[r][3][1] if grad[r] else np.zeros(0, np.float32) for r in rs]
+        os.makedirs(os.path.dirname(os.path.abspath(args.served_samples)), exist_ok=True)
+        np.savez(args.served_samples, request=np.array(rs), design=which[rs], grad=grad[rs],
+                 jitter=np.array(rs) % n_jit, scalars=np.stack([results[r][2] for r in rs]),
+                 grad_offsets=np.cumsum([0] + [len(a) for a in dx]), dx=np.concatenate(dx), dy=np.concatenate(dy),
+                 latency_ms=np.array([results[r][0] for r in rs]) + lag[rs], gamma=10.0)
     cap_many = burst(args.serve_slots)
     cap_one = burst(1)
     lat = np.array([results[r][0] for r in range(n_req)]) + lag
@@ -795,6 +883,54 @@ def run_serve(args) -> dict:
     }
 
 
+def check_served(path: str, gamma: float = 10.0) -> dict:
+    """Checks served results saved by --served-samples against the FP64 oracle on the host:
+    the designs and jittered coordinates are regenerated from their seeds.  Scalars must meet
+    1e-4 relative (1e-3 ps absolute); gradient entries are counted against
+    1e-3 |g| + 1e-6 max|g| and at most 2e-4 of them may exceed it (the full-size parity
+    test's cap: values float32 cannot pin down in these extrapolated designs)."""
+    from gen.netlist import batch_designs, jitter
+    from oracle import sta_oracle as O
+    z = np.load(path)
+    designs = batch_designs(12, 5_000, 2_500_000, cfg_id=4)
+    out = []
+    t0 = time.perf_counter()
+    for i, r in enumerate(z["request"]):
+        k, gr = int(z["design"][i]), bool(z["grad"][i])
+        d = designs[k]
+        x, y = jitter(d, 2.0, stream=500 + int(z["jitter"][i])) if gr else (d.x, d.y)
+        c0 = time.perf_counter()
+        ref = O.run(d, x=x, y=y, gamma=gamma, grad="tns" if gr else None)
+        sc = z["scalars"][i]
+        errs = [abs(sc[j] - ref[n]) / (1e-4 * abs(ref[n]) + 1e-3) for j, n in enumerate(("wns", "tns", "wns_g", "tns_g"))]
+        rec = dict(request=int(r), design=k, pins=d.n_pins, grad=gr, scalar_worst_x_tol=round(max(errs), 4),
+                   oracle_s=round(time.perf_counter() - c0, 2))
+        ok = max(errs) <= 1.0
+        if gr:
+            o0, o1 = z["grad_offsets"][i], z["grad_offsets"][i + 1]
+            for name in ("dx", "dy"):
+                g = z[name][o0:o1].astype(np.float64)
+                ref_g = ref[name]
+                tol = 1e-3 * np.abs(ref_g) + 1e-6 * np.abs(ref_g).max()
+                n_out = int(np.count_nonzero(np.abs(g - ref_g) > tol))
+                norm = float(np.linalg.norm(g - ref_g) / max(np.linalg.norm(ref_g), 1e-300))
+                rec[name] = dict(outside=n_out, norm_rel=norm)
+                ok = ok and n_out <= 2e-4 * len(g)
+        rec["ok"] = bool(ok)
+        out.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    return {"checked": len(out), "ok": sum(r["ok"] for r in out), "designs": sorted({r["design"] for r in out}),
+            "largest_pins": max(r["pins"] for r in out), "grad_results": sum(r["grad"] for r in out),
+            "host_s": round(time.perf_counter() - t0, 1), "results": out}
+
+
+def part_of_line(res: dict) -> dict:
+    """A workload's result as a sub-object of the headline line."""
+    keep = ("metric", "value", "unit", "ms_per_step", "config", "plain_sequential", "serving", "roofline",
+            "cpu_baseline", "setup_s")
+    return {k: res[k] for k in keep if k in res and res[k] is not None}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -823,7 +959,16 @@ def main(argv=None) -> int:
                     help="cfg0-2: log2 of the smallest backward lane group (the schedule's sweep_group_log2)")
     ap.add_argument("--trees", action="store_true",
                     help="cfg0-2 with an RC tree per net (binary heaps by distance) instead of stars")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="cfg2: skip the batched and served parts of the metric")
+    ap.add_argument("--served-samples", default="",
+                    help="cfg4: save every 100th served result (request, inputs' seeds, outputs) to this .npz")
+    ap.add_argument("--check-served", default="",
+                    help="check a --served-samples file against the FP64 oracle on the host (no GPU)")
     args = ap.parse_args(argv)
+    if args.check_served:
+        print(json.dumps(check_served(args.check_served, args.gamma)), flush=True)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the STA sweep of one design runs on a single device "
               "(independent designs would be routed one per GPU); run with --gpus 1.", file=sys.stderr)
@@ -839,6 +984,18 @@ def main(argv=None) -> int:
     run = {"cfg3": run_batch, "cfg4": run_serve, "fusion": run_fusion, "rc": run_rc,
            "place": run_place}.get(args.workload, run_single)
     res = run(args)
+    if args.workload == "cfg2" and not args.headline_only and not args.trees:
+        # The rest of the metric: the batched form against plain calls, and the served form.
+        import gc
+        import torch
+        gc.collect()
+        torch.cuda.empty_cache()
+        res["batched"] = part_of_line(run_batch(argparse.Namespace(**{**vars(args), "lean": True,
+                                                                        "steps": max(5, args.steps // 2)})))
+        gc.collect()
+        torch.cuda.empty_cache()
+        res["served"] = part_of_line(run_serve(argparse.Namespace(**{**vars(args), "serve_seconds": min(
+            args.serve_seconds, 15.0)})))
     line = {"metric": res.pop("metric"), "value": res.pop("value"), "unit": res.pop("unit"), "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"),
             "higher_is_better": res.pop("higher_is_better", True), "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"),
