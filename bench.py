@@ -26,27 +26,30 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 
-def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict:
+def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None, snapshots: int = 1) -> dict:
     """Bytes each kernel family must move per step (float32 values, int32 indices).
 
     `level` is the net level of every net of d; the per-level lists are indexed by level
     (fwd_level: levels 1..L-1; bwd_level: levels L-1..0, the launch order), so the lists of
-    designs swept together in one batch add up element by element.
+    designs swept together in one batch add up element by element.  With `snapshots` S
+    placements of d swept together, topology is counted once and every per-placement value
+    S times.
 
     Counts only what the method reads and writes once; re-reads served by caches are not
-    counted.  Per unit:
-      rc         per net 4 sched + 4 offset + 8 driver x,y + 4 driver cap + 4 load write
-                 (+40 record write for level-0 nets); per sink 8 x,y + 4 cap + 8 wire write
-      fwd_level  per cell 16 (type, offset, arc base, load) + 40 record write; per cell
-                 input 9 (source net, pin, unateness) + 8 wire + 40 source record
-      ep_partial per endpoint 28 (pin, net, late AT 8, smoothed AT 8, wire delay 4) + 16
-                 (its smoothed slack and weights, kept for the seeds)
-      ep_seed    per endpoint 4 pin + 16 kept values + 32 (required-time and adjoint seeds)
-      bwd_level  per net 4 sched + 4 offset + 32 record + 8 driver x,y; per cell 16; per
-                 cell input 9 + 8 wire + 24 source slew/smoothed AT + 32 seed writes;
-                 per sink 16 RAT + 16 adjoint + 8 wire + 8 x,y + 4 cap; per pin 72 output
-                 writes (AT, slew, RAT, slack, dx, dy)
+    counted.  Per unit, as topology + per placement:
+      rc         per net 12 (sched, offset, driver cap) + 12 (driver x, y, load write), +40
+                 record write for level-0 nets; per sink 4 (cap) + 16 (x, y, wire write)
+      fwd_level  per cell 12 (type, offset, arc base) + 44 (load, record write); per cell
+                 input 9 (source net, pin, unateness) + 48 (wire, source record)
+      ep_partial per endpoint 8 (pin, net) + 36 (late AT 8, smoothed AT 8, wire delay 4, its
+                 smoothed slack and weights kept for the seeds 16)
+      ep_seed    per endpoint 4 (pin) + 48 (kept values, required-time and adjoint seeds)
+      bwd_level  per net 8 (sched, offset) + 40 (record, driver x, y); per cell 12 + 4 (load);
+                 per cell input 9 + 64 (wire, source slew and smoothed AT, seed writes); per
+                 sink 4 (cap) + 48 (RAT, adjoint, wire, x, y); per pin 72 output writes (AT,
+                 slew, RAT, slack, dx, dy)
     """
+    S = int(snapshots)
     N, P = d.n_nets, d.n_pins
     sinks = np.diff(d.net_offsets).astype(np.int64) - 1
     level = level.astype(np.int64)
@@ -65,12 +68,13 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None) -> dict
     E = int(np.count_nonzero((d.pin_kind == 3) | (d.pin_kind == 4)))
     n0 = int(nets_l[0])
     out = {}
-    out["rc"] = np.array([float(N * 24 + n0 * 40 + sinks.sum() * 20)])
-    out["fwd_level"] = np.array([float(cells_l[l] * 56 + ins_l[l] * 57) for l in range(1, L)])
-    out["ep_partial"] = np.array([float(E * 44)])
-    out["ep_seed"] = np.array([float(E * 52)])
-    out["bwd_level"] = np.array([float(nets_l[l] * 48 + cells_l[l] * 16 + ins_l[l] * 73 + sinks_l[l] * 52
-                                       + pins_l[l] * 72) for l in range(L - 1, -1, -1)])
+    out["rc"] = np.array([float(N * (12 + 12 * S) + n0 * 40 * S + sinks.sum() * (4 + 16 * S))])
+    out["fwd_level"] = np.array([float(cells_l[l] * (12 + 44 * S) + ins_l[l] * (9 + 48 * S)) for l in range(1, L)])
+    out["ep_partial"] = np.array([float(E * (8 + 36 * S))])
+    out["ep_seed"] = np.array([float(E * (4 + 48 * S))])
+    out["bwd_level"] = np.array([float(nets_l[l] * (8 + 40 * S) + cells_l[l] * (12 + 4 * S) + ins_l[l] * (9 + 64 * S)
+                                       + sinks_l[l] * (4 + 48 * S) + pins_l[l] * 72 * S)
+                                 for l in range(L - 1, -1, -1)])
     return out
 
 
@@ -274,9 +278,15 @@ def run_batch(args) -> dict:
     L1 = g1.levelize()
     perm1 = g1.levelization()["pin_perm"]
     g1.set_snapshots(64)
+    inner = args.snapshot_layout == "inner"
+    g1.set_snapshot_layout(inner)
     g1.upload()
-    x1 = torch.from_numpy(np.stack([sx[perm1] for sx, _ in snaps])).to(dev)
-    y1 = torch.from_numpy(np.stack([sy[perm1] for _, sy in snaps])).to(dev)
+    x1 = np.stack([sx[perm1] for sx, _ in snaps])
+    y1 = np.stack([sy[perm1] for _, sy in snaps])
+    if inner:                                   # snapshot innermost: [pin][snapshot]
+        x1, y1 = np.ascontiguousarray(x1.T), np.ascontiguousarray(y1.T)
+    x1 = torch.from_numpy(x1).to(dev)
+    y1 = torch.from_numpy(y1).to(dev)
     u16 = Graph.batch([Graph.from_design(d) for d in others])
     L16 = u16.levelize()
     u16.upload()
@@ -358,10 +368,10 @@ def run_batch(args) -> dict:
         torch.cuda.synchronize()
         prof = g1.profile_read()
         g1.profile(False)
-        alg = {k: 64 * v for k, v in algorithmic_bytes(d1, g1.levelization()["level"]).items()}
+        alg = algorithmic_bytes(d1, g1.levelization()["level"], snapshots=64)
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
-        roofline["traffic"] = counted_traffic("k_" + roofline["kernel"], "sta_batched_64snap_kernel_stats.md")
+        roofline["traffic"] = None
 
     cpu = None
     if not args.no_cpu_baseline and not getattr(args, "lean", False):
@@ -383,7 +393,8 @@ def run_batch(args) -> dict:
         "dtype": "f32",
         "config": {"workload": f"cfg3: 64 snapshots (sigma 5 um) of the {d1.n_pins}-pin design + 16 designs "
                                f"of 10k-400k pins; {P} pins, fwd+bwd with d TNS_g/dx,dy, gamma {args.gamma} ps; "
-                               f"snapshots share one graph ({L1} levels) on one stream, the 16 designs one batch "
+                               f"snapshots share one graph ({L1} levels, snapshot-{args.snapshot_layout} layout) on "
+                               f"one stream, the 16 designs one batch "
                                f"graph ({L16} levels) on another, "
                                + ("launched directly" if args.no_batch_capture else "both hipGraph-captured"),
                    "pins": P, "members": 80, "schedule_snapshots": best1, "schedule_designs": best16,
@@ -422,10 +433,10 @@ def snapshot_graph_only(args, g1, d1, x1, y1, dev, best1, t_setup) -> dict:
         torch.cuda.synchronize()
         prof = g1.profile_read()
         g1.profile(False)
-        alg = {k: 64 * v for k, v in algorithmic_bytes(d1, g1.levelization()["level"]).items()}
+        alg = algorithmic_bytes(d1, g1.levelization()["level"], snapshots=64)
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
-        roofline["traffic"] = counted_traffic("k_" + roofline["kernel"], "sta_batched_64snap_kernel_stats.md")
+        roofline["traffic"] = None
     P = 64 * d1.n_pins
     return {
         "metric": "STA fwd+bwd pins/sec, 64 placement snapshots in one sweep",
@@ -754,8 +765,16 @@ def run_serve(args) -> dict:
     which = rng.integers(len(designs), size=n_req)
     grad = rng.random(n_req) < 0.3
     t_setup = time.time() - t0
-    for i in ids:                                   # warm every design once
-        srv.wait(srv.submit(i, grad=True, x=jit[i][0][0], y=jit[i][0][1]))
+    # Warm every slot on every (design, kind, new or resident coordinates) it may serve, so
+    # that no capture falls in the timed window: a burst of `slots` requests of one key at a
+    # time occupies every slot.
+    for i in ids:
+        for g_ in (False, True):
+            tk = [srv.submit(i, grad=g_, x=jit[i][0][0] if g_ else None, y=jit[i][0][1] if g_ else None)
+                  for _ in range(args.serve_slots)]
+            for q in tk:
+                srv.wait(q)
+    warm = srv.stats()
     tickets = [None] * n_req
     lag = np.zeros(n_req)
     results = [None] * n_req
@@ -788,6 +807,8 @@ def run_serve(args) -> dict:
         lag[r] = (time.perf_counter() - due) * 1e3
     th.join()
     elapsed = time.perf_counter() - start
+    after = srv.stats()
+    captures_in_window = after["captures"] - warm["captures"]
     srv.close()
 
     def burst(slots: int, n: int = 400) -> dict:
@@ -815,15 +836,19 @@ def run_serve(args) -> dict:
         return {"slots": slots, "requests": n, "s": round(dt, 4), "pins_per_s": round(pp / dt, 1)}
 
     if getattr(args, "served_samples", ""):
-        # every 100th result with what regenerates its inputs, for check_served on the host
+        # Every 100th result with what regenerates its inputs, for check_served on the host:
+        # the scalars, and of a gradient result the entries of up to SAMPLE_PINS seeded pins.
         rs = list(range(0, n_req, sample_every))
-        dx = [results[r][3][0] if grad[r] else np.zeros(0, np.float32) for r in rs]
-        dy = [results[r][3][1] if grad[r] else np.zeros(0, np.float32) for r in rs]
+        picks = [served_sample_pins(designs[int(which[r])].n_pins, r) if grad[r] else np.zeros(0, np.int64)
+                 for r in rs]
+        dx = [results[r][3][0][pk] if grad[r] else np.zeros(0, np.float32) for r, pk in zip(rs, picks)]
+        dy = [results[r][3][1][pk] if grad[r] else np.zeros(0, np.float32) for r, pk in zip(rs, picks)]
         os.makedirs(os.path.dirname(os.path.abspath(args.served_samples)), exist_ok=True)
-        np.savez(args.served_samples, request=np.array(rs), design=which[rs], grad=grad[rs],
-                 jitter=np.array(rs) % n_jit, scalars=np.stack([results[r][2] for r in rs]),
-                 grad_offsets=np.cumsum([0] + [len(a) for a in dx]), dx=np.concatenate(dx), dy=np.concatenate(dy),
-                 latency_ms=np.array([results[r][0] for r in rs]) + lag[rs], gamma=10.0)
+        np.savez_compressed(args.served_samples, request=np.array(rs), design=which[rs], grad=grad[rs],
+                            jitter=np.array(rs) % n_jit, scalars=np.stack([results[r][2] for r in rs]),
+                            grad_offsets=np.cumsum([0] + [len(a) for a in dx]), pins=np.concatenate(picks),
+                            dx=np.concatenate(dx), dy=np.concatenate(dy),
+                            latency_ms=np.array([results[r][0] for r in rs]) + lag[rs], gamma=10.0)
     cap_many = burst(args.serve_slots)
     cap_one = burst(1)
     lat = np.array([results[r][0] for r in range(n_req)]) + lag
@@ -874,6 +899,7 @@ def run_serve(args) -> dict:
                     "fwd_p50_ms": round(float(np.percentile(lat[~grad], 50)), 4),
                     "fwd_bwd_p50_ms": round(float(np.percentile(lat[grad], 50)), 4) if grad.any() else None,
                     "achieved_req_per_s": round(n_req / elapsed, 2), "elapsed_s": round(elapsed, 3),
+                    "captures_warmup": warm["captures"], "captures_in_window": captures_in_window,
                     "capacity": cap_many, "capacity_one_at_a_time": cap_one,
                     "capacity_speedup": round(cap_many["pins_per_s"] / cap_one["pins_per_s"], 3),
                     "oracle_checked": checked},
@@ -883,10 +909,21 @@ def run_serve(args) -> dict:
     }
 
 
+SAMPLE_PINS = 20_000
+
+
+def served_sample_pins(n_pins: int, request: int) -> np.ndarray:
+    """The pins (original ids) whose gradient entries a served sample keeps: all of a small
+    design, else SAMPLE_PINS seeded by the request number."""
+    if n_pins <= SAMPLE_PINS:
+        return np.arange(n_pins)
+    return np.sort(np.random.default_rng([260328381, 4, 100, request]).choice(n_pins, SAMPLE_PINS, replace=False))
+
+
 def check_served(path: str, gamma: float = 10.0) -> dict:
     """Checks served results saved by --served-samples against the FP64 oracle on the host:
     the designs and jittered coordinates are regenerated from their seeds.  Scalars must meet
-    1e-4 relative (1e-3 ps absolute); gradient entries are counted against
+    1e-4 relative (1e-3 ps absolute); the sampled gradient entries are counted against
     1e-3 |g| + 1e-6 max|g| and at most 2e-4 of them may exceed it (the full-size parity
     test's cap: values float32 cannot pin down in these extrapolated designs)."""
     from gen.netlist import batch_designs, jitter
@@ -908,10 +945,11 @@ def check_served(path: str, gamma: float = 10.0) -> dict:
         ok = max(errs) <= 1.0
         if gr:
             o0, o1 = z["grad_offsets"][i], z["grad_offsets"][i + 1]
+            pk = z["pins"][o0:o1]
             for name in ("dx", "dy"):
                 g = z[name][o0:o1].astype(np.float64)
-                ref_g = ref[name]
-                tol = 1e-3 * np.abs(ref_g) + 1e-6 * np.abs(ref_g).max()
+                ref_g = ref[name][pk]
+                tol = 1e-3 * np.abs(ref_g) + 1e-6 * np.abs(ref[name]).max()
                 n_out = int(np.count_nonzero(np.abs(g - ref_g) > tol))
                 norm = float(np.linalg.norm(g - ref_g) / max(np.linalg.norm(ref_g), 1e-300))
                 rec[name] = dict(outside=n_out, norm_rel=norm)
@@ -945,6 +983,9 @@ def main(argv=None) -> int:
     ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")
     ap.add_argument("--no-batch-capture", action="store_true",
                     help="cfg3: launch the batched sweeps directly instead of replaying captured hipGraphs")
+    ap.add_argument("--snapshot-layout", default="inner", choices=["inner", "outer"],
+                    help="cfg3: the 64-snapshot graph with the snapshot innermost (lanes over snapshots) "
+                         "or outermost (each snapshot its own workgroups)")
     ap.add_argument("--snapshots-only", action="store_true",
                     help="cfg3: only the 64-snapshot graph, launched directly on the default stream")
     ap.add_argument("--no-ckpt-compare", dest="ckpt_compare", action="store_false",

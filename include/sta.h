@@ -261,6 +261,25 @@ sta_status sta_backward_noalloc(sta_graph* g, const float* x, const float* y, co
 sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
 
 /* ---------------------------------------------------------------------------------------
+ * Snapshot layout.  STA_SNAP_OUTER (default): per-call arrays hold the S snapshots back to
+ * back, as above, and each snapshot is swept by its own workgroups with the lane-group
+ * schedule.  STA_SNAP_INNER: every per-call array has the snapshot innermost - x, y
+ * [n_pins][S]; at, slew, rat, slack [n_pins][S][4]; atg [n_pins][S][2]; dx, dy [n_pins][S];
+ * scalars stay [S][n_designs][4] - and so does the opaque state and workspace; the lanes of
+ * a wave then take snapshots (one net or cell for 64 snapshots, or for S <= 32 several
+ * items of a power of two of lanes each), so topology and table reads serve every snapshot
+ * and each state access is one contiguous run.  Same results up to float summation order
+ * (a net's sinks and the endpoints are summed in index order per snapshot); the schedule
+ * does not apply and sta_tune leaves it unchanged.  Meant for S of 32 or more.
+ * Errors: STA_E_STATE if not levelized; STA_E_INVALID for an unknown layout, and for
+ * STA_SNAP_INNER with checkpointing on or RC trees (pin_parent); sta_forward / sta_backward
+ * return STA_E_INVALID when an array of all snapshots would reach 4 GiB.
+ * ------------------------------------------------------------------------------------- */
+#define STA_SNAP_OUTER 0
+#define STA_SNAP_INNER 1
+sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
+
+/* ---------------------------------------------------------------------------------------
  * Lane-group schedule.  Nets are served by lane groups sized from their sink count: the
  * level kernels use groups of (1 << sweep_group_log2) lanes and doublings up to a wave
  * (4 lanes at least: a backward cell step spreads 4 conditions x 4 arcs over 16 lanes, over
@@ -397,6 +416,17 @@ sta_status sta_wait(sta_server* s, uint64_t ticket, sta_result* r);
 sta_status sta_release(sta_server* s, uint64_t ticket);
 /* Waits for the requests on the device, drops queued ones and frees everything. */
 void sta_server_destroy(sta_server* s);
+
+/* Counters of a server since it was created.  A slot captures the launch sequence of each
+ * (design, kind, new-or-resident coordinates, gamma) it runs the first time, keeping at most
+ * 64 per slot (the oldest is dropped first); captures run outside the server's lock, so
+ * clients can submit and poll meanwhile. */
+typedef struct sta_server_stats {
+  int64_t completed;           /* requests finished successfully */
+  int64_t captures;            /* launch sequences captured into hipGraphs */
+  double capture_ms;           /* host time of the requests that captured, admission to enqueued */
+} sta_server_stats;
+sta_status sta_server_stats_get(sta_server* s, sta_server_stats* out);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel timing with HIP events (a profiling aid).  While enabled, each run of consecutive

@@ -183,6 +183,23 @@ void build_groups(sta_graph* g) {
   g->sched_all.assign(N, 0);
   for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
   g->all_range = group_range(cnt, 0, g->sched_cfg.flat_group_log2);
+  // Snapshot-inner layout: each level's nets of more than kSiHeavy sinks (a suffix of the
+  // level, whose nets ascend in pin count) and the list of all of them.
+  g->si_heavy.clear();
+  g->si_huge.clear();
+  g->si_hs.assign(g->L, 0);
+  g->si_us.assign(g->L, 0);
+  auto sinks = [&](int n) { return g->c_net_off[n + 1] - g->c_net_off[n] - 1; };
+  for (int l = 0; l < g->L; ++l) {
+    int u = g->level_off[l + 1];
+    while (u > g->level_off[l] && sinks(u - 1) > kSiHuge) --u;
+    int h = u;
+    while (h > g->level_off[l] && sinks(h - 1) > kSiHeavy) --h;
+    g->si_hs[l] = h;
+    g->si_us[l] = u;
+    for (int n = h; n < u; ++n) g->si_heavy.push_back(n);
+    for (int n = u; n < g->level_off[l + 1]; ++n) g->si_huge.push_back(n);
+  }
 }
 
 // Record slots and the cell inputs in a padded slot layout per level: input j of the k-th
@@ -780,6 +797,7 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   int k = stride_levels;
   if (k < 0) k = std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, g->L - 1))));
+  if (k > 0 && g->snap_inner) return fail(STA_E_INVALID, "checkpointing is not available with STA_SNAP_INNER");
   g->ckpt_stride = k;
   try {
     build_ell(g);
@@ -795,6 +813,19 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots) {
   if (!g) return fail(STA_E_INVALID, "graph is NULL");
   if (n_snapshots < 1 || n_snapshots > 65535) return fail(STA_E_INVALID, "snapshot count out of range");
   g->n_snap = n_snapshots;
+  drop_captured(g);
+  return STA_OK;
+}
+
+sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (layout != STA_SNAP_OUTER && layout != STA_SNAP_INNER) return fail(STA_E_INVALID, "unknown snapshot layout");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (layout == STA_SNAP_INNER && g->ckpt_stride > 0)
+    return fail(STA_E_INVALID, "STA_SNAP_INNER is not available with checkpointing");
+  if (layout == STA_SNAP_INNER && !g->c_parent.empty())
+    return fail(STA_E_INVALID, "STA_SNAP_INNER is not available for RC trees");
+  g->snap_inner = layout == STA_SNAP_INNER;
   drop_captured(g);
   return STA_OK;
 }
@@ -875,7 +906,8 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_rec)) || (s = up(d.pin_perm, g->pin_perm)) ||
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
-      (s = up(d.sched_all, g->sched_all)) || (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
+      (s = up(d.sched_all, g->sched_all)) || (s = up(d.si_heavy, g->si_heavy)) || (s = up(d.si_huge, g->si_huge)) ||
+      (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
       (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)) ||
                                 (s = up(d.tree_node, g->c_tree_node)) || (s = up(d.tree_blk_net, g->tree_blk_net)) ||
                                 (s = up(d.tree_blk_depth, g->tree_blk_depth)) || (s = up(d.tree_big, g->tree_big)))) ||

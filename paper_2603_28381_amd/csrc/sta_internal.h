@@ -19,6 +19,9 @@ constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
 constexpr int kFlatG0Default = 2;    // flat kernels (RC, outputs): smallest group 4 lanes
 constexpr int kSweepG0Default = 2;   // level kernels: smallest backward group 4 lanes (one per condition)
 constexpr int kTreeChunk = 1024;     // RC trees: pins of whole nets swept by one workgroup in LDS
+constexpr int kSiHeavy = 16;         // snapshot-inner layout: nets with more sinks take a whole
+                                     // 1024-thread workgroup for up to 64 snapshots,
+constexpr int kSiHuge = 128;         // nets with more than this a workgroup per 8 snapshots
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0
 // lanes: the smallest wave group (doubling from 1 << g0) in which every lane holds at most
@@ -93,6 +96,8 @@ struct DeviceGraph {
   int* tree_big = nullptr;        // RC trees only: nets over the chunk size
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
+  int* si_heavy = nullptr;     // snapshot-inner RC: canonical nets of kSiHeavy+1..kSiHuge sinks,
+  int* si_huge = nullptr;      // and of more than kSiHuge
   size_t bytes = 0;
 };
 
@@ -140,6 +145,13 @@ struct sta_graph {
   // seg_lo (levels [seg_lo[j], seg_lo[j+1])), and the endpoints' record slots.
   int ckpt_stride = 0, n_rec = 0, n_kept = 0;
   int n_snap = 1;                              // placement snapshots per call (shared topology)
+  bool snap_inner = false;                     // STA_SNAP_INNER: snapshot-innermost arrays, lanes
+                                               // over snapshots
+  std::vector<int> si_heavy, si_huge;          // canonical nets of kSiHeavy+1..kSiHuge sinks,
+                                               // and of more than kSiHuge
+  std::vector<int> si_hs, si_us;               // per level: its first net of more than kSiHeavy
+                                               // and of more than kSiHuge sinks (a level's nets
+                                               // ascend in pin count)
   std::vector<int> rec_loc, seg_lo, ep_rec;
   sta::StateLayout state{};
   sta::WorkLayout work{};

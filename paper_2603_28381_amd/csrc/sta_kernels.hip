@@ -1972,8 +1972,15 @@ sta_status check_ready(sta_graph* g) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != g->dev.device) return fail(STA_E_STATE, "graph lives on another device than the current one");
   // Snapshot offsets of the state reach the level kernels as 32-bit scalars.
-  if (g->n_snap > 1 && g->state.total > (size_t)INT32_MAX)
+  if (!g->snap_inner && g->n_snap > 1 && g->state.total > (size_t)INT32_MAX)
     return fail(STA_E_INVALID, "forward state of one snapshot exceeds 2 GiB; sweep fewer pins per snapshot");
+  // Snapshot-inner arrays are addressed through 32-bit byte offsets over all snapshots.
+  if (g->snap_inner) {
+    const uint64_t S = (uint64_t)g->n_snap, lim = 1ull << 32;
+    if (32ull * (uint64_t)g->P * S >= lim || 16ull * 4ull * (uint64_t)std::max(1, g->n_rec) * S >= lim ||
+        40ull * (uint64_t)std::max(1, g->n_ep_blocks) * S >= lim)
+      return fail(STA_E_INVALID, "with STA_SNAP_INNER an array of all snapshots reaches 4 GiB; sweep fewer");
+  }
   return STA_OK;
 }
 
@@ -2015,6 +2022,712 @@ struct LaunchTimer {
     ++g->run_count;
   }
 };
+
+// ============================================================================ snapshot lanes
+// The snapshot-inner layout (sta_set_snapshot_layout(g, STA_SNAP_INNER)): every per-call and
+// state array holds the S snapshots of an item side by side, element (i, s) at i*S + s (an
+// arrival record's chunk k of net slot r at (4r + k)*S + s; a sink's required times at
+// 2p*S + s and its adjoint at (2p + 1)*S + s).  The lanes of a wave then take snapshots: a
+// wave serves one net or cell for 64 snapshots (or 64 >> sl2 items of 1 << sl2 lanes each
+// when S <= 32), so the topology and tables it reads are the same for every lane of an item,
+// and every state load or store moves one contiguous run per item.  Sums over a net's sinks
+// and merges over a cell's arcs run inside each lane, in index order; nets of more than
+// kSiHeavy sinks take a whole kSiBlock workgroup whose threads split the sinks and meet in
+// LDS in thread order.
+constexpr int kSiBlock = 1024;
+constexpr int kSiWaves = kSiBlock / 64;
+
+struct SiLane {
+  int item;   // item of the lane counted from the launch's first (or, in a heavy workgroup,
+              // the thread's position among the threads of its snapshot)
+  int s;      // snapshot
+  bool on;    // s < S
+};
+
+__device__ __forceinline__ SiLane si_lane(int sl2, int S, int wave) {
+  const int lane = threadIdx.x & 63;
+  SiLane r;
+  r.item = (wave << (6 - sl2)) + (lane >> sl2);
+  r.s = (lane & ((1 << sl2) - 1)) + 64 * (int)blockIdx.y;
+  r.on = r.s < S;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t si_at(int i, uint32_t S, int s) { return (uint32_t)i * S + (uint32_t)s; }
+
+// Workgroups of heavy nets: each takes 1 << hl2 snapshots, so that 1024 >> hl2 threads split
+// the sinks of each snapshot; hl2 = sl2 for nets of up to kSiHuge sinks (a workgroup per net
+// and block of up to 64 snapshots) and min(sl2, 3) beyond (a workgroup per 8 snapshots).
+// Workgroup hb of a class serves net hb / nch of the class and snapshot chunk hb % nch.
+__device__ __forceinline__ int chunks_of(int S, int hl2) { return (S + (1 << hl2) - 1) >> hl2; }
+__device__ __forceinline__ SiLane si_heavy_lane(int hl2, int S, int chunk) {
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  SiLane r;
+  r.item = (w << (6 - hl2)) + (lane >> hl2);
+  r.s = chunk * (1 << hl2) + (lane & ((1 << hl2) - 1));
+  r.on = r.s < S;
+  return r;
+}
+
+// ---------------------------------------------------------------- RC net delay, snapshot lanes
+struct RcSiArgs {
+  const int* __restrict__ net_off;
+  const float* __restrict__ pin_cap;
+  const float* __restrict__ x;          // [pins][S], canonical order or through io_perm
+  const float* __restrict__ y;
+  const int* __restrict__ io_perm;
+  const int* __restrict__ heavy;        // nets of kSiHeavy+1..kSiHuge sinks
+  const int* __restrict__ huge;         // nets of more than kSiHuge sinks
+  float2* __restrict__ wire;            // [P][S]
+  float* __restrict__ load;             // [N][S]
+  float4* __restrict__ rec;             // [4 N][S]
+  int N, N0, S, sl2, n_heavy, n_huge;
+  float r, c, pi_at, pi_slew;
+};
+
+// Sink p of a star net in snapshot s: wire delay and impulse (Eq. 2-3) and its share of the
+// root load (Eq. 1), as rc_sink computes them.
+__device__ __forceinline__ float rc_sink_si(const RcSiArgs& a, int p, int s, float xd, float yd) {
+  const uint32_t S = (uint32_t)a.S;
+  const int q = a.io_perm ? ld(a.io_perm, (uint32_t)p) : p;
+  const float cp = ld(a.pin_cap, (uint32_t)p);
+  const float len = fabsf(ld(a.x, si_at(q, S, s)) - xd) + fabsf(ld(a.y, si_at(q, S, s)) - yd);
+  const float res = a.r * len;
+  const float cw = a.c * len;
+  const float cap = fmaf(0.5f, cw, cp);
+  const float dly = 1e-3f * res * cap;
+  const float arg = 2.0f * (1e-3f * res * cap) * dly - dly * dly;
+  const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
+  *at32(a.wire, si_at(p, S, s)) = make_float2(dly, imp);
+  return cp + cw;
+}
+
+__device__ __forceinline__ void rc_root_si(const RcSiArgs& a, int n, int p0, int s, float sum) {
+  const uint32_t S = (uint32_t)a.S;
+  *at32(a.load, si_at(n, S, s)) = ld(a.pin_cap, (uint32_t)p0) + sum;
+  *at32(a.wire, si_at(p0, S, s)) = make_float2(0.f, 0.f);
+  if (n < a.N0) {
+#pragma unroll
+    for (int k = 0; k < kRecChunks; ++k)
+      *at32(a.rec, si_at(kRecChunks * n + k, S, s)) = make_float4(a.pi_at, a.pi_slew, k >= 2 ? a.pi_at : 0.f, 0.f);
+  }
+}
+
+__device__ __forceinline__ void driver_xy_si(const float* __restrict__ x, const float* __restrict__ y,
+                                             const int* __restrict__ io, int p0, uint32_t S, int s, float& xd,
+                                             float& yd) {
+  const int q = io ? ld(io, (uint32_t)p0) : p0;
+  xd = ld(x, si_at(q, S, s));
+  yd = ld(y, si_at(q, S, s));
+}
+
+// The RC of heavy net n for the snapshots of one workgroup (threads split the sinks).
+__device__ __forceinline__ void rc_heavy_si(const RcSiArgs& a, int n, const SiLane& ln, int hl2, float* sh) {
+  const uint32_t S = (uint32_t)a.S;
+  const int lanes = 1 << hl2;
+  const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
+  float sum = 0.f;
+  if (ln.on) {
+    float xd, yd;
+    driver_xy_si(a.x, a.y, a.io_perm, p0, S, ln.s, xd, yd);
+    for (int p = p0 + 1 + ln.item; p < p1; p += kSiBlock / lanes) sum += rc_sink_si(a, p, ln.s, xd, yd);
+  }
+  sh[threadIdx.x] = sum;
+  __syncthreads();
+  if ((int)threadIdx.x < lanes && ln.on) {
+    float tot = 0.f;
+    for (int t = (int)threadIdx.x; t < kSiBlock; t += lanes) tot += sh[t];
+    rc_root_si(a, n, p0, ln.s, tot);
+  }
+}
+
+// RC of every net: huge and heavy nets first (workgroups per net and snapshot chunk), then
+// (64 >> sl2) nets per wave.
+__global__ __launch_bounds__(kSiBlock) void k_rc_si(RcSiArgs a) {
+  __shared__ float sh[kSiBlock];
+  const int w = (int)(threadIdx.x >> 6);
+  const int b = (int)blockIdx.x;
+  const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
+  const int nbu = a.n_huge * nchu, nbh = a.n_heavy * nchh;
+  if (b < nbu + nbh) {
+    if (blockIdx.y != 0) return;               // these workgroups cover their snapshots along x
+    if (b < nbu)
+      rc_heavy_si(a, ld(a.huge, (uint32_t)(b / nchu)), si_heavy_lane(hl2u, a.S, b % nchu), hl2u, sh);
+    else
+      rc_heavy_si(a, ld(a.heavy, (uint32_t)((b - nbu) / nchh)), si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2,
+                  sh);
+    return;
+  }
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiWaves + w);
+  const int n = ln.item;
+  if (n >= a.N || !ln.on) return;
+  const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
+  if (p1 - p0 - 1 > kSiHeavy) return;          // a heavy workgroup's net
+  const uint32_t S = (uint32_t)a.S;
+  float xd, yd;
+  driver_xy_si(a.x, a.y, a.io_perm, p0, S, ln.s, xd, yd);
+  float sum = 0.f;
+  for (int p = p0 + 1; p < p1; ++p) sum += rc_sink_si(a, p, ln.s, xd, yd);
+  rc_root_si(a, n, p0, ln.s, sum);
+}
+
+// ---------------------------------------------------------------- forward level, snapshot lanes
+struct FwdSiArgs {
+  const int4* __restrict__ ell;
+  const float* __restrict__ load;
+  const float2* __restrict__ wire;
+  float4* __restrict__ rec;
+  const float4* __restrict__ grid;
+  const float4* __restrict__ coef;
+  LutKeys keys;
+  float gamma, inv_gamma;
+  int smooth, S, sl2;
+};
+
+// Chunk of a source record in the input transition of output transition t (unateness
+// `same`: positive unate keeps the transition) for mode m, from the two chunks of that mode.
+__device__ __forceinline__ float4 pick_tr(bool same, int t, const float4& c_r, const float4& c_f) {
+  return (same == (t == 0)) ? c_r : c_f;
+}
+
+// One forward level (Sec. 3.1.2): each lane takes one cell of one snapshot and merges its
+// arcs in registers, condition by condition, as k_fwd_level_narrow with one lane per
+// condition does: max / min arrival, worst slew, log-sum-exp of the late candidates (Eq. 4).
+__global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int base, int F, FwdSiArgs a) {
+  const SiLane ln = si_lane(a.sl2, a.S, (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  const int kc = ln.item;
+  if (kc >= nc || !ln.on) return;
+  const uint32_t S = (uint32_t)a.S;
+  const int s = ln.s, n = n0 + kc;
+  const float load = ld(a.load, si_at(n, S, s));
+  float bat[4], bsl[4], lm[2] = {-kInf, -kInf}, ls[2] = {0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bat[k] = bsl[k] = k >= 2 ? -kInf : kInf;
+  for (int j0 = 0; j0 < F; j0 += kArcLanes) {
+    int4 e[kArcLanes];
+    bool valid[kArcLanes];
+    float2 w[kArcLanes];
+#pragma unroll
+    for (int i = 0; i < kArcLanes; ++i) {
+      const int j = j0 + i;
+      e[i] = ld(a.ell, (uint32_t)(base + min(j, F - 1) * nc + kc));
+      valid[i] = j < F && e[i].x >= 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kArcLanes; ++i) w[i] = ld(a.wire, si_at(e[i].y, S, s));
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      float4 cr[kArcLanes], cf[kArcLanes];
+#pragma unroll
+      for (int i = 0; i < kArcLanes; ++i) {
+        const int src = kRecChunks * max(e[i].x, 0) + 2 * m;
+        cr[i] = ld(a.rec, si_at(src, S, s));
+        cf[i] = ld(a.rec, si_at(src + 1, S, s));
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int k = 2 * m + t;
+        const float neutral = m ? -kInf : kInf;
+        float cm = neutral, sm = neutral, gm = -kInf, g[kArcLanes];
+#pragma unroll
+        for (int i = 0; i < kArcLanes; ++i) {
+          const float4 ci = pick_tr(e[i].w > 0, t, cr[i], cf[i]);
+          const float sl_in = sink_slew(ci.y, w[i].y);
+          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, e[i].z, t, sl_in, load);
+          const float cand = valid[i] ? (ci.x + w[i].x) + v.d : neutral;
+          const float sv = valid[i] ? v.s : neutral;
+          g[i] = valid[i] ? (ci.z + w[i].x) + v.d : -kInf;
+          if (m) {
+            cm = fmaxf(cm, cand);
+            sm = fmaxf(sm, sv);
+            gm = fmaxf(gm, g[i]);
+          } else {
+            cm = fminf(cm, cand);
+            sm = fminf(sm, sv);
+          }
+        }
+        if (m) {
+          bat[k] = fmaxf(bat[k], cm);
+          bsl[k] = fmaxf(bsl[k], sm);
+          if (a.smooth) {
+            float gs = 0.f;
+#pragma unroll
+            for (int i = 0; i < kArcLanes; ++i) gs += valid[i] ? fexp((g[i] - gm) * a.inv_gamma) : 0.f;
+            lse_merge(lm[t], ls[t], gm, gs, a.inv_gamma);
+          }
+        } else {
+          bat[k] = fminf(bat[k], cm);
+          bsl[k] = fminf(bsl[k], sm);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int m = k >> 1, t = k & 1;
+    const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls[t]), lm[t]) : __builtin_nanf("")) : 0.f;
+    *at32(a.rec, si_at(kRecChunks * n + k, S, s)) = make_float4(bat[k], bsl[k], ag, 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- endpoints, snapshot lanes
+struct EpSiArgs {
+  const int* __restrict__ ep_pin;
+  const int* __restrict__ ep_net;
+  const int* __restrict__ ep_design;
+  const int* __restrict__ ep_design_off;
+  const int* __restrict__ ep_blk_off;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
+  double* part;        // [blocks * 5][S]
+  double* fin;         // [designs * 8][S]
+  double* scalars;     // [S][designs][4] or NULL
+  float4* sink;        // [2 P][S]
+  float4* epv;         // [E][S]
+  const double* scale_dev;
+  int E, n_designs, S, sl2, seed_adj, smooth, wns_mode;
+  float rat_late, hold, gamma, inv_gamma, scale;
+};
+
+__device__ __forceinline__ EpVals endpoint_values_si(const EpSiArgs& a, int i, int s) {
+  const uint32_t S = (uint32_t)a.S;
+  const int e = ld(a.ep_pin, (uint32_t)i), r = ld(a.ep_net, (uint32_t)i);
+  const float4 c2 = ld(a.rec, si_at(kRecChunks * r + 2, S, s));   // late rise
+  const float4 c3 = ld(a.rec, si_at(kRecChunks * r + 3, S, s));   // late fall
+  const float dl = ld(a.wire, si_at(e, S, s)).x;
+  EpVals v;
+  v.worst = fminf(a.rat_late - (c2.x + dl), a.rat_late - (c3.x + dl));
+  const float u0 = -(a.rat_late - (c2.z + dl));
+  const float u1 = -(a.rat_late - (c3.z + dl));
+  const float mx = fmaxf(u0, u1);
+  const float e0 = expf((u0 - mx) * a.inv_gamma), e1 = expf((u1 - mx) * a.inv_gamma);
+  const float z = e0 + e1;
+  v.sg = -(mx + a.gamma * logf(z));
+  v.w0 = e0 / z;
+  v.w1 = e1 / z;
+  return v;
+}
+
+// Merges (m2, s2) into the shifted sum of exponentials (m, s): sum exp((v - m) / gamma).
+__device__ __forceinline__ void lse_merge_d(double& m, double& s, double m2, double s2, double g) {
+  if (s2 <= 0.0) return;
+  if (s <= 0.0) {
+    m = m2;
+    s = s2;
+  } else if (m2 > m) {
+    s = s * exp((m - m2) / g) + s2;
+    m = m2;
+  } else {
+    s += s2 * exp((m2 - m) / g);
+  }
+}
+
+// Per-block partials of each snapshot over the block's endpoints (the blocks of k_ep_partials),
+// in float64: each thread sums its endpoints in order, then the threads of a snapshot meet in
+// LDS in thread order.
+__global__ __launch_bounds__(kBlock) void k_ep_partials_si(EpSiArgs a) {
+  __shared__ double sh[5 * kBlock];
+  const uint32_t S = (uint32_t)a.S;
+  int dsg = 0;
+  while (dsg + 1 < a.n_designs && (int)blockIdx.x >= a.ep_blk_off[dsg + 1]) ++dsg;
+  const int i0 = a.ep_design_off[dsg] + ((int)blockIdx.x - a.ep_blk_off[dsg]) * kBlock;
+  const int i1 = min(i0 + kBlock, a.ep_design_off[dsg + 1]);
+  const SiLane ln = si_lane(a.sl2, a.S, (int)(threadIdx.x >> 6));
+  double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, m = 0.0, sm = 0.0;
+  if (ln.on) {
+    for (int i = i0 + ln.item; i < i1; i += kBlock >> a.sl2) {
+      const EpVals ev = endpoint_values_si(a, i, ln.s);
+      *at32(a.epv, si_at(i, S, ln.s)) = make_float4(ev.sg, ev.w0, ev.w1, 0.f);
+      tns += fmin(0.0, (double)ev.worst);
+      wmin = fmin(wmin, (double)ev.worst);
+      const double sg = ev.sg, g = a.gamma;
+      tnsg += -(fmax(0.0, -sg) + g * log1p(exp(-fabs(sg) / g)));
+      lse_merge_d(m, sm, -sg, 1.0, g);
+    }
+  }
+  const int t = (int)threadIdx.x;
+  sh[t] = tns;
+  sh[kBlock + t] = wmin;
+  sh[2 * kBlock + t] = tnsg;
+  sh[3 * kBlock + t] = m;
+  sh[4 * kBlock + t] = sm;
+  __syncthreads();
+  if (t < (1 << a.sl2) && ln.on) {
+    double r0 = 0.0, r1 = __builtin_huge_val(), r2 = 0.0, r3 = 0.0, r4 = 0.0;
+    for (int u = t; u < kBlock; u += 1 << a.sl2) {
+      r0 += sh[u];
+      r1 = fmin(r1, sh[kBlock + u]);
+      r2 += sh[2 * kBlock + u];
+      lse_merge_d(r3, r4, sh[3 * kBlock + u], sh[4 * kBlock + u], (double)a.gamma);
+    }
+    double* p = a.part;
+    const int b = (int)blockIdx.x;
+    p[si_at(5 * b + 0, S, ln.s)] = r0;
+    p[si_at(5 * b + 1, S, ln.s)] = r1;
+    p[si_at(5 * b + 2, S, ln.s)] = r2;
+    p[si_at(5 * b + 3, S, ln.s)] = r4 > 0.0 ? r3 : -__builtin_huge_val();
+    p[si_at(5 * b + 4, S, ln.s)] = r4;
+  }
+}
+
+// Scalars of design blockIdx.x in snapshot blockIdx.y, from its partial blocks (fixed order:
+// threads over blocks, then block_reduce), as k_ep_finalize.
+__global__ __launch_bounds__(kBlock) void k_ep_finalize_si(EpSiArgs a) {
+  __shared__ double sh[kBlock];
+  const uint32_t S = (uint32_t)a.S;
+  const int dsg = blockIdx.x, s = blockIdx.y;
+  const int b0 = a.ep_blk_off[dsg], b1 = a.ep_blk_off[dsg + 1];
+  const double g = a.gamma;
+  double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, mx = -__builtin_huge_val();
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
+    tns += a.part[si_at(5 * b + 0, S, s)];
+    wmin = fmin(wmin, a.part[si_at(5 * b + 1, S, s)]);
+    tnsg += a.part[si_at(5 * b + 2, S, s)];
+    mx = fmax(mx, a.part[si_at(5 * b + 3, S, s)]);
+  }
+  double r4[4] = {tns, -wmin, tnsg, mx};
+  block_reduce<4>(r4, {false, true, false, true}, sh);
+  const double M = fmax(0.0, r4[3]);   // {0} joins the WNS_g set
+  double tot = 0.0;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += kBlock) {
+    const double p4 = a.part[si_at(5 * b + 4, S, s)];
+    if (p4 > 0.0) tot += p4 * exp((a.part[si_at(5 * b + 3, S, s)] - M) / g);
+  }
+  double r1[1] = {tot};
+  block_reduce<1>(r1, {false}, sh);
+  if (threadIdx.x == 0) {
+    const double lse_all = M + g * log(r1[0] + exp(-M / g));
+    const double nan = __builtin_nan("");
+    const double v[5] = {fmin(0.0, -r4[1]), r4[0], a.smooth ? -lse_all : nan, a.smooth ? r4[2] : nan, lse_all};
+    for (int q = 0; q < 5; ++q) a.fin[si_at(8 * dsg + q, S, s)] = v[q];
+    if (a.scalars) {
+      for (int q = 0; q < 4; ++q) a.scalars[((size_t)s * a.n_designs + dsg) * 4 + q] = v[q];
+    }
+  }
+}
+
+// Backward seeds of every (endpoint, snapshot), as k_ep_seed.
+__global__ __launch_bounds__(kBlock) void k_ep_seed_si(EpSiArgs a) {
+  const SiLane ln = si_lane(a.sl2, a.S, (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  const int i = ln.item;
+  if (i >= a.E || !ln.on) return;
+  const uint32_t S = (uint32_t)a.S;
+  const int s = ln.s;
+  const int e = ld(a.ep_pin, (uint32_t)i);
+  *at32(a.sink, si_at(2 * e, S, s)) = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
+  if (a.seed_adj) {
+    const float4 q = ld(a.epv, si_at(i, S, s));
+    float coef;
+    if (a.wns_mode) {
+      const double lse_all = a.fin[si_at(8 * ld(a.ep_design, (uint32_t)i) + 4, S, s)];
+      coef = (float)exp((-(double)q.x - lse_all) / (double)a.gamma);
+    } else {
+      coef = 1.0f / (1.0f + expf(q.x * a.inv_gamma));
+    }
+    const float sc = a.scale_dev ? a.scale * (float)a.scale_dev[0] : a.scale;
+    *at32(a.sink, si_at(2 * e + 1, S, s)) = make_float4(-sc * coef * q.y, -sc * coef * q.z, 0.f, 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- per-pin forward outputs
+struct ExpandSiArgs {
+  const int* __restrict__ net_off;
+  const int* __restrict__ io_perm;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
+  float4* at;
+  float4* slew;
+  float2* atg;
+  int N, S, sl2;
+};
+
+__global__ __launch_bounds__(kBlock) void k_expand_si(ExpandSiArgs a) {
+  const SiLane ln = si_lane(a.sl2, a.S, (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+  const int n = ln.item;
+  if (n >= a.N || !ln.on) return;
+  const uint32_t S = (uint32_t)a.S;
+  const int s = ln.s;
+  const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
+  float4 c[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = ld(a.rec, si_at(kRecChunks * n + k, S, s));
+  for (int p = p0; p < p1; ++p) {
+    const float2 w = ld(a.wire, si_at(p, S, s));
+    const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
+    if (a.at) store_stream(at32(a.at, o), make_float4(c[0].x + w.x, c[1].x + w.x, c[2].x + w.x, c[3].x + w.x));
+    if (a.slew)
+      store_stream(at32(a.slew, o), make_float4(sink_slew(c[0].y, w.y), sink_slew(c[1].y, w.y),
+                                                sink_slew(c[2].y, w.y), sink_slew(c[3].y, w.y)));
+    if (a.atg) store_stream(at32(a.atg, o), make_float2(c[2].z + w.x, c[3].z + w.x));
+  }
+}
+
+// ---------------------------------------------------------------- backward level, snapshot lanes
+struct BwdSiArgs {
+  const int* __restrict__ net_off;
+  const float* __restrict__ pin_cap;
+  const int4* __restrict__ ell;
+  const int* __restrict__ io_perm;
+  const float* __restrict__ x;
+  const float* __restrict__ y;
+  const float4* __restrict__ grid;
+  const float4* __restrict__ coef;
+  LutKeys keys;
+  const float4* __restrict__ rec;
+  const float2* __restrict__ wire;
+  const float* __restrict__ load;
+  float4* __restrict__ sink;   // a net's sinks are read, other nets' input pins written
+  float4* __restrict__ at_out;
+  float4* __restrict__ slew_out;
+  float4* __restrict__ rat_out;
+  float4* __restrict__ slack_out;
+  float* __restrict__ dx;
+  float* __restrict__ dy;
+  int N0, S, sl2;
+  float r, c, inv_gamma;
+};
+
+struct SinkSi {
+  float gx, gy, rest;
+  uint32_t o;   // the pin's element in the caller's per-pin arrays
+};
+
+// Sink p of snapshot s in the net step (as sink_step): per-pin outputs when `write`, and its
+// contribution to the driver's reductions.
+template <bool kGrad>
+__device__ __forceinline__ SinkSi sink_si(const BwdSiArgs& a, int p, int s, const float4& at_d, const float4& sl_d,
+                                          float xd, float yd, float (&acc)[N_ACC], bool write) {
+  const uint32_t S = (uint32_t)a.S;
+  const float4 rt = ld(a.sink, si_at(2 * p, S, s));
+  const float2 w = ld(a.wire, si_at(p, S, s));
+  const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
+  const float4 ats = make_float4(at_d.x + w.x, at_d.y + w.x, at_d.z + w.x, at_d.w + w.x);
+  const float4 sls = make_float4(sink_slew(sl_d.x, w.y), sink_slew(sl_d.y, w.y), sink_slew(sl_d.z, w.y),
+                                 sink_slew(sl_d.w, w.y));
+  if (write) {
+    if (a.at_out) store_stream(at32(a.at_out, o), ats);
+    if (a.slew_out) store_stream(at32(a.slew_out, o), sls);
+    if (a.rat_out) store_stream(at32(a.rat_out, o), rt);
+    if (a.slack_out)
+      store_stream(at32(a.slack_out, o), make_float4(ats.x - rt.x, ats.y - rt.y, rt.z - ats.z, rt.w - ats.w));
+  }
+  acc[R_E0] = fmaxf(acc[R_E0], rt.x - w.x);
+  acc[R_E1] = fmaxf(acc[R_E1], rt.y - w.x);
+  acc[R_L0] = fminf(acc[R_L0], rt.z - w.x);
+  acc[R_L1] = fminf(acc[R_L1], rt.w - w.x);
+  SinkSi k{0.f, 0.f, 0.f, o};
+  if (kGrad) {
+    const float4 aj = ld(a.sink, si_at(2 * p + 1, S, s));
+    const float xs = ld(a.x, o), ys = ld(a.y, o), cp = ld(a.pin_cap, (uint32_t)p);
+    const float q0 = sls.z > 0.f ? aj.z * frcp(sls.z) : 0.f;
+    const float q1 = sls.w > 0.f ? aj.w * frcp(sls.w) : 0.f;
+    acc[A_R] += aj.x;
+    acc[A_F] += aj.y;
+    acc[S_R] += q0 * sl_d.z;
+    acc[S_F] += q1 * sl_d.w;
+    const float dbar = aj.x + aj.y;
+    const float ibar = (q0 + q1) * w.y;
+    const float len = fabsf(xs - xd) + fabsf(ys - yd);
+    k.rest = (dbar + ibar) * (1e-3f * a.r * fmaf(a.c, len, cp));
+    k.gx = sgnf(xs - xd);
+    k.gy = sgnf(ys - yd);
+    acc[X_RS] += k.gx * k.rest;
+    acc[X_N] += k.gx;
+    acc[Y_RS] += k.gy * k.rest;
+    acc[Y_N] += k.gy;
+  }
+  return k;
+}
+
+__device__ __forceinline__ void set_comp(float4& v, int i, float x) {
+  v.x = i == 0 ? x : v.x;
+  v.y = i == 1 ? x : v.y;
+  v.z = i == 2 ? x : v.z;
+  v.w = i == 3 ? x : v.w;
+}
+
+// Cell step of cell kc in snapshot s (as the 4-lane backward group's, in one lane): the
+// inputs' required times, and with the gradient the softmax split of the driver's adjoint
+// over the arcs (normaliser and arg-max slew taken chunk by chunk of 4 arcs), the slew
+// adjoint and the load adjoint, which it returns.
+template <bool kGrad>
+__device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& sl, int kc, int s, float load,
+                                              const float (&acc)[N_ACC]) {
+  const uint32_t S = (uint32_t)a.S;
+  float xmax[2] = {-kInf, -kInf}, z[2] = {0.f, 0.f}, smax[2] = {-kInf, -kInf};
+  int jstar[2] = {STA_MAX_FANIN, STA_MAX_FANIN};
+  if (kGrad) {
+    for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        float xg[kArcLanes], cm = -kInf, cz = 0.f, s2 = -kInf;
+        int j2 = STA_MAX_FANIN;
+        bool valid[kArcLanes];
+#pragma unroll
+        for (int i = 0; i < kArcLanes; ++i) {
+          const int j = j0 + i;
+          const int4 e = ld(a.ell, (uint32_t)(sl.base + min(j, sl.F - 1) * sl.nc + kc));
+          valid[i] = j < sl.F && e.x >= 0;
+          const int src = kRecChunks * max(e.x, 0) + 2;
+          const float4 ci = pick_tr(e.w > 0, t, ld(a.rec, si_at(src, S, s)), ld(a.rec, si_at(src + 1, S, s)));
+          const float2 w = ld(a.wire, si_at(e.y, S, s));
+          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, e.z, t, sink_slew(ci.y, w.y), load);
+          xg[i] = valid[i] ? (ci.z + w.x) + v.d : -kInf;
+          cm = fmaxf(cm, xg[i]);
+          const bool take = valid[i] && (j2 == STA_MAX_FANIN || v.s > s2);
+          s2 = take ? v.s : s2;
+          j2 = take ? j : j2;
+        }
+#pragma unroll
+        for (int i = 0; i < kArcLanes; ++i) cz += valid[i] ? fexp((xg[i] - cm) * a.inv_gamma) : 0.f;
+        if (j0 == 0) {
+          xmax[t] = cm;
+          z[t] = cz;
+          smax[t] = s2;
+          jstar[t] = j2;
+        } else {
+          lse_merge(xmax[t], z[t], cm, cz, a.inv_gamma);
+          if (s2 > smax[t]) {
+            smax[t] = s2;
+            jstar[t] = j2;
+          }
+        }
+      }
+    }
+  }
+  const float rat_o[4] = {acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]};
+  const float abar[2] = {acc[A_R], acc[A_F]}, sbar[2] = {acc[S_R], acc[S_F]};
+  const float inv_z[2] = {kGrad ? frcp(z[0]) : 0.f, kGrad ? frcp(z[1]) : 0.f};
+  float lb[2] = {0.f, 0.f};
+#pragma unroll 2
+  for (int j = 0; j < sl.F; ++j) {
+    const int4 e = ld(a.ell, (uint32_t)(sl.base + j * sl.nc + kc));
+    if (e.x < 0) continue;
+    const bool same = e.w > 0;
+    const float2 w = ld(a.wire, si_at(e.y, S, s));
+    float4 c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] = ld(a.rec, si_at(kRecChunks * e.x + q, S, s));
+    float4 rat_in = make_float4(0.f, 0.f, 0.f, 0.f), adj_in = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int m = k >> 1, t = k & 1;
+      const int tp = same ? t : 1 - t;
+      const float4 ci = pick_tr(same, t, c[2 * m], c[2 * m + 1]);
+      const LutVal v = lut_eval<kGrad>(a.grid, a.coef, a.keys, e.z, t, sink_slew(ci.y, w.y), load);
+      set_comp(rat_in, 2 * m + tp, rat_o[k] - v.d);
+      if (kGrad && m == 1) {
+        const float xg = (ci.z + w.x) + v.d;
+        const float dbar = fexp((xg - xmax[t]) * a.inv_gamma) * inv_z[t] * abar[t];
+        const float s_j = j == jstar[t] ? sbar[t] : 0.f;
+        set_comp(adj_in, tp, dbar);
+        set_comp(adj_in, 2 + tp, fmaf(dbar, v.ddx, s_j * v.dsx));
+        lb[t] = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb[t]));
+      }
+    }
+    *at32(a.sink, si_at(2 * e.y, S, s)) = rat_in;
+    if (kGrad) *at32(a.sink, si_at(2 * e.y + 1, S, s)) = adj_in;
+  }
+  return lb[0] + lb[1];
+}
+
+// Backward work of net n for the lane's snapshot (the three phases of bwd_net).  In a heavy
+// workgroup (kHeavy) the 1024 >> hl2 threads of a snapshot split the sinks and their
+// reductions meet in LDS in thread order; the first thread of each snapshot then runs the
+// cell step.
+template <bool kGrad, bool kHeavy>
+__device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, int n, const SiLane& ln, int hl2,
+                                           float* sh) {
+  const uint32_t S = (uint32_t)a.S;
+  const int s = ln.on ? ln.s : 0;
+  const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
+  float4 c[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c[k] = ld(a.rec, si_at(kRecChunks * n + k, S, s));
+  const float4 at_d = make_float4(c[0].x, c[1].x, c[2].x, c[3].x);
+  const float4 sl_d = make_float4(c[0].y, c[1].y, c[2].y, c[3].y);
+  float xd = 0.f, yd = 0.f;
+  if (kGrad && ln.on) driver_xy_si(a.x, a.y, a.io_perm, p0, S, s, xd, yd);
+  float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int lanes = 1 << hl2;                   // heavy workgroups: snapshots per workgroup
+  const int first = kHeavy ? ln.item : 0;
+  const int stride = kHeavy ? kSiBlock / lanes : 1;
+  if (ln.on) {
+#pragma unroll 4
+    for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
+  }
+  const bool leader = !kHeavy || (int)threadIdx.x < lanes;
+  if (kHeavy) {
+#pragma unroll
+    for (int i = 0; i < N_ACC; ++i) sh[i * kSiBlock + threadIdx.x] = acc[i];
+    __syncthreads();
+    if (leader) {
+      for (int u = (int)threadIdx.x + lanes; u < kSiBlock; u += lanes) {
+        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kSiBlock + u]);
+        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kSiBlock + u]);
+        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kSiBlock + u]);
+        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kSiBlock + u]);
+#pragma unroll
+        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kSiBlock + u];
+      }
+    }
+  }
+  float lbar = 0.f;
+  if (leader && ln.on) {
+    if (n >= a.N0) lbar = cell_step_si<kGrad>(a, sl, n - a.N0 - sl.c0, s, ld(a.load, si_at(n, S, s)), acc);
+    const uint32_t o0 = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p0) : p0, S, s);
+    if (a.at_out) store_stream(at32(a.at_out, o0), at_d);
+    if (a.slew_out) store_stream(at32(a.slew_out, o0), sl_d);
+    if (a.rat_out) store_stream(at32(a.rat_out, o0), make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]));
+    if (a.slack_out)
+      store_stream(at32(a.slack_out, o0),
+                   make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w));
+    if (kGrad) {
+      const float cl = a.c * lbar;
+      if (a.dx) *at32(a.dx, o0) = -(acc[X_RS] + cl * acc[X_N]);
+      if (a.dy) *at32(a.dy, o0) = -(acc[Y_RS] + cl * acc[Y_N]);
+    }
+  }
+  if (kHeavy) {
+    if (leader) sh[N_ACC * kSiBlock + threadIdx.x] = lbar;
+    __syncthreads();
+    lbar = sh[N_ACC * kSiBlock + (threadIdx.x & (unsigned)(lanes - 1))];
+  }
+  // Elmore adjoint of every sink (the sinks are read again).
+  if (kGrad && ln.on && (a.dx || a.dy)) {
+    const float cl = a.c * lbar;
+#pragma unroll 4
+    for (int p = p0 + 1 + first; p < p1; p += stride) {
+      float scratch[N_ACC] = {};
+      const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, scratch, false);
+      if (a.dx) *at32(a.dx, k.o) = k.gx * (cl + k.rest);
+      if (a.dy) *at32(a.dy, k.o) = k.gy * (cl + k.rest);
+    }
+  }
+}
+
+// One backward level: the level's huge nets [nu0, ne) and heavy nets [nh0, nu0) first, a
+// workgroup per net and snapshot chunk, then the nets [nb, nh0), (64 >> sl2) per wave.
+template <bool kGrad>
+__global__ __launch_bounds__(kSiBlock) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
+  __shared__ float sh[N_ACC * kSiBlock + kSiBlock];
+  const int w = (int)(threadIdx.x >> 6);
+  const int b = (int)blockIdx.x;
+  const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
+  const int nbu = (ne - nu0) * nchu, nbh = (nu0 - nh0) * nchh;
+  if (b < nbu + nbh) {
+    if (blockIdx.y != 0) return;               // these workgroups cover their snapshots along x
+    if (b < nbu)
+      bwd_net_si<kGrad, true>(a, sl, nu0 + b / nchu, si_heavy_lane(hl2u, a.S, b % nchu), hl2u, sh);
+    else
+      bwd_net_si<kGrad, true>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
+    return;
+  }
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiWaves + w);
+  const int n = nb + ln.item;
+  if (n >= nh0 || !ln.on) return;
+  bwd_net_si<kGrad, false>(a, sl, n, ln, a.sl2, sh);
+}
 
 }  // namespace
 }  // namespace sta
@@ -2075,8 +2788,134 @@ void fwd_level_launch(const sta_graph* g, hipStream_t s, const Slots& sl, int mi
   }
 }
 
+// ---------------------------------------------------------------- snapshot-inner launches
+struct SiDims {
+  int S, sl2;
+  unsigned gy;   // blocks of 64 snapshots (sl2 = 6) along y
+  int hch, uch;  // workgroups per heavy and per huge net (chunks_of)
+};
+
+SiDims si_dims(const sta_graph* g) {
+  const int S = g->n_snap;
+  int sl2 = 0;
+  while ((1 << sl2) < S && sl2 < 6) ++sl2;
+  const int hw = 1 << sl2, uw = 1 << std::min(sl2, 3);
+  return SiDims{S, sl2, (unsigned)(sl2 == 6 ? (S + 63) / 64 : 1), (S + hw - 1) / hw, (S + uw - 1) / uw};
+}
+
+// Workgroups of `waves` waves covering `items` items at 64 >> sl2 items per wave.
+unsigned si_blocks(int items, int sl2, int waves) {
+  const int per = waves << (6 - sl2);
+  return (unsigned)((items + per - 1) / per);
+}
+
+EpSiArgs ep_si_args(const sta_graph* g, char* sb, double* scalars, float4* sink, const double* scale_dev, int seed_adj,
+                    int smooth, int wns_mode, float gamma, float scale) {
+  const DeviceGraph& d = g->dev;
+  const SiDims D = si_dims(g);
+  const size_t S = (size_t)D.S;
+  return EpSiArgs{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off,
+                  reinterpret_cast<float4*>(sb + S * g->state.rec), reinterpret_cast<float2*>(sb + S * g->state.wire),
+                  reinterpret_cast<double*>(sb + S * g->state.part), reinterpret_cast<double*>(sb + S * g->state.fin),
+                  scalars, sink, reinterpret_cast<float4*>(sb + S * g->state.epv), scale_dev, g->E, g->n_designs, D.S,
+                  D.sl2, seed_adj, smooth, wns_mode, g->cons.t_clk - g->cons.setup, g->cons.hold, gamma,
+                  1.0f / gamma, scale};
+}
+
+sta_status launch_forward_si(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
+                             float gamma_ps, hipStream_t s) {
+  const bool smooth = (flags & STA_SMOOTH) != 0;
+  const DeviceGraph& d = g->dev;
+  const SiDims D = si_dims(g);
+  const size_t S = (size_t)D.S;
+  char* sb = static_cast<char*>(out->state);
+  float4* rec = reinterpret_cast<float4*>(sb + S * g->state.rec);
+  float2* wire = reinterpret_cast<float2*>(sb + S * g->state.wire);
+  float* load = reinterpret_cast<float*>(sb + S * g->state.load);
+  const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
+  {
+    LaunchTimer t(g, s, STA_K_RC);
+    const int nh = (int)g->si_heavy.size(), nu = (int)g->si_huge.size();
+    const RcSiArgs ra{d.net_off, d.pin_cap, x, y, io, d.si_heavy, d.si_huge, wire, load, rec, g->N, g->N0, D.S, D.sl2,
+                      nh, nu, g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew};
+    k_rc_si<<<dim3((unsigned)(nh * D.hch + nu * D.uch) + si_blocks(g->N, D.sl2, kSiWaves), D.gy), kSiBlock, 0,
+              s>>>(ra);
+  }
+  const FwdSiArgs fa{d.ell, load, wire, rec, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps,
+                     smooth ? 1.0f / gamma_ps : 0.f, smooth ? 1 : 0, D.S, D.sl2};
+  for (int l = 1; l < g->L; ++l) {
+    const Slots sl = level_slots(g, l);
+    if (sl.nc == 0) continue;
+    LaunchTimer t(g, s, STA_K_FWD_LEVEL);
+    k_fwd_level_si<<<dim3(si_blocks(sl.nc, D.sl2, kWavesPerBlock), D.gy), kBlock, 0, s>>>(sl.nc, g->N0 + sl.c0,
+                                                                                            sl.base, sl.F, fa);
+  }
+  const EpSiArgs ea = ep_si_args(g, sb, out->scalars, nullptr, nullptr, 0, smooth ? 1 : 0, 0, smooth ? gamma_ps : 1.0f,
+                                 1.0f);
+  if (g->n_ep_blocks > 0) {
+    LaunchTimer t(g, s, STA_K_EP_PARTIAL);
+    k_ep_partials_si<<<dim3(g->n_ep_blocks, D.gy), kBlock, 0, s>>>(ea);
+  }
+  {
+    LaunchTimer t(g, s, STA_K_EP_FINAL);
+    k_ep_finalize_si<<<dim3(g->n_designs, D.S), kBlock, 0, s>>>(ea);
+  }
+  if (out->at || out->slew || out->atg) {
+    const ExpandSiArgs xa{d.net_off, io, rec, wire, reinterpret_cast<float4*>(out->at),
+                          reinterpret_cast<float4*>(out->slew), reinterpret_cast<float2*>(out->atg), g->N, D.S, D.sl2};
+    LaunchTimer t(g, s, STA_K_EXPAND);
+    k_expand_si<<<dim3(si_blocks(g->N, D.sl2, kWavesPerBlock), D.gy), kBlock, 0, s>>>(xa);
+  }
+  if (g->profiling) end_run(g, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return STA_OK;
+}
+
+sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
+                              const sta_bwd_out* out, uint32_t flags, float gamma_ps, hipStream_t s) {
+  const bool grad = (flags & STA_GRAD) != 0;
+  const DeviceGraph& d = g->dev;
+  const SiDims D = si_dims(g);
+  const size_t S = (size_t)D.S;
+  char* sb = static_cast<char*>(fwd->state);
+  char* wb = static_cast<char*>(out->workspace);
+  float4* sink = reinterpret_cast<float4*>(wb + S * g->work.sink);
+  const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
+  const EpSiArgs ea = ep_si_args(g, sb, nullptr, sink, out->grad_scale_dev, grad ? 1 : 0, 1,
+                                 (flags & STA_GRAD_WNS) ? 1 : 0, grad ? gamma_ps : 1.0f, out->grad_scale);
+  if (g->E > 0) {
+    LaunchTimer t(g, s, STA_K_EP_SEED);
+    k_ep_seed_si<<<dim3(si_blocks(g->E, D.sl2, kWavesPerBlock), D.gy), kBlock, 0, s>>>(ea);
+  }
+  const BwdSiArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
+                     reinterpret_cast<const float4*>(sb + S * g->state.rec),
+                     reinterpret_cast<const float2*>(sb + S * g->state.wire),
+                     reinterpret_cast<const float*>(sb + S * g->state.load), sink,
+                     reinterpret_cast<float4*>(out->at), reinterpret_cast<float4*>(out->slew),
+                     reinterpret_cast<float4*>(out->rat), reinterpret_cast<float4*>(out->slack), out->dx, out->dy,
+                     g->N0, D.S, D.sl2, g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f};
+  for (int l = g->L - 1; l >= 0; --l) {
+    const int lo = g->level_off[l], hi = g->level_off[l + 1], hs = g->si_hs[l], us = g->si_us[l];
+    if (hi == lo) continue;
+    const unsigned blocks =
+        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kSiWaves);
+    LaunchTimer t(g, s, STA_K_BWD_LEVEL);
+    const Slots sl = level_slots(g, l);
+    if (grad)
+      k_bwd_level_si<true><<<dim3(blocks, D.gy), kSiBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
+    else
+      k_bwd_level_si<false><<<dim3(blocks, D.gy), kSiBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
+  }
+  if (g->profiling) end_run(g, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return STA_OK;
+}
+
 sta_status launch_forward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
                           float gamma_ps, hipStream_t s) {
+  if (g->snap_inner) return launch_forward_si(g, x, y, out, flags, gamma_ps, s);
   const bool smooth = (flags & STA_SMOOTH) != 0;
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(out->state);
@@ -2143,6 +2982,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
 
 sta_status launch_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                            const sta_bwd_out* out, uint32_t flags, float gamma_ps, hipStream_t s) {
+  if (g->snap_inner) return launch_backward_si(g, x, y, fwd, out, flags, gamma_ps, s);
   const bool grad = (flags & STA_GRAD) != 0;
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(fwd->state);
@@ -2422,6 +3262,10 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   if (st != STA_OK) return st;
   if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
   if (!(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  if (g->snap_inner) {         // the snapshot-lane kernels take no schedule
+    if (best) *best = g->sched_cfg;
+    return STA_OK;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t P = (size_t)g->P;
   const size_t S = (size_t)g->n_snap;

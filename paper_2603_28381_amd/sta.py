@@ -27,12 +27,13 @@ STA_GRAD_WNS = 1 << 4
 STA_GRAPH = 1 << 5
 STA_REQ_FWD, STA_REQ_FWD_BWD = 0, 1
 STA_RC_GROUPS, STA_RC_CTE, STA_RC_THREAD = 0, 1, 2
+STA_SNAP_OUTER, STA_SNAP_INNER = 0, 1
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
             "sta_forward", "sta_backward", "sta_backward_noalloc", "sta_get_schedule", "sta_set_schedule", "sta_tune",
-            "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_server_create", "sta_server_add_design",
-            "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy",
+            "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_set_snapshot_layout", "sta_server_create", "sta_server_add_design",
+            "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy", "sta_server_stats_get",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
@@ -88,6 +89,10 @@ class StaResult(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_pins", ctypes.c_int32), ("scalars", ctypes.c_double * 4),
                 ("dx", ctypes.POINTER(ctypes.c_float)), ("dy", ctypes.POINTER(ctypes.c_float)),
                 ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class StaServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("captures", ctypes.c_int64), ("capture_ms", ctypes.c_double)]
 
 
 class StaFwdOut(ctypes.Structure):
@@ -149,6 +154,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_tune.restype = S
     lib.sta_set_snapshots.argtypes = [_P, ctypes.c_int32]
     lib.sta_set_snapshots.restype = S
+    lib.sta_set_snapshot_layout.argtypes = [_P, ctypes.c_int32]
+    lib.sta_set_snapshot_layout.restype = S
     lib.sta_set_checkpointing.argtypes = [_P, ctypes.c_int32]
     lib.sta_set_checkpointing.restype = S
     lib.sta_get_checkpointing.argtypes = [_P, _I32P, _I32P, _I32P]
@@ -166,6 +173,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_release.restype = S
     lib.sta_server_destroy.argtypes = [_P]
     lib.sta_server_destroy.restype = None
+    lib.sta_server_stats_get.argtypes = [_P, ctypes.POINTER(StaServerStats)]
+    lib.sta_server_stats_get.restype = S
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_enable.restype = S
     lib.sta_profile_read.argtypes = [_P, _P, _P]
@@ -347,6 +356,20 @@ class Graph:
         snapshot dimension)."""
         _check(_lib.sta_set_snapshots(self._h, int(n)))
 
+    def set_snapshot_layout(self, inner: bool):
+        """inner: every per-call array has the snapshot innermost ([pins][S]...), and the
+        lanes of a wave take snapshots (STA_SNAP_INNER); else snapshots outermost."""
+        _check(_lib.sta_set_snapshot_layout(self._h, STA_SNAP_INNER if inner else STA_SNAP_OUTER))
+        self._inner = bool(inner)
+
+    def _pin_shape(self, S: int, *tail) -> tuple:
+        """Shape of a per-pin array of one call: [P, *tail], with the snapshots outermost or
+        (snapshot-inner layout) right after the pin."""
+        P = self.n_pins
+        if S <= 1:
+            return (P,) + tail
+        return (P, S) + tail if getattr(self, "_inner", False) else (S, P) + tail
+
     def set_checkpointing(self, stride_levels: int = -1):
         """Per-level checkpointing of the arrival state: 0 off, < 0 picks ceil(sqrt(L-1))."""
         _check(_lib.sta_set_checkpointing(self._h, int(stride_levels)))
@@ -379,7 +402,7 @@ class Graph:
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
         inf = self.info()
-        P, S, nd = self.n_pins, inf["n_snapshots"], inf["n_designs"]
+        S, nd = inf["n_snapshots"], inf["n_designs"]
         lead = (S,) if S > 1 else ()
         state = self.new_state(dev) if state is None else state
         if scalars is None:
@@ -388,9 +411,9 @@ class Graph:
         if out is not None:
             at, slew, atg = out.get("at"), out.get("slew"), out.get("atg")
         elif pins:
-            at = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
-            slew = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
-            atg = torch.empty(lead + (P, 2), dtype=torch.float32, device=dev) if smooth else None
+            at = torch.empty(self._pin_shape(S, 4), dtype=torch.float32, device=dev)
+            slew = torch.empty(self._pin_shape(S, 4), dtype=torch.float32, device=dev)
+            atg = torch.empty(self._pin_shape(S, 2), dtype=torch.float32, device=dev) if smooth else None
         fo = StaFwdOut(_ptr(state), _ptr(at), _ptr(slew), _ptr(atg), _ptr(scalars))
         flags = ((STA_SMOOTH if smooth else 0) | (STA_CANONICAL_IO if canonical else 0)
                  | (STA_GRAPH if capture else 0))
@@ -407,8 +430,7 @@ class Graph:
         dev = fwd.state.device
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)
-        P, S = self.n_pins, self.info()["n_snapshots"]
-        lead = (S,) if S > 1 else ()
+        S = self.info()["n_snapshots"]
         if noalloc and (workspace is not None or capture):
             raise ValueError("noalloc takes neither a workspace nor capture")
         ws = None if noalloc else (self.new_workspace(dev) if workspace is None else workspace)
@@ -416,13 +438,13 @@ class Graph:
             out = {}
             if pins:
                 for k in ("at", "slew"):
-                    out[k] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
+                    out[k] = torch.empty(self._pin_shape(S, 4), dtype=torch.float32, device=dev)
             if rat:
-                out["rat"] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
-                out["slack"] = torch.empty(lead + (P, 4), dtype=torch.float32, device=dev)
+                out["rat"] = torch.empty(self._pin_shape(S, 4), dtype=torch.float32, device=dev)
+                out["slack"] = torch.empty(self._pin_shape(S, 4), dtype=torch.float32, device=dev)
             if grad:
-                out["dx"] = torch.empty(lead + (P,), dtype=torch.float32, device=dev)
-                out["dy"] = torch.empty(lead + (P,), dtype=torch.float32, device=dev)
+                out["dx"] = torch.empty(self._pin_shape(S), dtype=torch.float32, device=dev)
+                out["dy"] = torch.empty(self._pin_shape(S), dtype=torch.float32, device=dev)
         bo = StaBwdOut(_ptr(ws), _ptr(out.get("at")), _ptr(out.get("slew")), _ptr(out.get("rat")),
                        _ptr(out.get("slack")), _ptr(out.get("dx")), _ptr(out.get("dy")), float(grad_scale),
                        _ptr(grad_scale_dev))
@@ -494,6 +516,11 @@ class Server:
 
     def release(self, ticket: int):
         _check(_lib.sta_release(self._h, ctypes.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        st = StaServerStats()
+        _check(_lib.sta_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in StaServerStats._fields_}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
