@@ -88,6 +88,9 @@ struct Ticket {
 // A slot runs one request at a time on its own stream, in a device buffer it keeps between
 // requests, with the launch sequence of each (design, kind, coordinates) captured once into
 // a hipGraph over that buffer and replayed afterwards.
+using GraphKey = std::tuple<int, int, int, uint32_t>;   // (design, kind, new x/y, gamma bits)
+constexpr size_t kMaxSlotGraphs = 64;   // captured sequences kept per slot; the oldest goes first
+
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
@@ -95,7 +98,18 @@ struct Slot {
   bool busy = false;
   void* buf = nullptr;          // from the server's pool
   size_t cap = 0;
-  std::map<std::tuple<int, int, int, uint32_t>, hipGraphExec_t> graphs;   // (design, kind, new x/y, gamma)
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  std::deque<GraphKey> graph_order;   // capture order, for eviction
+};
+
+// What issuing a request needs, copied out of the ticket and the design table so that the
+// scheduler can capture and enqueue without holding the server's lock.
+struct Issue {
+  int design, kind;
+  float gamma;
+  const float *hx, *hy;
+  float *hdx, *hdy;
+  double* hsc;
 };
 
 // Where a request's buffers sit inside its slot's buffer.
@@ -126,6 +140,7 @@ struct sta_server {
   bool stop = false;
   std::thread worker;
   PinnedPool pinned;
+  sta_server_stats stats{};
 
   size_t request_bytes(const Design& d, int kind, bool new_xy) const {
     size_t b = align256(d.state_bytes) + align256(4 * sizeof(double));
@@ -166,6 +181,7 @@ struct sta_server {
   void drop_graphs(Slot& sl) {
     for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
     sl.graphs.clear();
+    sl.graph_order.clear();
   }
 
   // Picks an idle slot for a request of `need` bytes and makes its buffer large enough,
@@ -211,27 +227,28 @@ struct sta_server {
     return grow;
   }
 
-  // The captured launch sequence of (design, kind, coordinates) over slot k's buffer.
-  sta_status graph_for(Slot& sl, const Ticket& t, hipGraphExec_t* out) {
+  // The captured launch sequence of (design, kind, coordinates, gamma) over the slot's
+  // buffer, captured on first use.  Called by the scheduler thread without the lock: the
+  // slot is marked busy, so nothing else touches it, and the design is a copy.
+  sta_status graph_for(Slot& sl, const Design& d, const Issue& q, hipGraphExec_t* out, int* captured) {
     uint32_t gb;
-    std::memcpy(&gb, &t.gamma, sizeof(gb));
-    const auto key = std::make_tuple(t.design, t.kind, t.hx ? 1 : 0, gb);
+    std::memcpy(&gb, &q.gamma, sizeof(gb));
+    const GraphKey key = std::make_tuple(q.design, q.kind, q.hx ? 1 : 0, gb);
     auto it = sl.graphs.find(key);
     if (it != sl.graphs.end()) {
       *out = it->second;
       return STA_OK;
     }
-    const Design& d = designs[t.design];
-    const Carve c = carve(sl.buf, d, t.kind, t.hx != nullptr);
-    const float* x = t.hx ? c.x : d.x;
-    const float* y = t.hx ? c.y : d.y;
+    const Carve c = carve(sl.buf, d, q.kind, q.hx != nullptr);
+    const float* x = q.hx ? c.x : d.x;
+    const float* y = q.hx ? c.y : d.y;
     hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     sta_fwd_out fo{c.state, nullptr, nullptr, nullptr, c.sc};
-    sta_status st = sta_forward(d.g, x, y, &fo, STA_SMOOTH, t.gamma, cap_stream);
-    if (st == STA_OK && t.kind == STA_REQ_FWD_BWD) {
+    sta_status st = sta_forward(d.g, x, y, &fo, STA_SMOOTH, q.gamma, cap_stream);
+    if (st == STA_OK && q.kind == STA_REQ_FWD_BWD) {
       sta_bwd_out bo{c.ws, nullptr, nullptr, nullptr, nullptr, c.dx, c.dy, 1.0f, nullptr};
-      st = sta_backward(d.g, x, y, &fo, &bo, STA_GRAD, t.gamma, cap_stream);
+      st = sta_backward(d.g, x, y, &fo, &bo, STA_GRAD, q.gamma, cap_stream);
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap_stream, &graph);
@@ -244,39 +261,42 @@ struct sta_server {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (sl.graphs.size() >= kMaxSlotGraphs) {      // bounded cache: evict the oldest capture
+      auto old = sl.graphs.find(sl.graph_order.front());
+      (void)hipGraphExecDestroy(old->second);
+      sl.graphs.erase(old);
+      sl.graph_order.pop_front();
+    }
     sl.graphs.emplace(key, exec);
+    sl.graph_order.push_back(key);
     *out = exec;
+    *captured = 1;
     return STA_OK;
   }
 
-  // Issues a request on slot k: coordinates in, the captured sweeps, results out.  Called
-  // with mu held.
-  sta_status launch(uint64_t id, Ticket& t, int k) {
-    Slot& sl = slots[k];
-    const Design& d = designs[t.design];
-    const Carve c = carve(sl.buf, d, t.kind, t.hx != nullptr);
+  // Issues a request on slot sl: coordinates in, the captured sweeps, results out.  Runs
+  // on the scheduler thread without the lock (see graph_for).
+  sta_status issue(Slot& sl, const Design& d, const Issue& q, int* captured) {
+    const Carve c = carve(sl.buf, d, q.kind, q.hx != nullptr);
     const size_t fb = sizeof(float) * (size_t)d.P;
     hipError_t e;
     hipGraphExec_t exec = nullptr;
-    sta_status st = graph_for(sl, t, &exec);
+    sta_status st = graph_for(sl, d, q, &exec, captured);
     if (st != STA_OK) return st;
-    if (t.hx) {
-      if ((e = hipMemcpyAsync(c.x, t.hx, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(c.y, t.hy, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess)
+    if (q.hx) {
+      if ((e = hipMemcpyAsync(c.x, q.hx, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess ||
+          (e = hipMemcpyAsync(c.y, q.hy, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     }
     if ((e = hipGraphLaunch(exec, sl.s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    if (t.kind == STA_REQ_FWD_BWD) {
-      if ((e = hipMemcpyAsync(t.hdx, c.dx, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(t.hdy, c.dy, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+    if (q.kind == STA_REQ_FWD_BWD) {
+      if ((e = hipMemcpyAsync(q.hdx, c.dx, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
+          (e = hipMemcpyAsync(q.hdy, c.dy, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     }
-    if ((e = hipMemcpyAsync(t.hsc, c.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(q.hsc, c.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
       return hip_fail(e, "hipMemcpyAsync");
     if ((e = hipEventRecord(sl.done, sl.s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    sl.busy = true;
-    sl.ticket = id;
-    t.slot = k;
     return STA_OK;
   }
 
@@ -305,6 +325,7 @@ struct sta_server {
         Ticket& t = tickets[sl.ticket];
         if (e == hipSuccess) {
           finish(t, kDone);
+          ++stats.completed;
         } else {
           t.err = hip_fail(e, "request execution");
           t.msg = sta_last_error();
@@ -331,11 +352,28 @@ struct sta_server {
         queue.pop_front();
         t.t_admit = Clock::now();
         t.st = kRunning;
-        sta_status st = launch(id, t, k);
+        t.slot = k;
+        Slot& sl = slots[k];
+        sl.busy = true;
+        sl.ticket = id;
+        const Issue q{t.design, t.kind, t.gamma, t.hx, t.hy, t.hdx, t.hdy, t.hsc};
+        const Design d = designs[t.design];
+        // Capture (first use of a key on this slot) and enqueue without the lock, so that
+        // clients can submit and poll meanwhile.
+        int captured = 0;
+        const auto c0 = Clock::now();
+        lk.unlock();
+        sta_status st = issue(sl, d, q, &captured);
+        std::string msg = st == STA_OK ? std::string() : std::string(sta_last_error());
+        lk.lock();
+        stats.captures += captured;
+        if (captured) stats.capture_ms += ms_between(c0, Clock::now());
         if (st != STA_OK) {
-          t.err = st;
-          t.msg = sta_last_error();
-          finish(t, kFailed);
+          Ticket& tf = tickets[id];
+          tf.err = st;
+          tf.msg = msg;
+          finish(tf, kFailed);
+          sl.busy = false;
           finished.notify_all();
           continue;
         }
@@ -529,6 +567,13 @@ static sta_status fill_result(sta_server* s, uint64_t ticket, sta_result* r) {
     r->queue_ms = ms_between(t.t_submit, t.t_admit);
     r->latency_ms = ms_between(t.t_submit, t.t_done);
   }
+  return STA_OK;
+}
+
+sta_status sta_server_stats_get(sta_server* s, sta_server_stats* out) {
+  if (!s || !out) return fail(STA_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
   return STA_OK;
 }
 
