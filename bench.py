@@ -371,7 +371,8 @@ def run_batch(args) -> dict:
         alg = algorithmic_bytes(d1, g1.levelization()["level"], snapshots=64)
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
-        roofline["traffic"] = None
+        roofline["traffic"] = (counted_traffic("k_bwd_level_si", "sta_snapshot_lanes_64snap_kernel_stats.md")
+                               if inner and roofline["kernel"] == "bwd_level" else None)
 
     cpu = None
     if not args.no_cpu_baseline and not getattr(args, "lean", False):
@@ -679,28 +680,38 @@ def run_rc(args) -> dict:
             g.backward(x, y, f, rat=True, grad=True, workspace=ws, out=outs)
 
         r = {"pins": P, "rc_alg_bytes": float(np.sum(alg["rc"]))}
-        for scheme in ("groups", "cte", "thread"):
-            g.set_schedule(2, 2, 64, scheme)
+        # RC stage as lane groups, task pool or one thread per net (level kernels in lane
+        # groups), and one thread per net and cell in every stage ("thread_all")
+        for scheme, level in (("groups", "groups"), ("cte", "groups"), ("thread", "groups"),
+                              ("thread_all", "thread")):
+            g.set_schedule(2, 2, 64, "thread" if scheme == "thread_all" else scheme, 16, level)
             ms = timed(step, args.steps, args.warmup)[0]
             g.profile(True)
             for _ in range(args.steps):
                 step()
             torch.cuda.synchronize()
-            n_rc, t_rc = g.profile_read()["rc"]
+            prof = g.profile_read()
+            n_rc, t_rc = prof["rc"]
             g.profile(False)
             us = 1e3 * t_rc / n_rc
             r[scheme] = {"rc_us": round(us, 2), "rc_gbs": round(r["rc_alg_bytes"] / (us * 1e-6) / 1e9, 1),
+                         "fwd_level_us": round(1e3 * prof["fwd_level"][1] / max(1, prof["fwd_level"][0]), 2),
+                         "bwd_level_us": round(1e3 * prof["bwd_level"][1] / max(1, prof["bwd_level"][0]), 2),
                          "step_ms": round(ms, 4)}
+        g.set_schedule(2, 2, 64, "groups", 16, "groups")
         r["groups_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["groups"]["rc_us"], 2)
         r["cte_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["cte"]["rc_us"], 2)
+        r["step_speedup_vs_thread_all"] = {k: round(r["thread_all"]["step_ms"] / r[k]["step_ms"], 3)
+                                           for k in ("groups", "cte", "thread")}
         res[name] = r
         del state, ws, outs, g
         torch.cuda.empty_cache()
     c2 = res["cfg2"]
     return {"metric": "RC net delay kernel speedup of lane groups over one thread per net", "value":
             c2["groups_speedup_vs_thread"], "unit": "x", "ms_per_step": c2["groups"]["step_ms"], "dtype": "f32",
-            "config": {"workload": "RC mapping ablation: lane groups (pin-based), CTE task pool, one thread per net; "
-                                   "800k-pin and 2.5M-pin designs", "io": "canonical order, HBM resident"},
+            "config": {"workload": "mapping ablation: RC stage as lane groups (pin-based), CTE task pool or one "
+                                   "thread per net, and one thread per net and cell in every stage; 800k-pin and "
+                                   "2.5M-pin designs", "io": "canonical order, HBM resident"},
             "variants": res,
             "paper": "Table 2 (RTX 4090, whole STA): pin-based 236% and CTE 124% of GPU-Timer's speed"}
 

@@ -292,8 +292,12 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
  * is the number of lanes per cell in the forward level kernel: 16 (one per condition and
  * arc, merged across lanes), 8 (two per condition, two arcs each) or 4 (one per condition,
  * each lane looking up all of the cell's arcs): fewer lanes launch fewer waves, which pays
- * when many snapshots fill the chip, while one design's short levels favour 16.  Defaults
- * {2, 2, 64, STA_RC_GROUPS, 16}.
+ * when many snapshots fill the chip, while one design's short levels favour 16.
+ * level_scheme STA_LEVEL_THREAD runs the whole sweep with one thread per net and per cell
+ * (the snapshot-lane kernels with one lane per item; other fields then do not apply); it
+ * needs one snapshot, no checkpointing and star nets (else STA_E_INVALID, and
+ * sta_set_checkpointing refuses a stride while it is set).  Defaults
+ * {2, 2, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS}.
  * Setting a schedule rebuilds the launch plan (no result changes beyond float summation
  * order).  Errors: STA_E_INVALID for out-of-range fields,
  * STA_E_STATE if not levelized.
@@ -302,12 +306,18 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
 #define STA_RC_CTE 1      /* workgroup task pool (Alg. 2) */
 #define STA_RC_THREAD 2   /* one thread per net */
 
+#define STA_LEVEL_GROUPS 0   /* level kernels: lane groups per net, 4-16 lanes per cell */
+#define STA_LEVEL_THREAD 1   /* one thread per net and per cell in every stage (RC, levels,
+                                endpoints), the mapping of earlier GPU timers; one snapshot,
+                                no checkpointing, star nets */
+
 typedef struct sta_schedule {
   int32_t sweep_group_log2;   /* 2..6 */
   int32_t flat_group_log2;    /* 2..6 */
   int32_t heavy_sinks;        /* 1..64 */
   int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */
   int32_t fwd_cell_lanes;     /* 16, 8 or 4 */
+  int32_t level_scheme;       /* STA_LEVEL_GROUPS or STA_LEVEL_THREAD */
 } sta_schedule;
 
 sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);
@@ -318,7 +328,8 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
  * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Candidates:
  * sweep_group_log2 2..6 x flat_group_log2 2..4 x heavy_sinks {32, 64} with lane-group RC
  * and 16 forward lanes, then on the best of those the CTE and thread RC mappings, then 8
- * and 4 forward lanes.  Allocates
+ * and 4 forward lanes, then (one snapshot, no checkpointing, star nets) one thread per net
+ * in every stage.  Allocates
  * and frees its own device buffers; synchronizes the stream.  Errors: as sta_forward. */
 sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
                     sta_schedule* best, sta_stream stream);

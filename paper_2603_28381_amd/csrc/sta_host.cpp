@@ -774,9 +774,13 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   if (sch->sweep_group_log2 < 2 || sch->sweep_group_log2 > 6 || sch->flat_group_log2 < 2 ||
       sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64 || sch->rc_scheme < STA_RC_GROUPS ||
       sch->rc_scheme > STA_RC_THREAD ||
-      (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4))
+      (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4) ||
+      (sch->level_scheme != STA_LEVEL_GROUPS && sch->level_scheme != STA_LEVEL_THREAD))
     return fail(STA_E_INVALID, "schedule out of range");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  if (sch->level_scheme == STA_LEVEL_THREAD && (g->n_snap != 1 || g->snap_inner || g->ckpt_stride > 0 ||
+                                                !g->c_parent.empty()))
+    return fail(STA_E_INVALID, "one thread per net needs one snapshot, no checkpointing and star nets");
   g->sched_cfg = *sch;
   try {
     build_groups(g);
@@ -797,7 +801,8 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   int k = stride_levels;
   if (k < 0) k = std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, g->L - 1))));
-  if (k > 0 && g->snap_inner) return fail(STA_E_INVALID, "checkpointing is not available with STA_SNAP_INNER");
+  if (k > 0 && g->lanes_kernels())
+    return fail(STA_E_INVALID, "checkpointing is not available with STA_SNAP_INNER or one thread per net");
   g->ckpt_stride = k;
   try {
     build_ell(g);
@@ -812,6 +817,8 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
 sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots) {
   if (!g) return fail(STA_E_INVALID, "graph is NULL");
   if (n_snapshots < 1 || n_snapshots > 65535) return fail(STA_E_INVALID, "snapshot count out of range");
+  if (n_snapshots > 1 && g->sched_cfg.level_scheme == STA_LEVEL_THREAD)
+    return fail(STA_E_INVALID, "one thread per net sweeps one snapshot");
   g->n_snap = n_snapshots;
   drop_captured(g);
   return STA_OK;
@@ -825,6 +832,8 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout) {
     return fail(STA_E_INVALID, "STA_SNAP_INNER is not available with checkpointing");
   if (layout == STA_SNAP_INNER && !g->c_parent.empty())
     return fail(STA_E_INVALID, "STA_SNAP_INNER is not available for RC trees");
+  if (layout == STA_SNAP_INNER && g->sched_cfg.level_scheme == STA_LEVEL_THREAD)
+    return fail(STA_E_INVALID, "STA_SNAP_INNER replaces the thread-per-net schedule; set lane groups first");
   g->snap_inner = layout == STA_SNAP_INNER;
   drop_captured(g);
   return STA_OK;

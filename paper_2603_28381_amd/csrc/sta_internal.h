@@ -139,7 +139,7 @@ struct sta_graph {
   std::vector<int> tree_big;                   // RC trees: nets over kTreeChunk pins
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
-  sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS, 16};
+  sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS};
   // Checkpointing (stride 0 = off): record slot of each canonical net (kept nets first,
   // level-0 nets at their own index, then the shared segment buffer), segment boundaries
   // seg_lo (levels [seg_lo[j], seg_lo[j+1])), and the endpoints' record slots.
@@ -147,6 +147,9 @@ struct sta_graph {
   int n_snap = 1;                              // placement snapshots per call (shared topology)
   bool snap_inner = false;                     // STA_SNAP_INNER: snapshot-innermost arrays, lanes
                                                // over snapshots
+  // The snapshot-lane kernels run the sweep: with the snapshot-inner layout, and for one
+  // snapshot under the thread-per-net schedule (one lane per item, no heavy-net workgroups).
+  bool lanes_kernels() const { return snap_inner || sched_cfg.level_scheme == STA_LEVEL_THREAD; }
   std::vector<int> si_heavy, si_huge;          // canonical nets of kSiHeavy+1..kSiHuge sinks,
                                                // and of more than kSiHuge
   std::vector<int> si_hs, si_us;               // per level: its first net of more than kSiHeavy

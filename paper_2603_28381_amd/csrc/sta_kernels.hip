@@ -2082,6 +2082,7 @@ struct RcSiArgs {
   float* __restrict__ load;             // [N][S]
   float4* __restrict__ rec;             // [4 N][S]
   int N, N0, S, sl2, n_heavy, n_huge;
+  int max_sinks;                        // nets with more sinks are a heavy workgroup's
   float r, c, pi_at, pi_slew;
 };
 
@@ -2162,7 +2163,7 @@ __global__ __launch_bounds__(kSiBlock) void k_rc_si(RcSiArgs a) {
   const int n = ln.item;
   if (n >= a.N || !ln.on) return;
   const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
-  if (p1 - p0 - 1 > kSiHeavy) return;          // a heavy workgroup's net
+  if (p1 - p0 - 1 > a.max_sinks) return;       // a heavy workgroup's net
   const uint32_t S = (uint32_t)a.S;
   float xd, yd;
   driver_xy_si(a.x, a.y, a.io_perm, p0, S, ln.s, xd, yd);
@@ -2793,6 +2794,7 @@ struct SiDims {
   int S, sl2;
   unsigned gy;   // blocks of 64 snapshots (sl2 = 6) along y
   int hch, uch;  // workgroups per heavy and per huge net (chunks_of)
+  bool split;    // heavy nets take workgroups (else every net one lane: one thread per net)
 };
 
 SiDims si_dims(const sta_graph* g) {
@@ -2800,7 +2802,8 @@ SiDims si_dims(const sta_graph* g) {
   int sl2 = 0;
   while ((1 << sl2) < S && sl2 < 6) ++sl2;
   const int hw = 1 << sl2, uw = 1 << std::min(sl2, 3);
-  return SiDims{S, sl2, (unsigned)(sl2 == 6 ? (S + 63) / 64 : 1), (S + hw - 1) / hw, (S + uw - 1) / uw};
+  return SiDims{S, sl2, (unsigned)(sl2 == 6 ? (S + 63) / 64 : 1), (S + hw - 1) / hw, (S + uw - 1) / uw,
+                g->snap_inner};
 }
 
 // Workgroups of `waves` waves covering `items` items at 64 >> sl2 items per wave.
@@ -2835,9 +2838,10 @@ sta_status launch_forward_si(sta_graph* g, const float* x, const float* y, const
   const int* io = (flags & STA_CANONICAL_IO) ? nullptr : d.pin_perm;
   {
     LaunchTimer t(g, s, STA_K_RC);
-    const int nh = (int)g->si_heavy.size(), nu = (int)g->si_huge.size();
+    const int nh = D.split ? (int)g->si_heavy.size() : 0, nu = D.split ? (int)g->si_huge.size() : 0;
     const RcSiArgs ra{d.net_off, d.pin_cap, x, y, io, d.si_heavy, d.si_huge, wire, load, rec, g->N, g->N0, D.S, D.sl2,
-                      nh, nu, g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew};
+                      nh, nu, D.split ? kSiHeavy : INT32_MAX, g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at,
+                      g->cons.pi_slew};
     k_rc_si<<<dim3((unsigned)(nh * D.hch + nu * D.uch) + si_blocks(g->N, D.sl2, kSiWaves), D.gy), kSiBlock, 0,
               s>>>(ra);
   }
@@ -2896,7 +2900,8 @@ sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, cons
                      reinterpret_cast<float4*>(out->rat), reinterpret_cast<float4*>(out->slack), out->dx, out->dy,
                      g->N0, D.S, D.sl2, g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f};
   for (int l = g->L - 1; l >= 0; --l) {
-    const int lo = g->level_off[l], hi = g->level_off[l + 1], hs = g->si_hs[l], us = g->si_us[l];
+    const int lo = g->level_off[l], hi = g->level_off[l + 1];
+    const int hs = D.split ? g->si_hs[l] : hi, us = D.split ? g->si_us[l] : hi;
     if (hi == lo) continue;
     const unsigned blocks =
         (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kSiWaves);
@@ -2915,7 +2920,7 @@ sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, cons
 
 sta_status launch_forward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* out, uint32_t flags,
                           float gamma_ps, hipStream_t s) {
-  if (g->snap_inner) return launch_forward_si(g, x, y, out, flags, gamma_ps, s);
+  if (g->lanes_kernels()) return launch_forward_si(g, x, y, out, flags, gamma_ps, s);
   const bool smooth = (flags & STA_SMOOTH) != 0;
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(out->state);
@@ -2982,7 +2987,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
 
 sta_status launch_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                            const sta_bwd_out* out, uint32_t flags, float gamma_ps, hipStream_t s) {
-  if (g->snap_inner) return launch_backward_si(g, x, y, fwd, out, flags, gamma_ps, s);
+  if (g->lanes_kernels()) return launch_backward_si(g, x, y, fwd, out, flags, gamma_ps, s);
   const bool grad = (flags & STA_GRAD) != 0;
   const DeviceGraph& d = g->dev;
   char* sb = static_cast<char*>(fwd->state);
@@ -3312,20 +3317,27 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
     }
   };
   // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
-  // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell.
+  // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell,
+  // then one thread per net in every stage.
   for (int sweep = 2; sweep <= 6 && st == STA_OK; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
-        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16});
+        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS});
   const sta_schedule lanes = best_s;
   for (int rc : {STA_RC_CTE, STA_RC_THREAD})
     if (st == STA_OK)
-      try_schedule(sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16});
+      try_schedule(
+          sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16, STA_LEVEL_GROUPS});
   const sta_schedule wide = best_s;
   for (int fl : {8, 4}) {
     sta_schedule narrow = wide;
     narrow.fwd_cell_lanes = fl;
     if (st == STA_OK) try_schedule(narrow);
+  }
+  if (st == STA_OK && g->n_snap == 1 && g->ckpt_stride == 0 && g->c_parent.empty()) {
+    sta_schedule thread = best_s;           // one thread per net in every stage
+    thread.level_scheme = STA_LEVEL_THREAD;
+    try_schedule(thread);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

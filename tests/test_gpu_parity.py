@@ -398,7 +398,8 @@ def test_graph_capture_replays_match_plain_calls():
 def test_schedules_agree_with_oracle():
     # Every schedule sweeps the same arithmetic (summation order aside): lane groups, the RC
     # stage as Alg. 2's task pool (pools of 256 nets that span several LDS chunks of sinks
-    # here) or one thread per net, and 4 lanes per forward cell.
+    # here) or one thread per net, 4 lanes per forward cell, and one thread per net and cell
+    # in every stage (nets of up to 500 sinks walked by one thread).
     d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
     ref = O.run(d, gamma=GAMMA, grad="tns")
     g = Graph.from_design(d)
@@ -408,7 +409,7 @@ def test_schedules_agree_with_oracle():
     assert pools.max() > 2 * 1024, pools.max()
     for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
                 (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4), (2, 2, 64, "cte", 4),
-                (2, 2, 1, "thread", 8)):
+                (2, 2, 1, "thread", 8), (2, 2, 64, "groups", 16, "thread")):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
