@@ -573,7 +573,10 @@ def checkpoint_comparison(g, x, y, P, dev, args) -> dict:
                          peak_bytes=torch.cuda.max_memory_allocated() - base + info["device_bytes"])
         del state, ws, scal, out
     g.set_checkpointing(0)
+    for k in ("plain", "checkpointed"):
+        res[k]["sweep_bytes"] = res[k]["fwd_state_bytes"] + res[k]["workspace_bytes"]
     res["state_ratio"] = round(res["checkpointed"]["fwd_state_bytes"] / res["plain"]["fwd_state_bytes"], 4)
+    res["sweep_ratio"] = round(res["checkpointed"]["sweep_bytes"] / res["plain"]["sweep_bytes"], 4)
     res["peak_ratio"] = round(res["checkpointed"]["peak_bytes"] / res["plain"]["peak_bytes"], 4)
     res["time_ratio"] = round(res["checkpointed"]["ms_per_step"] / res["plain"]["ms_per_step"], 4)
     return res

@@ -345,7 +345,10 @@ sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps
  * sta_backward walks the segments last to first, recomputes the dropped records of a
  * segment from the frontier, then runs that segment's backward levels.  Results are
  * bit-identical to the run without checkpointing; fwd_state_bytes shrinks (see
- * sta_get_checkpointing), the backward pays one extra forward pass over the dropped nets.
+ * sta_get_checkpointing), and on star-net graphs bwd_workspace_bytes too (a sink's required
+ * times and adjoint live from the cell step writing them to its net's step: nets whose sinks
+ * are all written and read inside one segment share a buffer that the next segment
+ * reuses); the backward pays one extra forward pass over the dropped nets.
  *
  * stride_levels: 0 switches checkpointing off, a negative value picks ceil(sqrt(L-1)).
  * Changing it rebuilds the launch plan, changes fwd_state_bytes and releases the device

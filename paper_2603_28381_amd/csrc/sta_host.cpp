@@ -49,7 +49,7 @@ void compute_layouts(sta_graph* g) {
   g->state.epv = take(sizeof(float4) * (size_t)std::max(1, g->E));
   g->state.total = off;
   off = 0;
-  g->work.sink = take(2 * sizeof(float4) * (size_t)g->P);
+  g->work.sink = take(2 * sizeof(float4) * (size_t)(g->n_sslots > 0 ? g->n_sslots : g->P));
   g->work.tree_adj = take(tree ? sizeof(float2) * (size_t)g->P : 0);
   g->work.tree_bar = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
   g->work.total = off;
@@ -113,9 +113,57 @@ static GroupRange group_range(const int* cls_count, int base, int g0) {
 // level at or past that end reads it, if it drives an endpoint, or if l = 0; kept nets get
 // slots in canonical order (level-0 nets first, so their slot is their index), the other
 // nets of a segment share the slots after them.  Without checkpointing slot = net.
+// Sink workspace slots under checkpointing (see sta_graph::sink_base).  lvl: level of each
+// canonical net.
+static void build_sink_slots(sta_graph* g, const std::vector<int>& lvl) {
+  const int N = g->N, P = g->P, k = g->ckpt_stride;
+  auto seg = [&](int l) { return l == 0 ? -1 : (l - 1) / k; };
+  std::vector<int> reader_level(P, -1);          // level of the cell reading each input pin
+  for (int c = 0; c < g->C; ++c)
+    for (int a = g->c_cin_off[c]; a < g->c_cin_off[c + 1]; ++a) reader_level[g->c_cin_pin[a]] = lvl[g->N0 + c];
+  std::vector<char> is_ep(P, 0);
+  for (int e : g->ep_pin) is_ep[e] = 1;
+  std::vector<char> kept(N, 0);
+  for (int n = 0; n < N; ++n) {
+    const int l = lvl[n];
+    for (int p = g->c_net_off[n] + 1; p < g->c_net_off[n + 1] && !kept[n]; ++p)
+      if (l == 0 || is_ep[p] || reader_level[p] < 0 || seg(reader_level[p]) != seg(l)) kept[n] = 1;
+  }
+  g->sink_base.assign(N, 0);
+  int next = 0;
+  for (int n = 0; n < N; ++n)
+    if (kept[n]) {
+      g->sink_base[n] = next;
+      next += g->c_net_off[n + 1] - g->c_net_off[n] - 1;
+    }
+  const int kept_slots = next;
+  int widest = 0;
+  for (size_t j = 0; j + 1 < g->seg_lo.size(); ++j) {
+    int t = 0;
+    for (int n = g->level_off[g->seg_lo[j]]; n < g->level_off[g->seg_lo[j + 1]]; ++n)
+      if (!kept[n]) {
+        g->sink_base[n] = kept_slots + t;
+        t += g->c_net_off[n + 1] - g->c_net_off[n] - 1;
+      }
+    widest = std::max(widest, t);
+  }
+  g->n_sslots_kept = kept_slots;
+  g->n_sslots = std::max(1, kept_slots + widest);
+  g->sslot.assign(P, 0);
+  for (int n = 0; n < N; ++n)
+    for (int p = g->c_net_off[n] + 1; p < g->c_net_off[n + 1]; ++p)
+      g->sslot[p] = g->sink_base[n] + (p - g->c_net_off[n] - 1);
+  g->ep_sslot.resize(g->ep_pin.size());
+  for (size_t i = 0; i < g->ep_pin.size(); ++i) g->ep_sslot[i] = g->sslot[g->ep_pin[i]];
+}
+
 static void build_checkpoints(sta_graph* g) {
   const int N = g->N, L = g->L, k = g->ckpt_stride;
   g->seg_lo.clear();
+  g->sink_base.clear();
+  g->sslot.clear();
+  g->ep_sslot.clear();
+  g->n_sslots = g->n_sslots_kept = 0;
   if (k <= 0) {
     g->rec_loc.clear();
     g->n_rec = g->n_kept = N;
@@ -153,6 +201,7 @@ static void build_checkpoints(sta_graph* g) {
   g->n_rec = nk + widest;
   g->ep_rec.resize(g->ep_net.size());
   for (size_t i = 0; i < g->ep_net.size(); ++i) g->ep_rec[i] = g->rec_loc[g->ep_net[i]];
+  if (g->c_parent.empty()) build_sink_slots(g, lvl);
 }
 
 // Lane-group work lists: per-level ranges for the level kernels and all nets ordered by
@@ -215,15 +264,20 @@ void build_ell(sta_graph* g) {
     for (int c = c0; c < c1; ++c) F = std::max(F, g->c_cin_off[c + 1] - g->c_cin_off[c]);
     g->ell_base[l] = (int)g->ell.size();
     g->ell_slots[l] = F;
-    g->ell.resize(g->ell.size() + (size_t)F * nc, make_int4(-1, 0, 0, 1));
+    g->ell.resize(g->ell.size() + (size_t)F * nc, make_int4(-1, 0, 0, 0));
     for (int c = c0; c < c1; ++c)
-      for (int j = 0; j < g->c_cin_off[c + 1] - g->c_cin_off[c]; ++j)
-        g->ell[g->ell_base[l] + (size_t)j * nc + (c - c0)] = g->c_cin[g->c_cin_off[c] + j];
+      for (int j = 0; j < g->c_cin_off[c + 1] - g->c_cin_off[c]; ++j) {
+        // {source net, input pin, arc with the sign bit set for negative unateness, the
+        // input pin's sink workspace slot}
+        const int4 e = g->c_cin[g->c_cin_off[c] + j];
+        g->ell[g->ell_base[l] + (size_t)j * nc + (c - c0)] =
+            make_int4(e.x, e.y, (int)((uint32_t)e.z | (e.w < 0 ? 0x80000000u : 0u)), g->sslot.empty() ? e.y : g->sslot[e.y]);
+      }
   }
   if (g->ckpt_stride > 0)
     for (int4& e : g->ell)
       if (e.x >= 0) e.x = g->rec_loc[e.x];      // sources addressed by record slot
-  if (g->ell.empty()) g->ell.push_back(make_int4(-1, 0, 0, 1));
+  if (g->ell.empty()) g->ell.push_back(make_int4(-1, 0, 0, 0));
 }
 
 void build_schedule(sta_graph* g) {
@@ -916,6 +970,7 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
       (s = up(d.sched_all, g->sched_all)) || (s = up(d.si_heavy, g->si_heavy)) || (s = up(d.si_huge, g->si_huge)) ||
+      (!g->sink_base.empty() && ((s = up(d.sink_base, g->sink_base)) || (s = up(d.ep_sslot, g->ep_sslot)))) ||
       (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
       (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)) ||
                                 (s = up(d.tree_node, g->c_tree_node)) || (s = up(d.tree_blk_net, g->tree_blk_net)) ||

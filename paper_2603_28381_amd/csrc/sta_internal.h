@@ -96,6 +96,8 @@ struct DeviceGraph {
   int* tree_big = nullptr;        // RC trees only: nets over the chunk size
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
+  int* sink_base = nullptr;    // [N] checkpointing (stars): first workspace slot of each net's sinks
+  int* ep_sslot = nullptr;     // [E] checkpointing (stars): workspace slot of each endpoint
   int* si_heavy = nullptr;     // snapshot-inner RC: canonical nets of kSiHeavy+1..kSiHuge sinks,
   int* si_huge = nullptr;      // and of more than kSiHuge
   size_t bytes = 0;
@@ -156,6 +158,14 @@ struct sta_graph {
                                                // and of more than kSiHuge sinks (a level's nets
                                                // ascend in pin count)
   std::vector<int> rec_loc, seg_lo, ep_rec;
+  // Sink workspace slots under checkpointing (star nets): a sink's required times and
+  // adjoint live from the cell step that writes them to its net's step; sinks whose net and
+  // reading cell share a segment (and are not endpoints) share a segment buffer, the others
+  // keep a slot.  A net's sinks take consecutive slots from sink_base[net] (kept nets first,
+  // then each segment's other nets from the buffer's start).  Empty without segmentation:
+  // the slot of a sink is its pin.
+  std::vector<int> sink_base, sslot, ep_sslot;
+  int n_sslots = 0, n_sslots_kept = 0;
   sta::StateLayout state{};
   sta::WorkLayout work{};
   int n_ep_blocks = 0;

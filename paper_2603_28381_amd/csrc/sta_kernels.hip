@@ -987,8 +987,14 @@ struct Slots {
 struct ArcIn {          // one cell input seen from one condition
   float at, slew, atg;  // arrival, slew and smoothed arrival at the input pin
   int arc, tp, pin;
+  int slot;             // the input pin's sink workspace slot
   bool valid;
 };
+
+// Input slot entries are {source record slot, input pin, arc with the sign bit set for
+// negative unateness, the input pin's sink workspace slot}.
+__device__ __forceinline__ int ell_arc(const int4& e) { return e.z & 0x7fffffff; }
+__device__ __forceinline__ bool ell_positive(const int4& e) { return e.z >= 0; }
 
 // Input j of cell kc for output condition (m, t): the source net's driver record plus the
 // wire to the input pin, in the input transition the arc's unateness selects.  Missing
@@ -1003,9 +1009,10 @@ __device__ __forceinline__ ArcIn arc_input_entry(const int4 e, bool valid, const
                                                  const float2* __restrict__ wire, int m, int t) {
   ArcIn r;
   r.valid = valid && e.x >= 0;
-  r.arc = e.z;
-  r.tp = e.w > 0 ? t : 1 - t;
+  r.arc = ell_arc(e);
+  r.tp = ell_positive(e) ? t : 1 - t;
   r.pin = e.y;
+  r.slot = e.w;
   const int kp = 2 * m + r.tp;
   const float4 c = ld(rec, (uint32_t)(kRecChunks * max(e.x, 0) + kp));
   const float2 w = ld(wire, (uint32_t)e.y);
@@ -1021,9 +1028,10 @@ __device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const S
   const int4 e = ell[sl.base + (size_t)min(j, sl.F - 1) * sl.nc + kc];
   ArcIn r;
   r.valid = j < sl.F && e.x >= 0;
-  r.arc = e.z;
-  r.tp = e.w > 0 ? t : 1 - t;
+  r.arc = ell_arc(e);
+  r.tp = ell_positive(e) ? t : 1 - t;
   r.pin = e.y;
+  r.slot = e.w;
   const int kp = 2 * m + r.tp;
   const float4 c = rec[kRecChunks * (size_t)max(e.x, 0) + kp];   // {AT, slew, smoothed AT} of kp
   const float2 w = wire[e.y];
@@ -1225,6 +1233,7 @@ struct EpArgs {
   int smooth, wns_mode;
   Snap snap;
   float4* epv;        // per endpoint {s_e, w_rise, w_fall, 0}: written by the partials, read by the seeds
+  const int* ep_sslot;  // checkpointing: each endpoint's workspace slot (NULL: its pin)
 };
 
 // The endpoint arguments of snapshot blockIdx.y.
@@ -1382,7 +1391,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
   const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
   if (i >= a0.E) return;
   const EpArgs a = ep_snap(a0);
-  const int e = a.ep_pin[i];
+  const int e = a.ep_sslot ? a.ep_sslot[i] : a.ep_pin[i];   // the endpoint's workspace slot
   a.sink[rat_at(e)] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
   if (a.seed_adj) {
     // s_e and its weights as the forward computed them (same coordinates and gamma).
@@ -1485,6 +1494,8 @@ struct BwdArgs {
   int grad;
   Snap snap;
   float2* tree_adj;   // RC trees: the Elmore adjoint is left to k_rc_tree_adjoint (else NULL)
+  const int* __restrict__ sink_base;  // checkpointing: first workspace slot of each net's sinks
+                                      // (NULL: a sink's slot is its pin)
 };
 
 // Accumulators of the net step (reduced over the group).
@@ -1504,17 +1515,18 @@ struct SinkIn {
   int q;
 };
 
+// Sink p, whose workspace slot is `slot` (its pin without checkpointing).
 template <bool kCanon, bool kGrad>
-__device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p) {
+__device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p, int slot) {
   SinkIn in;
   const uint32_t u = (uint32_t)p;
-  in.rt = ld(a.sink, rat_at(u));
+  in.rt = ld(a.sink, rat_at((uint32_t)slot));
   in.w = ld(a.wire, u);
   in.q = kCanon ? p : ld(a.io_perm, u);
   in.aj = make_float4(0.f, 0.f, 0.f, 0.f);
   in.xs = in.ys = in.cp = 0.f;
   if (kGrad) {
-    in.aj = ld(a.sink, adj_at(u));
+    in.aj = ld(a.sink, adj_at((uint32_t)slot));
     in.xs = ld(a.x, (uint32_t)in.q);
     in.ys = ld(a.y, (uint32_t)in.q);
     in.cp = ld(a.pin_cap, u);
@@ -1572,7 +1584,7 @@ __device__ __forceinline__ SinkKeep sink_step(const BwdArgs& a, const SinkIn& in
 
 struct ArcBwd {         // one arc of the cell step, seen from one condition's lane
   float d, xg, s, ddx, ddy, dsx, dsy;
-  int pin, tp;
+  int pin, tp, slot;
   bool valid;
 };
 
@@ -1583,6 +1595,7 @@ __device__ __forceinline__ ArcBwd arc_backward(const BwdArgs& a, const Slots& sl
   r.valid = in.valid;
   r.pin = in.pin;
   r.tp = in.tp;
+  r.slot = in.slot;
   r.d = r.s = r.ddx = r.ddy = r.dsx = r.dsy = 0.f;
   r.xg = -kInf;
   if (in.valid) {
@@ -1607,6 +1620,7 @@ __device__ __forceinline__ ArcBwd arc_from_input(const BwdArgs& a, const ArcIn& 
   r.valid = in.valid;
   r.pin = in.pin;
   r.tp = in.tp;
+  r.slot = in.slot;
   r.d = in.valid ? v.d : 0.f;
   r.s = in.valid ? v.s : 0.f;
   r.xg = in.valid ? in.atg + v.d : -kInf;
@@ -1690,6 +1704,8 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const float load = ld(a.load, (uint32_t)n);
   const int slot = a.loc ? ld(a.loc, (uint32_t)n) : n;
   const int p1 = gs.active ? p1v : p0;
+  // workspace slot of sink p: sk0 + p (its pin without checkpointing)
+  const int sk0 = a.sink_base ? ld(a.sink_base, (uint32_t)n) - (p0 + 1) : 0;
 
   // Wave 2: the cell input's source record and wire first (the table lookup waits for
   // them), then the driver's record and coordinates and the sinks, whose loads stay in
@@ -1698,9 +1714,10 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     ain[i].valid = cell_lane && jl + AL * i < sl.F && e[i].x >= 0;
-    ain[i].arc = e[i].z;
-    ain[i].tp = e[i].w > 0 ? t : 1 - t;
+    ain[i].arc = ell_arc(e[i]);
+    ain[i].tp = ell_positive(e[i]) ? t : 1 - t;
     ain[i].pin = e[i].y;
+    ain[i].slot = e[i].w;
     const int kp = 2 * m + ain[i].tp;
     const float4 c = ld(a.rec, (uint32_t)(kRecChunks * max(e[i].x, 0) + kp));
     const float2 w = ld(a.wire, (uint32_t)e[i].y);
@@ -1722,9 +1739,9 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   const int gstride = block ? kBlock : G;
   const bool has0 = s0 < p1;
   const bool has1 = block && s0 + gstride < p1;
-  const SinkIn in0 = sink_load<kCanon, kGrad>(a, has0 ? s0 : p0);
+  const SinkIn in0 = sink_load<kCanon, kGrad>(a, has0 ? s0 : p0, has0 ? sk0 + s0 : 0);
   SinkIn in1{};
-  if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0);
+  if (block) in1 = sink_load<kCanon, kGrad>(a, has1 ? s0 + gstride : p0, has1 ? sk0 + s0 + gstride : 0);
   __builtin_amdgcn_sched_barrier(0);          // keep wave 2 ahead of the lookup below
 
   // 2a. Cell-step lookups (wave 3): lane (k, jl) of the cell lanes takes arcs jl + AL * i.
@@ -1794,7 +1811,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
   if (has1) keep1 = sink_step<kGrad>(a, in1, at_d, sl_d, xd, yd, acc, true, s0 + gstride);
   if (block) {
     for (int p = s0 + 2 * gstride; p < p1; p += gstride)
-      sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, acc, true, p);
+      sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p, sk0 + p), at_d, sl_d, xd, yd, acc, true, p);
   }
   reduce_acc<G>(acc, block, sh);
 
@@ -1815,11 +1832,11 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
       if (cell_lane && v.valid) {
         // RAT(input, k') = RAT(output, k) - arc delay.
         float* sw = reinterpret_cast<float*>(a.sink);
-        *at32(sw, 4 * rat_at((uint32_t)v.pin) + (uint32_t)(2 * m + v.tp)) = rat_o - v.d;
+        *at32(sw, 4 * rat_at((uint32_t)v.slot) + (uint32_t)(2 * m + v.tp)) = rat_o - v.d;
         if (kGrad && m == 1) {
           const float dbar = fexp((v.xg - xmax) * a.inv_gamma) * inv_z * abar;   // softmax weight x adjoint
           const float s_j = (j0 + jl + AL * i) == jstar ? sbar : 0.f;
-          const uint32_t aj = 4 * adj_at((uint32_t)v.pin);
+          const uint32_t aj = 4 * adj_at((uint32_t)v.slot);
           *at32(sw, aj + (uint32_t)v.tp) = dbar;
           *at32(sw, aj + 2u + (uint32_t)v.tp) = fmaf(dbar, v.ddx, s_j * v.dsx);
           lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
@@ -1858,7 +1875,8 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     if (block) {
       for (int p = s0 + 2 * gstride; p < p1; p += gstride) {
         float scratch[N_ACC] = {};
-        const SinkKeep kk = sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p), at_d, sl_d, xd, yd, scratch, false, p);
+        const SinkKeep kk =
+            sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p, sk0 + p), at_d, sl_d, xd, yd, scratch, false, p);
         if (a.dx) a.dx[kk.q] = kk.gx * (cl + kk.rest);
         if (a.dy) a.dy[kk.q] = kk.gy * (cl + kk.rest);
       }
@@ -2232,9 +2250,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int bas
         float cm = neutral, sm = neutral, gm = -kInf, g[kArcLanes];
 #pragma unroll
         for (int i = 0; i < kArcLanes; ++i) {
-          const float4 ci = pick_tr(e[i].w > 0, t, cr[i], cf[i]);
+          const float4 ci = pick_tr(ell_positive(e[i]), t, cr[i], cf[i]);
           const float sl_in = sink_slew(ci.y, w[i].y);
-          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, e[i].z, t, sl_in, load);
+          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, ell_arc(e[i]), t, sl_in, load);
           const float cand = valid[i] ? (ci.x + w[i].x) + v.d : neutral;
           const float sv = valid[i] ? v.s : neutral;
           g[i] = valid[i] ? (ci.z + w[i].x) + v.d : -kInf;
@@ -2570,9 +2588,9 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
           const int4 e = ld(a.ell, (uint32_t)(sl.base + min(j, sl.F - 1) * sl.nc + kc));
           valid[i] = j < sl.F && e.x >= 0;
           const int src = kRecChunks * max(e.x, 0) + 2;
-          const float4 ci = pick_tr(e.w > 0, t, ld(a.rec, si_at(src, S, s)), ld(a.rec, si_at(src + 1, S, s)));
+          const float4 ci = pick_tr(ell_positive(e), t, ld(a.rec, si_at(src, S, s)), ld(a.rec, si_at(src + 1, S, s)));
           const float2 w = ld(a.wire, si_at(e.y, S, s));
-          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, e.z, t, sink_slew(ci.y, w.y), load);
+          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(ci.y, w.y), load);
           xg[i] = valid[i] ? (ci.z + w.x) + v.d : -kInf;
           cm = fmaxf(cm, xg[i]);
           const bool take = valid[i] && (j2 == STA_MAX_FANIN || v.s > s2);
@@ -2604,7 +2622,7 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
   for (int j = 0; j < sl.F; ++j) {
     const int4 e = ld(a.ell, (uint32_t)(sl.base + j * sl.nc + kc));
     if (e.x < 0) continue;
-    const bool same = e.w > 0;
+    const bool same = ell_positive(e);
     const float2 w = ld(a.wire, si_at(e.y, S, s));
     float4 c[4];
 #pragma unroll
@@ -2615,7 +2633,7 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
       const int m = k >> 1, t = k & 1;
       const int tp = same ? t : 1 - t;
       const float4 ci = pick_tr(same, t, c[2 * m], c[2 * m + 1]);
-      const LutVal v = lut_eval<kGrad>(a.grid, a.coef, a.keys, e.z, t, sink_slew(ci.y, w.y), load);
+      const LutVal v = lut_eval<kGrad>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(ci.y, w.y), load);
       set_comp(rat_in, 2 * m + tp, rat_o[k] - v.d);
       if (kGrad && m == 1) {
         const float xg = (ci.z + w.x) + v.d;
@@ -2963,7 +2981,7 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
             nullptr, 0, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
             smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn,
-            reinterpret_cast<float4*>(sb + g->state.epv)};
+            reinterpret_cast<float4*>(sb + g->state.epv), d.ep_sslot};
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
     k_ep_partials<<<dim3(g->n_ep_blocks, g->n_snap), kBlock, 0, s>>>(ea);
@@ -3002,7 +3020,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
             reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), nullptr, sink,
             grad ? 1 : 0, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
             g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
-            (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g), reinterpret_cast<float4*>(sb + g->state.epv)};
+            (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g), reinterpret_cast<float4*>(sb + g->state.epv), d.ep_sslot};
   if (g->E > 0) {
     LaunchTimer t(g, s, STA_K_EP_SEED);
     k_ep_seed<<<dim3((g->E + kBlock - 1) / kBlock, g->n_snap), kBlock, 0, s>>>(ea);
@@ -3014,7 +3032,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
              reinterpret_cast<float4*>(out->slew), reinterpret_cast<float4*>(out->rat),
              reinterpret_cast<float4*>(out->slack), out->dx, out->dy, g->N0,
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g),
-             (grad && tree) ? reinterpret_cast<float2*>(wb + g->work.tree_adj) : nullptr};
+             (grad && tree) ? reinterpret_cast<float2*>(wb + g->work.tree_adj) : nullptr, d.sink_base};
   const int ss = (int)g->state.total;
   auto bwd_level = [&](int l) {
     const GroupRange& r = g->lvl_ranges[l];

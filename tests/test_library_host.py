@@ -239,6 +239,48 @@ def _expected_checkpoint_counts(d, k):
     return int(kept.sum()), int(kept.sum()) + widest
 
 
+def _expected_sink_slots(d, k):
+    """Backward workspace slots under checkpointing with stride k, from the netlist: a net keeps
+    its sinks' slots when it sits at level 0, or one of its sinks is an endpoint, feeds no
+    cell, or feeds a cell of another segment; the other nets of a segment share a buffer."""
+    lv = O.levelize(d)
+    N, lvl, L = d.n_nets, lv.level, lv.n_levels
+    net_of_pin = np.empty(d.n_pins, np.int64)
+    net_of_pin[d.net_pins] = np.repeat(np.arange(N), np.diff(d.net_offsets))
+    cell_level = lvl[net_of_pin[d.cell_out_pin]]
+    reader = np.full(d.n_pins, -1)
+    reader[d.cell_in_pins] = np.repeat(cell_level, np.diff(d.cell_in_offsets))
+    seg = lambda l: np.where(l == 0, -1, (l - 1) // k)
+    sinks = np.ones(d.n_pins, bool)
+    sinks[d.net_pins[d.net_offsets[:-1]]] = False                     # drivers
+    is_ep = (d.pin_kind == PIN_FF_D) | (d.pin_kind == PIN_PO)
+    own = lvl[net_of_pin]
+    out = sinks & ((own == 0) | is_ep | (reader < 0) | (seg(np.maximum(reader, 0)) != seg(own)))
+    kept = np.zeros(N, bool)
+    kept[net_of_pin[out]] = True
+    n_sinks = np.diff(d.net_offsets) - 1
+    per_seg = [int(n_sinks[~kept & (lvl >= 1) & ((lvl - 1) // k == j)].sum()) for j in range((L - 2) // k + 1)]
+    return int(n_sinks[kept].sum()) + max(per_seg + [0])
+
+
+@pytest.mark.parametrize("k", [1, 3, 100])
+def test_checkpoint_segments_backward_workspace(k):
+    d = make_design(CFG0)
+    g = S.Graph.from_design(d)
+    g.levelize()
+    up = lambda b: -(-b // 256) * 256                                 # pieces start 256-aligned
+    plain = g.info()["bwd_workspace_bytes"]
+    assert plain == up(32 * d.n_pins)
+    g.set_checkpointing(k)
+    slots = _expected_sink_slots(d, k)
+    sinks = d.n_pins - d.n_nets
+    assert slots < sinks if k == 3 else slots == sinks                # one level, one segment: no reuse
+    assert g.info()["bwd_workspace_bytes"] == up(32 * max(slots, 1))
+    g.set_checkpointing(0)
+    assert g.info()["bwd_workspace_bytes"] == plain
+    g.close()
+
+
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 100])
 def test_checkpoint_frontier_counts(k):
     d = make_design(CFG0)
