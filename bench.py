@@ -769,7 +769,7 @@ def run_serve(args) -> dict:
         g = Graph.from_design(d)
         g.levelize()
         graphs.append(g)
-    srv = Server(200 << 30, max_slots=args.serve_slots, queue_capacity=1 << 16)
+    srv = Server(200 << 30, max_slots=args.serve_slots, queue_capacity=1 << 16, max_merge=args.serve_merge)
     ids = [srv.add_design(g, d.x, d.y) for g, d in zip(graphs, designs)]
     n_jit = 4
     jit = [[jitter(d, 2.0, stream=500 + j) for j in range(n_jit)] for d in designs]
@@ -779,13 +779,24 @@ def run_serve(args) -> dict:
     which = rng.integers(len(designs), size=n_req)
     grad = rng.random(n_req) < 0.3
     t_setup = time.time() - t0
-    # Warm every slot on every (design, kind, new or resident coordinates) it may serve, so
-    # that no capture falls in the timed window: a burst of `slots` requests of one key at a
-    # time occupies every slot.
+    # Warm every slot on every (design, kind, new or resident coordinates) it may serve alone,
+    # so that few captures fall in the timed window: with merging off, a burst of `slots`
+    # requests of one key at a time occupies every slot.  Merged sweeps capture when they
+    # first occur on a slot; the line counts the captures in the window.
+    srv.set_max_merge(1)
     for i in ids:
         for g_ in (False, True):
             tk = [srv.submit(i, grad=g_, x=jit[i][0][0] if g_ else None, y=jit[i][0][1] if g_ else None)
                   for _ in range(args.serve_slots)]
+            for q in tk:
+                srv.wait(q)
+    srv.set_max_merge(args.serve_merge)
+    # Then bursts that merge (the first request of a burst runs alone, the others wait and
+    # are swept together), so that merged sweeps have run before the window.
+    for i in ids:
+        for g_ in (False, True):
+            tk = [srv.submit(i, grad=g_, x=jit[i][0][0] if g_ else None, y=jit[i][0][1] if g_ else None)
+                  for _ in range(4 * args.serve_slots)]
             for q in tk:
                 srv.wait(q)
     warm = srv.stats()
@@ -798,10 +809,14 @@ def run_serve(args) -> dict:
         for r in range(n_req):
             while tickets[r] is None:
                 time.sleep(0.0002)
-            res = srv.wait(tickets[r])
+            res = srv.wait(tickets[r], grad=r % sample_every == 0)
             results[r] = (res["latency_ms"], res["queue_ms"], res["scalars"],
                           (res.get("dx"), res.get("dy")) if r % sample_every == 0 else None)
 
+    # The client's own pauses count as submission lag: no garbage collection in the window.
+    import gc
+    gc.collect()
+    gc.disable()
     th = threading.Thread(target=collect)
     th.start()
     start = time.perf_counter()
@@ -813,21 +828,24 @@ def run_serve(args) -> dict:
                 break
             time.sleep(min(due - now, 0.001))
         k = int(which[r])
+        # lag: scheduled arrival to the submit call (the server's latency starts inside it)
+        lag[r] = (time.perf_counter() - due) * 1e3
         if grad[r]:
             x, y = jit[k][r % n_jit]
             tickets[r] = srv.submit(ids[k], grad=True, x=x, y=y)
         else:
             tickets[r] = srv.submit(ids[k], grad=False)
-        lag[r] = (time.perf_counter() - due) * 1e3
     th.join()
     elapsed = time.perf_counter() - start
+    gc.enable()
     after = srv.stats()
     captures_in_window = after["captures"] - warm["captures"]
     srv.close()
 
-    def burst(slots: int, n: int = 400) -> dict:
-        """Capacity: n requests of the same mix submitted at once, served with `slots` slots."""
-        b = Server(200 << 30, max_slots=slots, queue_capacity=1 << 16)
+    def burst(slots: int, merge: int, n: int = 400) -> dict:
+        """Capacity: n requests of the same mix submitted at once, served with `slots` slots,
+        waiting requests of one design and kind merged up to `merge` per sweep."""
+        b = Server(200 << 30, max_slots=slots, queue_capacity=1 << 16, max_merge=merge)
         bid = [b.add_design(g, d.x, d.y) for g, d in zip(graphs, designs)]
         def run_all():
             tk = []
@@ -839,15 +857,24 @@ def run_serve(args) -> dict:
                 else:
                     tk.append(b.submit(bid[k], grad=False))
             for q in tk:
-                b.wait(q)
+                b.wait(q, grad=False)      # results are on the host; no client copy
 
-        run_all()                      # every slot captures its launch sequences
+        for _ in range(6):             # until a pass captures no new launch sequence
+            c0 = b.stats()["captures"]
+            run_all()
+            if b.stats()["captures"] == c0:
+                break
+        s0 = b.stats()
         t = time.perf_counter()
         run_all()
         dt = time.perf_counter() - t
+        s1 = b.stats()
         b.close()
         pp = float(sum(designs[int(which[r])].n_pins for r in range(n)))
-        return {"slots": slots, "requests": n, "s": round(dt, 4), "pins_per_s": round(pp / dt, 1)}
+        return {"slots": slots, "max_merge": merge, "requests": n, "s": round(dt, 4), "pins_per_s": round(pp / dt, 1),
+                "sweeps": s1["sweeps"] - s0["sweeps"], "merged": s1["merged"] - s0["merged"],
+                "captures": s1["captures"] - s0["captures"],
+                "capture_ms": round(s1["capture_ms"] - s0["capture_ms"], 3)}
 
     if getattr(args, "served_samples", ""):
         # Every 100th result with what regenerates its inputs, for check_served on the host:
@@ -863,8 +890,9 @@ def run_serve(args) -> dict:
                             grad_offsets=np.cumsum([0] + [len(a) for a in dx]), pins=np.concatenate(picks),
                             dx=np.concatenate(dx), dy=np.concatenate(dy),
                             latency_ms=np.array([results[r][0] for r in rs]) + lag[rs], gamma=10.0)
-    cap_many = burst(args.serve_slots)
-    cap_one = burst(1)
+    cap_many = burst(args.serve_slots, args.serve_merge)
+    cap_alone = burst(args.serve_slots, 1)
+    cap_one = burst(1, 1)
     lat = np.array([results[r][0] for r in range(n_req)]) + lag
     qms = np.array([results[r][1] for r in range(n_req)])
     pins = np.array([designs[int(k)].n_pins for k in which], np.float64)
@@ -903,19 +931,31 @@ def run_serve(args) -> dict:
         "config": {"workload": f"cfg4: {len(designs)} resident designs of {min(d.n_pins for d in designs)}-"
                                f"{max(d.n_pins for d in designs)} pins, Poisson {args.serve_rate} req/s for "
                                f"{args.serve_seconds} s, 30% fwd+bwd (jitter 2 um), budget 200 GB, "
-                               f"{args.serve_slots} slots",
+                               f"{args.serve_slots} slots, merging up to {args.serve_merge}",
                    "designs_pins": [d.n_pins for d in designs], "requests": n_req},
         "serving": {"p50_ms": round(float(np.percentile(lat, 50)), 4),
                     "p99_ms": round(float(np.percentile(lat, 99)), 4),
                     "max_ms": round(float(lat.max()), 4),
                     "p99_queue_ms": round(float(np.percentile(qms, 99)), 4),
+                    "slowest": [{"ms": round(float(lat[r]), 3), "queue_ms": round(float(qms[r]), 3),
+                                 "submit_lag_ms": round(float(lag[r]), 3),
+                                 "pins": int(pins[r]), "grad": bool(grad[r]), "arrival_s": round(float(arrivals[r]), 3)}
+                                for r in np.argsort(lat)[::-1][:6]],
+                    "capture_ms_in_window": round(after["capture_ms"] - warm["capture_ms"], 3),
+                    "slot_grows_in_window": after["slot_grows"] - warm["slot_grows"],
+                    "grow_ms_in_window": round(after["grow_ms"] - warm["grow_ms"], 3),
+                    "pinned_allocs_in_window": after["pinned_allocs"] - warm["pinned_allocs"],
+                    "pinned_ms_in_window": round(after["pinned_ms"] - warm["pinned_ms"], 3),
                     "p99_submit_lag_ms": round(float(np.percentile(lag, 99)), 4),
                     "fwd_p50_ms": round(float(np.percentile(lat[~grad], 50)), 4),
                     "fwd_bwd_p50_ms": round(float(np.percentile(lat[grad], 50)), 4) if grad.any() else None,
                     "achieved_req_per_s": round(n_req / elapsed, 2), "elapsed_s": round(elapsed, 3),
                     "captures_warmup": warm["captures"], "captures_in_window": captures_in_window,
-                    "capacity": cap_many, "capacity_one_at_a_time": cap_one,
+                    "sweeps_in_window": after["sweeps"] - warm["sweeps"],
+                    "merged_in_window": after["merged"] - warm["merged"],
+                    "capacity": cap_many, "capacity_unmerged": cap_alone, "capacity_one_at_a_time": cap_one,
                     "capacity_speedup": round(cap_many["pins_per_s"] / cap_one["pins_per_s"], 3),
+                    "merge_speedup": round(cap_many["pins_per_s"] / cap_alone["pins_per_s"], 3),
                     "oracle_checked": checked},
         "roofline": None,
         "cpu_baseline": None,
@@ -992,6 +1032,8 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-merge", type=int, default=8,
+                    help="waiting requests of one design and kind swept together as snapshots, at most")
     ap.add_argument("--serve-check", type=int, default=6, help="served results checked against the oracle")
     ap.add_argument("--gamma", type=float, default=10.0)
     ap.add_argument("--capture", action="store_true", help="replay each call from a captured hipGraph")

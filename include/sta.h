@@ -374,10 +374,14 @@ sta_status sta_get_checkpointing(const sta_graph* g, int32_t* stride_levels, int
  * dy), optionally on new coordinates.  The scheduler admits queued requests in arrival
  * order as soon as a slot is free whose buffer holds the request, or can grow to hold it
  * with the resident designs and every slot buffer within the budget; requests that arrive
- * while others run start at once and their levels overlap on the device.  A slot captures
- * the launch sequence of each (design, kind, coordinates, gamma) once into a hipGraph and
- * replays it, so a request costs a few host calls.  It is the same launch sequence as the
- * plain calls, so a result does not depend on what it ran beside.
+ * while others run start at once and their levels overlap on the device.  Requests of one
+ * design, kind and gamma that wait together are batched by level depth: up to max_merge of
+ * them (a power of two) run as placement snapshots of one sweep, each level launch
+ * advancing all of them (sta_set_snapshots), on one slot.  A slot captures the launch
+ * sequence of each (design, kind, coordinates, gamma, snapshots) once into a hipGraph and
+ * replays it, so a sweep costs a few host calls.  Every snapshot is computed by the same
+ * arithmetic in the same order as a call of its own, so a result is bitwise the same alone,
+ * beside other requests and merged with them.
  * ------------------------------------------------------------------------------------- */
 typedef struct sta_server sta_server;
 
@@ -385,6 +389,10 @@ typedef struct sta_server_config {
   int64_t hbm_budget_bytes;    /* device memory for resident designs plus requests in flight */
   int32_t max_slots;           /* requests on the device at once (1..64) */
   int32_t queue_capacity;      /* requests waiting for admission before STA_E_BUSY (>= 1) */
+  int32_t max_merge;           /* requests swept together as snapshots, at most (0 or 1: each
+                                  alone; else a power of two up to 64).  Merging needs the
+                                  snapshot-outer layout and lane-group schedules (a design
+                                  under STA_SNAP_INNER or STA_LEVEL_THREAD runs alone). */
 } sta_server_config;
 
 #define STA_REQ_FWD 0          /* forward sweep: scalars only */
@@ -439,8 +447,17 @@ typedef struct sta_server_stats {
   int64_t completed;           /* requests finished successfully */
   int64_t captures;            /* launch sequences captured into hipGraphs */
   double capture_ms;           /* host time of the requests that captured, admission to enqueued */
+  int64_t sweeps;              /* launch sequences issued (one per admitted batch) */
+  int64_t merged;              /* requests that ran in a sweep with at least one other */
+  int64_t slot_grows;          /* slot buffers (re)allocated from the pool */
+  double grow_ms;              /* host time of those allocations */
+  int64_t pinned_allocs;       /* pinned host staging buffers allocated (sta_submit reuses */
+  double pinned_ms;            /*   released ones of the same size), and their host time */
 } sta_server_stats;
 sta_status sta_server_stats_get(sta_server* s, sta_server_stats* out);
+/* Changes max_merge (as in sta_server_config) for sweeps admitted from now on, for example to
+ * warm every slot on single requests before merging.  Errors: STA_E_INVALID. */
+sta_status sta_server_set_max_merge(sta_server* s, int32_t max_merge);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel timing with HIP events (a profiling aid).  While enabled, each run of consecutive

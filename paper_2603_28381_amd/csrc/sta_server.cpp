@@ -41,8 +41,18 @@ class PinnedPool {
       }
     }
     void* p = nullptr;
-    if (hipHostMalloc(&p, std::max<size_t>(bytes, 1), hipHostMallocDefault) != hipSuccess) return nullptr;
-    return p;
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipError_t e = hipHostMalloc(&p, std::max<size_t>(bytes, 1), hipHostMallocDefault);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::lock_guard<std::mutex> lk(mu_);
+    ++allocs_;
+    alloc_ms_ += ms;
+    return e == hipSuccess ? p : nullptr;
+  }
+  void counts(int64_t* n, double* ms) {
+    std::lock_guard<std::mutex> lk(mu_);
+    *n = allocs_;
+    *ms = alloc_ms_;
   }
   void give(void* p, size_t bytes) {
     if (!p) return;
@@ -57,6 +67,8 @@ class PinnedPool {
  private:
   std::mutex mu_;
   std::map<size_t, std::vector<void*>> free_;
+  int64_t allocs_ = 0;     // hipHostMalloc calls and their host time
+  double alloc_ms_ = 0.0;
 };
 
 struct Design {
@@ -64,7 +76,8 @@ struct Design {
   int P = 0;
   float* x = nullptr;   // resident coordinates (device, original order)
   float* y = nullptr;
-  size_t state_bytes = 0, work_bytes = 0;
+  size_t state_bytes = 0, work_bytes = 0;   // of one snapshot
+  bool can_merge = false;                   // snapshot-outer layout with lane-group schedules
 };
 
 enum TicketState { kQueued, kRunning, kDone, kFailed };
@@ -85,16 +98,17 @@ struct Ticket {
   Clock::time_point t_submit, t_admit, t_done;
 };
 
-// A slot runs one request at a time on its own stream, in a device buffer it keeps between
-// requests, with the launch sequence of each (design, kind, coordinates) captured once into
-// a hipGraph over that buffer and replayed afterwards.
-using GraphKey = std::tuple<int, int, int, uint32_t>;   // (design, kind, new x/y, gamma bits)
-constexpr size_t kMaxSlotGraphs = 64;   // captured sequences kept per slot; the oldest goes first
+// A slot runs one sweep at a time on its own stream, in a device buffer it keeps between
+// sweeps, with the launch sequence of each (design, kind, coordinates, gamma, snapshots)
+// captured once into a hipGraph over that buffer and replayed afterwards.  A sweep serves
+// one request, or several of one design, kind and gamma as its snapshots.
+using GraphKey = std::tuple<int, int, int, uint32_t, int>;   // (design, kind, new x/y, gamma bits, S)
+constexpr size_t kMaxSlotGraphs = 128;  // captured sequences kept per slot; the oldest goes first
 
 struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t done = nullptr;
-  uint64_t ticket = 0;
+  std::vector<uint64_t> batch;  // tickets of the sweep on the device, snapshot order
   bool busy = false;
   void* buf = nullptr;          // from the server's pool
   size_t cap = 0;
@@ -102,14 +116,19 @@ struct Slot {
   std::deque<GraphKey> graph_order;   // capture order, for eviction
 };
 
-// What issuing a request needs, copied out of the ticket and the design table so that the
+// What issuing a sweep needs, copied out of the tickets and the design table so that the
 // scheduler can capture and enqueue without holding the server's lock.
+struct Member {                 // one request (snapshot) of the sweep
+  const float *hx, *hy;         // pinned new coordinates, or NULL: the design's
+  float *hdx, *hdy;
+  double* hsc;
+};
 struct Issue {
   int design, kind;
   float gamma;
-  const float *hx, *hy;
-  float *hdx, *hdy;
-  double* hsc;
+  int S;                        // snapshots: 1 runs the request's own graph of one snapshot
+  bool new_xy;                  // the sweep reads coordinates from its buffer (always when S > 1)
+  std::vector<Member> m;
 };
 
 // Where a request's buffers sit inside its slot's buffer.
@@ -142,35 +161,40 @@ struct sta_server {
   PinnedPool pinned;
   sta_server_stats stats{};
 
-  size_t request_bytes(const Design& d, int kind, bool new_xy) const {
-    size_t b = align256(d.state_bytes) + align256(4 * sizeof(double));
-    if (kind == STA_REQ_FWD_BWD) b += align256(d.work_bytes) + 2 * align256(sizeof(float) * (size_t)d.P);
-    if (new_xy) b += 2 * align256(sizeof(float) * (size_t)d.P);
+  // Device bytes of a sweep of S snapshots (every per-call buffer holds S copies back to back).
+  size_t request_bytes(const Design& d, int kind, bool new_xy, int S = 1) const {
+    const size_t n = (size_t)S;
+    size_t b = align256(n * d.state_bytes) + align256(n * 4 * sizeof(double));
+    if (kind == STA_REQ_FWD_BWD) b += align256(n * d.work_bytes) + 2 * align256(n * sizeof(float) * (size_t)d.P);
+    if (new_xy || S > 1) b += 2 * align256(n * sizeof(float) * (size_t)d.P);
     return b;
   }
 
-  static Carve carve(void* base, const Design& d, int kind, bool new_xy) {
+  static Carve carve(void* base, const Design& d, int kind, bool new_xy, int S) {
     char* p = static_cast<char*>(base);
     auto take = [&](size_t bytes) {
       char* r = p;
       p += align256(bytes);
       return r;
     };
-    const size_t fb = sizeof(float) * (size_t)d.P;
+    const size_t n = (size_t)S, fb = sizeof(float) * (size_t)d.P;
     Carve c{};
-    c.state = take(d.state_bytes);
-    c.sc = reinterpret_cast<double*>(take(4 * sizeof(double)));
+    c.state = take(n * d.state_bytes);
+    c.sc = reinterpret_cast<double*>(take(n * 4 * sizeof(double)));
     if (kind == STA_REQ_FWD_BWD) {
-      c.ws = take(d.work_bytes);
-      c.dx = reinterpret_cast<float*>(take(fb));
-      c.dy = reinterpret_cast<float*>(take(fb));
+      c.ws = take(n * d.work_bytes);
+      c.dx = reinterpret_cast<float*>(take(n * fb));
+      c.dy = reinterpret_cast<float*>(take(n * fb));
     }
-    if (new_xy) {
-      c.x = reinterpret_cast<float*>(take(fb));
-      c.y = reinterpret_cast<float*>(take(fb));
+    if (new_xy || S > 1) {
+      c.x = reinterpret_cast<float*>(take(n * fb));
+      c.y = reinterpret_cast<float*>(take(n * fb));
     }
     return c;
   }
+
+  int max_merge() const { return std::max(1, cfg.max_merge); }   // under mu
+  int merge_size = 1;   // the largest max_merge set so far: slot buffers grow to hold it
 
   size_t held() const {
     size_t b = 0;
@@ -184,23 +208,32 @@ struct sta_server {
     sl.graph_order.clear();
   }
 
-  // Picks an idle slot for a request of `need` bytes and makes its buffer large enough,
-  // within the budget: an idle slot that already fits, else the idle slot with the largest
-  // buffer grown (to the largest request any resident design makes, when that fits the
-  // budget), releasing other idle slots' buffers if needed.  -1: wait for a slot to finish.
-  int pick_slot(size_t need) {
+  // Picks an idle slot for a sweep of `need` bytes and makes its buffer large enough, within
+  // the budget: an idle slot that already fits (first one that holds the sweep's captured
+  // launch sequence, else the smallest), else the idle slot with the largest buffer grown
+  // (to the largest sweep any resident design makes, when that fits the budget), releasing
+  // other idle slots' buffers if needed.  -1: wait for a slot to finish.
+  int pick_slot(size_t need, const GraphKey& key) {
     int fit = -1, grow = -1;
+    bool fit_has = false;
     for (int i = 0; i < (int)slots.size(); ++i) {
       const Slot& sl = slots[i];
       if (sl.busy) continue;
-      if (sl.cap >= need && (fit < 0 || sl.cap < slots[fit].cap)) fit = i;
+      if (sl.cap >= need) {
+        const bool has = sl.graphs.count(key) != 0;
+        if (fit < 0 || (has && !fit_has) || (has == fit_has && sl.cap < slots[fit].cap)) {
+          fit = i;
+          fit_has = has;
+        }
+      }
       if (grow < 0 || sl.cap > slots[grow].cap) grow = i;
     }
     if (fit >= 0) return fit;
     if (grow < 0) return -1;
     const size_t budget = (size_t)cfg.hbm_budget_bytes;
     size_t target = need;
-    for (const Design& d : designs) target = std::max(target, request_bytes(d, STA_REQ_FWD_BWD, true));
+    for (const Design& d : designs)
+      target = std::max(target, request_bytes(d, STA_REQ_FWD_BWD, true, d.can_merge ? merge_size : 1));
     Slot& g = slots[grow];
     auto others = [&] { return held() - g.cap; };
     if (resident + others() + target > budget) target = need;
@@ -214,11 +247,14 @@ struct sta_server {
         }
       if (resident + others() + target > budget) return -1;
     }
+    const auto t0 = Clock::now();
     drop_graphs(g);
     if (g.buf) (void)hipFreeAsync(g.buf, g.s);
     g.buf = nullptr;
     g.cap = 0;
     hipError_t e = hipMallocFromPoolAsync(&g.buf, target, pool, g.s);
+    ++stats.slot_grows;
+    stats.grow_ms += ms_between(t0, Clock::now());
     if (e != hipSuccess) {
       g.buf = nullptr;
       return -2;
@@ -227,29 +263,37 @@ struct sta_server {
     return grow;
   }
 
-  // The captured launch sequence of (design, kind, coordinates, gamma) over the slot's
-  // buffer, captured on first use.  Called by the scheduler thread without the lock: the
-  // slot is marked busy, so nothing else touches it, and the design is a copy.
-  sta_status graph_for(Slot& sl, const Design& d, const Issue& q, hipGraphExec_t* out, int* captured) {
+  // The captured launch sequence of (design, kind, coordinates, gamma, snapshots) over the
+  // slot's buffer, captured on first use.  Called by the scheduler thread without the lock:
+  // the slot is marked busy, so nothing else touches it, and the design is a copy.  The
+  // server alone calls on a resident graph (sta_server_add_design), and only from this
+  // thread, so the snapshot count can be set for the capture and put back after it.
+  static GraphKey key_of(int design, int kind, bool new_xy, float gamma, int S) {
     uint32_t gb;
-    std::memcpy(&gb, &q.gamma, sizeof(gb));
-    const GraphKey key = std::make_tuple(q.design, q.kind, q.hx ? 1 : 0, gb);
+    std::memcpy(&gb, &gamma, sizeof(gb));
+    return std::make_tuple(design, kind, new_xy || S > 1 ? 1 : 0, gb, S);
+  }
+
+  sta_status graph_for(Slot& sl, const Design& d, const Issue& q, hipGraphExec_t* out, int* captured) {
+    const GraphKey key = key_of(q.design, q.kind, q.new_xy, q.gamma, q.S);
     auto it = sl.graphs.find(key);
     if (it != sl.graphs.end()) {
       *out = it->second;
       return STA_OK;
     }
-    const Carve c = carve(sl.buf, d, q.kind, q.hx != nullptr);
-    const float* x = q.hx ? c.x : d.x;
-    const float* y = q.hx ? c.y : d.y;
+    const Carve c = carve(sl.buf, d, q.kind, q.new_xy, q.S);
+    const float* x = q.new_xy ? c.x : d.x;
+    const float* y = q.new_xy ? c.y : d.y;
     hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    d.g->n_snap = q.S;
     sta_fwd_out fo{c.state, nullptr, nullptr, nullptr, c.sc};
     sta_status st = sta_forward(d.g, x, y, &fo, STA_SMOOTH, q.gamma, cap_stream);
     if (st == STA_OK && q.kind == STA_REQ_FWD_BWD) {
       sta_bwd_out bo{c.ws, nullptr, nullptr, nullptr, nullptr, c.dx, c.dy, 1.0f, nullptr};
       st = sta_backward(d.g, x, y, &fo, &bo, STA_GRAD, q.gamma, cap_stream);
     }
+    d.g->n_snap = 1;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap_stream, &graph);
     if (st != STA_OK) {
@@ -274,30 +318,58 @@ struct sta_server {
     return STA_OK;
   }
 
-  // Issues a request on slot sl: coordinates in, the captured sweeps, results out.  Runs
-  // on the scheduler thread without the lock (see graph_for).
+  // Issues a sweep on slot sl: coordinates in (snapshot j at offset j * P), the captured
+  // launch sequence, results out.  Runs on the scheduler thread without the lock (see
+  // graph_for).
   sta_status issue(Slot& sl, const Design& d, const Issue& q, int* captured) {
-    const Carve c = carve(sl.buf, d, q.kind, q.hx != nullptr);
-    const size_t fb = sizeof(float) * (size_t)d.P;
-    hipError_t e;
+    const Carve c = carve(sl.buf, d, q.kind, q.new_xy, q.S);
+    const size_t P = (size_t)d.P, fb = sizeof(float) * P;
+    hipError_t e = hipSuccess;
     hipGraphExec_t exec = nullptr;
     sta_status st = graph_for(sl, d, q, &exec, captured);
     if (st != STA_OK) return st;
-    if (q.hx) {
-      if ((e = hipMemcpyAsync(c.x, q.hx, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(c.y, q.hy, fb, hipMemcpyHostToDevice, sl.s)) != hipSuccess)
-        return hip_fail(e, "hipMemcpyAsync");
+    if (q.new_xy) {
+      for (size_t j = 0; j < q.m.size() && e == hipSuccess; ++j) {
+        const Member& m = q.m[j];
+        if (m.hx) {
+          if ((e = hipMemcpyAsync(c.x + j * P, m.hx, fb, hipMemcpyHostToDevice, sl.s)) == hipSuccess)
+            e = hipMemcpyAsync(c.y + j * P, m.hy, fb, hipMemcpyHostToDevice, sl.s);
+        } else if ((e = hipMemcpyAsync(c.x + j * P, d.x, fb, hipMemcpyDeviceToDevice, sl.s)) == hipSuccess) {
+          e = hipMemcpyAsync(c.y + j * P, d.y, fb, hipMemcpyDeviceToDevice, sl.s);
+        }
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     }
     if ((e = hipGraphLaunch(exec, sl.s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    if (q.kind == STA_REQ_FWD_BWD) {
-      if ((e = hipMemcpyAsync(q.hdx, c.dx, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
-          (e = hipMemcpyAsync(q.hdy, c.dy, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+    for (size_t j = 0; j < q.m.size(); ++j) {
+      const Member& m = q.m[j];
+      if (q.kind == STA_REQ_FWD_BWD) {
+        if ((e = hipMemcpyAsync(m.hdx, c.dx + j * P, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess ||
+            (e = hipMemcpyAsync(m.hdy, c.dy + j * P, fb, hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
+          return hip_fail(e, "hipMemcpyAsync");
+      }
+      if ((e = hipMemcpyAsync(m.hsc, c.sc + 4 * j, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     }
-    if ((e = hipMemcpyAsync(q.hsc, c.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, sl.s)) != hipSuccess)
-      return hip_fail(e, "hipMemcpyAsync");
     if ((e = hipEventRecord(sl.done, sl.s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return STA_OK;
+  }
+
+  // Queue positions of the requests a sweep headed by the queue's front request takes:
+  // itself and the earliest waiting requests of the same design, kind and gamma, as many
+  // as the largest power of two up to max_merge allows.
+  std::vector<size_t> batch_of(const Ticket& head) {
+    std::vector<size_t> pos{0};
+    if (!designs[head.design].can_merge) return pos;
+    const size_t lim = (size_t)max_merge();
+    for (size_t i = 1; i < queue.size() && pos.size() < lim; ++i) {
+      const Ticket& t = tickets[queue[i]];
+      if (t.design == head.design && t.kind == head.kind && t.gamma == head.gamma) pos.push_back(i);
+    }
+    size_t S = 1;
+    while (2 * S <= pos.size()) S *= 2;
+    pos.resize(S);
+    return pos;
   }
 
   void finish(Ticket& t, TicketState st) {
@@ -322,61 +394,91 @@ struct sta_server {
           ++busy;
           continue;
         }
-        Ticket& t = tickets[sl.ticket];
-        if (e == hipSuccess) {
-          finish(t, kDone);
-          ++stats.completed;
-        } else {
-          t.err = hip_fail(e, "request execution");
-          t.msg = sta_last_error();
-          finish(t, kFailed);
+        std::string msg;
+        sta_status err = STA_OK;
+        if (e != hipSuccess) {
+          err = hip_fail(e, "request execution");
+          msg = sta_last_error();
         }
+        for (uint64_t id : sl.batch) {
+          Ticket& t = tickets[id];
+          if (e == hipSuccess) {
+            finish(t, kDone);
+            ++stats.completed;
+          } else {
+            t.err = err;
+            t.msg = msg;
+            finish(t, kFailed);
+          }
+        }
+        sl.batch.clear();
         sl.busy = false;
         progress = true;
       }
       if (progress) finished.notify_all();
-      // Admissions, in arrival order.
+      // Admissions, in arrival order of the sweeps' first requests.
       while (!queue.empty()) {
-        const uint64_t id = queue.front();
-        Ticket& t = tickets[id];
-        const int k = pick_slot(t.need);
+        Ticket& head = tickets[queue.front()];
+        std::vector<size_t> pos = batch_of(head);
+        int k = -1;
+        for (;;) {                               // a smaller batch when a larger one cannot fit
+          const int S = (int)pos.size();
+          k = pick_slot(request_bytes(designs[head.design], head.kind, head.hx != nullptr, S),
+                        key_of(head.design, head.kind, head.hx != nullptr, head.gamma, S));
+          if (k != -1 || pos.size() == 1) break;
+          pos.resize(pos.size() / 2);
+        }
         if (k == -1) break;
         if (k == -2) {
+          const uint64_t id = queue.front();
           queue.pop_front();
+          Ticket& t = tickets[id];
           t.err = fail(STA_E_NOMEM, "slot buffer allocation failed");
           t.msg = sta_last_error();
           finish(t, kFailed);
           finished.notify_all();
           continue;
         }
-        queue.pop_front();
-        t.t_admit = Clock::now();
-        t.st = kRunning;
-        t.slot = k;
+        std::vector<uint64_t> ids;
+        for (size_t i : pos) ids.push_back(queue[i]);
+        for (size_t i = pos.size(); i-- > 0;) queue.erase(queue.begin() + (std::ptrdiff_t)pos[i]);
         Slot& sl = slots[k];
         sl.busy = true;
-        sl.ticket = id;
-        const Issue q{t.design, t.kind, t.gamma, t.hx, t.hy, t.hdx, t.hdy, t.hsc};
-        const Design d = designs[t.design];
+        sl.batch = ids;
+        const Ticket& t0 = tickets[ids[0]];
+        Issue q{t0.design, t0.kind, t0.gamma, (int)ids.size(), ids.size() > 1 || t0.hx != nullptr, {}};
+        const auto now = Clock::now();
+        for (uint64_t id : ids) {
+          Ticket& t = tickets[id];
+          t.t_admit = now;
+          t.st = kRunning;
+          t.slot = k;
+          q.m.push_back(Member{t.hx, t.hy, t.hdx, t.hdy, t.hsc});
+        }
+        const Design d = designs[t0.design];
         // Capture (first use of a key on this slot) and enqueue without the lock, so that
         // clients can submit and poll meanwhile.
         int captured = 0;
-        const auto c0 = Clock::now();
         lk.unlock();
         sta_status st = issue(sl, d, q, &captured);
         std::string msg = st == STA_OK ? std::string() : std::string(sta_last_error());
         lk.lock();
         stats.captures += captured;
-        if (captured) stats.capture_ms += ms_between(c0, Clock::now());
+        if (captured) stats.capture_ms += ms_between(now, Clock::now());
         if (st != STA_OK) {
-          Ticket& tf = tickets[id];
-          tf.err = st;
-          tf.msg = msg;
-          finish(tf, kFailed);
+          for (uint64_t id : ids) {
+            Ticket& tf = tickets[id];
+            tf.err = st;
+            tf.msg = msg;
+            finish(tf, kFailed);
+          }
+          sl.batch.clear();
           sl.busy = false;
           finished.notify_all();
           continue;
         }
+        ++stats.sweeps;
+        if (ids.size() > 1) stats.merged += (int64_t)ids.size();
         ++busy;
         progress = true;
       }
@@ -397,6 +499,8 @@ sta_status sta_server_create(const sta_server_config* cfg, sta_server** out) {
   if (!cfg || !out) return fail(STA_E_INVALID, "NULL argument");
   if (cfg->hbm_budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_slots > 64 || cfg->queue_capacity < 1)
     return fail(STA_E_INVALID, "server configuration out of range");
+  if (cfg->max_merge < 0 || cfg->max_merge > 64 || (cfg->max_merge & (cfg->max_merge - 1)) != 0)
+    return fail(STA_E_INVALID, "max_merge must be 0 or a power of two up to 64");
   *out = nullptr;
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -412,6 +516,7 @@ sta_status sta_server_create(const sta_server_config* cfg, sta_server** out) {
     return fail(STA_E_NOMEM, "host allocation failed");
   }
   s->cfg = *cfg;
+  s->merge_size = std::max(1, cfg->max_merge);
   s->device = dev;
   hipMemPoolProps props{};
   props.allocType = hipMemAllocationTypePinned;
@@ -477,6 +582,8 @@ sta_status sta_server_add_design(sta_server* s, sta_graph* g, const float* x, co
   d.P = g->P;
   d.state_bytes = g->state.total;
   d.work_bytes = g->work.total;
+  d.can_merge = !g->snap_inner && g->sched_cfg.level_scheme != STA_LEVEL_THREAD && g->n_designs == 1 &&
+                g->state.total <= (size_t)INT32_MAX;     // as sta_set_snapshots requires
   hipError_t e;
   if ((e = hipMalloc(&d.x, std::max<size_t>(fb, 4))) != hipSuccess) return hip_fail(e, "hipMalloc");
   if ((e = hipMalloc(&d.y, std::max<size_t>(fb, 4))) != hipSuccess) {
@@ -570,10 +677,21 @@ static sta_status fill_result(sta_server* s, uint64_t ticket, sta_result* r) {
   return STA_OK;
 }
 
+sta_status sta_server_set_max_merge(sta_server* s, int32_t max_merge) {
+  if (!s) return fail(STA_E_INVALID, "NULL argument");
+  if (max_merge < 0 || max_merge > 64 || (max_merge & (max_merge - 1)) != 0)
+    return fail(STA_E_INVALID, "max_merge must be 0 or a power of two up to 64");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->cfg.max_merge = max_merge;
+  s->merge_size = std::max(s->merge_size, max_merge);
+  return STA_OK;
+}
+
 sta_status sta_server_stats_get(sta_server* s, sta_server_stats* out) {
   if (!s || !out) return fail(STA_E_INVALID, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->stats;
+  s->pinned.counts(&out->pinned_allocs, &out->pinned_ms);
   return STA_OK;
 }
 

@@ -35,6 +35,7 @@ EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_grap
             "sta_forward", "sta_backward", "sta_backward_noalloc", "sta_get_schedule", "sta_set_schedule", "sta_tune",
             "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_set_snapshot_layout", "sta_server_create", "sta_server_add_design",
             "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy", "sta_server_stats_get",
+            "sta_server_set_max_merge",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
@@ -78,7 +79,7 @@ class StaSchedule(ctypes.Structure):
 
 class StaServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32)]
+                ("queue_capacity", ctypes.c_int32), ("max_merge", ctypes.c_int32)]
 
 
 class StaRequest(ctypes.Structure):
@@ -93,7 +94,9 @@ class StaResult(ctypes.Structure):
 
 
 class StaServerStats(ctypes.Structure):
-    _fields_ = [("completed", ctypes.c_int64), ("captures", ctypes.c_int64), ("capture_ms", ctypes.c_double)]
+    _fields_ = [("completed", ctypes.c_int64), ("captures", ctypes.c_int64), ("capture_ms", ctypes.c_double),
+                ("sweeps", ctypes.c_int64), ("merged", ctypes.c_int64), ("slot_grows", ctypes.c_int64),
+                ("grow_ms", ctypes.c_double), ("pinned_allocs", ctypes.c_int64), ("pinned_ms", ctypes.c_double)]
 
 
 class StaFwdOut(ctypes.Structure):
@@ -176,6 +179,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_server_destroy.restype = None
     lib.sta_server_stats_get.argtypes = [_P, ctypes.POINTER(StaServerStats)]
     lib.sta_server_stats_get.restype = S
+    lib.sta_server_set_max_merge.argtypes = [_P, ctypes.c_int32]
+    lib.sta_server_set_max_merge.restype = S
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_enable.restype = S
     lib.sta_profile_read.argtypes = [_P, _P, _P]
@@ -464,9 +469,11 @@ class Server:
     """Serving loop of libsta: resident designs, admission against a device-memory budget
     and continuous batching of requests (the C server's scheduler thread runs them)."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, queue_capacity: int = 4096):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 8, queue_capacity: int = 4096, max_merge: int = 8):
+        """max_merge: waiting requests of one design, kind and gamma swept together as
+        snapshots of one launch sequence, at most (a power of two; 1 runs each alone)."""
         load_library()
-        cfg = StaServerConfig(int(hbm_budget_bytes), int(max_slots), int(queue_capacity))
+        cfg = StaServerConfig(int(hbm_budget_bytes), int(max_slots), int(queue_capacity), int(max_merge))
         h = _P()
         _check(_lib.sta_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -493,10 +500,10 @@ class Server:
         return t.value
 
     @staticmethod
-    def _result(r: StaResult) -> dict:
+    def _result(r: StaResult, grad: bool = True) -> dict:
         out = dict(scalars=np.array(r.scalars[:], np.float64), queue_ms=r.queue_ms, latency_ms=r.latency_ms,
                    kind=r.kind)
-        if r.dx:
+        if r.dx and grad:
             out["dx"] = np.ctypeslib.as_array(r.dx, (r.n_pins,)).copy()
             out["dy"] = np.ctypeslib.as_array(r.dy, (r.n_pins,)).copy()
         return out
@@ -509,16 +516,21 @@ class Server:
         _check(code)
         return self._result(r)
 
-    def wait(self, ticket: int, release: bool = True) -> dict:
+    def wait(self, ticket: int, release: bool = True, grad: bool = True) -> dict:
+        """Blocks until the request is done; grad=False leaves out the copy of its gradient."""
         r = StaResult()
         _check(_lib.sta_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(r)))
-        out = self._result(r)
+        out = self._result(r, grad)
         if release:
             self.release(ticket)
         return out
 
     def release(self, ticket: int):
         _check(_lib.sta_release(self._h, ctypes.c_uint64(ticket)))
+
+    def set_max_merge(self, max_merge: int):
+        """Waiting requests swept together as snapshots from now on, at most (1: each alone)."""
+        _check(_lib.sta_server_set_max_merge(self._h, int(max_merge)))
 
     def stats(self) -> dict:
         st = StaServerStats()

@@ -1,5 +1,6 @@
 """GPU tests of the serving loop (C server through the C ABI): results in a mix of
-concurrent requests equal the same requests run alone, admission under a tight budget."""
+concurrent requests, and in sweeps that merge waiting requests as snapshots, equal the same
+requests run alone; admission under a tight budget."""
 from __future__ import annotations
 
 import numpy as np
@@ -53,8 +54,8 @@ def _alone(g, d, grad, xy):
     return res
 
 
-def _serve(ds, gs, reqs, budget, slots=4):
-    srv = Server(budget, max_slots=slots)
+def _serve(ds, gs, reqs, budget, slots=4, merge=8):
+    srv = Server(budget, max_slots=slots, max_merge=merge)
     ids = [srv.add_design(g, d.x, d.y) for g, d in zip(gs, ds)]
     tickets = []
     for k, grad, xy in reqs:
@@ -72,10 +73,11 @@ def _same(a, b):
         assert np.array_equal(a["dx"], b["dx"]) and np.array_equal(a["dy"], b["dy"])
 
 
-def test_served_mix_equals_requests_run_alone():
+@pytest.mark.parametrize("merge", [1, 8])
+def test_served_mix_equals_requests_run_alone(merge):
     ds, gs = _designs()
     reqs = _requests(ds)
-    served = _serve(ds, gs, reqs, budget=8 << 30, slots=4)
+    served = _serve(ds, gs, reqs, budget=8 << 30, slots=4, merge=merge)
     lat = np.array([r["latency_ms"] for r in served])
     print(f"latency p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
     for (k, grad, xy), r in zip(reqs, served):
@@ -150,3 +152,48 @@ def test_ticket_errors_and_full_queue():
     with pytest.raises(StaError):
         srv.submit(i, grad=False, gamma=-1.0)
     srv.close()
+
+
+def test_waiting_requests_merge_into_snapshot_sweeps():
+    # One slot: while the first request captures and runs, the others wait, and the scheduler
+    # sweeps waiting requests of one kind and gamma together as snapshots (2, 4 or 8), new and
+    # resident coordinates mixed.  A design under the thread-per-net schedule always runs alone.
+    d = make_design(scaled_spec(30_000, cfg_id=49, box_um=800.0))
+    g = Graph.from_design(d)
+    g.levelize()
+    t = Graph.from_design(d)
+    t.levelize()
+    t.set_schedule(2, 2, 64, level_scheme="thread")
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(23):
+        xy = jitter(d, 2.0, stream=300 + i) if rng.random() < 0.5 else None
+        reqs.append((i % 7 == 3, bool(rng.random() < 0.5), xy, 10.0 if i % 5 else 20.0))
+    srv = Server(8 << 30, max_slots=1, max_merge=8)
+    ids = [srv.add_design(g, d.x, d.y), srv.add_design(t, d.x, d.y)]
+    tickets = [srv.submit(ids[int(th)], grad=grad, x=None if xy is None else xy[0],
+                          y=None if xy is None else xy[1], gamma=gm) for th, grad, xy, gm in reqs]
+    out = [srv.wait(q) for q in tickets]
+    st = srv.stats()
+    srv.set_max_merge(1)                     # from now on each request alone
+    more = [srv.submit(ids[0], grad=False) for _ in range(8)]
+    again = [srv.wait(q) for q in more]
+    st2 = srv.stats()
+    srv.close()
+    print(st, st2)
+    assert st["completed"] == len(reqs) and st["merged"] >= 4 and st["sweeps"] < len(reqs)
+    assert st2["merged"] == st["merged"] and st2["sweeps"] == st["sweeps"] + 8
+    for r in again[1:]:
+        _same(r, again[0])
+    for (th, grad, xy, gm), r in zip(reqs, out):
+        h = t if th else g
+        x = torch.tensor(d.x if xy is None else xy[0], device="cuda")
+        y = torch.tensor(d.y if xy is None else xy[1], device="cuda")
+        f = h.forward(x, y, gamma=gm)
+        ref = {"scalars": None}
+        if grad:
+            o = h.backward(x, y, f, rat=False, grad=True, pins=False)
+            ref["dx"], ref["dy"] = o["dx"].cpu().numpy(), o["dy"].cpu().numpy()
+        torch.cuda.synchronize()
+        ref["scalars"] = f.scalars.cpu().numpy()
+        _same(r, ref)

@@ -305,12 +305,14 @@ def test_checkpoint_frontier_counts(k):
 def test_server_rejects_bad_configuration():
     lib = S.load_library()
     h = S._P()
-    for cfg in ((0, 4, 16), (1 << 30, 0, 16), (1 << 30, 65, 16), (1 << 30, 4, 0)):
+    for cfg in ((0, 4, 16), (1 << 30, 0, 16), (1 << 30, 65, 16), (1 << 30, 4, 0),
+                (1 << 30, 4, 16, 3), (1 << 30, 4, 16, -1), (1 << 30, 4, 16, 128)):   # max_merge: 0 or 2^k <= 64
         c = S.StaServerConfig(*cfg)
         assert lib.sta_server_create(ctypes.byref(c), ctypes.byref(h)) == S.STA_E_INVALID
     assert lib.sta_submit(None, None, None) == S.STA_E_INVALID
     assert lib.sta_poll(None, 1, None) == S.STA_E_INVALID
     assert lib.sta_release(None, 1) == S.STA_E_INVALID
+    assert lib.sta_server_set_max_merge(None, 2) == S.STA_E_INVALID
     lib.sta_server_destroy(None)
 
 
