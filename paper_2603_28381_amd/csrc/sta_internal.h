@@ -19,8 +19,8 @@ constexpr int kLutCells = (STA_LUT_N - 1) * (STA_LUT_N - 1);
 constexpr int kFlatG0Default = 2;    // flat kernels (RC, outputs): smallest group 4 lanes
 constexpr int kSweepG0Default = 2;   // level kernels: smallest backward group 4 lanes (one per condition)
 constexpr int kTreeChunk = 1024;     // RC trees: pins of whole nets swept by one workgroup in LDS
-constexpr int kSiHeavy = 16;         // snapshot-inner layout: nets with more sinks take a whole
-                                     // 1024-thread workgroup for up to 64 snapshots,
+constexpr int kSiHeavy = 12;         // snapshot-inner layout: nets with more sinks take a whole
+                                     // workgroup for up to 64 snapshots,
 constexpr int kSiHuge = 128;         // nets with more than this a workgroup per 8 snapshots
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0

@@ -2050,10 +2050,12 @@ struct LaunchTimer {
 // when S <= 32), so the topology and tables it reads are the same for every lane of an item,
 // and every state load or store moves one contiguous run per item.  Sums over a net's sinks
 // and merges over a cell's arcs run inside each lane, in index order; nets of more than
-// kSiHeavy sinks take a whole kSiBlock workgroup whose threads split the sinks and meet in
-// LDS in thread order.
-constexpr int kSiBlock = 1024;
-constexpr int kSiWaves = kSiBlock / 64;
+// kSiHeavy sinks take a whole workgroup (kSiRcBlock threads in the RC stage, kSiBwdBlock in
+// the backward) whose threads split the sinks and meet in LDS in thread order.  The light
+// nets' waves come in workgroups of the same size: smaller workgroups let a CU start new
+// waves sooner after its slowest one, larger ones give a heavy net more threads per snapshot.
+constexpr int kSiRcBlock = 256;
+constexpr int kSiBwdBlock = 512;
 
 struct SiLane {
   int item;   // item of the lane counted from the launch's first (or, in a heavy workgroup,
@@ -2073,9 +2075,10 @@ __device__ __forceinline__ SiLane si_lane(int sl2, int S, int wave) {
 
 __device__ __forceinline__ uint32_t si_at(int i, uint32_t S, int s) { return (uint32_t)i * S + (uint32_t)s; }
 
-// Workgroups of heavy nets: each takes 1 << hl2 snapshots, so that 1024 >> hl2 threads split
-// the sinks of each snapshot; hl2 = sl2 for nets of up to kSiHuge sinks (a workgroup per net
-// and block of up to 64 snapshots) and min(sl2, 3) beyond (a workgroup per 8 snapshots).
+// Workgroups of heavy nets: each takes 1 << hl2 snapshots, so that (workgroup size) >> hl2
+// threads split the sinks of each snapshot; hl2 = sl2 for nets of up to kSiHuge sinks (a
+// workgroup per net and block of up to 64 snapshots) and min(sl2, 3) beyond (a workgroup per
+// 8 snapshots).
 // Workgroup hb of a class serves net hb / nch of the class and snapshot chunk hb % nch.
 __device__ __forceinline__ int chunks_of(int S, int hl2) { return (S + (1 << hl2) - 1) >> hl2; }
 __device__ __forceinline__ SiLane si_heavy_lane(int hl2, int S, int chunk) {
@@ -2149,21 +2152,21 @@ __device__ __forceinline__ void rc_heavy_si(const RcSiArgs& a, int n, const SiLa
   if (ln.on) {
     float xd, yd;
     driver_xy_si(a.x, a.y, a.io_perm, p0, S, ln.s, xd, yd);
-    for (int p = p0 + 1 + ln.item; p < p1; p += kSiBlock / lanes) sum += rc_sink_si(a, p, ln.s, xd, yd);
+    for (int p = p0 + 1 + ln.item; p < p1; p += kSiRcBlock / lanes) sum += rc_sink_si(a, p, ln.s, xd, yd);
   }
   sh[threadIdx.x] = sum;
   __syncthreads();
   if ((int)threadIdx.x < lanes && ln.on) {
     float tot = 0.f;
-    for (int t = (int)threadIdx.x; t < kSiBlock; t += lanes) tot += sh[t];
+    for (int t = (int)threadIdx.x; t < kSiRcBlock; t += lanes) tot += sh[t];
     rc_root_si(a, n, p0, ln.s, tot);
   }
 }
 
 // RC of every net: huge and heavy nets first (workgroups per net and snapshot chunk), then
 // (64 >> sl2) nets per wave.
-__global__ __launch_bounds__(kSiBlock) void k_rc_si(RcSiArgs a) {
-  __shared__ float sh[kSiBlock];
+__global__ __launch_bounds__(kSiRcBlock) void k_rc_si(RcSiArgs a) {
+  __shared__ float sh[kSiRcBlock];
   const int w = (int)(threadIdx.x >> 6);
   const int b = (int)blockIdx.x;
   const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
@@ -2177,7 +2180,7 @@ __global__ __launch_bounds__(kSiBlock) void k_rc_si(RcSiArgs a) {
                   sh);
     return;
   }
-  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiWaves + w);
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiRcBlock / 64 + w);
   const int n = ln.item;
   if (n >= a.N || !ln.on) return;
   const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
@@ -2651,7 +2654,7 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
 }
 
 // Backward work of net n for the lane's snapshot (the three phases of bwd_net).  In a heavy
-// workgroup (kHeavy) the 1024 >> hl2 threads of a snapshot split the sinks and their
+// workgroup (kHeavy) the kSiBwdBlock >> hl2 threads of a snapshot split the sinks and their
 // reductions meet in LDS in thread order; the first thread of each snapshot then runs the
 // cell step.
 template <bool kGrad, bool kHeavy>
@@ -2670,7 +2673,7 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int lanes = 1 << hl2;                   // heavy workgroups: snapshots per workgroup
   const int first = kHeavy ? ln.item : 0;
-  const int stride = kHeavy ? kSiBlock / lanes : 1;
+  const int stride = kHeavy ? kSiBwdBlock / lanes : 1;
   if (ln.on) {
 #pragma unroll 4
     for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
@@ -2678,16 +2681,16 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   const bool leader = !kHeavy || (int)threadIdx.x < lanes;
   if (kHeavy) {
 #pragma unroll
-    for (int i = 0; i < N_ACC; ++i) sh[i * kSiBlock + threadIdx.x] = acc[i];
+    for (int i = 0; i < N_ACC; ++i) sh[i * kSiBwdBlock + threadIdx.x] = acc[i];
     __syncthreads();
     if (leader) {
-      for (int u = (int)threadIdx.x + lanes; u < kSiBlock; u += lanes) {
-        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kSiBlock + u]);
-        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kSiBlock + u]);
-        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kSiBlock + u]);
-        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kSiBlock + u]);
+      for (int u = (int)threadIdx.x + lanes; u < kSiBwdBlock; u += lanes) {
+        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kSiBwdBlock + u]);
+        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kSiBwdBlock + u]);
+        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kSiBwdBlock + u]);
+        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kSiBwdBlock + u]);
 #pragma unroll
-        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kSiBlock + u];
+        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kSiBwdBlock + u];
       }
     }
   }
@@ -2708,9 +2711,9 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
     }
   }
   if (kHeavy) {
-    if (leader) sh[N_ACC * kSiBlock + threadIdx.x] = lbar;
+    if (leader) sh[N_ACC * kSiBwdBlock + threadIdx.x] = lbar;
     __syncthreads();
-    lbar = sh[N_ACC * kSiBlock + (threadIdx.x & (unsigned)(lanes - 1))];
+    lbar = sh[N_ACC * kSiBwdBlock + (threadIdx.x & (unsigned)(lanes - 1))];
   }
   // Elmore adjoint of every sink (the sinks are read again).
   if (kGrad && ln.on && (a.dx || a.dy)) {
@@ -2728,8 +2731,8 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
 // One backward level: the level's huge nets [nu0, ne) and heavy nets [nh0, nu0) first, a
 // workgroup per net and snapshot chunk, then the nets [nb, nh0), (64 >> sl2) per wave.
 template <bool kGrad>
-__global__ __launch_bounds__(kSiBlock) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
-  __shared__ float sh[N_ACC * kSiBlock + kSiBlock];
+__global__ __launch_bounds__(kSiBwdBlock) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
+  __shared__ float sh[N_ACC * kSiBwdBlock + kSiBwdBlock];
   const int w = (int)(threadIdx.x >> 6);
   const int b = (int)blockIdx.x;
   const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
@@ -2742,7 +2745,7 @@ __global__ __launch_bounds__(kSiBlock) void k_bwd_level_si(int nb, int nh0, int 
       bwd_net_si<kGrad, true>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
     return;
   }
-  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiWaves + w);
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiBwdBlock / 64 + w);
   const int n = nb + ln.item;
   if (n >= nh0 || !ln.on) return;
   bwd_net_si<kGrad, false>(a, sl, n, ln, a.sl2, sh);
@@ -2860,7 +2863,7 @@ sta_status launch_forward_si(sta_graph* g, const float* x, const float* y, const
     const RcSiArgs ra{d.net_off, d.pin_cap, x, y, io, d.si_heavy, d.si_huge, wire, load, rec, g->N, g->N0, D.S, D.sl2,
                       nh, nu, D.split ? kSiHeavy : INT32_MAX, g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at,
                       g->cons.pi_slew};
-    k_rc_si<<<dim3((unsigned)(nh * D.hch + nu * D.uch) + si_blocks(g->N, D.sl2, kSiWaves), D.gy), kSiBlock, 0,
+    k_rc_si<<<dim3((unsigned)(nh * D.hch + nu * D.uch) + si_blocks(g->N, D.sl2, kSiRcBlock / 64), D.gy), kSiRcBlock, 0,
               s>>>(ra);
   }
   const FwdSiArgs fa{d.ell, load, wire, rec, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps,
@@ -2922,13 +2925,13 @@ sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, cons
     const int hs = D.split ? g->si_hs[l] : hi, us = D.split ? g->si_us[l] : hi;
     if (hi == lo) continue;
     const unsigned blocks =
-        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kSiWaves);
+        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kSiBwdBlock / 64);
     LaunchTimer t(g, s, STA_K_BWD_LEVEL);
     const Slots sl = level_slots(g, l);
     if (grad)
-      k_bwd_level_si<true><<<dim3(blocks, D.gy), kSiBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
+      k_bwd_level_si<true><<<dim3(blocks, D.gy), kSiBwdBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
     else
-      k_bwd_level_si<false><<<dim3(blocks, D.gy), kSiBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
+      k_bwd_level_si<false><<<dim3(blocks, D.gy), kSiBwdBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
   }
   if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
