@@ -684,10 +684,12 @@ def run_rc(args) -> dict:
 
         r = {"pins": P, "rc_alg_bytes": float(np.sum(alg["rc"]))}
         # RC stage as lane groups, task pool or one thread per net (level kernels in lane
-        # groups), and one thread per net and cell in every stage ("thread_all")
+        # groups), the task pool in the RC stage and the level kernels ("cte_all", the paper's
+        # whole-STA CTE column), and one thread per net and cell in every stage ("thread_all")
         for scheme, level in (("groups", "groups"), ("cte", "groups"), ("thread", "groups"),
-                              ("thread_all", "thread")):
-            g.set_schedule(2, 2, 64, "thread" if scheme == "thread_all" else scheme, 16, level)
+                              ("cte_all", "cte"), ("thread_all", "thread")):
+            rc = {"thread_all": "thread", "cte_all": "cte"}.get(scheme, scheme)
+            g.set_schedule(2, 2, 64, rc, 16, level)
             ms = timed(step, args.steps, args.warmup)[0]
             g.profile(True)
             for _ in range(args.steps):
@@ -705,7 +707,8 @@ def run_rc(args) -> dict:
         r["groups_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["groups"]["rc_us"], 2)
         r["cte_speedup_vs_thread"] = round(r["thread"]["rc_us"] / r["cte"]["rc_us"], 2)
         r["step_speedup_vs_thread_all"] = {k: round(r["thread_all"]["step_ms"] / r[k]["step_ms"], 3)
-                                           for k in ("groups", "cte", "thread")}
+                                           for k in ("groups", "cte", "thread", "cte_all")}
+        r["cte_all_step_vs_groups"] = round(r["cte_all"]["step_ms"] / r["groups"]["step_ms"], 3)
         res[name] = r
         del state, ws, outs, g
         torch.cuda.empty_cache()

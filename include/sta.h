@@ -294,9 +294,13 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
  * each lane looking up all of the cell's arcs): fewer lanes launch fewer waves, which pays
  * when many snapshots fill the chip, while one design's short levels favour 16.
  * level_scheme STA_LEVEL_THREAD runs the whole sweep with one thread per net and per cell
- * (the snapshot-lane kernels with one lane per item; other fields then do not apply); it
- * needs one snapshot, no checkpointing and star nets (else STA_E_INVALID, and
- * sta_set_checkpointing refuses a stride while it is set).  Defaults
+ * (the snapshot-lane kernels with one lane per item; other fields then do not apply), and
+ * STA_LEVEL_CTE runs the level kernels in the CTE scheme (Alg. 2 applied to arrival
+ * propagation and slack computation, Sec. 3.1.2: a workgroup pools the inputs of 16 cells,
+ * or the sinks and then the driving cells' inputs of 16 nets, and rebalances them over its
+ * 256 threads; rc_scheme still picks the RC stage).  Both need one snapshot, no checkpointing,
+ * the snapshot-outer layout and star nets (else STA_E_INVALID; sta_set_checkpointing,
+ * sta_set_snapshots and sta_set_snapshot_layout refuse what they exclude while set).  Defaults
  * {2, 2, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS}.
  * Setting a schedule rebuilds the launch plan (no result changes beyond float summation
  * order).  Errors: STA_E_INVALID for out-of-range fields,
@@ -310,6 +314,8 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
 #define STA_LEVEL_THREAD 1   /* one thread per net and per cell in every stage (RC, levels,
                                 endpoints), the mapping of earlier GPU timers; one snapshot,
                                 no checkpointing, star nets */
+#define STA_LEVEL_CTE 2      /* level kernels over a workgroup task pool (Alg. 2); one
+                                snapshot, no checkpointing, star nets */
 
 typedef struct sta_schedule {
   int32_t sweep_group_log2;   /* 2..6 */
@@ -317,7 +323,7 @@ typedef struct sta_schedule {
   int32_t heavy_sinks;        /* 1..64 */
   int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */
   int32_t fwd_cell_lanes;     /* 16, 8 or 4 */
-  int32_t level_scheme;       /* STA_LEVEL_GROUPS or STA_LEVEL_THREAD */
+  int32_t level_scheme;       /* STA_LEVEL_GROUPS, STA_LEVEL_THREAD or STA_LEVEL_CTE */
 } sta_schedule;
 
 sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);
@@ -328,8 +334,8 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
  * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Candidates:
  * sweep_group_log2 2..6 x flat_group_log2 2..4 x heavy_sinks {32, 64} with lane-group RC
  * and 16 forward lanes, then on the best of those the CTE and thread RC mappings, then 8
- * and 4 forward lanes, then (one snapshot, no checkpointing, star nets) one thread per net
- * in every stage.  Allocates
+ * and 4 forward lanes, then (one snapshot, no checkpointing, star nets) the CTE scheme in
+ * the RC stage and the level kernels, and one thread per net in every stage.  Allocates
  * and frees its own device buffers; synchronizes the stream.  Errors: as sta_forward. */
 sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
                     sta_schedule* best, sta_stream stream);
@@ -392,7 +398,8 @@ typedef struct sta_server_config {
   int32_t max_merge;           /* requests swept together as snapshots, at most (0 or 1: each
                                   alone; else a power of two up to 64).  Merging needs the
                                   snapshot-outer layout and lane-group schedules (a design
-                                  under STA_SNAP_INNER or STA_LEVEL_THREAD runs alone). */
+                                  under STA_SNAP_INNER, STA_LEVEL_THREAD or STA_LEVEL_CTE
+                                  runs alone). */
 } sta_server_config;
 
 #define STA_REQ_FWD 0          /* forward sweep: scalars only */

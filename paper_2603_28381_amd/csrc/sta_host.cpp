@@ -829,12 +829,14 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
       sch->flat_group_log2 > 6 || sch->heavy_sinks < 1 || sch->heavy_sinks > 64 || sch->rc_scheme < STA_RC_GROUPS ||
       sch->rc_scheme > STA_RC_THREAD ||
       (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4) ||
-      (sch->level_scheme != STA_LEVEL_GROUPS && sch->level_scheme != STA_LEVEL_THREAD))
+      (sch->level_scheme != STA_LEVEL_GROUPS && sch->level_scheme != STA_LEVEL_THREAD &&
+       sch->level_scheme != STA_LEVEL_CTE))
     return fail(STA_E_INVALID, "schedule out of range");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
-  if (sch->level_scheme == STA_LEVEL_THREAD && (g->n_snap != 1 || g->snap_inner || g->ckpt_stride > 0 ||
+  if (sch->level_scheme != STA_LEVEL_GROUPS && (g->n_snap != 1 || g->snap_inner || g->ckpt_stride > 0 ||
                                                 !g->c_parent.empty()))
-    return fail(STA_E_INVALID, "one thread per net needs one snapshot, no checkpointing and star nets");
+    return fail(STA_E_INVALID, "one thread per net and the CTE level kernels need one snapshot, no checkpointing "
+                               "and star nets");
   g->sched_cfg = *sch;
   try {
     build_groups(g);
@@ -855,8 +857,9 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   int k = stride_levels;
   if (k < 0) k = std::max(1, (int)std::ceil(std::sqrt((double)std::max(1, g->L - 1))));
-  if (k > 0 && g->lanes_kernels())
-    return fail(STA_E_INVALID, "checkpointing is not available with STA_SNAP_INNER or one thread per net");
+  if (k > 0 && (g->lanes_kernels() || g->sched_cfg.level_scheme != STA_LEVEL_GROUPS))
+    return fail(STA_E_INVALID,
+                "checkpointing is not available with STA_SNAP_INNER, one thread per net or the CTE level kernels");
   g->ckpt_stride = k;
   try {
     build_ell(g);
@@ -871,8 +874,8 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
 sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots) {
   if (!g) return fail(STA_E_INVALID, "graph is NULL");
   if (n_snapshots < 1 || n_snapshots > 65535) return fail(STA_E_INVALID, "snapshot count out of range");
-  if (n_snapshots > 1 && g->sched_cfg.level_scheme == STA_LEVEL_THREAD)
-    return fail(STA_E_INVALID, "one thread per net sweeps one snapshot");
+  if (n_snapshots > 1 && g->sched_cfg.level_scheme != STA_LEVEL_GROUPS)
+    return fail(STA_E_INVALID, "one thread per net and the CTE level kernels sweep one snapshot");
   g->n_snap = n_snapshots;
   drop_captured(g);
   return STA_OK;
@@ -886,8 +889,8 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout) {
     return fail(STA_E_INVALID, "STA_SNAP_INNER is not available with checkpointing");
   if (layout == STA_SNAP_INNER && !g->c_parent.empty())
     return fail(STA_E_INVALID, "STA_SNAP_INNER is not available for RC trees");
-  if (layout == STA_SNAP_INNER && g->sched_cfg.level_scheme == STA_LEVEL_THREAD)
-    return fail(STA_E_INVALID, "STA_SNAP_INNER replaces the thread-per-net schedule; set lane groups first");
+  if (layout == STA_SNAP_INNER && g->sched_cfg.level_scheme != STA_LEVEL_GROUPS)
+    return fail(STA_E_INVALID, "STA_SNAP_INNER replaces the level schedule; set lane groups first");
   g->snap_inner = layout == STA_SNAP_INNER;
   drop_captured(g);
   return STA_OK;

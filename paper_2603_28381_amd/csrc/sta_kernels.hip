@@ -438,6 +438,49 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
 // so a task is one sink rather than one (sink, condition) pair.  Root loads are summed in
 // task order from LDS, in chunks of kCteChunk tasks, by each net's own thread.
 constexpr int kCteChunk = 1024;
+
+// Work-efficient exclusive scan (Blelloch: up-sweep, then down-sweep) of the values of the
+// first kN threads of a workgroup (a power of two up to its size) into pre[0, kN); returns
+// the total.  Every thread of the workgroup calls it; it first waits until every thread is
+// done with the previous scan's pre[] and total.
+template <int kN = kBlock>
+__device__ __forceinline__ int cte_scan(int work, int* pre, int* total_sh) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if (t < kN) pre[t] = work;
+  for (int d = 1; d < kN; d <<= 1) {           // pre[t] becomes the sum of its subtree
+    __syncthreads();
+    if (t < kN && ((t + 1) & (2 * d - 1)) == 0) pre[t] += pre[t - d];
+  }
+  __syncthreads();
+  if (t == kN - 1) {
+    *total_sh = pre[t];
+    pre[t] = 0;
+  }
+  for (int d = kN / 2; d >= 1; d >>= 1) {      // exclusive prefix sums
+    __syncthreads();
+    if (t < kN && ((t + 1) & (2 * d - 1)) == 0) {
+      const int l = pre[t - d];
+      pre[t - d] = pre[t];
+      pre[t] += l;
+    }
+  }
+  __syncthreads();
+  return *total_sh;
+}
+
+// Owner of a task among kN items: the last one whose first task is not above it
+// (upper_bound - 1 on the exclusive scan).
+template <int kN = kBlock>
+__device__ __forceinline__ int cte_owner(const int* pre, int task) {
+  int lo = 0, hi = kN;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= task) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rc_cte(RcArgs a) {
   __shared__ int pre[kBlock];
   __shared__ int first[kBlock];
@@ -461,41 +504,16 @@ __global__ __launch_bounds__(kBlock) void k_rc_cte(RcArgs a) {
     xd = xs[q];
     yd = ys[q];
   }
-  pre[t] = work;
   first[t] = p0 + 1;
   dx_[t] = xd;
   dy_[t] = yd;
-  // Up-sweep: pre[t] becomes the sum of its subtree.
-  for (int d = 1; d < kBlock; d <<= 1) {
-    __syncthreads();
-    if (((t + 1) & (2 * d - 1)) == 0) pre[t] += pre[t - d];
-  }
-  __syncthreads();
-  if (t == kBlock - 1) {
-    total_sh = pre[t];
-    pre[t] = 0;
-  }
-  // Down-sweep: exclusive prefix sums.
-  for (int d = kBlock / 2; d >= 1; d >>= 1) {
-    __syncthreads();
-    if (((t + 1) & (2 * d - 1)) == 0) {
-      const int l = pre[t - d];
-      pre[t - d] = pre[t];
-      pre[t] += l;
-    }
-  }
-  __syncthreads();
-  const int total = total_sh;
+  const int total = cte_scan(work, pre, &total_sh);
   const int my0 = pre[t], my1 = t + 1 < kBlock ? pre[t + 1] : total;
   float sum = 0.f;
   for (int c0 = 0; c0 < total; c0 += kCteChunk) {
     const int c1 = min(total, c0 + kCteChunk);
     for (int task = c0 + t; task < c1; task += kBlock) {
-      int lo = 0, hi = kBlock;                 // upper_bound(pre, task) - 1
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= task) lo = mid; else hi = mid;
-      }
+      const int lo = cte_owner(pre, task);
       const int p = first[lo] + (task - pre[lo]);
       part[task - c0] = rc_sink(a, xs, ys, wire, p, dx_[lo], dy_[lo]);
     }
@@ -2041,6 +2059,306 @@ struct LaunchTimer {
   }
 };
 
+// Component i of v set to x (i known only at run time).
+__device__ __forceinline__ void set_comp(float4& v, int i, float x) {
+  v.x = i == 0 ? x : v.x;
+  v.y = i == 1 ? x : v.y;
+  v.z = i == 2 ? x : v.z;
+  v.w = i == 3 ? x : v.w;
+}
+
+// ============================================================================ CTE levels
+// The level kernels in the CTE scheme (Alg. 2; Sec. 3.1.2 applies the RC stage's mappings to
+// arrival propagation and slack computation): a workgroup takes kCteItems consecutive items
+// of a level, one per thread of its first kCteItems (cells in the forward, nets in the
+// backward), a work-efficient scan of their work numbers a pool of tasks (a cell's inputs, a
+// net's sinks), all 256 threads take tasks with a stride of 256, find the owning item with
+// cte_owner and leave their results in LDS, and each item's own thread merges its tasks in
+// task order (loops unrolled so that an item of many tasks reads its LDS entries in batches).  One snapshot, star nets, no
+// checkpointing (a net's record slot is the net, a sink's workspace slot its pin).  A
+// workgroup takes kCteItems items rather than one per thread: a level holds a few thousand
+// cells, and 256 per workgroup would leave most of the chip idle.
+constexpr int kCteLevelTasks = 512;   // tasks staged in LDS at a time
+constexpr int kCteItems = 16;         // items per workgroup
+
+// Valid inputs of cell kc: its input slots hold them first, then empty slots (source -1).
+// The slot entries are loaded together (a cell has at most STA_MAX_FANIN inputs).
+__device__ __forceinline__ int cell_fanin(const int4* __restrict__ ell, const Slots& sl, int kc) {
+  int f = 0;
+#pragma unroll
+  for (int j = 0; j < STA_MAX_FANIN; ++j)
+    f += j < sl.F && ell[sl.base + (size_t)min(j, sl.F - 1) * sl.nc + kc].x >= 0 ? 1 : 0;
+  return f;
+}
+
+// Forward level: a task is one input j of a cell, looked up for the four conditions; the
+// cell's thread merges its inputs in order (max / min arrival, worst slew, and the log-sum-exp
+// of the late smoothed candidates, Eq. 4) and writes the cell's output record.
+__global__ __launch_bounds__(kBlock) void k_fwd_level_cte(int nc, int n0, int base, int F,
+                                                          const int4* __restrict__ ell,
+                                                          const float* __restrict__ loads,
+                                                          float4* __restrict__ rec, FwdArgs a) {
+  __shared__ int pre[kBlock];
+  __shared__ int total_sh;
+  __shared__ float load_sh[kBlock];
+  __shared__ float part[10][kCteLevelTasks];   // per task: arrival and slew of conditions 0..3,
+                                               // then the late smoothed candidates
+  const Slots sl{base, F, 0, nc};
+  const int t = threadIdx.x;
+  const int kc = (int)blockIdx.x * kCteItems + t;
+  const bool own = t < kCteItems && kc < nc;
+  const int n = n0 + kc;
+  int work = 0;
+  if (own) {
+    work = cell_fanin(ell, sl, kc);
+    load_sh[t] = loads[n];
+  }
+  const int total = cte_scan<kCteItems>(work, pre, &total_sh);
+  const int my0 = own ? pre[t] : 0, my1 = own ? (t + 1 < kCteItems ? pre[t + 1] : total) : 0;
+  float bat[4], bsl[4], lm[2] = {-kInf, -kInf}, ls[2] = {0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bat[k] = bsl[k] = k >= 2 ? -kInf : kInf;
+  for (int c0 = 0; c0 < total; c0 += kCteLevelTasks) {
+    const int c1 = min(total, c0 + kCteLevelTasks);
+    for (int task = c0 + t; task < c1; task += kBlock) {
+      const int o = cte_owner<kCteItems>(pre, task);
+      const int ko = (int)blockIdx.x * kCteItems + o, j = task - pre[o];
+      const int4 e = ell[sl.base + (size_t)j * sl.nc + ko];
+      const float load = load_sh[o];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int m = k >> 1, tr = k & 1;
+        const ArcIn in = arc_input_entry(e, true, rec, a.wire, m, tr);
+        const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, tr, in.slew, load);
+        part[k][task - c0] = in.at + v.d;
+        part[4 + k][task - c0] = v.s;
+        if (m) part[8 + tr][task - c0] = in.atg + v.d;
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = max(my0, c0); i < min(my1, c1); ++i) {
+      const int q = i - c0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k >= 2) {
+          bat[k] = fmaxf(bat[k], part[k][q]);
+          bsl[k] = fmaxf(bsl[k], part[4 + k][q]);
+        } else {
+          bat[k] = fminf(bat[k], part[k][q]);
+          bsl[k] = fminf(bsl[k], part[4 + k][q]);
+        }
+      }
+      if (a.smooth) {
+        lse_merge(lm[0], ls[0], part[8][q], 1.f, a.inv_gamma);
+        lse_merge(lm[1], ls[1], part[9][q], 1.f, a.inv_gamma);
+      }
+    }
+    __syncthreads();
+  }
+  if (!own) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int m = k >> 1, tr = k & 1;
+    const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls[tr]), lm[tr]) : __builtin_nanf("")) : 0.f;
+    rec[kRecChunks * (size_t)n + k] = make_float4(bat[k], bsl[k], ag, 0.f);
+  }
+}
+
+// Backward level over nets [lo, hi): three task pools in turn.  The net step pools the
+// sinks (per-pin outputs, and each sink's share of the driver's reductions, merged by the
+// net's thread in sink order); the cell step pools the inputs of the driving cell (the late
+// lookups, whose softmax normaliser and arg-max slew the net's thread takes in input order,
+// then the four conditions' required times and adjoints written to the input pins and the
+// load adjoint summed in input order); the Elmore adjoint pools the sinks again.
+template <bool kCanon, bool kGrad>
+__global__ __launch_bounds__(kBlock) void k_bwd_level_cte(int lo, int hi, Slots sl, BwdArgs a) {
+  __shared__ int pre[kBlock];
+  __shared__ int first[kBlock];
+  __shared__ int total_sh;
+  __shared__ float4 at_sh[kBlock], sl_sh[kBlock];
+  __shared__ float xd_sh[kBlock], yd_sh[kBlock], load_sh[kBlock];
+  __shared__ float ro_sh[4][kBlock];            // the net's required times by condition
+  __shared__ float gs_sh[8][kBlock];            // abar[2], sbar[2], xmax[2], 1/z[2]
+  __shared__ int js_sh[2][kBlock];              // arg-max slew input per transition
+  __shared__ float cl_sh[kBlock];               // c * load adjoint
+  __shared__ float part[N_ACC][kCteLevelTasks];
+  const int t = threadIdx.x;
+  const int n = lo + (int)blockIdx.x * kCteItems + t;
+  const bool own = t < kCteItems && n < hi;
+  const bool cell = own && n >= a.N0 && sl.F > 0;
+  const int kc = n - a.N0 - sl.c0;
+  int p0 = 0, sinks = 0;
+  float4 at_d = make_float4(0.f, 0.f, 0.f, 0.f), sl_d = at_d;
+  float xd = 0.f, yd = 0.f;
+  if (own) {
+    p0 = a.net_off[n];
+    sinks = a.net_off[n + 1] - p0 - 1;
+    float4 c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = a.rec[kRecChunks * (size_t)n + k];
+    at_d = make_float4(c[0].x, c[1].x, c[2].x, c[3].x);
+    sl_d = make_float4(c[0].y, c[1].y, c[2].y, c[3].y);
+    if (kGrad) {
+      const int q = kCanon ? p0 : a.io_perm[p0];
+      xd = a.x[q];
+      yd = a.y[q];
+    }
+    if (cell) load_sh[t] = a.load[n];
+  }
+  first[t] = p0 + 1;
+  at_sh[t] = at_d;
+  sl_sh[t] = sl_d;
+  xd_sh[t] = xd;
+  yd_sh[t] = yd;
+
+  // Net step over the sinks.
+  float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int total = cte_scan<kCteItems>(sinks, pre, &total_sh);
+  int my0 = own ? pre[t] : 0, my1 = own ? (t + 1 < kCteItems ? pre[t + 1] : total) : 0;
+  for (int c0 = 0; c0 < total; c0 += kCteLevelTasks) {
+    const int c1 = min(total, c0 + kCteLevelTasks);
+    for (int task = c0 + t; task < c1; task += kBlock) {
+      const int o = cte_owner<kCteItems>(pre, task);
+      const int p = first[o] + (task - pre[o]);
+      float v[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      (void)sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p, p), at_sh[o], sl_sh[o], xd_sh[o], yd_sh[o], v, true, p);
+#pragma unroll
+      for (int i = 0; i < N_ACC; ++i) part[i][task - c0] = v[i];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = max(my0, c0); i < min(my1, c1); ++i) {
+      const int q = i - c0;
+      acc[R_E0] = fmaxf(acc[R_E0], part[R_E0][q]);
+      acc[R_E1] = fmaxf(acc[R_E1], part[R_E1][q]);
+      acc[R_L0] = fminf(acc[R_L0], part[R_L0][q]);
+      acc[R_L1] = fminf(acc[R_L1], part[R_L1][q]);
+#pragma unroll
+      for (int k = A_R; k < N_ACC; ++k) acc[k] += part[k][q];
+    }
+    __syncthreads();
+  }
+  ro_sh[0][t] = acc[R_E0];
+  ro_sh[1][t] = acc[R_E1];
+  ro_sh[2][t] = acc[R_L0];
+  ro_sh[3][t] = acc[R_L1];
+
+  // Cell step over the driving cell's inputs.
+  total = cte_scan<kCteItems>(cell ? cell_fanin(a.ell, sl, kc) : 0, pre, &total_sh);
+  my0 = own ? pre[t] : 0;
+  my1 = own ? (t + 1 < kCteItems ? pre[t + 1] : total) : 0;
+  float lbar = 0.f;
+  if (kGrad) {
+    // Late lookups: softmax normaliser and arg-max slew per output transition.
+    float xmax[2] = {-kInf, -kInf}, z[2] = {0.f, 0.f}, smax[2] = {-kInf, -kInf};
+    int jstar[2] = {STA_MAX_FANIN, STA_MAX_FANIN};
+    for (int c0 = 0; c0 < total; c0 += kCteLevelTasks) {
+      const int c1 = min(total, c0 + kCteLevelTasks);
+      for (int task = c0 + t; task < c1; task += kBlock) {
+        const int o = cte_owner<kCteItems>(pre, task);
+        const int ko = lo + (int)blockIdx.x * kCteItems + o - a.N0 - sl.c0, j = task - pre[o];
+        const int4 e = a.ell[sl.base + (size_t)j * sl.nc + ko];
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr) {
+          const ArcIn in = arc_input_entry(e, true, a.rec, a.wire, 1, tr);
+          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, in.arc, tr, in.slew, load_sh[o]);
+          part[2 * tr][task - c0] = in.atg + v.d;
+          part[2 * tr + 1][task - c0] = v.s;
+        }
+      }
+      __syncthreads();
+  #pragma unroll 8
+    for (int i = max(my0, c0); i < min(my1, c1); ++i) {
+        const int q = i - c0, j = i - my0;
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr) {
+          lse_merge(xmax[tr], z[tr], part[2 * tr][q], 1.f, a.inv_gamma);
+          if (jstar[tr] == STA_MAX_FANIN || part[2 * tr + 1][q] > smax[tr]) {
+            smax[tr] = part[2 * tr + 1][q];
+            jstar[tr] = j;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    gs_sh[0][t] = acc[A_R];
+    gs_sh[1][t] = acc[A_F];
+    gs_sh[2][t] = acc[S_R];
+    gs_sh[3][t] = acc[S_F];
+    gs_sh[4][t] = xmax[0];
+    gs_sh[5][t] = xmax[1];
+    gs_sh[6][t] = frcp(z[0]);
+    gs_sh[7][t] = frcp(z[1]);
+    js_sh[0][t] = jstar[0];
+    js_sh[1][t] = jstar[1];
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < total; c0 += kCteLevelTasks) {
+    const int c1 = min(total, c0 + kCteLevelTasks);
+    for (int task = c0 + t; task < c1; task += kBlock) {
+      const int o = cte_owner<kCteItems>(pre, task);
+      const int ko = lo + (int)blockIdx.x * kCteItems + o - a.N0 - sl.c0, j = task - pre[o];
+      const int4 e = a.ell[sl.base + (size_t)j * sl.nc + ko];
+      float4 rat_in = make_float4(0.f, 0.f, 0.f, 0.f), adj_in = rat_in;
+      float lb = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int m = k >> 1, tr = k & 1;
+        const ArcIn in = arc_input_entry(e, true, a.rec, a.wire, m, tr);
+        const LutVal v = lut_eval<kGrad>(a.grid, a.coef, a.keys, in.arc, tr, in.slew, load_sh[o]);
+        set_comp(rat_in, 2 * m + in.tp, ro_sh[k][o] - v.d);
+        if (kGrad && m == 1) {
+          const float dbar = fexp((in.atg + v.d - gs_sh[4 + tr][o]) * a.inv_gamma) * gs_sh[6 + tr][o] * gs_sh[tr][o];
+          const float s_j = j == js_sh[tr][o] ? gs_sh[2 + tr][o] : 0.f;
+          set_comp(adj_in, in.tp, dbar);
+          set_comp(adj_in, 2 + in.tp, fmaf(dbar, v.ddx, s_j * v.dsx));
+          lb = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb));
+        }
+      }
+      a.sink[rat_at(e.w)] = rat_in;
+      if (kGrad) a.sink[adj_at(e.w)] = adj_in;
+      part[0][task - c0] = lb;
+    }
+    __syncthreads();
+    if (kGrad) {
+#pragma unroll 8
+      for (int i = max(my0, c0); i < min(my1, c1); ++i) lbar += part[0][i - c0];
+    }
+    __syncthreads();
+  }
+
+  // The driver's outputs.
+  const float cl = a.c * lbar;
+  if (own) {
+    const uint32_t o0 = (uint32_t)(kCanon ? p0 : a.io_perm[p0]);
+    if (a.at_out) store_stream(at32(a.at_out, o0), at_d);
+    if (a.slew_out) store_stream(at32(a.slew_out, o0), sl_d);
+    if (a.rat_out) store_stream(at32(a.rat_out, o0), make_float4(acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]));
+    if (a.slack_out)
+      store_stream(at32(a.slack_out, o0),
+                   make_float4(at_d.x - acc[R_E0], at_d.y - acc[R_E1], acc[R_L0] - at_d.z, acc[R_L1] - at_d.w));
+    if (kGrad) {
+      if (a.dx) a.dx[o0] = -(acc[X_RS] + cl * acc[X_N]);
+      if (a.dy) a.dy[o0] = -(acc[Y_RS] + cl * acc[Y_N]);
+    }
+  }
+  if (!kGrad || !(a.dx || a.dy)) return;
+
+  // Elmore adjoint over the sinks.
+  cl_sh[t] = cl;
+  total = cte_scan<kCteItems>(sinks, pre, &total_sh);
+  for (int task = t; task < total; task += kBlock) {
+    const int o = cte_owner<kCteItems>(pre, task);
+    const int p = first[o] + (task - pre[o]);
+    float scratch[N_ACC] = {};
+    const SinkKeep k =
+        sink_step<kGrad>(a, sink_load<kCanon, kGrad>(a, p, p), at_sh[o], sl_sh[o], xd_sh[o], yd_sh[o], scratch, false, p);
+    if (a.dx) a.dx[k.q] = k.gx * (cl_sh[o] + k.rest);
+    if (a.dy) a.dy[k.q] = k.gy * (cl_sh[o] + k.rest);
+  }
+}
+
 // ============================================================================ snapshot lanes
 // The snapshot-inner layout (sta_set_snapshot_layout(g, STA_SNAP_INNER)): every per-call and
 // state array holds the S snapshots of an item side by side, element (i, s) at i*S + s (an
@@ -2561,13 +2879,6 @@ __device__ __forceinline__ SinkSi sink_si(const BwdSiArgs& a, int p, int s, cons
   return k;
 }
 
-__device__ __forceinline__ void set_comp(float4& v, int i, float x) {
-  v.x = i == 0 ? x : v.x;
-  v.y = i == 1 ? x : v.y;
-  v.z = i == 2 ? x : v.z;
-  v.w = i == 3 ? x : v.w;
-}
-
 // Cell step of cell kc in snapshot s (as the 4-lane backward group's, in one lane): the
 // inputs' required times, and with the gradient the softmax split of the driver's adjoint
 // over the arcs (normaliser and arg-max slew taken chunk by chunk of 4 arcs), the slew
@@ -2973,11 +3284,16 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
 
   const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, smooth ? 1.0f / gamma_ps : 0.f,
                    smooth ? 1 : 0};
+  const bool cte = g->sched_cfg.level_scheme == STA_LEVEL_CTE;
   for (int l = 1; l < g->L; ++l) {
     const Slots sl = level_slots(g, l);
     if (sl.nc == 0) continue;
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
-    fwd_level_launch(g, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
+    if (cte)
+      k_fwd_level_cte<<<(unsigned)((sl.nc + kCteItems - 1) / kCteItems), kBlock, 0, s>>>(
+          sl.nc, g->N0 + sl.c0, sl.base, sl.F, d.ell, load, rec, fa);
+    else
+      fwd_level_launch(g, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
   }
 
   EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
@@ -3037,7 +3353,23 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
              g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f, grad ? 1 : 0, snap_of(g),
              (grad && tree) ? reinterpret_cast<float2*>(wb + g->work.tree_adj) : nullptr, d.sink_base};
   const int ss = (int)g->state.total;
+  const bool cte = g->sched_cfg.level_scheme == STA_LEVEL_CTE;
   auto bwd_level = [&](int l) {
+    if (cte) {
+      const int lo = g->level_off[l], hi = g->level_off[l + 1];
+      if (hi == lo) return;
+      LaunchTimer t(g, s, STA_K_BWD_LEVEL);
+      const dim3 grid((unsigned)((hi - lo + kCteItems - 1) / kCteItems));
+      const Slots sl = level_slots(g, l);
+      if (io == nullptr) {
+        if (grad) k_bwd_level_cte<true, true><<<grid, kBlock, 0, s>>>(lo, hi, sl, ba);
+        else k_bwd_level_cte<true, false><<<grid, kBlock, 0, s>>>(lo, hi, sl, ba);
+      } else {
+        if (grad) k_bwd_level_cte<false, true><<<grid, kBlock, 0, s>>>(lo, hi, sl, ba);
+        else k_bwd_level_cte<false, false><<<grid, kBlock, 0, s>>>(lo, hi, sl, ba);
+      }
+      return;
+    }
     const GroupRange& r = g->lvl_ranges[l];
     const unsigned blocks = range_grid(r);
     if (blocks == 0) return;
@@ -3356,9 +3688,14 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
     if (st == STA_OK) try_schedule(narrow);
   }
   if (st == STA_OK && g->n_snap == 1 && g->ckpt_stride == 0 && g->c_parent.empty()) {
-    sta_schedule thread = best_s;           // one thread per net in every stage
+    const sta_schedule pin_based = best_s;
+    sta_schedule cte = pin_based;           // the CTE task pool in the level kernels too
+    cte.rc_scheme = STA_RC_CTE;
+    cte.level_scheme = STA_LEVEL_CTE;
+    try_schedule(cte);
+    sta_schedule thread = pin_based;        // one thread per net in every stage
     thread.level_scheme = STA_LEVEL_THREAD;
-    try_schedule(thread);
+    if (st == STA_OK) try_schedule(thread);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -582,7 +582,7 @@ sta_status sta_server_add_design(sta_server* s, sta_graph* g, const float* x, co
   d.P = g->P;
   d.state_bytes = g->state.total;
   d.work_bytes = g->work.total;
-  d.can_merge = !g->snap_inner && g->sched_cfg.level_scheme != STA_LEVEL_THREAD && g->n_designs == 1 &&
+  d.can_merge = !g->snap_inner && g->sched_cfg.level_scheme == STA_LEVEL_GROUPS && g->n_designs == 1 &&
                 g->state.total <= (size_t)INT32_MAX;     // as sta_set_snapshots requires
   hipError_t e;
   if ((e = hipMalloc(&d.x, std::max<size_t>(fb, 4))) != hipSuccess) return hip_fail(e, "hipMalloc");

@@ -28,7 +28,7 @@ STA_GRAPH = 1 << 5
 STA_REQ_FWD, STA_REQ_FWD_BWD = 0, 1
 STA_RC_GROUPS, STA_RC_CTE, STA_RC_THREAD = 0, 1, 2
 STA_SNAP_OUTER, STA_SNAP_INNER = 0, 1
-STA_LEVEL_GROUPS, STA_LEVEL_THREAD = 0, 1
+STA_LEVEL_GROUPS, STA_LEVEL_THREAD, STA_LEVEL_CTE = 0, 1, 2
 
 EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_graph_upload",
             "sta_graph_info_get", "sta_graph_destroy", "sta_batch_create", "sta_batch_pin_map",
@@ -341,16 +341,18 @@ class Graph:
                      rc_scheme: int | str = 0, fwd_cell_lanes: int = 16, level_scheme: int | str = 0):
         """rc_scheme: 0 / "groups" (lane groups, Alg. 1), 1 / "cte" (task pool, Alg. 2),
         2 / "thread" (one thread per net).  fwd_cell_lanes: 16, 8 or 4 lanes per cell in the
-        forward level kernel.  level_scheme: 0 / "groups", or 1 / "thread" (one thread per net
-        and cell in every stage)."""
+        forward level kernel.  level_scheme: 0 / "groups", 1 / "thread" (one thread per net
+        and cell in every stage) or 2 / "cte" (the level kernels over a workgroup task pool)."""
         rc = {"groups": STA_RC_GROUPS, "cte": STA_RC_CTE, "thread": STA_RC_THREAD}.get(rc_scheme, rc_scheme)
-        lv = {"groups": STA_LEVEL_GROUPS, "thread": STA_LEVEL_THREAD}.get(level_scheme, level_scheme)
+        lv = {"groups": STA_LEVEL_GROUPS, "thread": STA_LEVEL_THREAD, "cte": STA_LEVEL_CTE}.get(level_scheme,
+                                                                                               level_scheme)
         sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks, int(rc), int(fwd_cell_lanes), int(lv))
         _check(_lib.sta_set_schedule(self._h, ctypes.byref(sch)))
 
     def tune(self, x, y, gamma: float = 10.0, reps: int = 3, stream=None) -> dict:
         """Time the candidate schedules (lane groups, then the RC mappings, then 8 and 4 lanes
-        per forward cell) on these coordinates and keep the fastest."""
+        per forward cell, then the CTE and thread-per-net level schemes) on these coordinates
+        and keep the fastest."""
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)

@@ -398,8 +398,9 @@ def test_graph_capture_replays_match_plain_calls():
 def test_schedules_agree_with_oracle():
     # Every schedule sweeps the same arithmetic (summation order aside): lane groups, the RC
     # stage as Alg. 2's task pool (pools of 256 nets that span several LDS chunks of sinks
-    # here) or one thread per net, 4 lanes per forward cell, and one thread per net and cell
-    # in every stage (nets of up to 500 sinks walked by one thread).
+    # here) or one thread per net, 4 lanes per forward cell, one thread per net and cell in
+    # every stage (nets of up to 500 sinks walked by one thread), and the level kernels as
+    # task pools.
     d = make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0))
     ref = O.run(d, gamma=GAMMA, grad="tns")
     g = Graph.from_design(d)
@@ -409,13 +410,41 @@ def test_schedules_agree_with_oracle():
     assert pools.max() > 2 * 1024, pools.max()
     for sch in ((5, 3, 64), (6, 4, 32), (4, 6, 1), (4, 2, 64, "cte"), (5, 3, 32, "thread"), (4, 2, 64, "cte", 4),
                 (5, 3, 32, "groups", 8), (3, 2, 64), (3, 2, 4, "groups", 4), (2, 2, 64, "cte", 4),
-                (2, 2, 1, "thread", 8), (2, 2, 64, "groups", 16, "thread")):
+                (2, 2, 1, "thread", 8), (2, 2, 64, "groups", 16, "thread"), (2, 2, 64, "groups", 16, "cte")):
         g.levelize()
         g.set_schedule(*sch)
         print("schedule", sch)
         got = gpu_run(d, graph=g)
         check_values(d, got, ref)
         check_grad(got, ref, 1e-3, 1e-6)
+
+
+def test_cte_level_kernels_match_oracle():
+    # Alg. 2's task pool in the level kernels as well as the RC stage: pools of 256 cells or
+    # nets whose tasks span several LDS chunks, original and canonical pin order, a 1300-sink
+    # net behind a cell (its sinks alone fill several chunks), the WNS_g gradient, and the
+    # required-time pass without the gradient equal to the fused pass's required times.
+    from tests._designs import fanout_design
+    for d, wns in ((make_design(scaled_spec(60_000, cfg_id=41, box_um=300.0)), False),
+                   (fanout_design(via_cell=True), True)):
+        ref = O.run(d, gamma=GAMMA, grad="wns" if wns else "tns")
+        g = Graph.from_design(d)
+        g.levelize()
+        g.set_schedule(2, 2, 64, "cte", 16, "cte")
+        got = gpu_run(d, graph=g, wns=wns)
+        check_values(d, got, ref)
+        check_grad(got, ref, 1e-3, 1e-6)
+        canon = gpu_run(d, graph=g, canonical=True, wns=wns)
+        perm = g.levelization()["pin_perm"]
+        for k in ("at", "slew", "rat", "slack", "dx", "dy", "fwd_at", "atg"):
+            assert np.array_equal(got[k][perm], canon[k], equal_nan=True), k
+        x = torch.tensor(d.x, device="cuda")
+        y = torch.tensor(d.y, device="cuda")
+        f = g.forward(x, y, gamma=GAMMA)
+        o = g.backward(x, y, f, rat=True, grad=False, pins=True)
+        torch.cuda.synchronize()
+        for k in ("rat", "slack", "at", "slew"):
+            assert np.array_equal(o[k].cpu().numpy(), got[k], equal_nan=True), k
 
 
 def test_tune_keeps_a_valid_schedule():

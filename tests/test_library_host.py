@@ -147,7 +147,7 @@ def test_schedule_roundtrip_and_validation():
     assert g.schedule()["rc_scheme"] == S.STA_RC_THREAD
     for bad in ((1, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65), (4, 2, 64, 3),
                 (4, 2, 64, -1), (4, 2, 64, 0, 2), (4, 2, 64, 0, 0), (4, 2, 64, 0, 12), (4, 2, 64, 0, 32),
-                (4, 2, 64, 0, 16, 2), (4, 2, 64, 0, 16, -1)):
+                (4, 2, 64, 0, 16, 3), (4, 2, 64, 0, 16, -1)):
         with pytest.raises(S.StaError) as e:
             g.set_schedule(*bad)
         assert e.value.code == S.STA_E_INVALID
@@ -159,12 +159,26 @@ def test_schedule_roundtrip_and_validation():
         with pytest.raises(S.StaError) as e:      # one snapshot, no checkpointing, lane groups for snapshot lanes
             call()
         assert e.value.code == S.STA_E_INVALID
+    g.set_schedule(5, 3, 32, "cte", 16, "cte")
+    assert g.schedule()["level_scheme"] == S.STA_LEVEL_CTE
+    for call in (lambda: g.set_snapshots(2), lambda: g.set_checkpointing(-1), lambda: g.set_snapshot_layout(True)):
+        with pytest.raises(S.StaError) as e:      # the CTE level kernels: the same restrictions
+            call()
+        assert e.value.code == S.STA_E_INVALID
     g.set_schedule(5, 3, 32, "thread", 16, "groups")
     g.set_snapshots(2)
-    with pytest.raises(S.StaError) as e:
-        g.set_schedule(5, 3, 32, "thread", 16, "thread")
-    assert e.value.code == S.STA_E_INVALID
+    for lv in ("thread", "cte"):
+        with pytest.raises(S.StaError) as e:
+            g.set_schedule(5, 3, 32, "thread", 16, lv)
+        assert e.value.code == S.STA_E_INVALID
     g.close()
+    from gen.netlist import heap_trees
+    t = S.Graph.from_design(heap_trees(make_design(tiny_spec(20, 3, n_pi=3, seed=1))))
+    t.levelize()
+    with pytest.raises(S.StaError) as e:                # RC trees: lane groups only
+        t.set_schedule(2, 2, 64, "cte", 16, "cte")
+    assert e.value.code == S.STA_E_INVALID
+    t.close()
 
 
 def _members():
