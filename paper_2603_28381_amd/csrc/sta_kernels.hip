@@ -2498,7 +2498,7 @@ __global__ __launch_bounds__(kSiRcBlock) void k_rc_si(RcSiArgs a) {
                   sh);
     return;
   }
-  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiRcBlock / 64 + w);
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * (kSiRcBlock / 64) + w);
   const int n = ln.item;
   if (n >= a.N || !ln.on) return;
   const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
@@ -3056,7 +3056,7 @@ __global__ __launch_bounds__(kSiBwdBlock) void k_bwd_level_si(int nb, int nh0, i
       bwd_net_si<kGrad, true>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
     return;
   }
-  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * kSiBwdBlock / 64 + w);
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * (kSiBwdBlock / 64) + w);
   const int n = nb + ln.item;
   if (n >= nh0 || !ln.on) return;
   bwd_net_si<kGrad, false>(a, sl, n, ln, a.sl2, sh);

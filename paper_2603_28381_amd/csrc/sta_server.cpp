@@ -356,13 +356,14 @@ struct sta_server {
   }
 
   // Queue positions of the requests a sweep headed by the queue's front request takes:
-  // itself and the earliest waiting requests of the same design, kind and gamma, as many
-  // as the largest power of two up to max_merge allows.
+  // itself and the earliest waiting requests of the same design, kind and gamma among the
+  // next kMergeWindow, as many as the largest power of two up to max_merge allows.
+  static constexpr size_t kMergeWindow = 1024;
   std::vector<size_t> batch_of(const Ticket& head) {
     std::vector<size_t> pos{0};
     if (!designs[head.design].can_merge) return pos;
-    const size_t lim = (size_t)max_merge();
-    for (size_t i = 1; i < queue.size() && pos.size() < lim; ++i) {
+    const size_t lim = (size_t)max_merge(), end = std::min(queue.size(), kMergeWindow);
+    for (size_t i = 1; i < end && pos.size() < lim; ++i) {
       const Ticket& t = tickets[queue[i]];
       if (t.design == head.design && t.kind == head.kind && t.gamma == head.gamma) pos.push_back(i);
     }
