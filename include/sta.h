@@ -269,8 +269,8 @@ sta_status sta_set_snapshots(sta_graph* g, int32_t n_snapshots);
  * a wave then take snapshots (one net or cell for 64 snapshots, or for S <= 32 several
  * items of a power of two of lanes each), so topology and table reads serve every snapshot
  * and each state access is one contiguous run.  Same results up to float summation order
- * (a net's sinks and the endpoints are summed in index order per snapshot); the schedule
- * does not apply and sta_tune leaves it unchanged.  Meant for S of 32 or more.
+ * (a net's sinks and the endpoints are summed in index order per snapshot); of the schedule
+ * only lane_block applies, and sta_tune picks it.  Meant for S of 32 or more.
  * Errors: STA_E_STATE if not levelized; STA_E_INVALID for an unknown layout, and for
  * STA_SNAP_INNER with checkpointing on or RC trees (pin_parent); sta_forward / sta_backward
  * return STA_E_INVALID when an array of all snapshots would reach 4 GiB.
@@ -300,8 +300,12 @@ sta_status sta_set_snapshot_layout(sta_graph* g, int32_t layout);
  * or the sinks and then the driving cells' inputs of 16 nets, and rebalances them over its
  * 256 threads; rc_scheme still picks the RC stage).  Both need one snapshot, no checkpointing,
  * the snapshot-outer layout and star nets (else STA_E_INVALID; sta_set_checkpointing,
- * sta_set_snapshots and sta_set_snapshot_layout refuse what they exclude while set).  Defaults
- * {2, 2, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS}.
+ * sta_set_snapshots and sta_set_snapshot_layout refuse what they exclude while set).
+ * lane_block tiles the snapshot-lane backward level (STA_SNAP_INNER): the threads of one
+ * workgroup, which serves one net of more than 12 sinks or a wave's worth of light nets
+ * per 64 threads; smaller workgroups let a CU start new waves sooner after its slowest one,
+ * larger ones give a heavy net more threads per snapshot.  Defaults
+ * {2, 2, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS, 512}.
  * Setting a schedule rebuilds the launch plan (no result changes beyond float summation
  * order).  Errors: STA_E_INVALID for out-of-range fields,
  * STA_E_STATE if not levelized.
@@ -324,6 +328,8 @@ typedef struct sta_schedule {
   int32_t rc_scheme;          /* STA_RC_GROUPS, STA_RC_CTE or STA_RC_THREAD */
   int32_t fwd_cell_lanes;     /* 16, 8 or 4 */
   int32_t level_scheme;       /* STA_LEVEL_GROUPS, STA_LEVEL_THREAD or STA_LEVEL_CTE */
+  int32_t lane_block;         /* STA_SNAP_INNER: threads per workgroup of the backward level,
+                                 256, 512 or 1024 */
 } sta_schedule;
 
 sta_status sta_get_schedule(const sta_graph* g, sta_schedule* sch);
@@ -332,6 +338,7 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
 /* Autotuner: times one forward+backward (smoothed, gradient, canonical IO, every per-pin
  * output) of g on the given coordinates for each candidate schedule, `reps` times after a
  * warm-up, keeps the fastest (copied to *best if not NULL) and leaves it set.  Candidates:
+ * with STA_SNAP_INNER lane_block 256, 512 and 1024 and nothing else; otherwise
  * sweep_group_log2 2..6 x flat_group_log2 2..4 x heavy_sinks {32, 64} with lane-group RC
  * and 16 forward lanes, then on the best of those the CTE and thread RC mappings, then 8
  * and 4 forward lanes, then (one snapshot, no checkpointing, star nets) the CTE scheme in

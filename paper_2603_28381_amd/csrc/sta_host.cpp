@@ -830,7 +830,8 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
       sch->rc_scheme > STA_RC_THREAD ||
       (sch->fwd_cell_lanes != 16 && sch->fwd_cell_lanes != 8 && sch->fwd_cell_lanes != 4) ||
       (sch->level_scheme != STA_LEVEL_GROUPS && sch->level_scheme != STA_LEVEL_THREAD &&
-       sch->level_scheme != STA_LEVEL_CTE))
+       sch->level_scheme != STA_LEVEL_CTE) ||
+      (sch->lane_block != 256 && sch->lane_block != 512 && sch->lane_block != 1024))
     return fail(STA_E_INVALID, "schedule out of range");
   if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
   if (sch->level_scheme != STA_LEVEL_GROUPS && (g->n_snap != 1 || g->snap_inner || g->ckpt_stride > 0 ||

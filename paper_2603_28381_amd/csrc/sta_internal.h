@@ -141,7 +141,7 @@ struct sta_graph {
   std::vector<int> tree_big;                   // RC trees: nets over kTreeChunk pins
   std::vector<sta::GroupRange> lvl_ranges;   // per level
   sta::GroupRange all_range{};                 // all nets
-  sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS};
+  sta_schedule sched_cfg{sta::kSweepG0Default, sta::kFlatG0Default, 64, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS, 512};
   // Checkpointing (stride 0 = off): record slot of each canonical net (kept nets first,
   // level-0 nets at their own index, then the shared segment buffer), segment boundaries
   // seg_lo (levels [seg_lo[j], seg_lo[j+1])), and the endpoints' record slots.

@@ -2368,12 +2368,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_level_cte(int lo, int hi, Slots 
 // when S <= 32), so the topology and tables it reads are the same for every lane of an item,
 // and every state load or store moves one contiguous run per item.  Sums over a net's sinks
 // and merges over a cell's arcs run inside each lane, in index order; nets of more than
-// kSiHeavy sinks take a whole workgroup (kSiRcBlock threads in the RC stage, kSiBwdBlock in
-// the backward) whose threads split the sinks and meet in LDS in thread order.  The light
-// nets' waves come in workgroups of the same size: smaller workgroups let a CU start new
-// waves sooner after its slowest one, larger ones give a heavy net more threads per snapshot.
+// kSiHeavy sinks take a whole workgroup (kSiRcBlock threads in the RC stage; in the
+// backward the schedule's lane_block, 256, 512 or 1024) whose threads split the sinks and
+// meet in LDS in thread order.  The light nets' waves come in workgroups of the same size:
+// smaller workgroups let a CU start new waves sooner after its slowest one, larger ones give
+// a heavy net more threads per snapshot.
 constexpr int kSiRcBlock = 256;
-constexpr int kSiBwdBlock = 512;
 
 struct SiLane {
   int item;   // item of the lane counted from the launch's first (or, in a heavy workgroup,
@@ -2965,10 +2965,10 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
 }
 
 // Backward work of net n for the lane's snapshot (the three phases of bwd_net).  In a heavy
-// workgroup (kHeavy) the kSiBwdBlock >> hl2 threads of a snapshot split the sinks and their
+// workgroup (kHeavy) of kB threads the kB >> hl2 threads of a snapshot split the sinks and their
 // reductions meet in LDS in thread order; the first thread of each snapshot then runs the
 // cell step.
-template <bool kGrad, bool kHeavy>
+template <bool kGrad, bool kHeavy, int kB>
 __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, int n, const SiLane& ln, int hl2,
                                            float* sh) {
   const uint32_t S = (uint32_t)a.S;
@@ -2984,7 +2984,7 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int lanes = 1 << hl2;                   // heavy workgroups: snapshots per workgroup
   const int first = kHeavy ? ln.item : 0;
-  const int stride = kHeavy ? kSiBwdBlock / lanes : 1;
+  const int stride = kHeavy ? kB / lanes : 1;
   if (ln.on) {
 #pragma unroll 4
     for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
@@ -2992,16 +2992,16 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   const bool leader = !kHeavy || (int)threadIdx.x < lanes;
   if (kHeavy) {
 #pragma unroll
-    for (int i = 0; i < N_ACC; ++i) sh[i * kSiBwdBlock + threadIdx.x] = acc[i];
+    for (int i = 0; i < N_ACC; ++i) sh[i * kB + threadIdx.x] = acc[i];
     __syncthreads();
     if (leader) {
-      for (int u = (int)threadIdx.x + lanes; u < kSiBwdBlock; u += lanes) {
-        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kSiBwdBlock + u]);
-        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kSiBwdBlock + u]);
-        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kSiBwdBlock + u]);
-        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kSiBwdBlock + u]);
+      for (int u = (int)threadIdx.x + lanes; u < kB; u += lanes) {
+        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kB + u]);
+        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kB + u]);
+        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kB + u]);
+        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kB + u]);
 #pragma unroll
-        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kSiBwdBlock + u];
+        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kB + u];
       }
     }
   }
@@ -3022,9 +3022,9 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
     }
   }
   if (kHeavy) {
-    if (leader) sh[N_ACC * kSiBwdBlock + threadIdx.x] = lbar;
+    if (leader) sh[N_ACC * kB + threadIdx.x] = lbar;
     __syncthreads();
-    lbar = sh[N_ACC * kSiBwdBlock + (threadIdx.x & (unsigned)(lanes - 1))];
+    lbar = sh[N_ACC * kB + (threadIdx.x & (unsigned)(lanes - 1))];
   }
   // Elmore adjoint of every sink (the sinks are read again).
   if (kGrad && ln.on && (a.dx || a.dy)) {
@@ -3041,9 +3041,9 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
 
 // One backward level: the level's huge nets [nu0, ne) and heavy nets [nh0, nu0) first, a
 // workgroup per net and snapshot chunk, then the nets [nb, nh0), (64 >> sl2) per wave.
-template <bool kGrad>
-__global__ __launch_bounds__(kSiBwdBlock) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
-  __shared__ float sh[N_ACC * kSiBwdBlock + kSiBwdBlock];
+template <bool kGrad, int kB>
+__global__ __launch_bounds__(kB) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
+  __shared__ float sh[N_ACC * kB + kB];
   const int w = (int)(threadIdx.x >> 6);
   const int b = (int)blockIdx.x;
   const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
@@ -3051,15 +3051,15 @@ __global__ __launch_bounds__(kSiBwdBlock) void k_bwd_level_si(int nb, int nh0, i
   if (b < nbu + nbh) {
     if (blockIdx.y != 0) return;               // these workgroups cover their snapshots along x
     if (b < nbu)
-      bwd_net_si<kGrad, true>(a, sl, nu0 + b / nchu, si_heavy_lane(hl2u, a.S, b % nchu), hl2u, sh);
+      bwd_net_si<kGrad, true, kB>(a, sl, nu0 + b / nchu, si_heavy_lane(hl2u, a.S, b % nchu), hl2u, sh);
     else
-      bwd_net_si<kGrad, true>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
+      bwd_net_si<kGrad, true, kB>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
     return;
   }
-  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * (kSiBwdBlock / 64) + w);
+  const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * (kB / 64) + w);
   const int n = nb + ln.item;
   if (n >= nh0 || !ln.on) return;
-  bwd_net_si<kGrad, false>(a, sl, n, ln, a.sl2, sh);
+  bwd_net_si<kGrad, false, kB>(a, sl, n, ln, a.sl2, sh);
 }
 
 }  // namespace
@@ -3231,18 +3231,26 @@ sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, cons
                      reinterpret_cast<float4*>(out->at), reinterpret_cast<float4*>(out->slew),
                      reinterpret_cast<float4*>(out->rat), reinterpret_cast<float4*>(out->slack), out->dx, out->dy,
                      g->N0, D.S, D.sl2, g->cons.r_per_um, g->cons.c_per_um, grad ? 1.0f / gamma_ps : 0.f};
+  const int kb = g->sched_cfg.lane_block;    // 256, 512 or 1024 (sta_set_schedule checks)
   for (int l = g->L - 1; l >= 0; --l) {
     const int lo = g->level_off[l], hi = g->level_off[l + 1];
     const int hs = D.split ? g->si_hs[l] : hi, us = D.split ? g->si_us[l] : hi;
     if (hi == lo) continue;
     const unsigned blocks =
-        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kSiBwdBlock / 64);
+        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kb / 64);
     LaunchTimer t(g, s, STA_K_BWD_LEVEL);
     const Slots sl = level_slots(g, l);
-    if (grad)
-      k_bwd_level_si<true><<<dim3(blocks, D.gy), kSiBwdBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
-    else
-      k_bwd_level_si<false><<<dim3(blocks, D.gy), kSiBwdBlock, 0, s>>>(lo, hs, us, hi, sl, ba);
+    const dim3 grid(blocks, D.gy);
+    if (kb == 256) {
+      if (grad) k_bwd_level_si<true, 256><<<grid, 256, 0, s>>>(lo, hs, us, hi, sl, ba);
+      else k_bwd_level_si<false, 256><<<grid, 256, 0, s>>>(lo, hs, us, hi, sl, ba);
+    } else if (kb == 1024) {
+      if (grad) k_bwd_level_si<true, 1024><<<grid, 1024, 0, s>>>(lo, hs, us, hi, sl, ba);
+      else k_bwd_level_si<false, 1024><<<grid, 1024, 0, s>>>(lo, hs, us, hi, sl, ba);
+    } else {
+      if (grad) k_bwd_level_si<true, 512><<<grid, 512, 0, s>>>(lo, hs, us, hi, sl, ba);
+      else k_bwd_level_si<false, 512><<<grid, 512, 0, s>>>(lo, hs, us, hi, sl, ba);
+    }
   }
   if (g->profiling) end_run(g, s);
   hipError_t e = hipGetLastError();
@@ -3620,10 +3628,6 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
   if (st != STA_OK) return st;
   if (!x || !y) return fail(STA_E_INVALID, "x and y are required");
   if (!(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
-  if (g->snap_inner) {         // the snapshot-lane kernels take no schedule
-    if (best) *best = g->sched_cfg;
-    return STA_OK;
-  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t P = (size_t)g->P;
   const size_t S = (size_t)g->n_snap;
@@ -3669,25 +3673,34 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
       best_s = cand;
     }
   };
-  // Lane groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's
-  // task pool, one thread per net) on the best of those, then 8 and 4 lanes per forward cell,
-  // then one thread per net in every stage.
-  for (int sweep = 2; sweep <= 6 && st == STA_OK; ++sweep)
+  // The snapshot-lane kernels take the workgroup size of their backward level.  Otherwise lane
+  // groups of the level and one-pass kernels, then the other RC mappings (Alg. 2's task pool,
+  // one thread per net) on the best of those, then 8 and 4 lanes per forward cell, then the
+  // task pool in the level kernels and one thread per net in every stage.
+  for (int kb : {256, 512, 1024}) {
+    if (!g->snap_inner || st != STA_OK) break;
+    sta_schedule c = start;
+    c.lane_block = kb;
+    try_schedule(c);
+  }
+  for (int sweep = 2; sweep <= 6 && st == STA_OK && !g->snap_inner; ++sweep)
     for (int flat = 2; flat <= 4 && st == STA_OK; ++flat)
       for (int heavy : {32, 64})
-        if (st == STA_OK) try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS});
+        if (st == STA_OK)
+          try_schedule(sta_schedule{sweep, flat, heavy, STA_RC_GROUPS, 16, STA_LEVEL_GROUPS, start.lane_block});
   const sta_schedule lanes = best_s;
   for (int rc : {STA_RC_CTE, STA_RC_THREAD})
-    if (st == STA_OK)
+    if (st == STA_OK && !g->snap_inner)
       try_schedule(
-          sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16, STA_LEVEL_GROUPS});
+          sta_schedule{lanes.sweep_group_log2, lanes.flat_group_log2, lanes.heavy_sinks, rc, 16, STA_LEVEL_GROUPS,
+                       lanes.lane_block});
   const sta_schedule wide = best_s;
   for (int fl : {8, 4}) {
     sta_schedule narrow = wide;
     narrow.fwd_cell_lanes = fl;
-    if (st == STA_OK) try_schedule(narrow);
+    if (st == STA_OK && !g->snap_inner) try_schedule(narrow);
   }
-  if (st == STA_OK && g->n_snap == 1 && g->ckpt_stride == 0 && g->c_parent.empty()) {
+  if (st == STA_OK && !g->snap_inner && g->n_snap == 1 && g->ckpt_stride == 0 && g->c_parent.empty()) {
     const sta_schedule pin_based = best_s;
     sta_schedule cte = pin_based;           // the CTE task pool in the level kernels too
     cte.rc_scheme = STA_RC_CTE;

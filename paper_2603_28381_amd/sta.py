@@ -74,7 +74,7 @@ class StaGraphInfo(ctypes.Structure):
 class StaSchedule(ctypes.Structure):
     _fields_ = [("sweep_group_log2", ctypes.c_int32), ("flat_group_log2", ctypes.c_int32),
                 ("heavy_sinks", ctypes.c_int32), ("rc_scheme", ctypes.c_int32),
-                ("fwd_cell_lanes", ctypes.c_int32), ("level_scheme", ctypes.c_int32)]
+                ("fwd_cell_lanes", ctypes.c_int32), ("level_scheme", ctypes.c_int32), ("lane_block", ctypes.c_int32)]
 
 
 class StaServerConfig(ctypes.Structure):
@@ -338,21 +338,24 @@ class Graph:
         return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
 
     def set_schedule(self, sweep_group_log2: int, flat_group_log2: int, heavy_sinks: int,
-                     rc_scheme: int | str = 0, fwd_cell_lanes: int = 16, level_scheme: int | str = 0):
+                     rc_scheme: int | str = 0, fwd_cell_lanes: int = 16, level_scheme: int | str = 0,
+                     lane_block: int = 512):
         """rc_scheme: 0 / "groups" (lane groups, Alg. 1), 1 / "cte" (task pool, Alg. 2),
         2 / "thread" (one thread per net).  fwd_cell_lanes: 16, 8 or 4 lanes per cell in the
         forward level kernel.  level_scheme: 0 / "groups", 1 / "thread" (one thread per net
-        and cell in every stage) or 2 / "cte" (the level kernels over a workgroup task pool)."""
+        and cell in every stage) or 2 / "cte" (the level kernels over a workgroup task pool).
+        lane_block: threads per workgroup of the snapshot-lane backward level (256, 512, 1024)."""
         rc = {"groups": STA_RC_GROUPS, "cte": STA_RC_CTE, "thread": STA_RC_THREAD}.get(rc_scheme, rc_scheme)
         lv = {"groups": STA_LEVEL_GROUPS, "thread": STA_LEVEL_THREAD, "cte": STA_LEVEL_CTE}.get(level_scheme,
                                                                                                level_scheme)
-        sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks, int(rc), int(fwd_cell_lanes), int(lv))
+        sch = StaSchedule(sweep_group_log2, flat_group_log2, heavy_sinks, int(rc), int(fwd_cell_lanes), int(lv),
+                          int(lane_block))
         _check(_lib.sta_set_schedule(self._h, ctypes.byref(sch)))
 
     def tune(self, x, y, gamma: float = 10.0, reps: int = 3, stream=None) -> dict:
         """Time the candidate schedules (lane groups, then the RC mappings, then 8 and 4 lanes
-        per forward cell, then the CTE and thread-per-net level schemes) on these coordinates
-        and keep the fastest."""
+        per forward cell, then the CTE and thread-per-net level schemes; with snapshot lanes the
+        backward workgroup size) on these coordinates and keep the fastest."""
         dev = x.device if isinstance(x, torch.Tensor) and x.is_cuda else torch.device("cuda")
         x = _dev_f32(x, dev)
         y = _dev_f32(y, dev)

@@ -21,12 +21,13 @@ def _snapshots(d, S, sigma=5.0):
     return [(np.asarray(a, np.float32), np.asarray(b, np.float32)) for a, b in snaps]
 
 
-def _run(d, snaps, inner, canonical=False, wns=False, capture=False):
+def _run(d, snaps, inner, canonical=False, wns=False, capture=False, lane_block=512):
     """Forward + backward of all snapshots in one call; returns per-snapshot numpy outputs
     (original pin order)."""
     S = len(snaps)
     g = Graph.from_design(d)
     g.levelize()
+    g.set_schedule(2, 2, 64, lane_block=lane_block)
     g.set_snapshots(S)
     g.set_snapshot_layout(inner)
     perm = g.levelization()["pin_perm"]
@@ -67,14 +68,15 @@ def _check_snapshots(d, snaps, got, picks, wns=False):
         check_grad(got[s], ref, 1e-3, 1e-6)
 
 
-@pytest.mark.parametrize("S,canonical", [(64, True), (80, False), (3, True)])
-def test_snapshot_lanes_match_oracle_and_outer_layout(S, canonical):
+@pytest.mark.parametrize("S,canonical,lane_block", [(64, True, 512), (80, False, 1024), (3, True, 256)])
+def test_snapshot_lanes_match_oracle_and_outer_layout(S, canonical, lane_block):
     # Heavy-tailed nets (every lane-group class and nets over 12 sinks in the workgroup path),
-    # 64 snapshots (one wave per item), 80 (two blocks of snapshots), 3 (16 items per wave).
+    # 64 snapshots (one wave per item), 80 (two blocks of snapshots), 3 (16 items per wave),
+    # backward workgroups of 512, 1024 and 256 threads.
     d = make_design(scaled_spec(30_000, cfg_id=42, box_um=500.0))
     assert np.diff(d.net_offsets).max() - 1 > 128
     snaps = _snapshots(d, S)
-    got = _run(d, snaps, inner=True, canonical=canonical)
+    got = _run(d, snaps, inner=True, canonical=canonical, lane_block=lane_block)
     _check_snapshots(d, snaps, got, sorted({0, S // 2, S - 1}))
     outer = _run(d, snaps, inner=False, canonical=canonical)
     for s in range(S):

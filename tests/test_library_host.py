@@ -133,26 +133,29 @@ def test_schedule_roundtrip_and_validation():
     assert e.value.code == S.STA_E_STATE          # not levelized yet
     g.levelize()
     assert g.schedule() == dict(sweep_group_log2=2, flat_group_log2=2, heavy_sinks=64, rc_scheme=S.STA_RC_GROUPS,
-                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS)
+                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS, lane_block=512)
     g.set_schedule(5, 3, 32)
     assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_GROUPS,
-                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS)
+                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS, lane_block=512)
     g.set_schedule(5, 3, 32, "groups", 4)
     assert g.schedule()["fwd_cell_lanes"] == 4
     g.set_schedule(5, 3, 32, "groups", 8)
     assert g.schedule()["fwd_cell_lanes"] == 8
     g.set_schedule(5, 3, 32, "cte")
     assert g.schedule()["rc_scheme"] == S.STA_RC_CTE
+    g.set_schedule(5, 3, 32, "thread", 16, "groups", 1024)
+    assert g.schedule()["lane_block"] == 1024
     g.set_schedule(5, 3, 32, "thread")
     assert g.schedule()["rc_scheme"] == S.STA_RC_THREAD
     for bad in ((1, 2, 64), (7, 2, 64), (4, 1, 64), (4, 7, 64), (4, 2, 0), (4, 2, 65), (4, 2, 64, 3),
                 (4, 2, 64, -1), (4, 2, 64, 0, 2), (4, 2, 64, 0, 0), (4, 2, 64, 0, 12), (4, 2, 64, 0, 32),
-                (4, 2, 64, 0, 16, 3), (4, 2, 64, 0, 16, -1)):
+                (4, 2, 64, 0, 16, 3), (4, 2, 64, 0, 16, -1), (4, 2, 64, 0, 16, 0, 128), (4, 2, 64, 0, 16, 0, 768),
+                (4, 2, 64, 0, 16, 0, 2048)):
         with pytest.raises(S.StaError) as e:
             g.set_schedule(*bad)
         assert e.value.code == S.STA_E_INVALID
     assert g.schedule() == dict(sweep_group_log2=5, flat_group_log2=3, heavy_sinks=32, rc_scheme=S.STA_RC_THREAD,
-                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS)
+                                fwd_cell_lanes=16, level_scheme=S.STA_LEVEL_GROUPS, lane_block=512)
     g.set_schedule(5, 3, 32, "thread", 16, "thread")
     assert g.schedule()["level_scheme"] == S.STA_LEVEL_THREAD
     for call in (lambda: g.set_snapshots(2), lambda: g.set_checkpointing(-1), lambda: g.set_snapshot_layout(True)):
