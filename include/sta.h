@@ -347,6 +347,14 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch);
 sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
                     sta_schedule* best, sta_stream stream);
 
+/* Tuned schedules are cached per shape bucket, process-wide: the pin count's power of two,
+ * the snapshot count, the snapshot layout, whether checkpointing is on, whether the graph
+ * has RC trees and whether it batches several designs.  sta_tune stores its result under
+ * g's bucket (replacing an earlier one); sta_tune_cached sets the cached schedule of g's
+ * bucket on g (copied to *sch if not NULL) without timing anything.  Errors: STA_E_STATE
+ * if g is not levelized or its bucket has no tuned schedule yet (g keeps its schedule). */
+sta_status sta_tune_cached(sta_graph* g, sta_schedule* sch);
+
 /* ---------------------------------------------------------------------------------------
  * Per-level checkpointing of the arrival state (the memory/time trade-off of reverse-mode
  * differentiation applied to the level sweep).  With a stride of k levels, levels 1..L-1

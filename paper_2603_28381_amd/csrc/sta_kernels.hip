@@ -25,6 +25,7 @@
 //  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -3622,6 +3623,35 @@ extern "C" sta_status sta_backward_noalloc(sta_graph* g, const float* x, const f
   return launch_backward(g, x, y, fwd, &o, flags, gamma_ps, reinterpret_cast<hipStream_t>(stream));
 }
 
+namespace sta {
+namespace {
+// Shape bucket of a graph for the tuning cache (sta_tune_cached).
+std::vector<int64_t> tune_bucket(const sta_graph* g) {
+  int lg = 0;
+  while ((1ll << lg) < (int64_t)g->P) ++lg;
+  return {lg, g->n_snap, g->snap_inner ? 1 : 0, g->ckpt_stride > 0 ? 1 : 0, g->c_parent.empty() ? 0 : 1,
+          g->n_designs > 1 ? 1 : 0};
+}
+std::mutex tune_mu;
+std::map<std::vector<int64_t>, sta_schedule> tune_cache;
+}  // namespace
+}  // namespace sta
+
+extern "C" sta_status sta_tune_cached(sta_graph* g, sta_schedule* sch) {
+  if (!g) return fail(STA_E_INVALID, "graph is NULL");
+  if (!g->levelized) return fail(STA_E_STATE, "graph is not levelized");
+  sta_schedule c{};
+  {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    auto it = tune_cache.find(tune_bucket(g));
+    if (it == tune_cache.end()) return fail(STA_E_STATE, "no tuned schedule for this graph's shape bucket yet");
+    c = it->second;
+  }
+  const sta_status st = sta_set_schedule(g, &c);
+  if (st == STA_OK && sch) *sch = c;
+  return st;
+}
+
 extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, float gamma_ps, int32_t reps,
                                sta_schedule* best, sta_stream stream) {
   sta_status st = check_ready(g);
@@ -3718,6 +3748,10 @@ extern "C" sta_status sta_tune(sta_graph* g, const float* x, const float* y, flo
     return st;
   }
   st = sta_set_schedule(g, &best_s);
+  if (st == STA_OK) {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_cache[tune_bucket(g)] = best_s;
+  }
   if (best) *best = best_s;
   return st;
 }

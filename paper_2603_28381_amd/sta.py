@@ -35,7 +35,7 @@ EXPORTED = ["sta_build_graph", "sta_levelize", "sta_get_levelization", "sta_grap
             "sta_forward", "sta_backward", "sta_backward_noalloc", "sta_get_schedule", "sta_set_schedule", "sta_tune",
             "sta_set_checkpointing", "sta_get_checkpointing", "sta_set_snapshots", "sta_set_snapshot_layout", "sta_server_create", "sta_server_add_design",
             "sta_submit", "sta_poll", "sta_wait", "sta_release", "sta_server_destroy", "sta_server_stats_get",
-            "sta_server_set_max_merge",
+            "sta_server_set_max_merge", "sta_tune_cached",
             "sta_profile_enable", "sta_profile_read", "sta_last_error",
             "sta_version"]
 
@@ -179,6 +179,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.sta_server_destroy.restype = None
     lib.sta_server_stats_get.argtypes = [_P, ctypes.POINTER(StaServerStats)]
     lib.sta_server_stats_get.restype = S
+    lib.sta_tune_cached.argtypes = [_P, ctypes.POINTER(StaSchedule)]
+    lib.sta_tune_cached.restype = S
     lib.sta_server_set_max_merge.argtypes = [_P, ctypes.c_int32]
     lib.sta_server_set_max_merge.restype = S
     lib.sta_profile_enable.argtypes = [_P, ctypes.c_int32]
@@ -362,6 +364,16 @@ class Graph:
         sch = StaSchedule()
         _check(_lib.sta_tune(self._h, _ptr(x), _ptr(y), float(gamma), int(reps), ctypes.byref(sch),
                              _stream_handle(stream)))
+        return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
+
+    def tune_cached(self) -> dict | None:
+        """Set the schedule sta_tune last found for this graph's shape bucket (pin count's
+        power of two, snapshots, layout, checkpointing, trees, batch); None if there is none."""
+        sch = StaSchedule()
+        code = _lib.sta_tune_cached(self._h, ctypes.byref(sch))
+        if code == STA_E_STATE and (_lib.sta_last_error() or b"").startswith(b"no tuned schedule"):
+            return None
+        _check(code)
         return {k: getattr(sch, k) for k, _ in StaSchedule._fields_}
 
     def set_snapshots(self, n: int):

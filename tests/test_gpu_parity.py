@@ -458,6 +458,15 @@ def test_tune_keeps_a_valid_schedule():
     got = gpu_run(d, graph=g)
     check_values(d, got, ref)
     check_grad(got, ref, 1e-3, 1e-6)
+    # Another design in the same shape bucket takes the tuned schedule from the cache.
+    h = Graph.from_design(make_design(scaled_spec(2_800, cfg_id=44, box_um=300.0)))
+    h.levelize()
+    assert (h.info()["n_pins"] - 1).bit_length() == (g.info()["n_pins"] - 1).bit_length()
+    assert h.tune_cached() == best == h.schedule()
+    s = Graph.from_design(d)                         # several snapshots: another bucket
+    s.levelize()
+    s.set_snapshots(2)
+    assert s.tune_cached() is None
 
 
 def _ckpt_run(g, d, wns=False):

@@ -319,6 +319,18 @@ def test_checkpoint_frontier_counts(k):
     g.close()
 
 
+def test_tune_cache_lookup_before_any_tuning():
+    g = S.Graph.from_design(make_design(tiny_spec(20, 3, n_pi=3, seed=1)))
+    with pytest.raises(S.StaError) as e:
+        g.tune_cached()                              # not levelized
+    assert e.value.code == S.STA_E_STATE
+    g.levelize()
+    before = g.schedule()
+    assert g.tune_cached() is None                   # nothing tuned in this bucket yet
+    assert g.schedule() == before
+    g.close()
+
+
 def test_server_rejects_bad_configuration():
     lib = S.load_library()
     h = S._P()
