@@ -467,6 +467,7 @@ struct sta_server {
         stats.captures += captured;
         if (captured) stats.capture_ms += ms_between(now, Clock::now());
         if (st != STA_OK) {
+          (void)hipStreamSynchronize(sl.s);      // copies already queued still read the staging
           for (uint64_t id : ids) {
             Ticket& tf = tickets[id];
             tf.err = st;
