@@ -369,7 +369,9 @@ sta_status sta_tune_cached(sta_graph* g, sta_schedule* sch);
  * sta_get_checkpointing), and on star-net graphs bwd_workspace_bytes too (a sink's required
  * times and adjoint live from the cell step writing them to its net's step: nets whose sinks
  * are all written and read inside one segment share a buffer that the next segment
- * reuses); the backward pays one extra forward pass over the dropped nets.
+ * reuses; each sink's wire delay and impulse in the state follow the same slots, so the RC
+ * stage then runs in lane groups, in passes before each segment); the backward pays one
+ * extra forward pass, and RC pass, over the dropped nets.
  *
  * stride_levels: 0 switches checkpointing off, a negative value picks ceil(sqrt(L-1)).
  * Changing it rebuilds the launch plan, changes fwd_state_bytes and releases the device

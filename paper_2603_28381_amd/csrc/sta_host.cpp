@@ -40,7 +40,7 @@ void compute_layouts(sta_graph* g) {
   }
   g->n_ep_blocks = g->ep_blk_off[g->n_designs];
   g->state.rec = take(sizeof(float4) * 4 * (size_t)std::max(1, g->n_rec));
-  g->state.wire = take(sizeof(float2) * (size_t)g->P);
+  g->state.wire = take(sizeof(float2) * (size_t)(g->n_sslots > 0 ? g->n_sslots : g->P));
   g->state.load = take(sizeof(float) * (size_t)g->N);
   const bool tree = !g->c_parent.empty();
   g->state.tree = take(tree ? 2 * sizeof(float4) * (size_t)g->P : 0);
@@ -149,6 +149,9 @@ static void build_sink_slots(sta_graph* g, const std::vector<int>& lvl) {
   }
   g->n_sslots_kept = kept_slots;
   g->n_sslots = std::max(1, kept_slots + widest);
+  g->rc_seg.assign(N, -1);
+  for (int n = 0; n < N; ++n)
+    if (!kept[n]) g->rc_seg[n] = seg(lvl[n]);
   g->sslot.assign(P, 0);
   for (int n = 0; n < N; ++n)
     for (int p = g->c_net_off[n] + 1; p < g->c_net_off[n + 1]; ++p)
@@ -163,6 +166,7 @@ static void build_checkpoints(sta_graph* g) {
   g->sink_base.clear();
   g->sslot.clear();
   g->ep_sslot.clear();
+  g->rc_seg.clear();
   g->n_sslots = g->n_sslots_kept = 0;
   if (k <= 0) {
     g->rec_loc.clear();
@@ -232,6 +236,24 @@ void build_groups(sta_graph* g) {
   g->sched_all.assign(N, 0);
   for (int n = 0; n < N; ++n) g->sched_all[pos[cls[n]]++] = n;
   g->all_range = group_range(cnt, 0, g->sched_cfg.flat_group_log2);
+  // RC passes under checkpointing: kept nets, then each segment's other nets, by class.
+  g->rc_sched.clear();
+  g->rc_ranges.clear();
+  if (!g->rc_seg.empty()) {
+    const int n_pass = (int)g->seg_lo.size();      // kept nets, then one pass per segment
+    std::vector<std::vector<int>> by(n_pass * (kNumClasses + 1));
+    for (int n = 0; n < N; ++n) by[(g->rc_seg[n] + 1) * (kNumClasses + 1) + cls[n]].push_back(n);
+    for (int j = 0; j < n_pass; ++j) {
+      int pc[kNumClasses + 1];
+      const int base = (int)g->rc_sched.size();
+      for (int c = 0; c <= kNumClasses; ++c) {
+        const std::vector<int>& v = by[j * (kNumClasses + 1) + c];
+        pc[c] = (int)v.size();
+        g->rc_sched.insert(g->rc_sched.end(), v.begin(), v.end());
+      }
+      g->rc_ranges.push_back(group_range(pc, base, g->sched_cfg.flat_group_log2));
+    }
+  }
   // Snapshot-inner layout: each level's nets of more than kSiHeavy sinks (a suffix of the
   // level, whose nets ascend in pin count) and the list of all of them.
   g->si_heavy.clear();
@@ -846,8 +868,8 @@ sta_status sta_set_schedule(sta_graph* g, const sta_schedule* sch) {
   }
   drop_captured(g);
   if (g->uploaded) {
-    hipError_t e = hipMemcpy(g->dev.sched_all, g->sched_all.data(), g->sched_all.size() * sizeof(int),
-                             hipMemcpyHostToDevice);
+    const std::vector<int>& sched = g->rc_sched.empty() ? g->sched_all : g->rc_sched;
+    hipError_t e = hipMemcpy(g->dev.sched_all, sched.data(), sched.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
   }
   return STA_OK;
@@ -864,6 +886,7 @@ sta_status sta_set_checkpointing(sta_graph* g, int32_t stride_levels) {
   g->ckpt_stride = k;
   try {
     build_ell(g);
+    build_groups(g);
     compute_layouts(g);
   } catch (const std::bad_alloc&) {
     return fail(STA_E_NOMEM, "host allocation failed");
@@ -973,7 +996,7 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_pin, g->ep_pin)) || (s = up(d.ep_net, g->ep_rec)) || (s = up(d.pin_perm, g->pin_perm)) ||
       (s = up(d.ep_design, g->ep_design)) || (s = up(d.ep_design_off, g->ep_design_off)) ||
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
-      (s = up(d.sched_all, g->sched_all)) || (s = up(d.si_heavy, g->si_heavy)) || (s = up(d.si_huge, g->si_huge)) ||
+      (s = up(d.sched_all, g->rc_sched.empty() ? g->sched_all : g->rc_sched)) || (s = up(d.si_heavy, g->si_heavy)) || (s = up(d.si_huge, g->si_huge)) ||
       (!g->sink_base.empty() && ((s = up(d.sink_base, g->sink_base)) || (s = up(d.ep_sslot, g->ep_sslot)))) ||
       (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
       (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)) ||

@@ -54,7 +54,8 @@ struct LutKeys {
 struct StateLayout {
   size_t rec;      // float4[4 * record slots]: per net and condition k {AT, slew, smoothed AT
                    // (late k; 0 for early k), 0}
-  size_t wire;     // float2[P]: per pin {wire delay, impulse}; zero at drivers
+  size_t wire;     // float2 per sink slot {wire delay, impulse} (slot = pin, zero at drivers,
+                   // without checkpointing)
   size_t load;     // float[N]: root load of each net (Eq. 1)
   size_t tree;     // RC trees only, float4[2 * P]: per pin {length, Cap, Load, Delay} and
                    // {LDelay, Beta, Impulse, 0} of the tree passes
@@ -86,7 +87,7 @@ struct DeviceGraph {
   int* ep_design_off = nullptr;  // [n_designs+1] endpoint ranges by design
   int* ep_blk_off = nullptr;   // [n_designs+1] partial-sum blocks by design
   int* pin_perm = nullptr;     // [P] original id of each canonical pin
-  int* sched_all = nullptr;    // [N] all nets ordered by class
+  int* sched_all = nullptr;    // [N] all nets ordered by class (checkpointing on stars: rc_sched)
   int* rec_loc = nullptr;      // [N] record slot of each net (checkpointing only)
   int* parent = nullptr;       // [P] RC trees only: canonical parent pin, -1 at drivers
   int* tree_order = nullptr;   // [P] RC trees only: each net's pins in breadth-first order
@@ -96,7 +97,7 @@ struct DeviceGraph {
   int* tree_big = nullptr;        // RC trees only: nets over the chunk size
   float4* lut_grid = nullptr;  // [36] {x_i, 1/(x_i+1 - x_i), y_j, 1/(y_j+1 - y_j)}
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
-  int* sink_base = nullptr;    // [N] checkpointing (stars): first workspace slot of each net's sinks
+  int* sink_base = nullptr;    // [N] checkpointing (stars): first slot of each net's sinks
   int* ep_sslot = nullptr;     // [E] checkpointing (stars): workspace slot of each endpoint
   int* si_heavy = nullptr;     // snapshot-inner RC: canonical nets of kSiHeavy+1..kSiHuge sinks,
   int* si_huge = nullptr;      // and of more than kSiHuge
@@ -166,6 +167,14 @@ struct sta_graph {
   // the slot of a sink is its pin.
   std::vector<int> sink_base, sslot, ep_sslot;
   int n_sslots = 0, n_sslots_kept = 0;
+  // The per-sink wire values follow the same slots, so the RC stage runs in passes: the
+  // nets with kept slots once before the sweep (rc_ranges[0]), the other nets of segment j
+  // before each forward or recomputed pass over it (rc_ranges[1 + j]); rc_sched lists the
+  // nets of each pass by lane-group class and takes sched_all's place on the device (the
+  // kernels that read sched_all otherwise do not run under checkpointing).  rc_seg: each
+  // net's pass (-1 kept, else j).
+  std::vector<int> rc_seg, rc_sched;
+  std::vector<sta::GroupRange> rc_ranges;
   sta::StateLayout state{};
   sta::WorkLayout work{};
   int n_ep_blocks = 0;

@@ -23,6 +23,7 @@
 //    and xor butterflies inside the group, across waves through LDS in a fixed order
 //    (no atomics, Sec. 3.1.1).
 //  * The one-pass RC kernel and the forward output expansion use groups from 4 lanes.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -367,13 +368,15 @@ struct RcArgs {
   const int* __restrict__ net_list;     // RC trees: the nets of the fallback kernel
   int n_list;
   int n_chunks;
+  const int* __restrict__ sink_base;    // checkpointing (stars): first wire slot of each net's
+                                        // sinks; NULL: a sink's slot is its pin
 };
 
 // One sink p of a star net whose driver sits at (xd, yd): wire delay and impulse (Eq. 2-3)
-// to wire[p]; returns what the sink adds to the root load (Eq. 1): its pin cap plus the
-// whole wire, half of which sits at each end.
+// to wire[slot] (slot = p without checkpointing); returns what the sink adds to the root load
+// (Eq. 1): its pin cap plus the whole wire, half of which sits at each end.
 __device__ __forceinline__ float rc_sink(const RcArgs& a, const float* __restrict__ xs, const float* __restrict__ ys,
-                                         float2* __restrict__ wire, int p, float xd, float yd) {
+                                         float2* __restrict__ wire, int p, int slot, float xd, float yd) {
   const int q = a.io_perm ? a.io_perm[p] : p;
   const float cp = a.pin_cap[p];
   const float len = fabsf(xs[q] - xd) + fabsf(ys[q] - yd);
@@ -384,16 +387,17 @@ __device__ __forceinline__ float rc_sink(const RcArgs& a, const float* __restric
   const float dly = 1e-3f * res * load;        // Eq. 2 (ohm * fF = 1e-3 ps)
   const float arg = 2.0f * (1e-3f * res * cap) * dly - dly * dly;   // Eq. 3
   const float imp = arg > 0.f ? sqrtf(arg) : 0.f;
-  wire[p] = make_float2(dly, imp);
+  wire[slot] = make_float2(dly, imp);
   return cp + cw;
 }
 
 // Root of net n (driver pin p0) once its sinks' contributions are summed: the root load,
-// a zero wire at the driver, and the arrival record of a primary-input net.
+// a zero wire at the driver (wires by pin only), and the arrival record of a primary-input
+// net.
 __device__ __forceinline__ void rc_root(const RcArgs& a, float2* __restrict__ wire, float* __restrict__ loads,
                                         float4* __restrict__ rec, int n, int p0, float sum, bool is_total = false) {
   loads[n] = is_total ? sum : a.pin_cap[p0] + sum;   // Eq. 1 at the root
-  wire[p0] = make_float2(0.f, 0.f);
+  if (!a.sink_base) wire[p0] = make_float2(0.f, 0.f);
   if (n < a.N0) {
     float4* r = rec + kRecChunks * (size_t)n;
     r[0] = make_float4(a.pi_at, a.pi_slew, 0.f, 0.f);
@@ -425,8 +429,10 @@ __global__ __launch_bounds__(kBlock) void k_rc(RcArgs a) {
     xd = xs[q];
     yd = ys[q];
   }
+  // Wire slots: a net's sinks take consecutive slots from sink_base[n] under checkpointing.
+  const int sk0 = (gs.active && a.sink_base) ? a.sink_base[n] - (p0 + 1) : 0;
   float sum = 0.f;
-  for (int p = p0 + 1 + gs.gl; p < p1; p += gs.G) sum += rc_sink(a, xs, ys, wire, p, xd, yd);
+  for (int p = p0 + 1 + gs.gl; p < p1; p += gs.G) sum += rc_sink(a, xs, ys, wire, p, sk0 + p, xd, yd);
   sum = gs.block ? block_sum(sum, sh) : wave_group_sum(sum, gs.G);
   if (gs.active && gs.gl == 0) rc_root(a, wire, loads, rec, n, p0, sum);
 }
@@ -516,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_cte(RcArgs a) {
     for (int task = c0 + t; task < c1; task += kBlock) {
       const int lo = cte_owner(pre, task);
       const int p = first[lo] + (task - pre[lo]);
-      part[task - c0] = rc_sink(a, xs, ys, wire, p, dx_[lo], dy_[lo]);
+      part[task - c0] = rc_sink(a, xs, ys, wire, p, p, dx_[lo], dy_[lo]);   // wires by pin
     }
     __syncthreads();
     for (int i = max(my0, c0); i < min(my1, c1); ++i) sum += part[i - c0];
@@ -539,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_rc_thread(RcArgs a) {
   const int q = a.io_perm ? a.io_perm[p0] : p0;
   const float xd = xs[q], yd = ys[q];
   float sum = 0.f;
-  for (int p = p0 + 1; p < p1; ++p) sum += rc_sink(a, xs, ys, wire, p, xd, yd);
+  for (int p = p0 + 1; p < p1; ++p) sum += rc_sink(a, xs, ys, wire, p, p, xd, yd);   // wires by pin
   rc_root(a, wire, loads, rec, n, p0, sum);
 }
 
@@ -1011,7 +1017,7 @@ struct ArcIn {          // one cell input seen from one condition
 };
 
 // Input slot entries are {source record slot, input pin, arc with the sign bit set for
-// negative unateness, the input pin's sink workspace slot}.
+// negative unateness, the input pin's sink slot (its wire and its workspace records)}.
 __device__ __forceinline__ int ell_arc(const int4& e) { return e.z & 0x7fffffff; }
 __device__ __forceinline__ bool ell_positive(const int4& e) { return e.z >= 0; }
 
@@ -1034,7 +1040,7 @@ __device__ __forceinline__ ArcIn arc_input_entry(const int4 e, bool valid, const
   r.slot = e.w;
   const int kp = 2 * m + r.tp;
   const float4 c = ld(rec, (uint32_t)(kRecChunks * max(e.x, 0) + kp));
-  const float2 w = ld(wire, (uint32_t)e.y);
+  const float2 w = ld(wire, (uint32_t)e.w);
   r.at = c.x + w.x;
   r.slew = sink_slew(c.y, w.y);
   r.atg = c.z + w.x;
@@ -1053,7 +1059,7 @@ __device__ __forceinline__ ArcIn arc_input(const int4* __restrict__ ell, const S
   r.slot = e.w;
   const int kp = 2 * m + r.tp;
   const float4 c = rec[kRecChunks * (size_t)max(e.x, 0) + kp];   // {AT, slew, smoothed AT} of kp
-  const float2 w = wire[e.y];
+  const float2 w = wire[e.w];
   r.at = c.x + w.x;
   r.slew = sink_slew(c.y, w.y);
   r.atg = c.z + w.x;
@@ -1278,7 +1284,7 @@ __device__ __forceinline__ EpVals endpoint_values(const EpArgs& a, int i) {
   const int e = a.ep_pin[i];
   const float4 c2 = a.rec[kRecChunks * (size_t)a.ep_net[i] + 2];   // late rise
   const float4 c3 = a.rec[kRecChunks * (size_t)a.ep_net[i] + 3];   // late fall
-  const float dl = a.wire[e].x;
+  const float dl = a.wire[a.ep_sslot ? a.ep_sslot[i] : e].x;
   EpVals v;
   v.worst = fminf(a.rat_late - (c2.x + dl), a.rat_late - (c3.x + dl));
   // s_e = -LSE(-slack_g(rise), -slack_g(fall))
@@ -1540,7 +1546,7 @@ __device__ __forceinline__ SinkIn sink_load(const BwdArgs& a, int p, int slot) {
   SinkIn in;
   const uint32_t u = (uint32_t)p;
   in.rt = ld(a.sink, rat_at((uint32_t)slot));
-  in.w = ld(a.wire, u);
+  in.w = ld(a.wire, (uint32_t)slot);
   in.q = kCanon ? p : ld(a.io_perm, u);
   in.aj = make_float4(0.f, 0.f, 0.f, 0.f);
   in.xs = in.ys = in.cp = 0.f;
@@ -1739,7 +1745,7 @@ __device__ __forceinline__ void bwd_net(const BwdArgs& a, const Slots& sl, const
     ain[i].slot = e[i].w;
     const int kp = 2 * m + ain[i].tp;
     const float4 c = ld(a.rec, (uint32_t)(kRecChunks * max(e[i].x, 0) + kp));
-    const float2 w = ld(a.wire, (uint32_t)e[i].y);
+    const float2 w = ld(a.wire, (uint32_t)e[i].w);
     ain[i].at = c.x + w.x;
     ain[i].slew = sink_slew(c.y, w.y);
     ain[i].atg = c.z + w.x;
@@ -3122,6 +3128,15 @@ void fwd_level_launch(const sta_graph* g, hipStream_t s, const Slots& sl, int mi
   }
 }
 
+// RC pass p of a checkpointed star graph (rc_ranges: 0 the kept nets, 1 + j segment j's other
+// nets), in lane groups over rc_sched (uploaded in sched_all's place).
+void rc_pass(const sta_graph* g, hipStream_t s, RcArgs ra, int p) {
+  ra.sched = g->dev.sched_all;
+  ra.range = g->rc_ranges[p];
+  const unsigned blocks = range_grid(ra.range);
+  if (blocks > 0) k_rc<<<snap_grid(g, blocks), kBlock, 0, s>>>(ra);
+}
+
 // ---------------------------------------------------------------- snapshot-inner launches
 struct SiDims {
   int S, sl2;
@@ -3276,11 +3291,16 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
   RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0, g->N,
             g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, sn, d.parent, d.tree_order,
             tree ? reinterpret_cast<float4*>(sb + g->state.tree) : nullptr, d.tree_node, d.tree_blk_net,
-            d.tree_blk_depth, d.tree_big, n_big, n_chunks};
+            d.tree_blk_depth, d.tree_big, n_big, n_chunks, d.sink_base};
+  // With checkpointing the wire values share slots like the sink workspace: the RC stage runs
+  // in passes (lane groups), the kept nets' here and each segment's before its levels.
+  const bool rc_passes = !g->rc_ranges.empty();
   {
     LaunchTimer t(g, s, STA_K_RC);
     const unsigned per_net = (unsigned)((g->N + kBlock - 1) / kBlock);
-    if (tree) {
+    if (rc_passes) {
+      rc_pass(g, s, ra, 0);
+    } else if (tree) {
       if (n_chunks > 0) k_rc_tree_chunk<<<snap_grid(g, (unsigned)n_chunks), kBlock, 0, s>>>(ra);
       if (n_big > 0) k_rc_tree<<<snap_grid(g, (unsigned)((n_big + kBlock - 1) / kBlock)), kBlock, 0, s>>>(ra);
     } else if (g->sched_cfg.rc_scheme == STA_RC_CTE)
@@ -3295,6 +3315,13 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
                    smooth ? 1 : 0};
   const bool cte = g->sched_cfg.level_scheme == STA_LEVEL_CTE;
   for (int l = 1; l < g->L; ++l) {
+    if (rc_passes) {                           // a segment starts: its nets' RC pass
+      const auto it = std::find(g->seg_lo.begin(), g->seg_lo.end() - 1, l);
+      if (it != g->seg_lo.end() - 1) {
+        LaunchTimer t(g, s, STA_K_RC);
+        rc_pass(g, s, ra, 1 + (int)(it - g->seg_lo.begin()));
+      }
+    }
     const Slots sl = level_slots(g, l);
     if (sl.nc == 0) continue;
     LaunchTimer t(g, s, STA_K_FWD_LEVEL);
@@ -3411,8 +3438,15 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
     // smoothed arrival only where the gradient reads it.
     const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, grad ? 1.0f / gamma_ps : 0.f,
                      grad ? 1 : 0};
+    const RcArgs ra{d.net_off, d.pin_cap, x, y, io, d.sched_all, g->all_range, wire, load, rec, g->N0, g->N,
+                    g->cons.r_per_um, g->cons.c_per_um, g->cons.pi_at, g->cons.pi_slew, snap_of(g), nullptr,
+                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, d.sink_base};
     for (int j = (int)g->seg_lo.size() - 2; j >= 0; --j) {
       const int lo = g->seg_lo[j], hi = g->seg_lo[j + 1];
+      if (!g->rc_ranges.empty()) {             // the segment's wire values, rewritten
+        LaunchTimer t(g, s, STA_K_RC);
+        rc_pass(g, s, ra, 1 + j);
+      }
       for (int l = lo; l < hi; ++l) {
         const Slots sl = level_slots(g, l);
         if (sl.nc == 0) continue;

@@ -287,14 +287,20 @@ def test_checkpoint_segments_backward_workspace(k):
     g.levelize()
     up = lambda b: -(-b // 256) * 256                                 # pieces start 256-aligned
     plain = g.info()["bwd_workspace_bytes"]
+    state = g.info()["fwd_state_bytes"]
     assert plain == up(32 * d.n_pins)
     g.set_checkpointing(k)
     slots = _expected_sink_slots(d, k)
     sinks = d.n_pins - d.n_nets
     assert slots < sinks if k == 3 else slots == sinks                # one level, one segment: no reuse
     assert g.info()["bwd_workspace_bytes"] == up(32 * max(slots, 1))
+    # the wire values (8 bytes per sink slot instead of per pin) follow the same slots
+    recs = g.checkpointing()["record_slots"]
+    assert g.info()["fwd_state_bytes"] == state - (up(64 * d.n_nets) - up(64 * recs)) \
+        - (up(8 * d.n_pins) - up(8 * max(slots, 1)))
     g.set_checkpointing(0)
     assert g.info()["bwd_workspace_bytes"] == plain
+    assert g.info()["fwd_state_bytes"] == state
     g.close()
 
 
