@@ -197,3 +197,39 @@ def test_waiting_requests_merge_into_snapshot_sweeps():
         torch.cuda.synchronize()
         ref["scalars"] = f.scalars.cpu().numpy()
         _same(r, ref)
+
+
+def test_concurrent_clients_get_their_own_results():
+    # Four client threads submit and wait at once (mixed kinds, new and resident coordinates,
+    # merging on); every result equals the same request run alone.
+    import threading
+    ds, gs = _designs()
+    reqs = _requests(ds, n=48)
+    srv = Server(8 << 30, max_slots=4, max_merge=8)
+    ids = [srv.add_design(g, d.x, d.y) for g, d in zip(gs, ds)]
+    out = [None] * len(reqs)
+    errors = []
+
+    def client(part):
+        try:
+            mine = []
+            for i in part:
+                k, grad, xy = reqs[i]
+                mine.append((i, srv.submit(ids[k], grad=grad, x=None if xy is None else xy[0],
+                                           y=None if xy is None else xy[1], gamma=GAMMA)))
+            for i, t in mine:
+                out[i] = srv.wait(t)
+        except Exception as e:                  # reported below, on the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(range(c, len(reqs), 4),)) for c in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    st = srv.stats()
+    srv.close()
+    assert not errors, errors
+    assert st["completed"] == len(reqs)
+    for (k, grad, xy), r in zip(reqs, out):
+        _same(r, _alone(gs[k], ds[k], grad, xy))
