@@ -2671,9 +2671,11 @@ __device__ __forceinline__ void lse_merge_d(double& m, double& s, double m2, dou
 
 // Per-block partials of each snapshot over the block's endpoints (the blocks of k_ep_partials),
 // in float64: each thread sums its endpoints in order, then the threads of a snapshot meet in
-// LDS in thread order.
-__global__ __launch_bounds__(kBlock) void k_ep_partials_si(EpSiArgs a) {
-  __shared__ double sh[5 * kBlock];
+// LDS in thread order.  kEpSiThreads threads serve a block's kBlock endpoints, so that each
+// wave walks few of them (the float64 log and exp per endpoint and snapshot are long).
+constexpr int kEpSiThreads = 1024;
+__global__ __launch_bounds__(kEpSiThreads) void k_ep_partials_si(EpSiArgs a) {
+  __shared__ double sh[5 * kEpSiThreads];
   const uint32_t S = (uint32_t)a.S;
   int dsg = 0;
   while (dsg + 1 < a.n_designs && (int)blockIdx.x >= a.ep_blk_off[dsg + 1]) ++dsg;
@@ -2682,7 +2684,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials_si(EpSiArgs a) {
   const SiLane ln = si_lane(a.sl2, a.S, (int)(threadIdx.x >> 6));
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, m = 0.0, sm = 0.0;
   if (ln.on) {
-    for (int i = i0 + ln.item; i < i1; i += kBlock >> a.sl2) {
+    for (int i = i0 + ln.item; i < i1; i += kEpSiThreads >> a.sl2) {
       const EpVals ev = endpoint_values_si(a, i, ln.s);
       *at32(a.epv, si_at(i, S, ln.s)) = make_float4(ev.sg, ev.w0, ev.w1, 0.f);
       tns += fmin(0.0, (double)ev.worst);
@@ -2694,18 +2696,18 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials_si(EpSiArgs a) {
   }
   const int t = (int)threadIdx.x;
   sh[t] = tns;
-  sh[kBlock + t] = wmin;
-  sh[2 * kBlock + t] = tnsg;
-  sh[3 * kBlock + t] = m;
-  sh[4 * kBlock + t] = sm;
+  sh[kEpSiThreads + t] = wmin;
+  sh[2 * kEpSiThreads + t] = tnsg;
+  sh[3 * kEpSiThreads + t] = m;
+  sh[4 * kEpSiThreads + t] = sm;
   __syncthreads();
   if (t < (1 << a.sl2) && ln.on) {
     double r0 = 0.0, r1 = __builtin_huge_val(), r2 = 0.0, r3 = 0.0, r4 = 0.0;
-    for (int u = t; u < kBlock; u += 1 << a.sl2) {
+    for (int u = t; u < kEpSiThreads; u += 1 << a.sl2) {
       r0 += sh[u];
-      r1 = fmin(r1, sh[kBlock + u]);
-      r2 += sh[2 * kBlock + u];
-      lse_merge_d(r3, r4, sh[3 * kBlock + u], sh[4 * kBlock + u], (double)a.gamma);
+      r1 = fmin(r1, sh[kEpSiThreads + u]);
+      r2 += sh[2 * kEpSiThreads + u];
+      lse_merge_d(r3, r4, sh[3 * kEpSiThreads + u], sh[4 * kEpSiThreads + u], (double)a.gamma);
     }
     double* p = a.part;
     const int b = (int)blockIdx.x;
@@ -3206,7 +3208,7 @@ sta_status launch_forward_si(sta_graph* g, const float* x, const float* y, const
                                  1.0f);
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
-    k_ep_partials_si<<<dim3(g->n_ep_blocks, D.gy), kBlock, 0, s>>>(ea);
+    k_ep_partials_si<<<dim3(g->n_ep_blocks, D.gy), kEpSiThreads, 0, s>>>(ea);
   }
   {
     LaunchTimer t(g, s, STA_K_EP_FINAL);
