@@ -2994,9 +2994,28 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   const int lanes = 1 << hl2;                   // heavy workgroups: snapshots per workgroup
   const int first = kHeavy ? ln.item : 0;
   const int stride = kHeavy ? kB / lanes : 1;
+  // Outside heavy workgroups, what the Elmore adjoint needs of a lane's first kSiHeavy sinks
+  // stays on chip: the sink's share in this thread's column of the LDS array, the signs of its
+  // x and y offsets as 2-bit codes (sign + 1) in two registers.  The adjoint pass then reads
+  // none of those sinks again.
+  static_assert(kSiHeavy <= N_ACC + 1 && 2 * kSiHeavy <= 32, "sink cache must fit the LDS array and codes");
+  uint32_t gxs = 0, gys = 0;
   if (ln.on) {
+    if (kGrad && !kHeavy) {
+      int i = 0;
 #pragma unroll 4
-    for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
+      for (int p = p0 + 1; p < p1; ++p, ++i) {
+        const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
+        if (i < kSiHeavy) {
+          sh[i * kB + threadIdx.x] = k.rest;
+          gxs |= (uint32_t)(int)(k.gx + 1.f) << (2 * i);
+          gys |= (uint32_t)(int)(k.gy + 1.f) << (2 * i);
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
+    }
   }
   const bool leader = !kHeavy || (int)threadIdx.x < lanes;
   if (kHeavy) {
@@ -3035,11 +3054,26 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
     __syncthreads();
     lbar = sh[N_ACC * kB + (threadIdx.x & (unsigned)(lanes - 1))];
   }
-  // Elmore adjoint of every sink (the sinks are read again).
+  // Elmore adjoint of every sink: the cached ones from LDS and their codes, the rest (sinks
+  // of heavy workgroups, and beyond kSiHeavy when every net takes one lane) read again.
   if (kGrad && ln.on && (a.dx || a.dy)) {
     const float cl = a.c * lbar;
+    int from = first;
+    if (!kHeavy) {
+      const int nk = min(p1 - p0 - 1, kSiHeavy);
+      for (int i = 0; i < nk; ++i) {
+        const int p = p0 + 1 + i;
+        const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
+        const float rest = sh[i * kB + threadIdx.x];
+        const float gx = (float)((int)((gxs >> (2 * i)) & 3u) - 1);
+        const float gy = (float)((int)((gys >> (2 * i)) & 3u) - 1);
+        if (a.dx) *at32(a.dx, o) = gx * (cl + rest);
+        if (a.dy) *at32(a.dy, o) = gy * (cl + rest);
+      }
+      from = kSiHeavy;
+    }
 #pragma unroll 4
-    for (int p = p0 + 1 + first; p < p1; p += stride) {
+    for (int p = p0 + 1 + from; p < p1; p += stride) {
       float scratch[N_ACC] = {};
       const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, scratch, false);
       if (a.dx) *at32(a.dx, k.o) = k.gx * (cl + k.rest);
