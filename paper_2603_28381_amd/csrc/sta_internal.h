@@ -21,7 +21,8 @@ constexpr int kSweepG0Default = 2;   // level kernels: smallest backward group 4
 constexpr int kTreeChunk = 1024;     // RC trees: pins of whole nets swept by one workgroup in LDS
 constexpr int kSiHeavy = 12;         // snapshot-inner layout: nets with more sinks take a whole
                                      // workgroup for up to 64 snapshots,
-constexpr int kSiHuge = 128;         // nets with more than this a workgroup per 8 snapshots
+constexpr int kSiHuge = 128;         // nets with more than this a workgroup per 8 snapshots (RC,
+                                     // and the backward in 512-thread workgroups)
 
 // Lane-group class of a net with `sinks` sink pins when the smallest group has 1 << g0
 // lanes: the smallest wave group (doubling from 1 << g0) in which every lane holds at most

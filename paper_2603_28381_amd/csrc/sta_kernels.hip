@@ -2406,6 +2406,22 @@ __device__ __forceinline__ uint32_t si_at(int i, uint32_t S, int s) { return (ui
 // 8 snapshots).
 // Workgroup hb of a class serves net hb / nch of the class and snapshot chunk hb % nch.
 __device__ __forceinline__ int chunks_of(int S, int hl2) { return (S + (1 << hl2) - 1) >> hl2; }
+
+// Snapshots a backward heavy workgroup of kb threads takes (log2): each snapshot keeps at least
+// 8 threads for nets of up to kSiHuge sinks (64 snapshots at kb = 512) and at least 64 beyond
+// (8 snapshots).  Wider splits were measured slower: their extra workgroups take wave slots
+// the level's other nets need in the same round.
+__host__ __device__ constexpr int si_log2(int v) { return v <= 1 ? 0 : 1 + si_log2(v >> 1); }
+constexpr int kSiHeavyTpsL2 = 3;     // log2 of the threads per snapshot: nets of up to kSiHuge sinks
+constexpr int kSiHugeTpsL2 = 6;      // and beyond
+__host__ __device__ inline int si_bwd_hl2(int sl2, int kb, bool huge) {
+  const int l2 = si_log2(kb) - (huge ? kSiHugeTpsL2 : kSiHeavyTpsL2);
+  return sl2 < l2 ? sl2 : l2;
+}
+constexpr int kSiCacheHeavy = 4;     // sinks a heavy workgroup's thread keeps on chip
+constexpr int kSiRows = 17;          // LDS rows of kB floats in the backward: N_ACC reductions
+                                     // and lbar, then the sink cache (kSiHeavy rows outside
+                                     // heavy workgroups)
 __device__ __forceinline__ SiLane si_heavy_lane(int hl2, int S, int chunk) {
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   SiLane r;
@@ -2994,42 +3010,47 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   const int lanes = 1 << hl2;                   // heavy workgroups: snapshots per workgroup
   const int first = kHeavy ? ln.item : 0;
   const int stride = kHeavy ? kB / lanes : 1;
-  // Outside heavy workgroups, what the Elmore adjoint needs of a lane's first kSiHeavy sinks
-  // stays on chip: the sink's share in this thread's column of the LDS array, the signs of its
-  // x and y offsets as 2-bit codes (sign + 1) in two registers.  The adjoint pass then reads
-  // none of those sinks again.
-  static_assert(kSiHeavy <= N_ACC + 1 && 2 * kSiHeavy <= 32, "sink cache must fit the LDS array and codes");
+  // What the Elmore adjoint needs of a thread's first sinks stays on chip: the sink's share in
+  // this thread's column of the LDS array (rows from `crow`), the signs of its x and y offsets
+  // as 2-bit codes (sign + 1) in two registers.  The adjoint pass then reads none of those
+  // sinks again.  A lane outside heavy workgroups keeps kSiHeavy sinks (all of a net of that
+  // class), a heavy workgroup's thread kSiCacheHeavy.
+  constexpr int kCache = kHeavy ? kSiCacheHeavy : kSiHeavy;
+  constexpr int crow = kHeavy ? N_ACC + 1 : 0;
+  static_assert(crow + kCache <= kSiRows && 2 * kCache <= 32, "sink cache must fit the LDS array and codes");
   uint32_t gxs = 0, gys = 0;
   if (ln.on) {
-    if (kGrad && !kHeavy) {
-      int i = 0;
+    int i = 0;
 #pragma unroll 4
-      for (int p = p0 + 1; p < p1; ++p, ++i) {
-        const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
-        if (i < kSiHeavy) {
-          sh[i * kB + threadIdx.x] = k.rest;
-          gxs |= (uint32_t)(int)(k.gx + 1.f) << (2 * i);
-          gys |= (uint32_t)(int)(k.gy + 1.f) << (2 * i);
-        }
+    for (int p = p0 + 1 + first; p < p1; p += stride, ++i) {
+      const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
+      if (kGrad && i < kCache) {
+        sh[(crow + i) * kB + threadIdx.x] = k.rest;
+        gxs |= (uint32_t)(int)(k.gx + 1.f) << (2 * i);
+        gys |= (uint32_t)(int)(k.gy + 1.f) << (2 * i);
       }
-    } else {
-#pragma unroll 4
-      for (int p = p0 + 1 + first; p < p1; p += stride) sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, acc, true);
     }
   }
   const bool leader = !kHeavy || (int)threadIdx.x < lanes;
   if (kHeavy) {
+    // Tree over the threads of each snapshot (thread t and t + h meet while h >= lanes), in a
+    // fixed order: the leaders end with the totals.
+    const int t = (int)threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < N_ACC; ++i) sh[i * kB + threadIdx.x] = acc[i];
-    __syncthreads();
-    if (leader) {
-      for (int u = (int)threadIdx.x + lanes; u < kB; u += lanes) {
-        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kB + u]);
-        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kB + u]);
-        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kB + u]);
-        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kB + u]);
+    for (int i = 0; i < N_ACC; ++i) sh[i * kB + t] = acc[i];
+    for (int h = kB >> 1; h >= lanes; h >>= 1) {
+      __syncthreads();
+      if (t < h) {
+        acc[R_E0] = fmaxf(acc[R_E0], sh[R_E0 * kB + t + h]);
+        acc[R_E1] = fmaxf(acc[R_E1], sh[R_E1 * kB + t + h]);
+        acc[R_L0] = fminf(acc[R_L0], sh[R_L0 * kB + t + h]);
+        acc[R_L1] = fminf(acc[R_L1], sh[R_L1 * kB + t + h]);
 #pragma unroll
-        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kB + u];
+        for (int i = A_R; i < N_ACC; ++i) acc[i] += sh[i * kB + t + h];
+        if (h > lanes) {
+#pragma unroll
+          for (int i = 0; i < N_ACC; ++i) sh[i * kB + t] = acc[i];
+        }
       }
     }
   }
@@ -3054,26 +3075,21 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
     __syncthreads();
     lbar = sh[N_ACC * kB + (threadIdx.x & (unsigned)(lanes - 1))];
   }
-  // Elmore adjoint of every sink: the cached ones from LDS and their codes, the rest (sinks
-  // of heavy workgroups, and beyond kSiHeavy when every net takes one lane) read again.
+  // Elmore adjoint of every sink: the cached ones from LDS and their codes, the rest (beyond
+  // the cache) read again.
   if (kGrad && ln.on && (a.dx || a.dy)) {
     const float cl = a.c * lbar;
-    int from = first;
-    if (!kHeavy) {
-      const int nk = min(p1 - p0 - 1, kSiHeavy);
-      for (int i = 0; i < nk; ++i) {
-        const int p = p0 + 1 + i;
-        const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
-        const float rest = sh[i * kB + threadIdx.x];
-        const float gx = (float)((int)((gxs >> (2 * i)) & 3u) - 1);
-        const float gy = (float)((int)((gys >> (2 * i)) & 3u) - 1);
-        if (a.dx) *at32(a.dx, o) = gx * (cl + rest);
-        if (a.dy) *at32(a.dy, o) = gy * (cl + rest);
-      }
-      from = kSiHeavy;
+    int p = p0 + 1 + first;
+    for (int i = 0; i < kCache && p < p1; ++i, p += stride) {
+      const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
+      const float rest = sh[(crow + i) * kB + threadIdx.x];
+      const float gx = (float)((int)((gxs >> (2 * i)) & 3u) - 1);
+      const float gy = (float)((int)((gys >> (2 * i)) & 3u) - 1);
+      if (a.dx) *at32(a.dx, o) = gx * (cl + rest);
+      if (a.dy) *at32(a.dy, o) = gy * (cl + rest);
     }
 #pragma unroll 4
-    for (int p = p0 + 1 + from; p < p1; p += stride) {
+    for (; p < p1; p += stride) {
       float scratch[N_ACC] = {};
       const SinkSi k = sink_si<kGrad>(a, p, s, at_d, sl_d, xd, yd, scratch, false);
       if (a.dx) *at32(a.dx, k.o) = k.gx * (cl + k.rest);
@@ -3086,17 +3102,18 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
 // workgroup per net and snapshot chunk, then the nets [nb, nh0), (64 >> sl2) per wave.
 template <bool kGrad, int kB>
 __global__ __launch_bounds__(kB) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
-  __shared__ float sh[N_ACC * kB + kB];
+  __shared__ float sh[kSiRows * kB];
   const int w = (int)(threadIdx.x >> 6);
   const int b = (int)blockIdx.x;
-  const int hl2u = min(a.sl2, 3), nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, a.sl2);
+  const int hl2u = si_bwd_hl2(a.sl2, kB, true), hl2h = si_bwd_hl2(a.sl2, kB, false);
+  const int nchu = chunks_of(a.S, hl2u), nchh = chunks_of(a.S, hl2h);
   const int nbu = (ne - nu0) * nchu, nbh = (nu0 - nh0) * nchh;
   if (b < nbu + nbh) {
     if (blockIdx.y != 0) return;               // these workgroups cover their snapshots along x
     if (b < nbu)
       bwd_net_si<kGrad, true, kB>(a, sl, nu0 + b / nchu, si_heavy_lane(hl2u, a.S, b % nchu), hl2u, sh);
     else
-      bwd_net_si<kGrad, true, kB>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(a.sl2, a.S, (b - nbu) % nchh), a.sl2, sh);
+      bwd_net_si<kGrad, true, kB>(a, sl, nh0 + (b - nbu) / nchh, si_heavy_lane(hl2h, a.S, (b - nbu) % nchh), hl2h, sh);
     return;
   }
   const SiLane ln = si_lane(a.sl2, a.S, (b - nbu - nbh) * (kB / 64) + w);
@@ -3288,8 +3305,9 @@ sta_status launch_backward_si(sta_graph* g, const float* x, const float* y, cons
     const int lo = g->level_off[l], hi = g->level_off[l + 1];
     const int hs = D.split ? g->si_hs[l] : hi, us = D.split ? g->si_us[l] : hi;
     if (hi == lo) continue;
-    const unsigned blocks =
-        (unsigned)((hi - us) * D.uch + (us - hs) * D.hch) + si_blocks(hs - lo, D.sl2, kb / 64);
+    const int uch = (D.S + (1 << si_bwd_hl2(D.sl2, kb, true)) - 1) >> si_bwd_hl2(D.sl2, kb, true);
+    const int hch = (D.S + (1 << si_bwd_hl2(D.sl2, kb, false)) - 1) >> si_bwd_hl2(D.sl2, kb, false);
+    const unsigned blocks = (unsigned)((hi - us) * uch + (us - hs) * hch) + si_blocks(hs - lo, D.sl2, kb / 64);
     LaunchTimer t(g, s, STA_K_BWD_LEVEL);
     const Slots sl = level_slots(g, l);
     const dim3 grid(blocks, D.gy);
