@@ -218,7 +218,10 @@ sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out
  * it rebuilds records inside the state and calls on one state must not overlap.
  * Errors: STA_E_STATE (not levelized / not uploaded; with STA_GRAD also a state that the
  * latest of this graph's sta_forward calls into it did not compute with STA_SMOOTH and the
- * same gamma_ps, or that no sta_forward on this graph produced), STA_E_INVALID.
+ * same gamma_ps, or under a schedule of the other kernel family -- snapshot lanes or
+ * STA_LEVEL_THREAD against the lane-group schemes, whose backward takes the softmax
+ * normaliser and worst-slew arc of each cell from the forward's records -- or that no
+ * sta_forward on this graph produced), STA_E_INVALID.
  * ------------------------------------------------------------------------------------- */
 sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);

@@ -196,8 +196,10 @@ struct sta_graph {
 
   // The smoothing flag and gamma of the latest sta_forward into each state buffer (most
   // recent last, at most kFwdSeen entries), so that sta_backward can refuse a gradient
-  // against a state computed without the smoothed arrival or with another gamma.
-  struct FwdSeen { const void* state; bool smooth; float gamma; };
+  // against a state computed without the smoothed arrival or with another gamma, or by the
+  // other family of level kernels (lanes: the snapshot-lane / thread-per-net kernels, whose
+  // backward takes the softmax normaliser and worst-slew arc from their forward's records).
+  struct FwdSeen { const void* state; bool smooth; float gamma; bool lanes; };
   static constexpr size_t kFwdSeen = 256;
   std::vector<FwdSeen> fwd_seen;
 

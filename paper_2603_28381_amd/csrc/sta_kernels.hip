@@ -2904,58 +2904,20 @@ __device__ __forceinline__ SinkSi sink_si(const BwdSiArgs& a, int p, int s, cons
   return k;
 }
 
-// Cell step of cell kc in snapshot s (as the 4-lane backward group's, in one lane): the
-// inputs' required times, and with the gradient the softmax split of the driver's adjoint
-// over the arcs (normaliser and arg-max slew taken chunk by chunk of 4 arcs), the slew
-// adjoint and the load adjoint, which it returns.
+// Cell step of cell kc in snapshot s, one pass over its arcs: the inputs' required times, and
+// with the gradient the split of the driver's adjoint over the arcs and the slew and load
+// adjoints, which it returns.  The softmax weight of an arc is exp((x_j - ATg) / gamma), with
+// ATg the driver's smoothed arrival that the forward kept (its maximum plus gamma times the log
+// of its sum, Eq. 4); the slew adjoint goes to the first arc whose output slew equals the
+// driver's kept worst slew (the forward took that maximum over the same lookups, bit for bit).
 template <bool kGrad>
 __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& sl, int kc, int s, float load,
-                                              const float (&acc)[N_ACC]) {
+                                              const float (&acc)[N_ACC], float2 atg, float2 worst) {
   const uint32_t S = (uint32_t)a.S;
-  float xmax[2] = {-kInf, -kInf}, z[2] = {0.f, 0.f}, smax[2] = {-kInf, -kInf};
-  int jstar[2] = {STA_MAX_FANIN, STA_MAX_FANIN};
-  if (kGrad) {
-    for (int j0 = 0; j0 < sl.F; j0 += kArcLanes) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        float xg[kArcLanes], cm = -kInf, cz = 0.f, s2 = -kInf;
-        int j2 = STA_MAX_FANIN;
-        bool valid[kArcLanes];
-#pragma unroll
-        for (int i = 0; i < kArcLanes; ++i) {
-          const int j = j0 + i;
-          const int4 e = ld(a.ell, (uint32_t)(sl.base + min(j, sl.F - 1) * sl.nc + kc));
-          valid[i] = j < sl.F && e.x >= 0;
-          const int src = kRecChunks * max(e.x, 0) + 2;
-          const float4 ci = pick_tr(ell_positive(e), t, ld(a.rec, si_at(src, S, s)), ld(a.rec, si_at(src + 1, S, s)));
-          const float2 w = ld(a.wire, si_at(e.y, S, s));
-          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(ci.y, w.y), load);
-          xg[i] = valid[i] ? (ci.z + w.x) + v.d : -kInf;
-          cm = fmaxf(cm, xg[i]);
-          const bool take = valid[i] && (j2 == STA_MAX_FANIN || v.s > s2);
-          s2 = take ? v.s : s2;
-          j2 = take ? j : j2;
-        }
-#pragma unroll
-        for (int i = 0; i < kArcLanes; ++i) cz += valid[i] ? fexp((xg[i] - cm) * a.inv_gamma) : 0.f;
-        if (j0 == 0) {
-          xmax[t] = cm;
-          z[t] = cz;
-          smax[t] = s2;
-          jstar[t] = j2;
-        } else {
-          lse_merge(xmax[t], z[t], cm, cz, a.inv_gamma);
-          if (s2 > smax[t]) {
-            smax[t] = s2;
-            jstar[t] = j2;
-          }
-        }
-      }
-    }
-  }
   const float rat_o[4] = {acc[R_E0], acc[R_E1], acc[R_L0], acc[R_L1]};
   const float abar[2] = {acc[A_R], acc[A_F]}, sbar[2] = {acc[S_R], acc[S_F]};
-  const float inv_z[2] = {kGrad ? frcp(z[0]) : 0.f, kGrad ? frcp(z[1]) : 0.f};
+  const float ag[2] = {atg.x, atg.y}, smax[2] = {worst.x, worst.y};
+  bool open[2] = {true, true};    // the worst-slew arc of the transition not met yet
   float lb[2] = {0.f, 0.f};
 #pragma unroll 2
   for (int j = 0; j < sl.F; ++j) {
@@ -2976,8 +2938,10 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
       set_comp(rat_in, 2 * m + tp, rat_o[k] - v.d);
       if (kGrad && m == 1) {
         const float xg = (ci.z + w.x) + v.d;
-        const float dbar = fexp((xg - xmax[t]) * a.inv_gamma) * inv_z[t] * abar[t];
-        const float s_j = j == jstar[t] ? sbar[t] : 0.f;
+        const float dbar = fexp((xg - ag[t]) * a.inv_gamma) * abar[t];
+        const bool star = open[t] && v.s == smax[t];
+        open[t] = open[t] && !star;
+        const float s_j = star ? sbar[t] : 0.f;
         set_comp(adj_in, tp, dbar);
         set_comp(adj_in, 2 + tp, fmaf(dbar, v.ddx, s_j * v.dsx));
         lb[t] = fmaf(dbar, v.ddy, fmaf(s_j, v.dsy, lb[t]));
@@ -3056,7 +3020,9 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   }
   float lbar = 0.f;
   if (leader && ln.on) {
-    if (n >= a.N0) lbar = cell_step_si<kGrad>(a, sl, n - a.N0 - sl.c0, s, ld(a.load, si_at(n, S, s)), acc);
+    if (n >= a.N0)
+      lbar = cell_step_si<kGrad>(a, sl, n - a.N0 - sl.c0, s, ld(a.load, si_at(n, S, s)), acc,
+                                 make_float2(c[2].z, c[3].z), make_float2(c[2].y, c[3].y));
     const uint32_t o0 = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p0) : p0, S, s);
     if (a.at_out) store_stream(at32(a.at_out, o0), at_d);
     if (a.slew_out) store_stream(at32(a.slew_out, o0), sl_d);
@@ -3589,7 +3555,7 @@ void note_forward(sta_graph* g, const void* state, bool smooth, float gamma) {
       break;
     }
   if (v.size() >= sta_graph::kFwdSeen) v.erase(v.begin());
-  v.push_back(sta_graph::FwdSeen{state, smooth, gamma});
+  v.push_back(sta_graph::FwdSeen{state, smooth, gamma, g->lanes_kernels()});
 }
 
 // A gradient needs the smoothed arrivals of a forward with the same gamma on this graph.
@@ -3600,6 +3566,9 @@ sta_status check_grad_state(const sta_graph* g, const void* state, float gamma) 
       return fail(STA_E_STATE, "the gradient needs a forward state computed with STA_SMOOTH");
     if (bits(it->gamma) != bits(gamma))
       return fail(STA_E_STATE, "the gradient's gamma differs from the gamma of the forward state");
+    if (it->lanes != g->lanes_kernels())
+      return fail(STA_E_STATE, "the forward state was computed under a schedule of the other kernel family "
+                               "(snapshot lanes or thread per net against lane groups); run sta_forward again");
     return STA_OK;
   }
   return fail(STA_E_STATE, "the forward state was not produced by sta_forward on this graph");

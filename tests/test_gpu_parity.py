@@ -1,6 +1,7 @@
 """GPU parity: the HIP sweep (through the C ABI) against the FP64 oracle, element by element."""
 from __future__ import annotations
 
+import dataclasses
 import math
 
 import numpy as np
@@ -445,6 +446,38 @@ def test_cte_level_kernels_match_oracle():
         torch.cuda.synchronize()
         for k in ("rat", "slack", "at", "slew"):
             assert np.array_equal(o[k].cpu().numpy(), got[k], equal_nan=True), k
+
+
+def test_gradient_refuses_a_mismatched_forward_state():
+    # sta_backward with STA_GRAD checks the state it is given: a forward without the smoothed
+    # arrival, with another gamma, or under a schedule of the other kernel family (the
+    # thread-per-net backward takes each cell's softmax normaliser and worst-slew arc from its
+    # own forward's records) is refused; the same state then works under its own schedule.
+    from paper_2603_28381_amd.sta import STA_E_STATE, StaError
+    d = make_design(CFG0)
+    ref = O.run(d, gamma=GAMMA, grad="tns")
+    g = Graph.from_design(d)
+    g.levelize()
+    x = torch.tensor(d.x, device="cuda")
+    y = torch.tensor(d.y, device="cuda")
+    f0 = g.forward(x, y, gamma=GAMMA, smooth=False)
+    f1 = g.forward(x, y, gamma=GAMMA)
+    for f in (f0, dataclasses.replace(f1, gamma=2 * GAMMA)):     # the binding passes f.gamma
+        with pytest.raises(StaError) as e:
+            g.backward(x, y, f, rat=False, grad=True, pins=False)
+        assert e.value.code == STA_E_STATE
+    for first, second in (("groups", "thread"), ("thread", "groups")):
+        g.set_schedule(2, 2, 64, "groups", 16, first)
+        f = g.forward(x, y, gamma=GAMMA)
+        g.set_schedule(2, 2, 64, "groups", 16, second)
+        with pytest.raises(StaError) as e:
+            g.backward(x, y, f, rat=False, grad=True, pins=False)
+        assert e.value.code == STA_E_STATE and "kernel family" in str(e.value)
+        g.set_schedule(2, 2, 64, "groups", 16, first)
+        o = g.backward(x, y, f, rat=False, grad=True, pins=False)
+        torch.cuda.synchronize()
+        got = {"dx": o["dx"].cpu().numpy(), "dy": o["dy"].cpu().numpy()}
+        check_grad(got, ref, 1e-3, 1e-6)
 
 
 def test_tune_keeps_a_valid_schedule():
