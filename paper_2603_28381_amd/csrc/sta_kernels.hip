@@ -2418,8 +2418,9 @@ __host__ __device__ inline int si_bwd_hl2(int sl2, int kb, bool huge) {
   const int l2 = si_log2(kb) - (huge ? kSiHugeTpsL2 : kSiHeavyTpsL2);
   return sl2 < l2 ? sl2 : l2;
 }
-constexpr int kSiCacheHeavy = 4;     // sinks a heavy workgroup's thread keeps on chip
-constexpr int kSiRows = 17;          // LDS rows of kB floats in the backward: N_ACC reductions
+constexpr int kSiCacheHeavy = 16;    // sinks a heavy workgroup's thread keeps on chip (all of a
+                                     // net of up to 128 sinks at 8 threads per snapshot)
+constexpr int kSiRows = 29;          // LDS rows of kB floats in the backward: N_ACC reductions
                                      // and lbar, then the sink cache (kSiHeavy rows outside
                                      // heavy workgroups)
 __device__ __forceinline__ SiLane si_heavy_lane(int hl2, int S, int chunk) {
@@ -3068,7 +3069,7 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
 // workgroup per net and snapshot chunk, then the nets [nb, nh0), (64 >> sl2) per wave.
 template <bool kGrad, int kB>
 __global__ __launch_bounds__(kB) void k_bwd_level_si(int nb, int nh0, int nu0, int ne, Slots sl, BwdSiArgs a) {
-  __shared__ float sh[kSiRows * kB];
+  __shared__ float sh[(kGrad ? kSiRows : N_ACC + 1) * kB];   // the sink cache only with the gradient
   const int w = (int)(threadIdx.x >> 6);
   const int b = (int)blockIdx.x;
   const int hl2u = si_bwd_hl2(a.sl2, kB, true), hl2h = si_bwd_hl2(a.sl2, kB, false);
