@@ -216,12 +216,14 @@ sta_status sta_forward(sta_graph* g, const float* x, const float* y, sta_fwd_out
  * so several backward calls on one state (e.g. a required-time sweep and a gradient sweep
  * on two streams, each with its own workspace) may run concurrently; with checkpointing
  * it rebuilds records inside the state and calls on one state must not overlap.
- * Errors: STA_E_STATE (not levelized / not uploaded; with STA_GRAD also a state that the
- * latest of this graph's sta_forward calls into it did not compute with STA_SMOOTH and the
- * same gamma_ps, or under a schedule of the other kernel family -- snapshot lanes or
- * STA_LEVEL_THREAD against the lane-group schemes, whose backward takes the softmax
- * normaliser and worst-slew arc of each cell from the forward's records -- or that no
- * sta_forward on this graph produced), STA_E_INVALID.
+ * The forward and the backward of a state run under schedules of one kernel family: the
+ * snapshot-lane layout and STA_LEVEL_THREAD keep the state's records in another layout than
+ * the lane-group schemes, and their backward takes each cell's softmax normaliser and
+ * worst-slew arc from the forward's records.
+ * Errors: STA_E_STATE (not levelized / not uploaded; a state that the latest of this graph's
+ * sta_forward calls into it computed under a schedule of the other kernel family; with
+ * STA_GRAD also a state that call did not compute with STA_SMOOTH and the same gamma_ps, or
+ * that no sta_forward on this graph produced), STA_E_INVALID.
  * ------------------------------------------------------------------------------------- */
 sta_status sta_backward(sta_graph* g, const float* x, const float* y, const sta_fwd_out* fwd,
                         sta_bwd_out* out, uint32_t flags, float gamma_ps, sta_stream stream);

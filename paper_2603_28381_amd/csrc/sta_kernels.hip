@@ -2400,6 +2400,36 @@ __device__ __forceinline__ SiLane si_lane(int sl2, int S, int wave) {
 
 __device__ __forceinline__ uint32_t si_at(int i, uint32_t S, int s) { return (uint32_t)i * S + (uint32_t)s; }
 
+// Record r in the snapshot-lane kernels: three planes in its four 16-byte rows of S elements,
+// row 0 the arrival times of the four conditions (early rise, early fall, late rise, late
+// fall), row 1 their slews, the first half of row 2 (float2 element 2 (4 r + 2) S + s) the
+// late rise and fall smoothed arrivals; row 3 is unused.  A record of a snapshot moves 40
+// bytes, and a reader takes only the planes it needs.
+__device__ __forceinline__ float4 rec_at_si(const float4* __restrict__ rec, int r, uint32_t S, int s) {
+  return ld(rec, si_at(kRecChunks * r, S, s));
+}
+__device__ __forceinline__ float4 rec_sl_si(const float4* __restrict__ rec, int r, uint32_t S, int s) {
+  return ld(rec, si_at(kRecChunks * r + 1, S, s));
+}
+__device__ __forceinline__ uint32_t rec_ag_at(int r, uint32_t S, int s) {
+  return 2u * (uint32_t)(kRecChunks * r + 2) * S + (uint32_t)s;
+}
+__device__ __forceinline__ float2 rec_ag_si(const float4* __restrict__ rec, int r, uint32_t S, int s) {
+  return ld(reinterpret_cast<const float2*>(rec), rec_ag_at(r, S, s));
+}
+__device__ __forceinline__ void rec_store_si(float4* __restrict__ rec, int r, uint32_t S, int s, const float4& at,
+                                             const float4& sl, const float2& ag) {
+  *at32(rec, si_at(kRecChunks * r, S, s)) = at;
+  *at32(rec, si_at(kRecChunks * r + 1, S, s)) = sl;
+  *at32(reinterpret_cast<float2*>(rec), rec_ag_at(r, S, s)) = ag;
+}
+// Value of mode m (0 early, 1 late) for the input transition that drives output transition t
+// through an arc of unateness `same`, from a plane of the four conditions.
+__device__ __forceinline__ float plane_pick(const float4& v, int m, bool same, int t) {
+  const bool rise = same == (t == 0);
+  return m ? (rise ? v.z : v.w) : (rise ? v.x : v.y);
+}
+
 // Workgroups of heavy nets: each takes 1 << hl2 snapshots, so that (workgroup size) >> hl2
 // threads split the sinks of each snapshot; hl2 = sl2 for nets of up to kSiHuge sinks (a
 // workgroup per net and block of up to 64 snapshots) and min(sl2, 3) beyond (a workgroup per
@@ -2470,11 +2500,9 @@ __device__ __forceinline__ void rc_root_si(const RcSiArgs& a, int n, int p0, int
   const uint32_t S = (uint32_t)a.S;
   *at32(a.load, si_at(n, S, s)) = ld(a.pin_cap, (uint32_t)p0) + sum;
   *at32(a.wire, si_at(p0, S, s)) = make_float2(0.f, 0.f);
-  if (n < a.N0) {
-#pragma unroll
-    for (int k = 0; k < kRecChunks; ++k)
-      *at32(a.rec, si_at(kRecChunks * n + k, S, s)) = make_float4(a.pi_at, a.pi_slew, k >= 2 ? a.pi_at : 0.f, 0.f);
-  }
+  if (n < a.N0)
+    rec_store_si(a.rec, n, S, s, make_float4(a.pi_at, a.pi_at, a.pi_at, a.pi_at),
+                 make_float4(a.pi_slew, a.pi_slew, a.pi_slew, a.pi_slew), make_float2(a.pi_at, a.pi_at));
 }
 
 __device__ __forceinline__ void driver_xy_si(const float* __restrict__ x, const float* __restrict__ y,
@@ -2579,15 +2607,17 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int bas
     }
 #pragma unroll
     for (int i = 0; i < kArcLanes; ++i) w[i] = ld(a.wire, si_at(e[i].y, S, s));
+    float4 rat_[kArcLanes], rsl[kArcLanes];
+    float2 rag[kArcLanes];
+#pragma unroll
+    for (int i = 0; i < kArcLanes; ++i) {
+      const int src = max(e[i].x, 0);
+      rat_[i] = rec_at_si(a.rec, src, S, s);
+      rsl[i] = rec_sl_si(a.rec, src, S, s);
+      rag[i] = rec_ag_si(a.rec, src, S, s);
+    }
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      float4 cr[kArcLanes], cf[kArcLanes];
-#pragma unroll
-      for (int i = 0; i < kArcLanes; ++i) {
-        const int src = kRecChunks * max(e[i].x, 0) + 2 * m;
-        cr[i] = ld(a.rec, si_at(src, S, s));
-        cf[i] = ld(a.rec, si_at(src + 1, S, s));
-      }
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int k = 2 * m + t;
@@ -2595,12 +2625,13 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int bas
         float cm = neutral, sm = neutral, gm = -kInf, g[kArcLanes];
 #pragma unroll
         for (int i = 0; i < kArcLanes; ++i) {
-          const float4 ci = pick_tr(ell_positive(e[i]), t, cr[i], cf[i]);
-          const float sl_in = sink_slew(ci.y, w[i].y);
+          const bool same = ell_positive(e[i]);
+          const float sl_in = sink_slew(plane_pick(rsl[i], m, same, t), w[i].y);
           const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, ell_arc(e[i]), t, sl_in, load);
-          const float cand = valid[i] ? (ci.x + w[i].x) + v.d : neutral;
+          const float cand = valid[i] ? (plane_pick(rat_[i], m, same, t) + w[i].x) + v.d : neutral;
           const float sv = valid[i] ? v.s : neutral;
-          g[i] = valid[i] ? (ci.z + w[i].x) + v.d : -kInf;
+          const float ag_in = (same == (t == 0)) ? rag[i].x : rag[i].y;
+          g[i] = valid[i] ? (ag_in + w[i].x) + v.d : -kInf;
           if (m) {
             cm = fmaxf(cm, cand);
             sm = fmaxf(sm, sv);
@@ -2626,12 +2657,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int bas
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int m = k >> 1, t = k & 1;
-    const float ag = m ? (a.smooth ? fmaf(a.gamma, flog(ls[t]), lm[t]) : __builtin_nanf("")) : 0.f;
-    *at32(a.rec, si_at(kRecChunks * n + k, S, s)) = make_float4(bat[k], bsl[k], ag, 0.f);
-  }
+  const float2 ag = a.smooth ? make_float2(fmaf(a.gamma, flog(ls[0]), lm[0]), fmaf(a.gamma, flog(ls[1]), lm[1]))
+                             : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+  rec_store_si(a.rec, n, S, s, make_float4(bat[0], bat[1], bat[2], bat[3]), make_float4(bsl[0], bsl[1], bsl[2], bsl[3]),
+               ag);
 }
 
 // ---------------------------------------------------------------- endpoints, snapshot lanes
@@ -2656,13 +2685,13 @@ struct EpSiArgs {
 __device__ __forceinline__ EpVals endpoint_values_si(const EpSiArgs& a, int i, int s) {
   const uint32_t S = (uint32_t)a.S;
   const int e = ld(a.ep_pin, (uint32_t)i), r = ld(a.ep_net, (uint32_t)i);
-  const float4 c2 = ld(a.rec, si_at(kRecChunks * r + 2, S, s));   // late rise
-  const float4 c3 = ld(a.rec, si_at(kRecChunks * r + 3, S, s));   // late fall
+  const float4 at = rec_at_si(a.rec, r, S, s);    // late rise and fall in .z, .w
+  const float2 ag = rec_ag_si(a.rec, r, S, s);
   const float dl = ld(a.wire, si_at(e, S, s)).x;
   EpVals v;
-  v.worst = fminf(a.rat_late - (c2.x + dl), a.rat_late - (c3.x + dl));
-  const float u0 = -(a.rat_late - (c2.z + dl));
-  const float u1 = -(a.rat_late - (c3.z + dl));
+  v.worst = fminf(a.rat_late - (at.z + dl), a.rat_late - (at.w + dl));
+  const float u0 = -(a.rat_late - (ag.x + dl));
+  const float u1 = -(a.rat_late - (ag.y + dl));
   const float mx = fmaxf(u0, u1);
   const float e0 = expf((u0 - mx) * a.inv_gamma), e1 = expf((u1 - mx) * a.inv_gamma);
   const float z = e0 + e1;
@@ -2814,17 +2843,16 @@ __global__ __launch_bounds__(kBlock) void k_expand_si(ExpandSiArgs a) {
   const uint32_t S = (uint32_t)a.S;
   const int s = ln.s;
   const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
-  float4 c[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c[k] = ld(a.rec, si_at(kRecChunks * n + k, S, s));
+  const float4 at = rec_at_si(a.rec, n, S, s), sl = rec_sl_si(a.rec, n, S, s);
+  const float2 ag = a.atg ? rec_ag_si(a.rec, n, S, s) : make_float2(0.f, 0.f);
   for (int p = p0; p < p1; ++p) {
     const float2 w = ld(a.wire, si_at(p, S, s));
     const uint32_t o = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p) : p, S, s);
-    if (a.at) store_stream(at32(a.at, o), make_float4(c[0].x + w.x, c[1].x + w.x, c[2].x + w.x, c[3].x + w.x));
+    if (a.at) store_stream(at32(a.at, o), make_float4(at.x + w.x, at.y + w.x, at.z + w.x, at.w + w.x));
     if (a.slew)
-      store_stream(at32(a.slew, o), make_float4(sink_slew(c[0].y, w.y), sink_slew(c[1].y, w.y),
-                                                sink_slew(c[2].y, w.y), sink_slew(c[3].y, w.y)));
-    if (a.atg) store_stream(at32(a.atg, o), make_float2(c[2].z + w.x, c[3].z + w.x));
+      store_stream(at32(a.slew, o), make_float4(sink_slew(sl.x, w.y), sink_slew(sl.y, w.y), sink_slew(sl.z, w.y),
+                                                sink_slew(sl.w, w.y)));
+    if (a.atg) store_stream(at32(a.atg, o), make_float2(ag.x + w.x, ag.y + w.x));
   }
 }
 
@@ -2926,19 +2954,18 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
     if (e.x < 0) continue;
     const bool same = ell_positive(e);
     const float2 w = ld(a.wire, si_at(e.y, S, s));
-    float4 c[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) c[q] = ld(a.rec, si_at(kRecChunks * e.x + q, S, s));
+    const float4 isl = rec_sl_si(a.rec, e.x, S, s);             // the input's slews
+    const float2 iag = kGrad ? rec_ag_si(a.rec, e.x, S, s) : make_float2(0.f, 0.f);
     float4 rat_in = make_float4(0.f, 0.f, 0.f, 0.f), adj_in = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int m = k >> 1, t = k & 1;
       const int tp = same ? t : 1 - t;
-      const float4 ci = pick_tr(same, t, c[2 * m], c[2 * m + 1]);
-      const LutVal v = lut_eval<kGrad>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(ci.y, w.y), load);
+      const LutVal v =
+          lut_eval<kGrad>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(plane_pick(isl, m, same, t), w.y), load);
       set_comp(rat_in, 2 * m + tp, rat_o[k] - v.d);
       if (kGrad && m == 1) {
-        const float xg = (ci.z + w.x) + v.d;
+        const float xg = (((same == (t == 0)) ? iag.x : iag.y) + w.x) + v.d;
         const float dbar = fexp((xg - ag[t]) * a.inv_gamma) * abar[t];
         const bool star = open[t] && v.s == smax[t];
         open[t] = open[t] && !star;
@@ -2964,11 +2991,9 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   const uint32_t S = (uint32_t)a.S;
   const int s = ln.on ? ln.s : 0;
   const int p0 = ld(a.net_off, (uint32_t)n), p1 = ld(a.net_off, (uint32_t)n + 1u);
-  float4 c[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) c[k] = ld(a.rec, si_at(kRecChunks * n + k, S, s));
-  const float4 at_d = make_float4(c[0].x, c[1].x, c[2].x, c[3].x);
-  const float4 sl_d = make_float4(c[0].y, c[1].y, c[2].y, c[3].y);
+  const float4 at_d = rec_at_si(a.rec, n, S, s);
+  const float4 sl_d = rec_sl_si(a.rec, n, S, s);
+  const float2 ag_d = kGrad ? rec_ag_si(a.rec, n, S, s) : make_float2(0.f, 0.f);
   float xd = 0.f, yd = 0.f;
   if (kGrad && ln.on) driver_xy_si(a.x, a.y, a.io_perm, p0, S, s, xd, yd);
   float acc[N_ACC] = {-kInf, -kInf, kInf, kInf, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -3022,8 +3047,8 @@ __device__ __forceinline__ void bwd_net_si(const BwdSiArgs& a, const Slots& sl, 
   float lbar = 0.f;
   if (leader && ln.on) {
     if (n >= a.N0)
-      lbar = cell_step_si<kGrad>(a, sl, n - a.N0 - sl.c0, s, ld(a.load, si_at(n, S, s)), acc,
-                                 make_float2(c[2].z, c[3].z), make_float2(c[2].y, c[3].y));
+      lbar = cell_step_si<kGrad>(a, sl, n - a.N0 - sl.c0, s, ld(a.load, si_at(n, S, s)), acc, ag_d,
+                                 make_float2(sl_d.z, sl_d.w));
     const uint32_t o0 = si_at(a.io_perm ? ld(a.io_perm, (uint32_t)p0) : p0, S, s);
     if (a.at_out) store_stream(at32(a.at_out, o0), at_d);
     if (a.slew_out) store_stream(at32(a.slew_out, o0), sl_d);
@@ -3559,6 +3584,20 @@ void note_forward(sta_graph* g, const void* state, bool smooth, float gamma) {
   v.push_back(sta_graph::FwdSeen{state, smooth, gamma, g->lanes_kernels()});
 }
 
+// The two families of level kernels keep records in different layouts (the snapshot-lane
+// and thread-per-net kernels in planes): a backward reads a state that a forward of its own
+// family wrote.  A state this graph's forward calls never wrote passes here.
+sta_status check_state_family(const sta_graph* g, const void* state) {
+  for (auto it = g->fwd_seen.rbegin(); it != g->fwd_seen.rend(); ++it) {
+    if (it->state != state) continue;
+    if (it->lanes != g->lanes_kernels())
+      return fail(STA_E_STATE, "the forward state was computed under a schedule of the other kernel family "
+                               "(snapshot lanes or thread per net against lane groups); run sta_forward again");
+    return STA_OK;
+  }
+  return STA_OK;
+}
+
 // A gradient needs the smoothed arrivals of a forward with the same gamma on this graph.
 sta_status check_grad_state(const sta_graph* g, const void* state, float gamma) {
   for (auto it = g->fwd_seen.rbegin(); it != g->fwd_seen.rend(); ++it) {
@@ -3606,6 +3645,8 @@ extern "C" sta_status sta_backward(sta_graph* g, const float* x, const float* y,
   const bool grad = (flags & STA_GRAD) != 0;
   if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
   if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  st = check_state_family(g, fwd->state);
+  if (st != STA_OK) return st;
   if (grad) {
     st = check_grad_state(g, fwd->state, gamma_ps);
     if (st != STA_OK) return st;
@@ -3669,6 +3710,8 @@ extern "C" sta_status sta_backward_noalloc(sta_graph* g, const float* x, const f
   const bool grad = (flags & STA_GRAD) != 0;
   if (grad && (!x || !y)) return fail(STA_E_INVALID, "x and y are required for the gradient");
   if (grad && !(gamma_ps > 0.f && std::isfinite(gamma_ps))) return fail(STA_E_INVALID, "gamma must be positive");
+  st = check_state_family(g, fwd->state);
+  if (st != STA_OK) return st;
   if (grad) {
     st = check_grad_state(g, fwd->state, gamma_ps);
     if (st != STA_OK) return st;

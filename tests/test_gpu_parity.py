@@ -448,11 +448,13 @@ def test_cte_level_kernels_match_oracle():
             assert np.array_equal(o[k].cpu().numpy(), got[k], equal_nan=True), k
 
 
-def test_gradient_refuses_a_mismatched_forward_state():
-    # sta_backward with STA_GRAD checks the state it is given: a forward without the smoothed
-    # arrival, with another gamma, or under a schedule of the other kernel family (the
-    # thread-per-net backward takes each cell's softmax normaliser and worst-slew arc from its
-    # own forward's records) is refused; the same state then works under its own schedule.
+def test_backward_refuses_a_mismatched_forward_state():
+    # sta_backward checks the state it is given: a gradient against a forward without the
+    # smoothed arrival or with another gamma is refused, and so is any backward (required
+    # times alone too) under a schedule of the other kernel family (the thread-per-net kernels
+    # keep records in planes, and their backward takes each cell's softmax normaliser and
+    # worst-slew arc from the forward's records); the same state then works under its own
+    # schedule.
     from paper_2603_28381_amd.sta import STA_E_STATE, StaError
     d = make_design(CFG0)
     ref = O.run(d, gamma=GAMMA, grad="tns")
@@ -470,9 +472,10 @@ def test_gradient_refuses_a_mismatched_forward_state():
         g.set_schedule(2, 2, 64, "groups", 16, first)
         f = g.forward(x, y, gamma=GAMMA)
         g.set_schedule(2, 2, 64, "groups", 16, second)
-        with pytest.raises(StaError) as e:
-            g.backward(x, y, f, rat=False, grad=True, pins=False)
-        assert e.value.code == STA_E_STATE and "kernel family" in str(e.value)
+        for grad in (True, False):
+            with pytest.raises(StaError) as e:
+                g.backward(x, y, f, rat=True, grad=grad, pins=False)
+            assert e.value.code == STA_E_STATE and "kernel family" in str(e.value)
         g.set_schedule(2, 2, 64, "groups", 16, first)
         o = g.backward(x, y, f, rat=False, grad=True, pins=False)
         torch.cuda.synchronize()
