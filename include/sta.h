@@ -366,15 +366,16 @@ sta_status sta_tune_cached(sta_graph* g, sta_schedule* sch);
  * are cut into segments of k levels.  The forward keeps the arrival record (AT, slew,
  * smoothed AT of the driver) only of the nets still needed after their segment ends: nets
  * read by a cell in a later segment (the live frontier of a segment boundary; the graph is
- * a DAG, so a net can be read many levels later), nets driving an endpoint and level-0
- * nets.  All other nets of a segment share one buffer that the next segment overwrites.
+ * a DAG, so a net can be read many levels later) and level-0 nets.  All other nets of a
+ * segment share one buffer that the next segment overwrites; the forward takes the values
+ * of a segment's endpoints (late arrival, smoothed slack and its weights) before that.
  * sta_backward walks the segments last to first, recomputes the dropped records of a
- * segment from the frontier, then runs that segment's backward levels.  Results are
+ * segment from the frontier, seeds its endpoints, then runs its backward levels.  Results are
  * bit-identical to the run without checkpointing; fwd_state_bytes shrinks (see
  * sta_get_checkpointing), and on star-net graphs bwd_workspace_bytes too (a sink's required
- * times and adjoint live from the cell step writing them to its net's step: nets whose sinks
- * are all written and read inside one segment share a buffer that the next segment
- * reuses; each sink's wire delay and impulse in the state follow the same slots, so the RC
+ * times and adjoint live from the cell step or endpoint seed writing them to its net's step:
+ * nets whose sinks are all written and read inside one segment share a buffer that the next
+ * segment reuses; each sink's wire delay and impulse in the state follow the same slots, so the RC
  * stage then runs in lane groups, in passes before each segment); the backward pays one
  * extra forward pass, and RC pass, over the dropped nets.
  *

@@ -110,9 +110,11 @@ static GroupRange group_range(const int* cls_count, int base, int g0) {
 
 // Record slots under checkpointing (stride k > 0): a net of level l >= 1 belongs to
 // segment (l-1)/k, which ends at level 1 + k*((l-1)/k + 1).  It is kept if a cell of a
-// level at or past that end reads it, if it drives an endpoint, or if l = 0; kept nets get
-// slots in canonical order (level-0 nets first, so their slot is their index), the other
-// nets of a segment share the slots after them.  Without checkpointing slot = net.
+// level at or past that end reads it, or if l = 0; kept nets get slots in canonical order
+// (level-0 nets first, so their slot is their index), the other nets of a segment share the
+// slots after them.  Without checkpointing slot = net.  Endpoints need no kept record: the
+// forward takes their values while their segment is in the buffer, and the backward seeds
+// them right before their segment (ep_grp).
 // Sink workspace slots under checkpointing (see sta_graph::sink_base).  lvl: level of each
 // canonical net.
 static void build_sink_slots(sta_graph* g, const std::vector<int>& lvl) {
@@ -127,7 +129,7 @@ static void build_sink_slots(sta_graph* g, const std::vector<int>& lvl) {
   for (int n = 0; n < N; ++n) {
     const int l = lvl[n];
     for (int p = g->c_net_off[n] + 1; p < g->c_net_off[n + 1] && !kept[n]; ++p)
-      if (l == 0 || is_ep[p] || reader_level[p] < 0 || seg(reader_level[p]) != seg(l)) kept[n] = 1;
+      if (l == 0 || (reader_level[p] < 0 ? !is_ep[p] : seg(reader_level[p]) != seg(l))) kept[n] = 1;
   }
   g->sink_base.assign(N, 0);
   int next = 0;
@@ -166,6 +168,8 @@ static void build_checkpoints(sta_graph* g) {
   g->sink_base.clear();
   g->sslot.clear();
   g->ep_sslot.clear();
+  g->ep_grp.clear();
+  g->ep_grp_off.clear();
   g->rc_seg.clear();
   g->n_sslots = g->n_sslots_kept = 0;
   if (k <= 0) {
@@ -185,7 +189,6 @@ static void build_checkpoints(sta_graph* g) {
       maxc[g->c_cin_src[a]] = std::max(maxc[g->c_cin_src[a]], lc);
   }
   std::vector<char> kept(N, 0);
-  for (int n : g->ep_net) kept[n] = 1;
   for (int n = 0; n < N; ++n) {
     const int l = lvl[n];
     if (l == 0 || maxc[n] >= 1 + k * ((l - 1) / k + 1)) kept[n] = 1;
@@ -205,6 +208,16 @@ static void build_checkpoints(sta_graph* g) {
   g->n_rec = nk + widest;
   g->ep_rec.resize(g->ep_net.size());
   for (size_t i = 0; i < g->ep_net.size(); ++i) g->ep_rec[i] = g->rec_loc[g->ep_net[i]];
+  // Endpoints grouped by their net: group 0 the level-0 nets' (kept records and slots),
+  // group 1 + j segment j's; ascending endpoint index within a group.
+  const int n_seg = (int)g->seg_lo.size() - 1;
+  g->ep_grp_off.assign((size_t)n_seg + 2, 0);
+  auto grp = [&](int i) { const int l = lvl[g->ep_net[i]]; return l == 0 ? 0 : 1 + (l - 1) / k; };
+  for (size_t i = 0; i < g->ep_net.size(); ++i) ++g->ep_grp_off[(size_t)grp((int)i) + 1];
+  for (int j = 0; j <= n_seg; ++j) g->ep_grp_off[(size_t)j + 1] += g->ep_grp_off[(size_t)j];
+  g->ep_grp.assign(g->ep_net.size(), 0);
+  std::vector<int> fill(g->ep_grp_off.begin(), g->ep_grp_off.end() - 1);
+  for (size_t i = 0; i < g->ep_net.size(); ++i) g->ep_grp[(size_t)fill[(size_t)grp((int)i)]++] = (int)i;
   if (g->c_parent.empty()) build_sink_slots(g, lvl);
 }
 
@@ -998,7 +1011,7 @@ sta_status sta_graph_upload(sta_graph* g) {
       (s = up(d.ep_blk_off, g->ep_blk_off)) ||
       (s = up(d.sched_all, g->rc_sched.empty() ? g->sched_all : g->rc_sched)) || (s = up(d.si_heavy, g->si_heavy)) || (s = up(d.si_huge, g->si_huge)) ||
       (!g->sink_base.empty() && ((s = up(d.sink_base, g->sink_base)) || (s = up(d.ep_sslot, g->ep_sslot)))) ||
-      (g->ckpt_stride > 0 && (s = up(d.rec_loc, g->rec_loc))) ||
+      (g->ckpt_stride > 0 && ((s = up(d.rec_loc, g->rec_loc)) || (s = up(d.ep_grp, g->ep_grp)))) ||
       (!g->c_parent.empty() && ((s = up(d.parent, g->c_parent)) || (s = up(d.tree_order, g->c_tree_order)) ||
                                 (s = up(d.tree_node, g->c_tree_node)) || (s = up(d.tree_blk_net, g->tree_blk_net)) ||
                                 (s = up(d.tree_blk_depth, g->tree_blk_depth)) || (s = up(d.tree_big, g->tree_big)))) ||

@@ -100,6 +100,7 @@ struct DeviceGraph {
   float4* lut_coef = nullptr;  // [n_arcs * 2 * 36 * 2] bilinear coefficients {a, b, c, d}
   int* sink_base = nullptr;    // [N] checkpointing (stars): first slot of each net's sinks
   int* ep_sslot = nullptr;     // [E] checkpointing (stars): workspace slot of each endpoint
+  int* ep_grp = nullptr;       // [E] checkpointing: endpoint indices grouped by segment
   int* si_heavy = nullptr;     // snapshot-inner RC: canonical nets of kSiHeavy+1..kSiHuge sinks,
   int* si_huge = nullptr;      // and of more than kSiHuge
   size_t bytes = 0;
@@ -160,10 +161,13 @@ struct sta_graph {
                                                // and of more than kSiHuge sinks (a level's nets
                                                // ascend in pin count)
   std::vector<int> rec_loc, seg_lo, ep_rec;
+  // Checkpointing: endpoint indices by the segment of their net, group g at
+  // ep_grp[ep_grp_off[g] .. ep_grp_off[g + 1]) (group 0: level-0 nets, 1 + j: segment j).
+  std::vector<int> ep_grp, ep_grp_off;
   // Sink workspace slots under checkpointing (star nets): a sink's required times and
-  // adjoint live from the cell step that writes them to its net's step; sinks whose net and
-  // reading cell share a segment (and are not endpoints) share a segment buffer, the others
-  // keep a slot.  A net's sinks take consecutive slots from sink_base[net] (kept nets first,
+  // adjoint live from the cell step (or, at an endpoint, the seed) that writes them to its
+  // net's step; sinks whose net and reading cell share a segment, and endpoints, share a
+  // segment buffer, the others keep a slot.  A net's sinks take consecutive slots from sink_base[net] (kept nets first,
   // then each segment's other nets from the buffer's start).  Empty without segmentation:
   // the slot of a sink is its pin.
   std::vector<int> sink_base, sslot, ep_sslot;

@@ -1257,8 +1257,10 @@ struct EpArgs {
   float rat_late, hold, gamma, inv_gamma, scale;
   int smooth, wns_mode;
   Snap snap;
-  float4* epv;        // per endpoint {s_e, w_rise, w_fall, 0}: written by the partials, read by the seeds
+  float4* epv;        // per endpoint {s_e, w_rise, w_fall, worst slack}: written by the partials
+                      // (by k_ep_values under checkpointing), read by the seeds
   const int* ep_sslot;  // checkpointing: each endpoint's workspace slot (NULL: its pin)
+  int from_epv = 0;     // the partials read epv instead of records (checkpointing)
 };
 
 // The endpoint arguments of snapshot blockIdx.y.
@@ -1338,8 +1340,14 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
   const bool act = i < a.ep_design_off[dsg + 1];
   double tns = 0.0, wmin = __builtin_huge_val(), tnsg = 0.0, v = -__builtin_huge_val();
   if (act) {
-    const EpVals ev = endpoint_values(a, i);
-    a.epv[i] = make_float4(ev.sg, ev.w0, ev.w1, 0.f);   // kept for the backward's seeds
+    EpVals ev;
+    if (a.from_epv) {                                  // taken per segment (k_ep_values)
+      const float4 q = a.epv[i];
+      ev = EpVals{q.w, q.x, q.y, q.z};
+    } else {
+      ev = endpoint_values(a, i);
+      a.epv[i] = make_float4(ev.sg, ev.w0, ev.w1, ev.worst);   // kept for the backward's seeds
+    }
     tns = fmin(0.0, (double)ev.worst);
     wmin = ev.worst;
     const double s = ev.sg, g = a.gamma;
@@ -1412,9 +1420,11 @@ __global__ __launch_bounds__(kBlock) void k_ep_finalize(EpArgs a0) {
 
 // Seeds of the backward sweep at the endpoints: constrained required times, and the
 // adjoint of the smoothed objective with respect to each endpoint's smoothed arrival.
-__global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
-  const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
-  if (i >= a0.E) return;
+// Seeds of the endpoints list[0..n) (every endpoint when list is NULL and n = E).
+__global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0, const int* __restrict__ list, int n) {
+  const int t = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (t >= n) return;
+  const int i = list ? list[t] : t;
   const EpArgs a = ep_snap(a0);
   const int e = a.ep_sslot ? a.ep_sslot[i] : a.ep_pin[i];   // the endpoint's workspace slot
   a.sink[rat_at(e)] = make_float4(a.hold, a.hold, a.rat_late, a.rat_late);
@@ -1436,6 +1446,17 @@ __global__ __launch_bounds__(kBlock) void k_ep_seed(EpArgs a0) {
     const float sc = a.scale_dev ? a.scale * (float)a.scale_dev[0] : a.scale;
     a.sink[adj_at(e)] = make_float4(-sc * coef * ev.w0, -sc * coef * ev.w1, 0.f, 0.f);
   }
+}
+
+// Under checkpointing: the values of the endpoints list[0..n), taken while their nets'
+// records and wire values are in the segment's slots; the partials and seeds read them.
+__global__ __launch_bounds__(kBlock) void k_ep_values(EpArgs a0, const int* __restrict__ list, int n) {
+  const int t = (int)(blockIdx.x * kBlock + threadIdx.x);
+  if (t >= n) return;
+  const EpArgs a = ep_snap(a0);
+  const int i = list[t];
+  const EpVals ev = endpoint_values(a, i);
+  a.epv[i] = make_float4(ev.sg, ev.w0, ev.w1, ev.worst);
 }
 
 // ---------------------------------------------------------------------------- outputs
@@ -3357,15 +3378,35 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
       k_rc<<<snap_grid(g, range_grid(g->all_range)), kBlock, 0, s>>>(ra);
   }
 
+  EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
+            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
+            nullptr, 0, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
+            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn,
+            reinterpret_cast<float4*>(sb + g->state.epv), d.ep_sslot};
+  // Under checkpointing each group of endpoints takes its values while its segment's records
+  // and wire values are in their slots: group 0 (level-0 nets) after the RC stage, segment j's
+  // before segment j + 1's RC pass, the last after the sweep.
+  const bool ckpt = g->ckpt_stride > 0;
+  auto ep_values = [&](int grp) {
+    const int lo = g->ep_grp_off[(size_t)grp], n = g->ep_grp_off[(size_t)grp + 1] - lo;
+    if (n <= 0) return;
+    LaunchTimer t(g, s, STA_K_EP_PARTIAL);
+    k_ep_values<<<dim3((unsigned)((n + kBlock - 1) / kBlock), g->n_snap), kBlock, 0, s>>>(ea, d.ep_grp + lo, n);
+  };
+  if (ckpt) ep_values(0);
   const FwdArgs fa{wire, d.lut_grid, d.lut_coef, lut_keys(g), gamma_ps, smooth ? 1.0f / gamma_ps : 0.f,
                    smooth ? 1 : 0};
   const bool cte = g->sched_cfg.level_scheme == STA_LEVEL_CTE;
   for (int l = 1; l < g->L; ++l) {
-    if (rc_passes) {                           // a segment starts: its nets' RC pass
+    if (ckpt) {                                // a segment starts: its nets' RC pass
       const auto it = std::find(g->seg_lo.begin(), g->seg_lo.end() - 1, l);
       if (it != g->seg_lo.end() - 1) {
-        LaunchTimer t(g, s, STA_K_RC);
-        rc_pass(g, s, ra, 1 + (int)(it - g->seg_lo.begin()));
+        const int j = (int)(it - g->seg_lo.begin());
+        if (j > 0) ep_values(j);               // the previous segment's endpoints
+        if (rc_passes) {
+          LaunchTimer t(g, s, STA_K_RC);
+          rc_pass(g, s, ra, 1 + j);
+        }
       }
     }
     const Slots sl = level_slots(g, l);
@@ -3378,11 +3419,8 @@ sta_status launch_forward(sta_graph* g, const float* x, const float* y, const st
       fwd_level_launch(g, s, sl, 0, (int)sn.state, d.ell, load, d.rec_loc, rec, fa);
   }
 
-  EpArgs ea{d.ep_pin, d.ep_net, d.ep_design, d.ep_design_off, d.ep_blk_off, rec, wire,
-            reinterpret_cast<double*>(sb + g->state.part), reinterpret_cast<double*>(sb + g->state.fin), out->scalars,
-            nullptr, 0, nullptr, g->E, g->n_designs, g->cons.t_clk - g->cons.setup, g->cons.hold,
-            smooth ? gamma_ps : 1.0f, smooth ? 1.0f / gamma_ps : 1.0f, 1.0f, smooth ? 1 : 0, 0, sn,
-            reinterpret_cast<float4*>(sb + g->state.epv), d.ep_sslot};
+  if (ckpt && g->seg_lo.size() > 1) ep_values((int)g->seg_lo.size() - 1);   // the last segment's
+  ea.from_epv = ckpt ? 1 : 0;
   if (g->n_ep_blocks > 0) {
     LaunchTimer t(g, s, STA_K_EP_PARTIAL);
     k_ep_partials<<<dim3(g->n_ep_blocks, g->n_snap), kBlock, 0, s>>>(ea);
@@ -3422,10 +3460,17 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
             grad ? 1 : 0, out->grad_scale_dev, g->E, g->n_designs, g->cons.t_clk - g->cons.setup,
             g->cons.hold, grad ? gamma_ps : 1.0f, grad ? 1.0f / gamma_ps : 1.0f, out->grad_scale, 1,
             (flags & STA_GRAD_WNS) ? 1 : 0, snap_of(g), reinterpret_cast<float4*>(sb + g->state.epv), d.ep_sslot};
-  if (g->E > 0) {
+  // Seeds: every endpoint at once, or under checkpointing each group right before its
+  // segment's levels (its slots may be a segment buffer's), level-0 nets' first.
+  auto ep_seed = [&](const int* list, int n) {
+    if (n <= 0) return;
     LaunchTimer t(g, s, STA_K_EP_SEED);
-    k_ep_seed<<<dim3((g->E + kBlock - 1) / kBlock, g->n_snap), kBlock, 0, s>>>(ea);
-  }
+    k_ep_seed<<<dim3((unsigned)((n + kBlock - 1) / kBlock), g->n_snap), kBlock, 0, s>>>(ea, list, n);
+  };
+  if (g->ckpt_stride <= 0)
+    ep_seed(nullptr, g->E);
+  else
+    ep_seed(d.ep_grp, g->ep_grp_off[1]);
 
   const bool tree = !g->c_parent.empty();
   BwdArgs ba{d.net_off, d.pin_cap, d.ell, io, x, y, d.lut_grid, d.lut_coef, lut_keys(g),
@@ -3499,6 +3544,7 @@ sta_status launch_backward(sta_graph* g, const float* x, const float* y, const s
         LaunchTimer t(g, s, STA_K_RECOMPUTE);
         fwd_level_launch(g, s, sl, g->n_kept, ss, d.ell, load, d.rec_loc, rec, fa);
       }
+      ep_seed(d.ep_grp + g->ep_grp_off[(size_t)j + 1], g->ep_grp_off[(size_t)j + 2] - g->ep_grp_off[(size_t)j + 1]);
       for (int l = hi - 1; l >= lo; --l) bwd_level(l);
     }
     bwd_level(0);
