@@ -124,16 +124,16 @@ struct LutVal {
 // Bilinear table lookup with linear extrapolation (Sec. 3.1.2).  The delay and slew tables
 // of one arc and output transition share the cell, so both come from two 16-byte loads of
 // precomputed coefficients v = a + b*tx + c*ty + d*tx*ty.
+__device__ __forceinline__ int lut_cell(const LutKeys& keys, float xv, float yv) {
+  return find_cell(xv, keys.x) * (STA_LUT_N - 1) + find_cell(yv, keys.y);
+}
+__device__ __forceinline__ uint32_t lut_coef_at(int arc, int tr, int cell) {
+  return ((uint32_t)(arc * 2 + tr) * kLutCells + (uint32_t)cell) * 2;
+}
 template <bool kPartials>
-__device__ __forceinline__ LutVal lut_eval(const float4* __restrict__ grid, const float4* __restrict__ coef,
-                                           const LutKeys& keys, int arc, int tr, float xv, float yv) {
-  const int cell = find_cell(xv, keys.x) * (STA_LUT_N - 1) + find_cell(yv, keys.y);
-  const float4 g = ld(grid, (uint32_t)cell);
+__device__ __forceinline__ LutVal lut_apply(const float4& g, const float4& cd, const float4& cs, float xv, float yv) {
   const float tx = (xv - g.x) * g.y;
   const float ty = (yv - g.z) * g.w;
-  const uint32_t ci = ((uint32_t)(arc * 2 + tr) * kLutCells + (uint32_t)cell) * 2;
-  const float4 cd = ld(coef, ci);
-  const float4 cs = ld(coef, ci + 1);
   const float bd = fmaf(cd.w, ty, cd.y);
   const float bs = fmaf(cs.w, ty, cs.y);
   LutVal r;
@@ -148,6 +148,43 @@ __device__ __forceinline__ LutVal lut_eval(const float4* __restrict__ grid, cons
     r.ddx = r.ddy = r.dsx = r.dsy = 0.f;
   }
   return r;
+}
+template <bool kPartials>
+__device__ __forceinline__ LutVal lut_eval(const float4* __restrict__ grid, const float4* __restrict__ coef,
+                                           const LutKeys& keys, int arc, int tr, float xv, float yv) {
+  const int cell = lut_cell(keys, xv, yv);
+  const uint32_t ci = lut_coef_at(arc, tr, cell);
+  return lut_apply<kPartials>(ld(grid, (uint32_t)cell), ld(coef, ci), ld(coef, ci + 1), xv, yv);
+}
+
+// Table memory read as constant (it is never written while a kernel runs), so that a load
+// whose address is uniform over the wave can take the scalar path.
+struct alignas(16) Raw4 { float x, y, z, w; };
+typedef const __attribute__((address_space(4))) Raw4 ConstRaw4;
+__device__ __forceinline__ float4 ld_const(const float4* base, uint32_t i) {
+  ConstRaw4* p = (ConstRaw4*)(const __attribute__((address_space(4))) void*)base;
+  return make_float4(p[i].x, p[i].y, p[i].z, p[i].w);
+}
+
+// The same lookup in the snapshot-lane kernels, whose wave usually serves one arc for 64
+// snapshots that fall in one table cell: the first active lane's coefficients come through
+// scalar loads for the whole wave, and only lanes that want another cell load their own
+// through the vector cache (none, when every lane shares the cell).  The values, and so the
+// results, are the same either way.
+template <bool kPartials>
+__device__ __forceinline__ LutVal lut_eval_si(const float4* __restrict__ grid, const float4* __restrict__ coef,
+                                              const LutKeys& keys, int arc, int tr, float xv, float yv) {
+  const int cell = lut_cell(keys, xv, yv);
+  const uint32_t ci = lut_coef_at(arc, tr, cell);
+  const uint32_t c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)ci);
+  const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane(cell);
+  float4 g = ld_const(grid, k0), cd = ld_const(coef, c0), cs = ld_const(coef, c0 + 1);
+  if (ci != c0) {
+    g = ld(grid, (uint32_t)cell);
+    cd = ld(coef, ci);
+    cs = ld(coef, ci + 1);
+  }
+  return lut_apply<kPartials>(g, cd, cs, xv, yv);
 }
 
 // Hardware approximations (about 1 ulp) of exp, log, square root and reciprocal: one
@@ -2648,7 +2685,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_level_si(int nc, int n0, int bas
         for (int i = 0; i < kArcLanes; ++i) {
           const bool same = ell_positive(e[i]);
           const float sl_in = sink_slew(plane_pick(rsl[i], m, same, t), w[i].y);
-          const LutVal v = lut_eval<false>(a.grid, a.coef, a.keys, ell_arc(e[i]), t, sl_in, load);
+          const LutVal v = lut_eval_si<false>(a.grid, a.coef, a.keys, ell_arc(e[i]), t, sl_in, load);
           const float cand = valid[i] ? (plane_pick(rat_[i], m, same, t) + w[i].x) + v.d : neutral;
           const float sv = valid[i] ? v.s : neutral;
           const float ag_in = (same == (t == 0)) ? rag[i].x : rag[i].y;
@@ -2983,7 +3020,7 @@ __device__ __forceinline__ float cell_step_si(const BwdSiArgs& a, const Slots& s
       const int m = k >> 1, t = k & 1;
       const int tp = same ? t : 1 - t;
       const LutVal v =
-          lut_eval<kGrad>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(plane_pick(isl, m, same, t), w.y), load);
+          lut_eval_si<kGrad>(a.grid, a.coef, a.keys, ell_arc(e), t, sink_slew(plane_pick(isl, m, same, t), w.y), load);
       set_comp(rat_in, 2 * m + tp, rat_o[k] - v.d);
       if (kGrad && m == 1) {
         const float xg = (((same == (t == 0)) ? iag.x : iag.y) + w.x) + v.d;
