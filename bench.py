@@ -501,7 +501,7 @@ def run_single(args) -> dict:
         kernels, roofline = kernel_table(prof, algorithmic_bytes(d, lev["level"]), args.steps)
         if args.workload == "cfg2" and not args.trees and args.fwd_cell_lanes == 16 and args.sweep_group_log2 == 2:
             roofline["traffic"] = counted_traffic("k_" + roofline["kernel"])
-        # The per-launch floor of this box for comparison: back-to-back dependent launches of
+        # The per-launch floor of this machine for comparison: back-to-back dependent launches of
         # a trivial elementwise kernel over as many threads as a level launch has.
         roofline["launch_floor_us"] = round(launch_floor_us(dev, 256 * 450), 2)
         if not args.trees:
