@@ -78,7 +78,7 @@ def algorithmic_bytes(d, level: np.ndarray, n_levels: int | None = None, snapsho
     return out
 
 
-def survey_bytes(d) -> dict:
+def whole_sweep_bytes(d) -> dict:
     """The per-step byte model of the sweep as a whole, written per pin (P pins, N nets,
     S = P - N sinks, C cells, A cell inputs; float32 values, int32 indices):
       forward   8P x,y + 4S cap + 4N offsets + 8C type and input offset + 4A input pin ids
@@ -96,14 +96,14 @@ def survey_bytes(d) -> dict:
     return {"forward": float(fwd), "backward": float(bwd)}
 
 
-def survey_roofline(d, kernels: dict, ms_step: float) -> dict:
-    """Fractions of HBM peak under survey_bytes: the backward level kernel (the whole backward
+def whole_sweep_roofline(d, kernels: dict, ms_step: float) -> dict:
+    """Fractions of HBM peak under whole_sweep_bytes: the backward level kernel (the whole backward
     sweep's bytes over its summed launch time), the forward sweep (RC, levels, endpoint
     scalars) and the whole step."""
-    b = survey_bytes(d)
+    b = whole_sweep_bytes(d)
     fwd_ms = sum(kernels[k]["ms_per_step"] for k in ("rc", "fwd_level", "ep_partial", "ep_final") if k in kernels)
     bl = kernels["bwd_level"]
-    out = {"model": "survey_bytes (whole-sweep byte model per pin)",
+    out = {"model": "whole_sweep_bytes (whole-sweep byte model per pin)",
            "bwd_level": {"bytes_per_launch": round(b["backward"] / bl["launches_per_step"], 1),
                          "avg_launch_us": round(bl["avg_us"], 3)},
            "forward_sweep": {"bytes": b["forward"], "ms": round(fwd_ms, 4)},
@@ -505,7 +505,7 @@ def run_single(args) -> dict:
         # a trivial elementwise kernel over as many threads as a level launch has.
         roofline["launch_floor_us"] = round(launch_floor_us(dev, 256 * 450), 2)
         if not args.trees:
-            roofline["survey_model"] = survey_roofline(d, kernels, ms)
+            roofline["whole_sweep_model"] = whole_sweep_roofline(d, kernels, ms)
 
     ckpt = None
     if args.ckpt_compare:
