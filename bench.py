@@ -437,7 +437,9 @@ def snapshot_graph_only(args, g1, d1, x1, y1, dev, best1, t_setup) -> dict:
         alg = algorithmic_bytes(d1, g1.levelization()["level"], snapshots=64)
         kernels, roofline = kernel_table(prof, alg, args.steps)
         roofline["scope"] = "the 64-snapshot graph's launches"
-        roofline["traffic"] = None
+        roofline["traffic"] = (counted_traffic("k_bwd_level_si", "sta_snapshot_lanes_64snap_kernel_stats.md")
+                               if args.snapshot_layout == "inner" and roofline["kernel"] == "bwd_level"
+                               else None)
     P = 64 * d1.n_pins
     return {
         "metric": "STA fwd+bwd pins/sec, 64 placement snapshots in one sweep",
