@@ -1387,10 +1387,10 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
     }
     tns = fmin(0.0, (double)ev.worst);
     wmin = ev.worst;
-    const double s = ev.sg, g = a.gamma;
-    // -LSE_g(0, -s) = -(max(0,-s) + g*log1p(exp(-|s|/g)))
-    tnsg = -(fmax(0.0, -s) + g * log1p(exp(-fabs(s) / g)));
-    v = -s;
+    // -LSE_g(0, -s) = -(max(0,-s) + g*log1p(exp(-|s|/g))), each term in float (about 1e-7
+    // relative); the sums run in float64 in a fixed order.
+    tnsg = -(double)(fmaxf(0.f, -ev.sg) + a.gamma * log1pf(expf(-fabsf(ev.sg) * a.inv_gamma)));
+    v = -(double)ev.sg;
   }
   double r4[4] = {tns, -wmin, tnsg, v};
   block_reduce<4>(r4, {false, true, false, true}, sh);
@@ -1398,7 +1398,7 @@ __global__ __launch_bounds__(kBlock) void k_ep_partials(EpArgs a0) {
   wmin = -r4[1];
   tnsg = r4[2];
   const double mb = r4[3];
-  double r1[1] = {act ? exp((v - mb) / (double)a.gamma) : 0.0};
+  double r1[1] = {act ? (double)expf((float)(v - mb) * a.inv_gamma) : 0.0};
   block_reduce<1>(r1, {false}, sh);
   const double sb = r1[0];
   if (threadIdx.x == 0) {
@@ -2793,9 +2793,18 @@ __global__ __launch_bounds__(kEpSiThreads) void k_ep_partials_si(EpSiArgs a) {
       *at32(a.epv, si_at(i, S, ln.s)) = make_float4(ev.sg, ev.w0, ev.w1, 0.f);
       tns += fmin(0.0, (double)ev.worst);
       wmin = fmin(wmin, (double)ev.worst);
-      const double sg = ev.sg, g = a.gamma;
-      tnsg += -(fmax(0.0, -sg) + g * log1p(exp(-fabs(sg) / g)));
-      lse_merge_d(m, sm, -sg, 1.0, g);
+      // Each term in float (about 1e-7 relative), summed in float64 in the fixed order.
+      tnsg += -(double)(fmaxf(0.f, -ev.sg) + a.gamma * log1pf(expf(-fabsf(ev.sg) * a.inv_gamma)));
+      const double v = -(double)ev.sg;
+      if (sm <= 0.0) {
+        m = v;
+        sm = 1.0;
+      } else if (v > m) {
+        sm = fma(sm, (double)expf((float)(m - v) * a.inv_gamma), 1.0);
+        m = v;
+      } else {
+        sm += (double)expf((float)(v - m) * a.inv_gamma);
+      }
     }
   }
   const int t = (int)threadIdx.x;
